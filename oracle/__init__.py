@@ -1,0 +1,206 @@
+"""FP64 CPU oracle for the real-space half of the split spherical convolution.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  It shares no code
+with the HIP library in ``paper_1211_3556_amd``; neither imports the other.
+
+The heavy loops live in ``arkcos_oracle.c`` (plain C, FP64, OpenMP), loaded
+through ctypes.  This module adds:
+
+* ``gaussian_bl`` -- the beam of the eq. 5 kernel family with C_l = 1,
+  b_l = exp(-l(l+1) sigma^2 / 2), sigma = FWHM / sqrt(8 ln 2) (Sec. 3);
+* ``legendre_coefficients`` -- the Legendre transform operator of eq. 1,
+  lambda_l = 2 pi int_0^theta_cut K(theta) P_l(cos theta) sin theta dtheta,
+  applied to the interpolated, truncated real-space kernel (Gauss-Legendre on
+  every linear segment of the table);
+* ``real_ylm`` -- real spherical harmonics for the Funk-Hecke checks.
+
+Parity pins for every function here are in ``tests/test_oracle_pins.py``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "arkcos_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_lp = ctypes.POINTER(ctypes.c_long)
+
+
+def build(force: bool = False) -> str:
+    """Compile the C oracle with gcc (FP64, no fast-math) into liboracle.so."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+               "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        build()
+        lib = ctypes.CDLL(_LIB)
+        lib.orc_ring.argtypes = [ctypes.c_long, ctypes.c_long, _dp, _dp, _dp, _lp, _lp, _dp]
+        lib.orc_pix2vec.argtypes = [ctypes.c_long, ctypes.c_long, _lp, _dp]
+        lib.orc_tabulate.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp]
+        for name in ("orc_convolve", "orc_convolve_exhaustive"):
+            getattr(lib, name).argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp,
+                                           _dp, ctypes.c_long, _lp, _dp, _lp]
+        lib.orc_knot_grad.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_long,
+                                      _dp, _dp, _dp]
+        lib.orc_threads.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _l(a):
+    return a.ctypes.data_as(_lp)
+
+
+def _check(rc, what):
+    if rc != 0:
+        raise ValueError("oracle %s failed with status %d" % (what, rc))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle runs with."""
+    return int(_load().orc_threads())
+
+
+def npix(nside: int) -> int:
+    return 12 * nside * nside
+
+
+def ring_geometry(nside: int) -> dict:
+    """Per-ring HEALPix RING geometry, rings 1..4N-1 (Gorski et al. 2005)."""
+    lib = _load()
+    nr = 4 * nside - 1
+    out = {k: np.empty(nr) for k in ("z", "s", "theta", "phi0")}
+    out["n"] = np.empty(nr, dtype=np.int64)
+    out["first"] = np.empty(nr, dtype=np.int64)
+    z, s, th, p0 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n, f = ctypes.c_long(), ctypes.c_long()
+    for i in range(1, nr + 1):
+        _check(lib.orc_ring(nside, i, ctypes.byref(z), ctypes.byref(s), ctypes.byref(th),
+                            ctypes.byref(n), ctypes.byref(f), ctypes.byref(p0)), "ring")
+        out["z"][i - 1], out["s"][i - 1], out["theta"][i - 1] = z.value, s.value, th.value
+        out["phi0"][i - 1], out["n"][i - 1], out["first"][i - 1] = p0.value, n.value, f.value
+    return out
+
+
+def pix2vec(nside: int, pix=None) -> np.ndarray:
+    """Unit vectors (npix, 3) of RING pixels (all pixels if pix is None)."""
+    if pix is None:
+        pix = np.arange(npix(nside), dtype=np.int64)
+    pix = np.ascontiguousarray(pix, dtype=np.int64)
+    out = np.empty((pix.size, 3))
+    _check(_load().orc_pix2vec(nside, pix.size, _l(pix), _d(out)), "pix2vec")
+    return out
+
+
+def gaussian_bl(fwhm_rad: float, lmax: int) -> np.ndarray:
+    """Gaussian beam b_l, l = 0..lmax (eq. 5 with C_l = 1)."""
+    sigma = fwhm_rad / np.sqrt(8.0 * np.log(2.0))
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    return np.exp(-0.5 * ell * (ell + 1.0) * sigma * sigma)
+
+
+def tabulate(bl, theta_cut: float, ntab: int) -> np.ndarray:
+    """Node table K(theta_k) = sum_l (2l+1)/(4 pi) b_l P_l(cos theta_k)."""
+    bl = np.ascontiguousarray(bl, dtype=np.float64)
+    out = np.empty(ntab)
+    _check(_load().orc_tabulate(_d(bl), bl.size - 1, float(theta_cut), ntab, _d(out)),
+           "tabulate")
+    return out
+
+
+def convolve(nside: int, theta_cut: float, ktab, x, pixels=None, exhaustive=False,
+             return_pairs=False):
+    """y[p] = Omega sum_{theta_pq < theta_cut} K(theta_pq) x[q] at `pixels`."""
+    lib = _load()
+    ktab = np.ascontiguousarray(ktab, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.size != npix(nside):
+        raise ValueError("map has %d pixels, Nside %d needs %d" % (x.size, nside, npix(nside)))
+    if pixels is None:
+        pix_ptr, neval = None, npix(nside)
+    else:
+        pixels = np.ascontiguousarray(pixels, dtype=np.int64)
+        pix_ptr, neval = _l(pixels), pixels.size
+    y = np.empty(neval)
+    pairs = np.empty(neval, dtype=np.int64)
+    fn = lib.orc_convolve_exhaustive if exhaustive else lib.orc_convolve
+    _check(fn(nside, float(theta_cut), ktab.size, _d(ktab), _d(x), neval, pix_ptr, _d(y),
+              _l(pairs)), "convolve")
+    return (y, pairs) if return_pairs else y
+
+
+def pair_counts(nside: int, theta_cut: float, pixels=None, exhaustive=False) -> np.ndarray:
+    """In-disc pair count per output pixel."""
+    _, pairs = convolve(nside, theta_cut, np.ones(2), np.zeros(npix(nside)), pixels,
+                        exhaustive, return_pairs=True)
+    return pairs
+
+
+def map_grad(nside: int, theta_cut: float, ktab, g) -> np.ndarray:
+    """dL/dx = A^T g.  The operator is symmetric (theta_pq = theta_qp and Omega
+    is the same for every pixel), so A^T g is the same direct sum applied to g."""
+    return convolve(nside, theta_cut, ktab, g)
+
+
+def knot_grad(nside: int, theta_cut: float, ntab: int, x, g) -> np.ndarray:
+    """dL/dK_k = Omega sum_p g[p] sum_q Lambda_k(theta_pq) x[q] (hat basis)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    out = np.empty(ntab)
+    _check(_load().orc_knot_grad(nside, float(theta_cut), ntab, _d(x), _d(g), _d(out)),
+           "knot_grad")
+    return out
+
+
+def legendre_coefficients(ktab, theta_cut: float, ells, order: int = 12) -> np.ndarray:
+    """lambda_l = 2 pi int_0^theta_cut K_lin(theta) P_l(cos theta) sin(theta) dtheta.
+
+    This is the Legendre transform operator of eq. 1 applied to the truncated,
+    linearly interpolated real-space kernel.  By the Funk-Hecke theorem a
+    band-limited Y_lm comes back from the continuous convolution scaled by
+    lambda_l.  Quadrature: Gauss-Legendre of `order` points on each segment.
+    """
+    from scipy.special import eval_legendre
+
+    ktab = np.asarray(ktab, dtype=np.float64)
+    ntab = ktab.size
+    h = theta_cut / (ntab - 1)
+    xg, wg = np.polynomial.legendre.leggauss(order)
+    tt = 0.5 * (xg + 1.0)                           # nodes on [0, 1]
+    ww = 0.5 * wg
+    k = np.arange(ntab - 1)[:, None]
+    theta = (k + tt[None, :]) * h                   # (ntab-1, order)
+    kval = (1.0 - tt[None, :]) * ktab[:-1, None] + tt[None, :] * ktab[1:, None]
+    base = 2.0 * np.pi * h * ww[None, :] * kval * np.sin(theta)
+    ct = np.cos(theta)
+    return np.array([np.sum(base * eval_legendre(int(l), ct)) for l in np.atleast_1d(ells)])
+
+
+def real_ylm(ell: int, m: int, vec) -> np.ndarray:
+    """Unnormalised real spherical harmonic P_l^m(z) cos(m phi) at unit vectors."""
+    from scipy.special import lpmv
+
+    vec = np.asarray(vec, dtype=np.float64)
+    z = np.clip(vec[:, 2], -1.0, 1.0)
+    phi = np.arctan2(vec[:, 1], vec[:, 0])
+    return lpmv(m, ell, z) * np.cos(m * phi)

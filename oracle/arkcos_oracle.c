@@ -1,0 +1,419 @@
+/*
+ * FP64 CPU oracle for the real-space half of the split spherical convolution.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.
+ * It shares no code, header, table or constant generator with the HIP
+ * library under paper_1211_3556_amd/.
+ *
+ * What it computes (Sutter, Wandelt & Elsner 2012, "Accelerating
+ * convolutions on the sphere with hybrid GPU/CPU kernel splitting"):
+ *
+ *   The kernel split of Sec. 2 (eq. 1) writes the approximate kernel as a
+ *   truncated harmonic-space part plus the Legendre transform of a
+ *   real-space part K_theta that is set to zero beyond theta_cut.  The
+ *   real-space part is applied to a pixelised map by direct summation on
+ *   the GPU (Sec. 2, the ARKCoS term of eq. 3), with the radial kernel
+ *   evaluated by interpolating a table of nodes (Sec. 3, the paragraph on
+ *   interpolation of the real-space kernel).  On a HEALPix map (Sec. 2,
+ *   Nside 2048) of equal-area pixels that sum is
+ *
+ *       y[p] = Omega * sum_{q : theta(p,q) < theta_cut} K(theta(p,q)) x[q],
+ *       Omega = 4 pi / Npix.
+ *
+ *   The kernel family of Sec. 3 (eq. 5) with C_l = 1 is a Gaussian beam
+ *   b_l; its real-space profile is the Legendre sum
+ *       K(theta) = sum_l (2l+1)/(4 pi) b_l P_l(cos theta),
+ *   i.e. the inverse of the Legendre transform operator P_{l theta} of eq. 1.
+ *
+ * Readings where the paper is silent (each listed in the design doc):
+ *   - the table has ntab nodes at theta_k = k h, h = theta_cut/(ntab-1),
+ *     and K is linear in theta between nodes;
+ *   - the cut is strict: pairs with theta >= theta_cut get K = 0;
+ *   - HEALPix RING pixel centres follow Gorski et al. (2005), the pixelisation
+ *     the paper names for its data.
+ *
+ * Everything is FP64, plain loops, one OpenMP "parallel for" over output
+ * pixels.  No blocking, no symmetry tricks, no approximation beyond the
+ * definition above.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* HEALPix RING geometry (Gorski et al. 2005).                               */
+/*   rings i = 1 .. 4N-1 from north to south                                 */
+/*   north cap  i <  N : z = 1 - i^2/(3N^2), 4i pixels, phi = (j+1/2) pi/(2i) */
+/*   belt  N <= i <= 3N: z = 4/3 - 2i/(3N), 4N pixels,                        */
+/*                       phi = (j + 1/2 [i-N even]) pi/(2N)                   */
+/*   south cap  i > 3N : mirror image of ring 4N-i                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double z;      /* cos(theta) of the ring                                  */
+    double s;      /* sin(theta), evaluated without cancellation near poles   */
+    double theta;  /* colatitude                                              */
+    long   n;      /* pixels in the ring                                     */
+    long   first;  /* RING index of the first pixel of the ring              */
+    double phi0;   /* longitude of pixel j = 0                                */
+    double dphi;   /* 2 pi / n                                                */
+} ring_rec;
+
+static void ring_of(long N, long i, ring_rec *r)
+{
+    const double dN = (double)N;
+    const long npix = 12L * N * N;
+    if (i < N) {                                   /* north polar cap */
+        double a = (double)i * (double)i / (3.0 * dN * dN);   /* 1 - z */
+        r->z = 1.0 - a;
+        r->s = sqrt(a * (2.0 - a));
+        r->n = 4 * i;
+        r->first = 2 * i * (i - 1);
+        r->phi0 = 0.5 * M_PI / (2.0 * (double)i);
+    } else if (i <= 3 * N) {                       /* equatorial belt */
+        r->z = 4.0 / 3.0 - 2.0 * (double)i / (3.0 * dN);
+        r->s = sqrt((1.0 - r->z) * (1.0 + r->z));
+        r->n = 4 * N;
+        r->first = 2 * N * (N - 1) + 4 * N * (i - N);
+        r->phi0 = (((i - N) % 2) == 0) ? 0.5 * M_PI / (2.0 * dN) : 0.0;
+    } else {                                       /* south polar cap */
+        long k = 4 * N - i;
+        double a = (double)k * (double)k / (3.0 * dN * dN);   /* 1 + z */
+        r->z = a - 1.0;
+        r->s = sqrt(a * (2.0 - a));
+        r->n = 4 * k;
+        r->first = npix - 2 * k * (k + 1);
+        r->phi0 = 0.5 * M_PI / (2.0 * (double)k);
+    }
+    r->theta = atan2(r->s, r->z);
+    r->dphi = 2.0 * M_PI / (double)r->n;
+}
+
+static ring_rec *ring_table(long N)
+{
+    long nr = 4 * N - 1;
+    ring_rec *t = (ring_rec *)malloc(sizeof(ring_rec) * (size_t)(nr + 1));
+    if (!t) return NULL;
+    for (long i = 1; i <= nr; ++i) ring_of(N, i, &t[i]);
+    return t;
+}
+
+/* ring index (1-based) and in-ring index of a RING-scheme pixel, by
+ * bisection on the first-pixel indices of the rings                       */
+static long ring_of_pixel(long N, const ring_rec *t, long p, long *j)
+{
+    long lo = 1, hi = 4 * N - 1;
+    while (lo < hi) {                       /* first ring whose end > p */
+        long mid = (lo + hi) / 2;
+        if (t[mid].first + t[mid].n <= p) lo = mid + 1; else hi = mid;
+    }
+    *j = p - t[lo].first;
+    return lo;
+}
+
+static void unit_vector(const ring_rec *r, long j, double v[3])
+{
+    double phi = r->phi0 + (double)j * r->dphi;
+    v[0] = r->s * cos(phi);
+    v[1] = r->s * sin(phi);
+    v[2] = r->z;
+}
+
+/* angular separation from the chord between unit vectors */
+static double separation(const double a[3], const double b[3])
+{
+    double dx = a[0] - b[0], dy = a[1] - b[1], dz = a[2] - b[2];
+    double half = 0.5 * sqrt(dx * dx + dy * dy + dz * dz);
+    if (half > 1.0) half = 1.0;
+    return 2.0 * asin(half);
+}
+
+/* linear interpolation of the node table on [0, theta_cut]; zero outside */
+static void interp_weights(double theta, double theta_cut, long ntab,
+                           long *i, double *t)
+{
+    double h = theta_cut / (double)(ntab - 1);
+    double u = theta / h;
+    long k = (long)floor(u);
+    if (k > ntab - 2) k = ntab - 2;
+    if (k < 0) k = 0;
+    *i = k;
+    *t = u - (double)k;
+}
+
+static double kernel_value(double theta, double theta_cut, long ntab,
+                           const double *ktab)
+{
+    if (!(theta < theta_cut)) return 0.0;
+    long i; double t;
+    interp_weights(theta, theta_cut, ntab, &i, &t);
+    return (1.0 - t) * ktab[i] + t * ktab[i + 1];
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour enumeration.  For output pixel p, every pixel q with            */
+/* theta(p,q) < theta_cut is listed once (with its separation).  Rings are   */
+/* admitted when |theta_ring - theta_p| < theta_cut; inside a ring the      */
+/* longitude window comes from the spherical law of cosines,                 */
+/*   cos dphi_max = (cos theta_cut - z_p z_s) / (s_p s_s),                   */
+/* widened by two pixels; the whole ring is taken when the window reaches   */
+/* around.  The exact separation test then decides membership.              */
+/* ------------------------------------------------------------------------ */
+typedef struct { long q; double theta; } orc_nb;
+typedef struct { orc_nb *v; long cap; int oom; } orc_list;
+
+static void list_push(orc_list *l, long count, long q, double th)
+{
+    if (count >= l->cap) {
+        long cap = l->cap ? 2 * l->cap : 4096;
+        orc_nb *nv = (orc_nb *)realloc(l->v, sizeof(orc_nb) * (size_t)cap);
+        if (!nv) { l->oom = 1; return; }
+        l->v = nv; l->cap = cap;
+    }
+    l->v[count].q = q;
+    l->v[count].theta = th;
+}
+
+static long neighbours(long N, const ring_rec *t, double theta_cut, long p,
+                       orc_list *out)
+{
+    long jp;
+    long ip = ring_of_pixel(N, t, p, &jp);
+    const ring_rec *rp = &t[ip];
+    double vp[3];
+    unit_vector(rp, jp, vp);
+    double phip = rp->phi0 + (double)jp * rp->dphi;
+    long count = 0;
+    for (long is = 1; is <= 4 * N - 1; ++is) {
+        const ring_rec *rs = &t[is];
+        if (!(fabs(rs->theta - rp->theta) < theta_cut + 1e-12)) continue;
+        double arg = (cos(theta_cut) - rp->z * rs->z) / (rp->s * rs->s);
+        long jlo, jhi, whole = 0;
+        if (arg <= -1.0) {
+            whole = 1;
+        } else {
+            if (arg > 1.0) arg = 1.0;
+            double half = acos(arg) + 2.0 * rs->dphi;
+            if (half >= M_PI) whole = 1;
+            else {
+                jlo = (long)ceil((phip - half - rs->phi0) / rs->dphi);
+                jhi = (long)floor((phip + half - rs->phi0) / rs->dphi);
+                if (jhi - jlo + 1 >= rs->n) whole = 1;
+            }
+        }
+        if (whole) { jlo = 0; jhi = rs->n - 1; }
+        for (long jj = jlo; jj <= jhi; ++jj) {
+            long jq = ((jj % rs->n) + rs->n) % rs->n;
+            double vq[3];
+            unit_vector(rs, jq, vq);
+            double th = separation(vp, vq);
+            if (th < theta_cut) {
+                list_push(out, count, rs->first + jq, th);
+                if (out->oom) return -1;
+                ++count;
+            }
+        }
+    }
+    return count;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported entry points (all return 0 on success, negative on bad input).   */
+/* ------------------------------------------------------------------------ */
+
+/* Geometry of ring i (1-based). */
+int orc_ring(long nside, long i, double *z, double *s, double *theta,
+             long *n, long *first, double *phi0)
+{
+    if (nside < 1 || i < 1 || i > 4 * nside - 1) return -1;
+    ring_rec r;
+    ring_of(nside, i, &r);
+    *z = r.z; *s = r.s; *theta = r.theta; *n = r.n; *first = r.first;
+    *phi0 = r.phi0;
+    return 0;
+}
+
+/* Unit vectors of a list of RING pixels, xyz is 3*npix doubles. */
+int orc_pix2vec(long nside, long npix, const long *pix, double *xyz)
+{
+    if (nside < 1) return -1;
+    ring_rec *t = ring_table(nside);
+    if (!t) return -2;
+    long total = 12L * nside * nside;
+    for (long k = 0; k < npix; ++k) {
+        if (pix[k] < 0 || pix[k] >= total) { free(t); return -1; }
+        long j;
+        long i = ring_of_pixel(nside, t, pix[k], &j);
+        unit_vector(&t[i], j, xyz + 3 * k);
+    }
+    free(t);
+    return 0;
+}
+
+/*
+ * Kernel table from a beam: K(theta_k) = sum_{l<=lmax} (2l+1)/(4 pi) b_l
+ * P_l(cos theta_k) at theta_k = k theta_cut/(ntab-1).  This is the inverse of
+ * the Legendre transform operator of eq. 1 applied to the eq. 5 kernel with
+ * C_l = 1.  Legendre polynomials by the three-term recurrence
+ *   (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}.
+ */
+int orc_tabulate(const double *bl, long lmax, double theta_cut, long ntab,
+                 double *ktab)
+{
+    if (lmax < 0 || ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI)
+        return -1;
+    double h = theta_cut / (double)(ntab - 1);
+    #pragma omp parallel for schedule(static)
+    for (long k = 0; k < ntab; ++k) {
+        double x = cos((double)k * h);
+        double pm1 = 1.0, p = x;          /* P_0, P_1 */
+        double sum = bl[0];               /* l = 0 term times 4 pi */
+        if (lmax >= 1) sum += 3.0 * bl[1] * x;
+        for (long l = 1; l < lmax; ++l) {
+            double pn = ((2.0 * l + 1.0) * x * p - (double)l * pm1) / (double)(l + 1);
+            pm1 = p; p = pn;
+            sum += (2.0 * (l + 1) + 1.0) * bl[l + 1] * p;
+        }
+        ktab[k] = sum / (4.0 * M_PI);
+    }
+    return 0;
+}
+
+/*
+ * Windowed direct sum at a list of output pixels (pix == NULL: all pixels,
+ * in RING order).  y has npix_eval entries; pairs_out (nullable) receives
+ * the number of in-disc pairs per evaluated pixel.
+ */
+int orc_convolve(long nside, double theta_cut, long ntab, const double *ktab,
+                 const double *x, long npix_eval, const long *pix, double *y,
+                 long *pairs_out)
+{
+    if (nside < 1 || ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI)
+        return -1;
+    long total = 12L * nside * nside;
+    if (!pix) npix_eval = total;
+    ring_rec *t = ring_table(nside);
+    if (!t) return -2;
+    double omega = 4.0 * M_PI / (double)total;
+    int bad = 0;
+    #pragma omp parallel
+    {
+        orc_list nb = {NULL, 0, 0};
+        #pragma omp for schedule(dynamic, 64)
+        for (long k = 0; k < npix_eval; ++k) {
+            long p = pix ? pix[k] : k;
+            if (p < 0 || p >= total) { bad = 1; continue; }
+            long cnt = neighbours(nside, t, theta_cut, p, &nb);
+            if (cnt < 0) { bad = 2; continue; }
+            double acc = 0.0;
+            for (long m = 0; m < cnt; ++m)
+                acc += kernel_value(nb.v[m].theta, theta_cut, ntab, ktab) * x[nb.v[m].q];
+            y[k] = omega * acc;
+            if (pairs_out) pairs_out[k] = cnt;
+        }
+        free(nb.v);
+    }
+    free(t);
+    return bad == 2 ? -2 : (bad ? -1 : 0);
+}
+
+/*
+ * Exhaustive all-pairs sum (every q tested, no windows); for small Nside.
+ */
+int orc_convolve_exhaustive(long nside, double theta_cut, long ntab,
+                            const double *ktab, const double *x,
+                            long npix_eval, const long *pix, double *y,
+                            long *pairs_out)
+{
+    if (nside < 1 || ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI)
+        return -1;
+    long total = 12L * nside * nside;
+    if (!pix) npix_eval = total;
+    ring_rec *t = ring_table(nside);
+    if (!t) return -2;
+    double *v = (double *)malloc(sizeof(double) * 3 * (size_t)total);
+    if (!v) { free(t); return -2; }
+    for (long i = 1; i <= 4 * nside - 1; ++i)
+        for (long j = 0; j < t[i].n; ++j)
+            unit_vector(&t[i], j, v + 3 * (t[i].first + j));
+    double omega = 4.0 * M_PI / (double)total;
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (long k = 0; k < npix_eval; ++k) {
+        long p = pix ? pix[k] : k;
+        if (p < 0 || p >= total) { bad = 1; continue; }
+        double acc = 0.0;
+        long cnt = 0;
+        for (long q = 0; q < total; ++q) {
+            double th = separation(v + 3 * p, v + 3 * q);
+            if (th < theta_cut) {
+                acc += kernel_value(th, theta_cut, ntab, ktab) * x[q];
+                ++cnt;
+            }
+        }
+        y[k] = omega * acc;
+        if (pairs_out) pairs_out[k] = cnt;
+    }
+    free(v);
+    free(t);
+    return bad ? -1 : 0;
+}
+
+/*
+ * Gradient of a loss with respect to the knots, given g = dL/dy over the
+ * whole map:  dL/dK_k = Omega sum_p g[p] sum_q Lambda_k(theta_pq) x[q],
+ * with Lambda_k the piecewise-linear hat of node k (weight 1-t to node i and
+ * t to node i+1), the derivative of the interpolated kernel with respect to
+ * its nodes.  gk has ntab entries.
+ */
+int orc_knot_grad(long nside, double theta_cut, long ntab, const double *x,
+                  const double *g, double *gk)
+{
+    if (nside < 1 || ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI)
+        return -1;
+    long total = 12L * nside * nside;
+    ring_rec *t = ring_table(nside);
+    if (!t) return -2;
+    double omega = 4.0 * M_PI / (double)total;
+    int nthr = omp_get_max_threads();
+    double *part = (double *)calloc((size_t)nthr * (size_t)ntab, sizeof(double));
+    if (!part) { free(t); return -2; }
+    int bad = 0;
+    #pragma omp parallel
+    {
+        double *mine = part + (size_t)omp_get_thread_num() * (size_t)ntab;
+        orc_list nb = {NULL, 0, 0};
+        #pragma omp for schedule(dynamic, 64)
+        for (long p = 0; p < total; ++p) {
+            if (g[p] == 0.0) continue;
+            long cnt = neighbours(nside, t, theta_cut, p, &nb);
+            if (cnt < 0) { bad = 1; continue; }
+            for (long m = 0; m < cnt; ++m) {
+                long i; double tt;
+                interp_weights(nb.v[m].theta, theta_cut, ntab, &i, &tt);
+                double c = omega * g[p] * x[nb.v[m].q];
+                mine[i] += (1.0 - tt) * c;
+                mine[i + 1] += tt * c;
+            }
+        }
+        free(nb.v);
+    }
+    for (long k = 0; k < ntab; ++k) {
+        double s = 0.0;
+        for (int th = 0; th < nthr; ++th) s += part[(size_t)th * ntab + k];
+        gk[k] = s;
+    }
+    free(part);
+    free(t);
+    return bad ? -2 : 0;
+}
+
+/* Number of threads the oracle runs with (for reporting). */
+int orc_threads(void) { return omp_get_max_threads(); }

@@ -1,0 +1,322 @@
+"""Pins for the FP64 oracle against facts fixed by the paper and by mathematics.
+
+Each test would fail on a plausible slip in the oracle: a wrong pixel centre or
+phi offset (golden HEALPix fixtures, symmetries, area identities), a dropped or
+wrong pixel area Omega (constant map vs the Legendre transform lambda_0), a
+wrong node spacing or interpolation (impulse maps against numpy.interp, the
+Funk-Hecke checks), a missing neighbour (exhaustive all-pairs), a Legendre
+recurrence slip (closed forms, scipy), or a wrong gradient (central finite
+differences, which are exact for a quadratic loss).
+"""
+import os
+
+import numpy as np
+import pytest
+from scipy.special import eval_legendre
+
+import oracle as O
+import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _load_golden(name):
+    return np.loadtxt(os.path.join(GOLDEN, name), comments="#")
+
+
+# ---------------------------------------------------------------- geometry --
+
+def test_golden_nside1_pixel_centres():
+    ref = _load_golden("healpix_nside1.txt")
+    v = O.pix2vec(1, ref[:, 0].astype(np.int64))
+    phi = np.degrees(np.arctan2(v[:, 1], v[:, 0])) % 360.0
+    np.testing.assert_allclose(v[:, 2], ref[:, 1], atol=1e-15)
+    np.testing.assert_allclose(phi, ref[:, 2], atol=1e-12)
+
+
+def test_golden_nside2_rings():
+    ref = _load_golden("healpix_nside2_rings.txt")
+    g = O.ring_geometry(2)
+    np.testing.assert_array_equal(g["n"], ref[:, 1].astype(int))
+    np.testing.assert_array_equal(g["first"], ref[:, 2].astype(int))
+    np.testing.assert_allclose(g["z"], ref[:, 3], atol=1e-15)
+    np.testing.assert_allclose(np.degrees(g["phi0"]), ref[:, 4], atol=1e-12)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 3, 5, 8, 64, 2048])
+def test_ring_counts_and_equal_area(nside):
+    """Rings tile the map; the area north of each ring centre, 2 pi (1 - z_i),
+    equals (pixels in earlier rings + half the ring) times Omega = 4 pi/Npix."""
+    g = O.ring_geometry(nside)
+    npix = 12 * nside * nside
+    assert g["n"].sum() == npix
+    np.testing.assert_array_equal(g["first"], np.concatenate([[0], np.cumsum(g["n"])[:-1]]))
+    omega = 4.0 * np.pi / npix
+    area_north = 2.0 * np.pi * (1.0 - g["z"])
+    np.testing.assert_allclose(area_north / omega, g["first"] + 0.5 * g["n"], rtol=1e-12,
+                               atol=1e-9)
+    # mirror symmetry z_i = -z_{4N-i}, and sin(theta) without cancellation
+    np.testing.assert_allclose(g["z"], -g["z"][::-1], atol=1e-15)
+    np.testing.assert_allclose(g["s"] ** 2 + g["z"] ** 2, 1.0, atol=4e-16)
+    np.testing.assert_allclose(g["theta"], np.arctan2(g["s"], g["z"]), atol=1e-15)
+
+
+# -------------------------------------------------------------- tabulation --
+
+def test_tabulation_closed_forms():
+    th = np.linspace(0.0, np.pi, 33)
+    # lmax = 0: K = b_0 / (4 pi)
+    np.testing.assert_allclose(O.tabulate([0.7], np.pi, 33), 0.7 / (4 * np.pi), rtol=1e-15)
+    # lmax = 1: K = (b_0 + 3 b_1 cos theta) / (4 pi)
+    np.testing.assert_allclose(O.tabulate([1.0, 0.4], np.pi, 33),
+                               (1.0 + 1.2 * np.cos(th)) / (4 * np.pi), atol=1e-15)
+    # b_l = 1: sum_l (2l+1) P_l(x) = (L+1)(P_L(x) - P_{L+1}(x)) / (1 - x), (L+1)^2 at x = 1
+    L = 40
+    k = O.tabulate(np.ones(L + 1), np.pi, 33)
+    x = np.cos(th)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        cd = (L + 1) * (eval_legendre(L, x) - eval_legendre(L + 1, x)) / (1.0 - x)
+    cd[0] = (L + 1) ** 2
+    np.testing.assert_allclose(4 * np.pi * k, cd, atol=1e-11 * (L + 1) ** 2)
+
+
+def test_tabulation_matches_scipy_legendre_sum():
+    rng = np.random.default_rng(7)
+    bl = rng.uniform(-1, 1, 61)
+    tc, ntab = 0.8, 50
+    th = np.arange(ntab) * tc / (ntab - 1)
+    ref = sum((2 * l + 1) * bl[l] * eval_legendre(l, np.cos(th)) for l in range(61)) / (4 * np.pi)
+    np.testing.assert_allclose(O.tabulate(bl, tc, ntab), ref, atol=1e-13 * np.abs(ref).max())
+
+
+def test_tabulation_orthogonality():
+    """With theta_cut = pi the Legendre transform of the table gives back b_l."""
+    bl = O.gaussian_bl(np.radians(20.0), 24)
+    k = O.tabulate(bl, np.pi, 8001)
+    lam = O.legendre_coefficients(k, np.pi, range(25))
+    np.testing.assert_allclose(lam, bl, atol=2e-6)
+
+
+def test_gaussian_beam_half_maximum():
+    """The tabulated eq. 5 kernel of a narrow Gaussian beam is, to O(sigma^2),
+    the flat-sky profile exp(-theta^2/2 sigma^2)/(2 pi sigma^2): it peaks at
+    1/(2 pi sigma^2) and falls to one half at theta = FWHM/2."""
+    fw = np.radians(1.0)
+    sigma = fw / np.sqrt(8 * np.log(2))
+    bl = O.gaussian_bl(fw, 2000)
+    k = O.tabulate(bl, fw, 3)                     # nodes at 0, FWHM/2, FWHM
+    assert abs(k[0] * 2 * np.pi * sigma ** 2 - 1.0) < 1e-4
+    assert abs(k[1] / k[0] - 0.5) < 1e-4
+    assert abs(k[2] / k[0] - 1.0 / 16.0) < 1e-4
+
+
+# ----------------------------------------------------- windows and the sum --
+
+@pytest.mark.parametrize("nside", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("tc_deg", [1.0, 6.0, 30.0, 90.0, 179.0])
+def test_windowed_equals_exhaustive(nside, tc_deg):
+    rng = np.random.default_rng(nside * 1000 + int(tc_deg))
+    x = rng.standard_normal(12 * nside * nside)
+    k = rng.standard_normal(37)
+    tc = np.radians(tc_deg)
+    y1, p1 = O.convolve(nside, tc, k, x, return_pairs=True)
+    y2, p2 = O.convolve(nside, tc, k, x, exhaustive=True, return_pairs=True)
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_allclose(y1, y2, rtol=0, atol=1e-14 * max(1.0, np.abs(y2).max()))
+
+
+@pytest.mark.parametrize("tc_deg", [3.0, 25.0])
+def test_windowed_equals_exhaustive_nside32(tc_deg):
+    nside = 32
+    x = np.random.default_rng(3).standard_normal(12 * nside * nside)
+    k = np.random.default_rng(4).standard_normal(100)
+    pix = W.eval_pixels(nside, 300, 5)
+    y1, p1 = O.convolve(nside, np.radians(tc_deg), k, x, pixels=pix, return_pairs=True)
+    y2, p2 = O.convolve(nside, np.radians(tc_deg), k, x, pixels=pix, exhaustive=True,
+                        return_pairs=True)
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_allclose(y1, y2, rtol=0, atol=1e-14 * np.abs(y2).max())
+
+
+@pytest.mark.parametrize("nside,q", [(8, 0), (8, 300), (16, 1500), (16, 767)])
+def test_impulse_map_samples_interpolated_kernel(nside, q):
+    """x = delta_q gives y_p = Omega K_lin(theta_pq): the node table linearly
+    interpolated (numpy.interp) at the true separation, zero at/after the cut."""
+    npix = 12 * nside * nside
+    tc = np.radians(40.0)
+    k = np.random.default_rng(q).uniform(0.5, 2.0, 29)
+    x = np.zeros(npix)
+    x[q] = 1.0
+    y = O.convolve(nside, tc, k, x)
+    v = O.pix2vec(nside)
+    cross = np.linalg.norm(np.cross(v, v[q]), axis=1)
+    theta = np.arctan2(cross, v @ v[q])
+    grid = np.arange(k.size) * tc / (k.size - 1)
+    ref = np.where(theta < tc, np.interp(theta, grid, k), 0.0) * 4 * np.pi / npix
+    np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-15)
+
+
+def _fh_kernel():
+    fw, tc = np.radians(6.0), np.radians(15.0)
+    k = O.tabulate(O.gaussian_bl(fw, 300), tc, 2048)
+    return tc, k
+
+
+def test_constant_map_gives_legendre_transform_l0():
+    """Constant map: y = W_p with W_p -> lambda_0 = 2 pi int K sin theta as the
+    pixel quadrature refines (second order in the pixel size)."""
+    tc, k = _fh_kernel()
+    lam0 = O.legendre_coefficients(k, tc, [0])[0]
+    errs = []
+    for nside in (16, 32, 64):
+        y = O.convolve(nside, tc, k, np.ones(12 * nside * nside))
+        errs.append(np.sqrt(np.mean((y / lam0 - 1.0) ** 2)))
+    assert errs[2] < 3e-3
+    assert errs[1] < errs[0] / 2.5 and errs[2] < errs[1] / 2.5
+
+
+@pytest.mark.parametrize("ell,m", [(1, 0), (1, 1), (2, 0), (2, 2), (8, 0), (8, 8)])
+def test_band_limited_ylm_funk_hecke(ell, m):
+    """Funk-Hecke: a Y_lm comes back scaled by lambda_l, the Legendre transform
+    (eq. 1's operator) of the truncated interpolated kernel; the pixel-sum
+    error falls as Nside grows."""
+    tc, k = _fh_kernel()
+    lam = O.legendre_coefficients(k, tc, [ell])[0]
+    errs = []
+    for nside in (16, 32, 64):
+        v = O.pix2vec(nside)
+        f = O.real_ylm(ell, m, v)
+        y = O.convolve(nside, tc, k, f)
+        errs.append(np.sqrt(np.mean((y - lam * f) ** 2) / np.mean((lam * f) ** 2)))
+    assert errs[2] < 2e-3
+    assert errs[1] < errs[0] / 2.0 and errs[2] < errs[1] / 2.0
+
+
+# --------------------------------------------------------------- symmetry --
+
+def _ring_perm(nside, fn):
+    """Pixel permutation built ring by ring from the HEALPix layout: fn(i, n,
+    half_offset, j) -> (i', j')."""
+    g = O.ring_geometry(nside)
+    perm = np.empty(12 * nside * nside, dtype=np.int64)
+    for i in range(1, 4 * nside):
+        n = int(g["n"][i - 1])
+        half = not (nside <= i <= 3 * nside and (i - nside) % 2 == 1)
+        j = np.arange(n)
+        i2, j2 = fn(i, n, half, j)
+        perm[g["first"][i - 1] + j] = g["first"][i2 - 1] + j2
+    return perm
+
+
+@pytest.mark.parametrize("nside,tc_deg", [(4, 50.0), (8, 20.0), (16, 8.0)])
+def test_exact_symmetries(nside, tc_deg):
+    """Rotation by pi/2, reflection phi -> -phi and the N-S mirror map pixel
+    centres onto pixel centres, so they commute with the operator."""
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(12 * nside * nside)
+    k = rng.uniform(0.1, 1.0, 57)
+    tc = np.radians(tc_deg)
+    y = O.convolve(nside, tc, k, x)
+    rot = _ring_perm(nside, lambda i, n, h, j: (i, (j + n // 4) % n))
+    refl = _ring_perm(nside, lambda i, n, h, j: (i, (n - 1 - j) if h else (n - j) % n))
+    mirr = _ring_perm(nside, lambda i, n, h, j: (4 * nside - i, j))
+    for perm in (rot, refl, mirr):
+        xp = np.empty_like(x)
+        xp[perm] = x
+        yp = O.convolve(nside, tc, k, xp)
+        np.testing.assert_allclose(yp[perm], y, rtol=0, atol=1e-13 * np.abs(y).max())
+
+
+def test_belt_one_pixel_shift():
+    """Shifting every belt ring by one pixel is a rotation by pi/(2N); outputs
+    on rings whose disc stays inside the belt commute with it."""
+    nside, tc = 16, np.radians(6.0)
+    g = O.ring_geometry(nside)
+    x = np.random.default_rng(5).standard_normal(12 * nside * nside)
+    k = np.random.default_rng(6).uniform(0.1, 1.0, 40)
+    shift = _ring_perm(nside, lambda i, n, h, j: (i, (j + 1) % n if nside <= i <= 3 * nside else j))
+    xs = np.empty_like(x)
+    xs[shift] = x
+    y, ys = O.convolve(nside, tc, k, x), O.convolve(nside, tc, k, xs)
+    zb = 2.0 / 3.0
+    th_edge = np.arccos(zb)
+    checked = 0
+    for i in range(nside, 3 * nside + 1):
+        th = g["theta"][i - 1]
+        if th - tc > th_edge + 1e-9 and th + tc < np.pi - th_edge - 1e-9:
+            sl = slice(g["first"][i - 1], g["first"][i - 1] + g["n"][i - 1])
+            np.testing.assert_allclose(ys[sl][shift[sl] - g["first"][i - 1]], y[sl], rtol=0,
+                                       atol=1e-12 * np.abs(y).max())
+            checked += 1
+    assert checked > 20
+
+
+def test_self_adjoint():
+    nside, tc = 16, np.radians(12.0)
+    rng = np.random.default_rng(9)
+    x, y = rng.standard_normal((2, 12 * nside * nside))
+    k = rng.uniform(-1, 1, 80)
+    ax, ay = O.convolve(nside, tc, k, x), O.convolve(nside, tc, k, y)
+    assert abs(ax @ y - x @ ay) < 1e-13 * np.abs(ax).max() * np.abs(y).sum()
+
+
+def test_total_pairs_match_disc_area():
+    """Sum of in-disc pairs ~ Npix^2 (1 - cos theta_cut)/2."""
+    for nside, tc in ((32, np.radians(10.0)), (64, np.radians(6.0))):
+        npix = 12 * nside * nside
+        tot = O.pair_counts(nside, tc).sum()
+        expect = npix * npix * (1 - np.cos(tc)) / 2
+        assert abs(tot / expect - 1) < 0.03
+
+
+# --------------------------------------------------------------- gradients --
+
+def _loss(y, t):
+    return float(np.sum((y - t) ** 2))
+
+
+def test_map_gradient_central_differences():
+    """L = sum (A x - t)^2 is quadratic in x, so central differences are exact
+    up to rounding: dL/dx_q = (A g)_q with g = 2 (A x - t)."""
+    nside, tc = 8, np.radians(25.0)
+    rng = np.random.default_rng(21)
+    x, t = rng.standard_normal((2, 12 * nside * nside))
+    k = rng.uniform(0.2, 1.0, 64)
+    y = O.convolve(nside, tc, k, x)
+    grad = O.map_grad(nside, tc, k, 2.0 * (y - t))
+    h = 1e-3
+    for q in (0, 5, 100, 383, 767):
+        e = np.zeros_like(x)
+        e[q] = h
+        fd = (_loss(O.convolve(nside, tc, k, x + e), t) - _loss(O.convolve(nside, tc, k, x - e), t)) / (2 * h)
+        assert abs(fd - grad[q]) < 1e-8 * max(1.0, abs(grad[q]))
+
+
+def test_knot_gradient_central_differences():
+    nside, tc = 8, np.radians(25.0)
+    rng = np.random.default_rng(22)
+    x, t = rng.standard_normal((2, 12 * nside * nside))
+    k = rng.uniform(0.2, 1.0, 32)
+    y = O.convolve(nside, tc, k, x)
+    gk = O.knot_grad(nside, tc, k.size, x, 2.0 * (y - t))
+    h = 1e-3 * np.abs(k).max()
+    for kk in range(0, 32, 3):
+        e = np.zeros_like(k)
+        e[kk] = h
+        fd = (_loss(O.convolve(nside, tc, k + e, x), t) - _loss(O.convolve(nside, tc, k - e, x), t)) / (2 * h)
+        assert abs(fd - gk[kk]) < 1e-8 * max(1.0, np.abs(gk).max())
+
+
+def test_gradient_euler_identities():
+    """y is linear in the knots and in x: <K, dL/dK> = <g, y> = <x, dL/dx>."""
+    nside, tc = 16, np.radians(10.0)
+    rng = np.random.default_rng(23)
+    x, t = rng.standard_normal((2, 12 * nside * nside))
+    k = rng.uniform(0.2, 1.0, 48)
+    y = O.convolve(nside, tc, k, x)
+    g = 2.0 * (y - t)
+    gk = O.knot_grad(nside, tc, k.size, x, g)
+    gx = O.map_grad(nside, tc, k, g)
+    gy = g @ y
+    assert abs(k @ gk - gy) < 1e-12 * np.abs(g).sum() * np.abs(y).max()
+    assert abs(x @ gx - gy) < 1e-12 * np.abs(g).sum() * np.abs(y).max()
