@@ -1,0 +1,240 @@
+/*
+ * arkcos -- real-space spherical convolution on MI355X (gfx950).
+ *
+ * C ABI of the GPU library libarkcos.so.  Every entry point takes plain host
+ * or device pointers and sizes; no C++ or framework types cross it.  Device
+ * pointers are HIP device memory on the current device; `stream` is a
+ * hipStream_t passed as void* (NULL = the default stream).
+ *
+ * The operation (Sutter, Wandelt & Elsner 2012, Sec. 2, eq. 1 and the
+ * ARKCoS term of eq. 3): the real-space part K_theta of a split radial
+ * kernel, truncated at theta_cut, applied to a HEALPix RING-ordered map by
+ * direct summation,
+ *
+ *     out[p] = Omega * sum_{q : theta(p,q) < theta_cut} K(theta(p,q)) in[q],
+ *     Omega  = 4 pi / Npix,  Npix = 12 Nside^2,
+ *
+ * where K is linear in theta between ntab nodes spaced h = theta_cut/(ntab-1)
+ * on [0, theta_cut] (Sec. 3, interpolation of the real-space kernel), and
+ * K = 0 for theta >= theta_cut.  Sums run in FP32 on the device.
+ *
+ * Conventions for every function:
+ *   - returns ARKCOS_OK (0) or a negative status; never aborts or throws;
+ *     arkcos_last_error() then holds a per-thread message;
+ *   - launches are asynchronous and stream-ordered; device faults surface at
+ *     the caller's next synchronisation;
+ *   - convolve/backward/batch calls never allocate or synchronise, so they
+ *     can be captured in a HIP graph; a plan (and a batch) is used by one
+ *     stream at a time, because its workspace (tile counter, gradient
+ *     partials) is shared by its calls.
+ */
+#ifndef ARKCOS_H
+#define ARKCOS_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct arkcos_plan *arkcos_plan_t;    /* opaque; owns host + device plan data */
+typedef struct arkcos_batch *arkcos_batch_t;  /* opaque; owns a tile queue over plans  */
+
+enum {
+    ARKCOS_OK = 0,
+    ARKCOS_EINVAL = -1,       /* bad argument                                 */
+    ARKCOS_ENOMEM = -2,       /* host or device allocation failed             */
+    ARKCOS_EDEVICE = -3,      /* a HIP call or kernel launch failed           */
+    ARKCOS_EUNSUPPORTED = -4, /* valid but not supported (size limits)        */
+    ARKCOS_ESTATE = -5        /* object not in a state that allows the call   */
+};
+
+/* plan flags */
+#define ARKCOS_PLAN_HOST_ONLY 1u  /* build host data only: no device memory, no launches */
+#define ARKCOS_PLAN_LEARNABLE 2u  /* knots may be replaced from device memory and
+                                     knot gradients may be requested             */
+
+/* Largest supported Nside (ring indices and longitudes stay exact in int32). */
+#define ARKCOS_MAX_NSIDE 8192
+/* Largest node count for which knot gradients are supported. */
+#define ARKCOS_MAX_GRAD_NTAB 8192
+
+typedef struct {
+    int nside;            /* HEALPix resolution, 1 .. ARKCOS_MAX_NSIDE (any integer)       */
+    double theta_cut;     /* radians, 0 < theta_cut <= pi                                 */
+    int ntab;             /* >= 2 nodes, uniform on [0, theta_cut] inclusive              */
+    const double *ktab;   /* host FP64 node values K(theta_k), length ntab; copied (the
+                             caller keeps ownership).  NULL only with ARKCOS_PLAN_LEARNABLE,
+                             in which case knots must be set before the first convolve */
+    int max_batch;        /* largest nbatch a call may pass (>= 1); sizes the workspace  */
+    int tile;             /* output pixels per tile, 0 = default; else 64 .. 4096,
+                             a multiple of 64                                           */
+    unsigned flags;       /* ARKCOS_PLAN_* bits                                         */
+} arkcos_plan_desc;
+
+typedef struct {
+    int nside;
+    int nrings;                    /* 4 Nside - 1                                       */
+    long long npix;                /* 12 Nside^2                                        */
+    long long ring_pairs;          /* (output ring, source ring) pairs in the plan      */
+    long long tiles;               /* work items per map                                */
+    long long candidates;          /* window pixels the kernels visit per map           */
+    double omega;                  /* 4 pi / Npix                                       */
+    int ntab;
+    int tile;
+    unsigned flags;
+    int threads_per_block;
+    long long device_bytes;        /* device memory the plan holds                      */
+} arkcos_plan_info;
+
+/* ----------------------------------------------------------------- host -- */
+
+/*
+ * Node table of the eq. 5 kernel family (Sec. 3) from its Legendre
+ * coefficients: K(theta_k) = sum_{l=0}^{lmax} (2l+1)/(4 pi) b_l P_l(cos theta_k),
+ * theta_k = k theta_cut/(ntab-1), k = 0..ntab-1 -- the inverse of the Legendre
+ * transform operator P_{l theta} of eq. 1.  Host FP64, three-term recurrence.
+ *   b_l      host, lmax+1 doubles (e.g. a Gaussian beam)       [in]
+ *   ktab_out host, ntab doubles, caller-allocated               [out]
+ * EINVAL on lmax < 0, ntab < 2, theta_cut outside (0, pi], NULL pointers.
+ */
+int arkcos_tabulate_legendre(const double *b_l, int lmax, double theta_cut, int ntab,
+                             double *ktab_out);
+
+/*
+ * HEALPix RING geometry of ring `ring` (1 .. 4 Nside - 1), as the library's
+ * plan computes it (Gorski et al. 2005; the paper's map format, Sec. 2):
+ * z = cos(theta), sin(theta) without cancellation, pixel count, RING index of
+ * the first pixel and the longitude of that pixel.  Host only; any out-pointer
+ * may be NULL.  EINVAL on nside outside 1..ARKCOS_MAX_NSIDE or ring out of range.
+ */
+int arkcos_ring_info(int nside, int ring, double *z, double *sin_theta, int *npix_ring,
+                     long long *first_pixel, double *phi0);
+
+/* ----------------------------------------------------------------- plan -- */
+
+/*
+ * Build a plan for one (Nside, theta_cut, node table): FP64 ring geometry,
+ * per output ring the contiguous range of source rings with
+ * |theta_r - theta_s| < theta_cut, per ring pair the FP32 chord constants and
+ * longitude window, and the tile list (Sec. 2: the part of the kernel that
+ * is applied in real space).  Unless ARKCOS_PLAN_HOST_ONLY is set, allocates
+ * and fills device memory on the current device (synchronously).
+ *   desc  host, read only                                            [in]
+ *   out   receives the plan; *out is NULL on failure                 [out]
+ * EINVAL on a bad descriptor, ENOMEM, EDEVICE on HIP failures,
+ * EUNSUPPORTED if ntab nodes do not fit in the per-workgroup LDS budget.
+ */
+int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out);
+
+/* Release a plan and its device memory.  Synchronises the device first.  A NULL
+ * plan is accepted. */
+int arkcos_plan_destroy(arkcos_plan_t plan);
+
+/* Plan statistics (host only). */
+int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info);
+
+/*
+ * Exact number of in-disc pairs (theta_pq < theta_cut, self-pairs included) per
+ * map, counted in FP64 from the haversine identity ring pair by ring pair (the
+ * unit of the throughput metric).  Host only; computed once and cached.
+ */
+int arkcos_plan_pair_count(arkcos_plan_t plan, unsigned long long *pairs);
+
+/*
+ * Longitude window the device kernels scan for output pixel j of ring
+ * `ring_out` on source ring `ring_src` (rings 1-based): unwrapped source
+ * indices lo..hi (hi - lo + 1 <= pixels of the source ring; indices are taken
+ * modulo the ring length).  *covered = 0 if ring_src is not a source ring of
+ * ring_out (lo > hi then).  Evaluated by the same FP32 code the kernels run.
+ * Host only; for tests of window completeness.
+ */
+int arkcos_plan_window(arkcos_plan_t plan, int ring_out, int ring_src, int j, int *lo,
+                       int *hi, int *covered);
+
+/*
+ * Replace the node table from host FP64 values (length ntab).  The device copy
+ * (FP32, pre-multiplied by Omega) is written with a synchronous copy.
+ * ESTATE for a host-only plan.
+ */
+int arkcos_plan_set_kernel_host(arkcos_plan_t plan, const double *ktab);
+
+/*
+ * Replace the node table from device FP32 values d_knots (length ntab), e.g.
+ * learnable knots.  Stream-ordered (a small kernel writes Omega * K into the
+ * plan's table); d_knots may be reused once the call's work has run.
+ * ESTATE unless the plan was created with ARKCOS_PLAN_LEARNABLE.
+ */
+int arkcos_plan_set_kernel(arkcos_plan_t plan, const float *d_knots, void *stream);
+
+/* ------------------------------------------------------------- compute -- */
+
+/*
+ * Forward real-space convolution of nbatch maps (the ARKCoS term, Sec. 2).
+ *   d_in   device FP32, nbatch x Npix, RING order, map b at d_in + b*Npix  [in]
+ *   d_out  device FP32, same layout, overwritten                          [out]
+ * d_in and d_out must not overlap.  1 <= nbatch <= max_batch.
+ * EINVAL on bad arguments, ESTATE for a host-only plan or unset knots,
+ * EDEVICE if a launch fails.
+ */
+int arkcos_convolve(arkcos_plan_t plan, const float *d_in, float *d_out, int nbatch,
+                    void *stream);
+
+/*
+ * Adjoint of arkcos_convolve for a loss L with d_grad_out = dL/d(out):
+ *   d_grad_in    = A^T g, the transposed gather; A is symmetric (theta_pq =
+ *                  theta_qp, one Omega), so this is the same sum applied to g;
+ *   d_grad_knots = dL/dK_k = Omega sum_p g[p] sum_q Lambda_k(theta_pq) in[q],
+ *                  summed over the batch, with Lambda_k the linear hat of node k
+ *                  (derivative of the interpolated kernel of Sec. 3 with respect
+ *                  to its nodes), with respect to the unscaled knots.
+ *   d_grad_out   device FP32, nbatch x Npix                                 [in]
+ *   d_in         device FP32, nbatch x Npix (needed only for knot gradients;
+ *                may be NULL when d_grad_knots is NULL)                      [in]
+ *   d_grad_in    device FP32, nbatch x Npix, overwritten, or NULL            [out]
+ *   d_grad_knots device FP32, ntab, overwritten, or NULL                      [out]
+ * At least one output must be non-NULL; outputs must not overlap inputs.
+ * Knot gradients need ARKCOS_PLAN_LEARNABLE and ntab <= ARKCOS_MAX_GRAD_NTAB
+ * (EUNSUPPORTED otherwise).  The knot gradient is reduced in a fixed order
+ * from FP64 partials.
+ */
+int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const float *d_in,
+                             float *d_grad_in, float *d_grad_knots, int nbatch, void *stream);
+
+/* ------------------------------------------------------------- batches -- */
+
+/*
+ * Group nmaps plans (mixed Nside, theta_cut and node tables) into one work
+ * queue that a single persistent launch drains; tiles are ordered
+ * longest-first.  The plans must outlive the batch and must not be
+ * host-only.  Allocates device memory (synchronously).  Each plan takes one
+ * map (nbatch 1) per call.
+ */
+int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *out);
+
+/*
+ * Convolve map k of the batch with plan k, k = 0..nmaps-1, in one launch.
+ *   d_in   host array of nmaps device pointers (FP32, Npix_k each)  [in]
+ *   d_out  host array of nmaps device pointers, overwritten          [out]
+ * The pointer arrays are copied into the launch arguments; no allocation.
+ */
+int arkcos_batch_convolve(arkcos_batch_t batch, const float *const *d_in, float *const *d_out,
+                          void *stream);
+
+/* Release a batch (not its plans).  NULL is accepted. */
+int arkcos_batch_destroy(arkcos_batch_t batch);
+
+/* ----------------------------------------------------------- diagnostics -- */
+
+/* Static text for a status code. */
+const char *arkcos_status_string(int status);
+
+/* Per-thread detail of the last failing call ("" if none). */
+const char *arkcos_last_error(void);
+
+/* Library version as MAJOR*10000 + MINOR*100 + PATCH. */
+int arkcos_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ARKCOS_H */

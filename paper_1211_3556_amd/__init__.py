@@ -1,0 +1,369 @@
+"""Real-space spherical convolution on MI355X (gfx950).
+
+Python binding of ``libarkcos.so`` (C ABI in ``include/arkcos.h``).  This layer
+only marshals arguments: every step of the computation runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current stream.  There is
+no CPU fallback: if the library is not built, importing the binding succeeds
+but every call raises.
+
+The operation is the real-space half of the split convolution of Sutter,
+Wandelt & Elsner (2012), Sec. 2 (eq. 1, the ARKCoS term of eq. 3):
+
+    out[p] = Omega * sum_{q : theta(p,q) < theta_cut} K(theta(p,q)) in[q]
+
+on HEALPix RING maps, with K linear in theta between ntab nodes on
+[0, theta_cut] (Sec. 3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+__all__ = ["ArkcosError", "Plan", "Batch", "ArkcosConvFn", "conv", "tabulate_legendre",
+           "ring_info", "gaussian_bl", "library_path", "load_library", "PLAN_HOST_ONLY",
+           "PLAN_LEARNABLE", "MAX_GRAD_NTAB", "MAX_NSIDE"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libarkcos.so")
+
+PLAN_HOST_ONLY = 1
+PLAN_LEARNABLE = 2
+MAX_NSIDE = 8192
+MAX_GRAD_NTAB = 8192
+
+_STATUS = {0: "ARKCOS_OK", -1: "ARKCOS_EINVAL", -2: "ARKCOS_ENOMEM", -3: "ARKCOS_EDEVICE",
+           -4: "ARKCOS_EUNSUPPORTED", -5: "ARKCOS_ESTATE"}
+
+
+class ArkcosError(RuntimeError):
+    """A libarkcos call returned a negative status."""
+
+    def __init__(self, status: int, fn: str, detail: str):
+        self.status = status
+        super().__init__("%s failed: %s (%s)" % (fn, _STATUS.get(status, status), detail))
+
+
+class _PlanDesc(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int), ("theta_cut", ctypes.c_double), ("ntab", ctypes.c_int),
+                ("ktab", ctypes.POINTER(ctypes.c_double)), ("max_batch", ctypes.c_int),
+                ("tile", ctypes.c_int), ("flags", ctypes.c_uint)]
+
+
+class _PlanInfo(ctypes.Structure):
+    _fields_ = [("nside", ctypes.c_int), ("nrings", ctypes.c_int), ("npix", ctypes.c_longlong),
+                ("ring_pairs", ctypes.c_longlong), ("tiles", ctypes.c_longlong),
+                ("candidates", ctypes.c_longlong), ("omega", ctypes.c_double),
+                ("ntab", ctypes.c_int), ("tile", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("threads_per_block", ctypes.c_int), ("device_bytes", ctypes.c_longlong)]
+
+
+_lib = None
+_vp = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int)
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def load_library():
+    """Load libarkcos.so (built in-tree by ``python -m paper_1211_3556_amd.build``)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libarkcos.so is not built (%s); run `python -m "
+                          "paper_1211_3556_amd.build` -- there is no CPU fallback" % _LIB_PATH)
+    lib = ctypes.CDLL(_LIB_PATH)
+    sig = {
+        "arkcos_tabulate_legendre": [_dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp],
+        "arkcos_ring_info": [ctypes.c_int, ctypes.c_int, _dp, _dp, _ip,
+                             ctypes.POINTER(ctypes.c_longlong), _dp],
+        "arkcos_plan_create": [ctypes.POINTER(_PlanDesc), ctypes.POINTER(_vp)],
+        "arkcos_plan_destroy": [_vp],
+        "arkcos_plan_get_info": [_vp, ctypes.POINTER(_PlanInfo)],
+        "arkcos_plan_pair_count": [_vp, ctypes.POINTER(ctypes.c_ulonglong)],
+        "arkcos_plan_window": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip],
+        "arkcos_plan_set_kernel_host": [_vp, _dp],
+        "arkcos_plan_set_kernel": [_vp, _vp, _vp],
+        "arkcos_convolve": [_vp, _vp, _vp, ctypes.c_int, _vp],
+        "arkcos_convolve_backward": [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp],
+        "arkcos_batch_create": [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)],
+        "arkcos_batch_convolve": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
+        "arkcos_batch_destroy": [_vp],
+        "arkcos_status_string": [ctypes.c_int],
+        "arkcos_last_error": [],
+        "arkcos_version": [],
+    }
+    for name, args in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_char_p if name in ("arkcos_status_string", "arkcos_last_error") \
+            else ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _call(name: str, *args) -> None:
+    lib = load_library()
+    rc = getattr(lib, name)(*args)
+    if rc != 0:
+        detail = lib.arkcos_last_error().decode(errors="replace")
+        raise ArkcosError(rc, name, detail)
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f32(t, name: str):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % name)
+    if t.dtype != torch.float32:
+        raise TypeError("%s must be float32, got %s" % (name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def gaussian_bl(fwhm: float, lmax: int) -> np.ndarray:
+    """Legendre coefficients b_l = exp(-l(l+1) sigma^2/2), sigma = FWHM/sqrt(8 ln 2), of the
+    Gaussian beam of the paper's eq. 5 kernels with C_l = 1 (Sec. 3)."""
+    sigma = fwhm / np.sqrt(8.0 * np.log(2.0))
+    ell = np.arange(lmax + 1, dtype=np.float64)
+    return np.exp(-0.5 * ell * (ell + 1.0) * sigma * sigma)
+
+
+def tabulate_legendre(b_l, theta_cut: float, ntab: int) -> np.ndarray:
+    """Host FP64 node table sum_l (2l+1)/(4 pi) b_l P_l(cos theta_k) (arkcos_tabulate_legendre)."""
+    b = np.ascontiguousarray(b_l, dtype=np.float64)
+    out = np.empty(ntab, dtype=np.float64)
+    _call("arkcos_tabulate_legendre", b.ctypes.data_as(_dp), b.size - 1, float(theta_cut), ntab,
+          out.ctypes.data_as(_dp))
+    return out
+
+
+def ring_info(nside: int, ring: int) -> dict:
+    """Geometry of ring `ring` (1-based) as the library's plan computes it."""
+    z, s, p0 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n, f = ctypes.c_int(), ctypes.c_longlong()
+    _call("arkcos_ring_info", nside, ring, ctypes.byref(z), ctypes.byref(s), ctypes.byref(n),
+          ctypes.byref(f), ctypes.byref(p0))
+    return {"z": z.value, "sin_theta": s.value, "n": n.value, "first": f.value, "phi0": p0.value}
+
+
+class Plan:
+    """A plan for one (Nside, theta_cut, node table) on the current device.
+
+    ``ktab`` is a host FP64 node table of ``ntab`` values (copied); with
+    ``learnable=True`` it may be omitted and knots set later with ``set_knots``.
+    """
+
+    def __init__(self, nside: int, theta_cut: float, ktab=None, ntab: int | None = None,
+                 max_batch: int = 1, tile: int = 0, learnable: bool = False,
+                 host_only: bool = False):
+        if ktab is not None:
+            ktab = np.ascontiguousarray(ktab, dtype=np.float64)
+            ntab = ktab.size if ntab is None else ntab
+            if ktab.size != ntab:
+                raise ValueError("ktab has %d values, ntab is %d" % (ktab.size, ntab))
+        if ntab is None:
+            raise ValueError("give ktab or ntab")
+        flags = (PLAN_LEARNABLE if learnable else 0) | (PLAN_HOST_ONLY if host_only else 0)
+        desc = _PlanDesc(int(nside), float(theta_cut), int(ntab),
+                         ktab.ctypes.data_as(_dp) if ktab is not None else None,
+                         int(max_batch), int(tile), flags)
+        h = _vp()
+        _call("arkcos_plan_create", ctypes.byref(desc), ctypes.byref(h))
+        self._h = h
+        self.nside = int(nside)
+        self.theta_cut = float(theta_cut)
+        self.ntab = int(ntab)
+        self.max_batch = int(max_batch)
+        self.learnable = learnable
+        self.host_only = host_only
+        self.npix = 12 * self.nside * self.nside
+
+    # -- lifetime -------------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().arkcos_plan_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    # -- queries --------------------------------------------------------------
+    def info(self) -> dict:
+        inf = _PlanInfo()
+        _call("arkcos_plan_get_info", self._h, ctypes.byref(inf))
+        return {k: getattr(inf, k) for k, _ in _PlanInfo._fields_}
+
+    def pair_count(self) -> int:
+        c = ctypes.c_ulonglong()
+        _call("arkcos_plan_pair_count", self._h, ctypes.byref(c))
+        return int(c.value)
+
+    def window(self, ring_out: int, ring_src: int, j: int):
+        lo, hi, cov = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _call("arkcos_plan_window", self._h, ring_out, ring_src, j, ctypes.byref(lo),
+              ctypes.byref(hi), ctypes.byref(cov))
+        return (lo.value, hi.value) if cov.value else None
+
+    # -- kernel table ---------------------------------------------------------
+    def set_ktab(self, ktab) -> None:
+        k = np.ascontiguousarray(ktab, dtype=np.float64)
+        if k.size != self.ntab:
+            raise ValueError("expected %d node values" % self.ntab)
+        _call("arkcos_plan_set_kernel_host", self._h, k.ctypes.data_as(_dp))
+
+    def set_knots(self, knots, stream=None) -> None:
+        """Stream-ordered replacement of the node table from device FP32 knots."""
+        k = _dev_f32(knots, "knots")
+        if k.numel() != self.ntab:
+            raise ValueError("expected %d knots" % self.ntab)
+        _call("arkcos_plan_set_kernel", self._h, _vp(k.data_ptr()), _stream_ptr(stream))
+
+    # -- compute --------------------------------------------------------------
+    def _shape(self, x):
+        if x.dim() == 1 and x.numel() == self.npix:
+            return 1
+        if x.dim() == 2 and x.shape[1] == self.npix:
+            return x.shape[0]
+        raise ValueError("map must have shape (Npix,) or (B, Npix) with Npix = %d" % self.npix)
+
+    def convolve(self, x, out=None, stream=None):
+        """Forward convolution of a (Npix,) or (B, Npix) FP32 device tensor."""
+        import torch
+        x = _dev_f32(x, "x")
+        nb = self._shape(x)
+        if out is None:
+            out = torch.empty_like(x)
+        else:
+            _dev_f32(out, "out")
+            if out.shape != x.shape:
+                raise ValueError("out must have the shape of x")
+        _call("arkcos_convolve", self._h, _vp(x.data_ptr()), _vp(out.data_ptr()), nb,
+              _stream_ptr(stream))
+        return out
+
+    def backward(self, grad_out, x=None, want_map: bool = True, want_knots: bool = False,
+                 stream=None):
+        """(dL/dx, dL/dknots) for dL/d(out) = grad_out; either may be None."""
+        import torch
+        g = _dev_f32(grad_out, "grad_out")
+        nb = self._shape(g)
+        gx = torch.empty_like(g) if want_map else None
+        gk = torch.empty(self.ntab, dtype=torch.float32, device=g.device) if want_knots else None
+        xp = _vp(_dev_f32(x, "x").data_ptr()) if x is not None else _vp()
+        if want_knots and x is None:
+            raise ValueError("knot gradients need the input map x")
+        _call("arkcos_convolve_backward", self._h, _vp(g.data_ptr()), xp,
+              _vp(gx.data_ptr()) if gx is not None else _vp(),
+              _vp(gk.data_ptr()) if gk is not None else _vp(), nb, _stream_ptr(stream))
+        return gx, gk
+
+
+def _make_conv_fn():
+    import torch
+
+    class ArkcosConvFn(torch.autograd.Function):
+        """y = conv(x; knots) with the plan's geometry.  Backward gives dL/dx (the
+        transposed gather) and dL/dknots (hat-basis gather), both on the GPU.  The
+        knots are re-bound to the plan in backward, so optimiser steps between
+        forward calls are safe."""
+
+        @staticmethod
+        def forward(ctx, x, knots, plan):
+            plan.set_knots(knots.detach().contiguous())
+            ctx.save_for_backward(x, knots)
+            ctx.plan = plan
+            return plan.convolve(x.contiguous())
+
+        @staticmethod
+        def backward(ctx, gy):
+            x, knots = ctx.saved_tensors
+            plan = ctx.plan
+            want_x, want_k = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
+            if not (want_x or want_k):
+                return None, None, None
+            plan.set_knots(knots.detach().contiguous())
+            gx, gk = plan.backward(gy.contiguous(), x.detach().contiguous() if want_k else None,
+                                   want_map=want_x, want_knots=want_k)
+            return gx, gk, None
+
+    return ArkcosConvFn
+
+
+_conv_fn = None
+
+
+def __getattr__(name):
+    # the autograd Function is created on first use so that importing the
+    # binding does not import torch
+    global _conv_fn
+    if name == "ArkcosConvFn":
+        if _conv_fn is None:
+            _conv_fn = _make_conv_fn()
+        return _conv_fn
+    raise AttributeError(name)
+
+
+def conv(x, plan: Plan, knots=None):
+    """Convolve x with the plan's kernel; with ``knots`` (learnable plan), differentiable in
+    both x and knots."""
+    if knots is None:
+        return plan.convolve(x)
+    return __getattr__("ArkcosConvFn").apply(x, knots, plan)
+
+
+class Batch:
+    """Several plans (one map each) convolved in one persistent launch."""
+
+    def __init__(self, plans):
+        self.plans = list(plans)
+        arr = (_vp * len(self.plans))(*[p.handle for p in self.plans])
+        h = _vp()
+        _call("arkcos_batch_create", arr, len(self.plans), ctypes.byref(h))
+        self._h = h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().arkcos_batch_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def convolve(self, xs, outs=None, stream=None):
+        import torch
+        if len(xs) != len(self.plans):
+            raise ValueError("need one map per plan")
+        if outs is None:
+            outs = [torch.empty_like(x) for x in xs]
+        for p, x, o in zip(self.plans, xs, outs):
+            _dev_f32(x, "x")
+            _dev_f32(o, "out")
+            if x.numel() != p.npix or o.numel() != p.npix:
+                raise ValueError("map size does not match its plan")
+        n = len(self.plans)
+        ins = (_vp * n)(*[x.data_ptr() for x in xs])
+        ous = (_vp * n)(*[o.data_ptr() for o in outs])
+        _call("arkcos_batch_convolve", self._h, ins, ous, _stream_ptr(stream))
+        return outs

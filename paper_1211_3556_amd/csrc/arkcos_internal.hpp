@@ -1,0 +1,175 @@
+// Internal declarations of libarkcos: plan layout shared by the host plan
+// builder and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "arkcos.h"
+
+namespace arkcos {
+
+// ---------------------------------------------------------------- errors --
+int fail(int status, const std::string &msg);   // records arkcos_last_error text
+void clear_error();
+
+#define ARKCOS_HIP_CHECK(call)                                                        \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return ::arkcos::fail(ARKCOS_EDEVICE, std::string(#call) + ": " +          \
+                                                      hipGetErrorString(e_));         \
+    } while (0)
+
+// ------------------------------------------------------------ device plan --
+// One HEALPix ring as the kernels see it (0-based ring index = ring - 1).
+struct DevRing {
+    int n;          // pixels in the ring
+    int first;      // RING index of pixel 0 (< 12 * 8192^2 < 2^31)
+    int two_o;      // 2 * phi offset in pixel units (1: half-pixel offset, 0: none)
+    int pair_begin; // first ring-pair entry of this ring as an output ring
+    int pair_end;
+    int pad0, pad1, pad2;
+};
+
+// One (output ring r, source ring s) pair.  The chord between pixel (r, j) and
+// pixel (s, j') is
+//     d^2 = A + B sin^2(dphi/2),  A = (z_r - z_s)^2 + (sin_r - sin_s)^2
+//                                   = 4 sin^2((theta_r - theta_s)/2),
+//                                 B = 4 sin_r sin_s,
+// with dphi/2 = m * xscale and m = (2j + 2o_r) n_s - (2j' + 2o_s) n_r an exact
+// integer.  The longitude window of output pixel j is centred at source index
+// c = j * a + b (a = n_s/n_r, b = o_r n_s/n_r - o_s) with half-width w source
+// pixels (margin included); whole != 0 means every pixel of ring s.
+struct DevPair {
+    float A;
+    float B;
+    float xscale;
+    float a;
+    float b;
+    float w;
+    int s;       // 0-based source ring
+    int whole;
+};
+static_assert(sizeof(DevPair) == 32, "DevPair layout");
+
+// One work item: pixels j0 .. j0 + len - 1 of output ring r.
+struct DevTile {
+    int r;
+    int j0;
+    int len;
+    int pad;
+};
+
+// Kernel-argument view of a plan (passed by value).
+struct DevPlanView {
+    const DevRing *rings;
+    const DevPair *pairs;
+    const DevTile *tiles;
+    const float *table;      // ntab FP32 values Omega * K_k
+    int ntiles;
+    int ntab;
+    int npix;
+    int large_angle;         // 1: theta_cut > 0.5 rad, full-range asin
+    float inv_h;             // (ntab - 1) / theta_cut
+    float u_max;             // ntab - 1 (strict upper bound of u = theta / h)
+};
+
+// ------------------------------------------------------- shared FP32 math --
+// Window of output pixel j of ring r on source ring s, exactly as the kernels
+// compute it.  Returns the unwrapped index range [lo, hi]; since
+// -1/2 <= c < n_s + 1/2 and w < n_s/2, -n_s < lo and hi < 2 n_s, so one
+// conditional add or subtract of n_s wraps any index into the ring.
+__host__ __device__ inline void pair_window(const DevPair &p, int n_s, int j, int &lo,
+                                            int &hi)
+{
+    float c = fmaf((float)j, p.a, p.b);
+    if (p.whole) {
+        // n_s consecutive pixels centred on c: |dphi| <= pi + pi/n_s
+        lo = (int)floorf(c + 0.5f) - (n_s >> 1);
+        hi = lo + n_s - 1;
+    } else {
+        lo = (int)ceilf(c - p.w);
+        hi = (int)floorf(c + p.w);
+    }
+}
+
+// --------------------------------------------------------------- host plan --
+struct HostRing {
+    double z, s, theta, phi0;
+    int n;
+    long long first;
+    int two_o;
+};
+
+struct Plan {
+    arkcos_plan_desc desc{};
+    int nside = 0;
+    int nrings = 0;
+    long long npix = 0;
+    double omega = 0.0;
+    int tile = 0;
+    int threads = 0;
+    bool host_only = false;
+    bool knots_set = false;
+    bool large_angle = false;
+
+    std::vector<HostRing> rings;      // 0-based
+    std::vector<DevRing> dev_rings;
+    std::vector<DevPair> pairs;
+    std::vector<DevTile> tiles;       // sorted by decreasing cost
+    std::vector<double> ktab;         // current host copy (FP64), if known
+    long long candidates = 0;
+    bool pairs_counted = false;
+    unsigned long long pair_count = 0;
+
+    // device memory
+    int device = -1;
+    DevRing *d_rings = nullptr;
+    DevPair *d_pairs = nullptr;
+    DevTile *d_tiles = nullptr;
+    float *d_table = nullptr;
+    unsigned int *d_counter = nullptr;  // persistent-queue counter (+ 1 spare)
+    double *d_kpart = nullptr;          // knot-gradient partials [grid][ntab] (learnable)
+    int grid = 0;                       // rows of d_kpart: most resident backward workgroups
+    int cus = 0;                        // compute units of the device
+    int occ_fwd[4] = {0, 0, 0, 0};      // resident workgroups per CU, NB = 1, 2, 4, 8
+    int occ_bwd_gxgk[4] = {0, 0, 0, 0};
+    int occ_bwd_gk[4] = {0, 0, 0, 0};
+    long long device_bytes = 0;
+
+    DevPlanView view() const;
+};
+
+struct Batch {
+    std::vector<Plan *> plans;
+    std::vector<int> tile_map;          // global tile -> plan (sorted, longest first)
+    std::vector<int> tile_local;        // global tile -> tile index inside its plan
+    int *d_tile_map = nullptr;          // device copies of the two arrays above
+    int *d_tile_local = nullptr;
+    DevPlanView *d_views = nullptr;
+    unsigned int *d_counter = nullptr;
+    int ntiles = 0;
+    int grid = 0;
+    int cus = 0;
+    int max_ntab = 0;
+    int device = -1;
+};
+
+// ----------------------------------------------------------------- launch --
+// Implemented in kernels.hip.
+int launch_set_table(const Plan &p, const float *d_knots, hipStream_t s);
+int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s);
+int launch_backward(const Plan &p, const float *g, const float *x, float *gx, float *gk,
+                    int nbatch, hipStream_t s);
+int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s);
+int device_lds_limit(int device, size_t *bytes);
+int prepare_launches(Plan &p);   // occupancy of every kernel variant, grid sizes
+int prepare_batch(Batch &b);
+int forward_threads();
+int batch_max_maps();
+
+}  // namespace arkcos

@@ -1,0 +1,212 @@
+// C ABI of the compute entry points: argument checks, then stream-ordered
+// launches (kernels.hip).  Plan construction lives in plan.hip.
+#include <algorithm>
+#include <cstdint>
+#include <numeric>
+#include <string>
+
+#include "arkcos_internal.hpp"
+
+using namespace arkcos;
+
+namespace {
+
+bool overlaps(const void *a, size_t na, const void *b, size_t nb)
+{
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+int check_compute(const Plan *P, int nbatch)
+{
+    if (P->host_only) return fail(ARKCOS_ESTATE, "host-only plan cannot launch kernels");
+    if (!P->knots_set) return fail(ARKCOS_ESTATE, "node table not set");
+    if (nbatch < 1 || nbatch > P->desc.max_batch)
+        return fail(ARKCOS_EINVAL, "nbatch must lie in 1..max_batch (" +
+                                       std::to_string(P->desc.max_batch) + ")");
+    return ARKCOS_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+int arkcos_convolve(arkcos_plan_t plan, const float *d_in, float *d_out, int nbatch,
+                    void *stream)
+{
+    clear_error();
+    if (!plan || !d_in || !d_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    int rc = check_compute(P, nbatch);
+    if (rc) return rc;
+    const size_t bytes = (size_t)nbatch * (size_t)P->npix * sizeof(float);
+    if (overlaps(d_in, bytes, d_out, bytes)) return fail(ARKCOS_EINVAL, "d_in and d_out overlap");
+    DeviceGuard g(P->device);
+    return launch_forward(*P, d_in, d_out, nbatch, (hipStream_t)stream);
+}
+
+int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const float *d_in,
+                             float *d_grad_in, float *d_grad_knots, int nbatch, void *stream)
+{
+    clear_error();
+    if (!plan || !d_grad_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    if (!d_grad_in && !d_grad_knots)
+        return fail(ARKCOS_EINVAL, "at least one of d_grad_in, d_grad_knots must be non-NULL");
+    int rc = check_compute(P, nbatch);
+    if (rc) return rc;
+    const size_t bytes = (size_t)nbatch * (size_t)P->npix * sizeof(float);
+    const size_t kbytes = (size_t)P->desc.ntab * sizeof(float);
+    if (d_grad_in && overlaps(d_grad_in, bytes, d_grad_out, bytes))
+        return fail(ARKCOS_EINVAL, "d_grad_in overlaps d_grad_out");
+    if (d_grad_knots) {
+        if (!(P->desc.flags & ARKCOS_PLAN_LEARNABLE))
+            return fail(ARKCOS_ESTATE, "knot gradients need ARKCOS_PLAN_LEARNABLE");
+        if (P->desc.ntab > ARKCOS_MAX_GRAD_NTAB || !P->d_kpart)
+            return fail(ARKCOS_EUNSUPPORTED, "knot gradients need ntab <= " +
+                                                 std::to_string(ARKCOS_MAX_GRAD_NTAB));
+        if (!d_in) return fail(ARKCOS_EINVAL, "knot gradients need d_in");
+        if (overlaps(d_grad_knots, kbytes, d_grad_out, bytes) ||
+            overlaps(d_grad_knots, kbytes, d_in, bytes))
+            return fail(ARKCOS_EINVAL, "d_grad_knots overlaps an input");
+        if (d_grad_in && (overlaps(d_grad_in, bytes, d_in, bytes) ||
+                          overlaps(d_grad_in, bytes, d_grad_knots, kbytes)))
+            return fail(ARKCOS_EINVAL, "d_grad_in overlaps d_in or d_grad_knots");
+    }
+    DeviceGuard g(P->device);
+    return launch_backward(*P, d_grad_out, d_in, d_grad_in, d_grad_knots, nbatch,
+                           (hipStream_t)stream);
+}
+
+int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *out)
+{
+    clear_error();
+    if (!out) return fail(ARKCOS_EINVAL, "NULL output pointer");
+    *out = nullptr;
+    if (!plans || nmaps < 1) return fail(ARKCOS_EINVAL, "need at least one plan");
+    if (nmaps > batch_max_maps())
+        return fail(ARKCOS_EUNSUPPORTED, "at most " + std::to_string(batch_max_maps()) +
+                                             " maps per batch");
+    Batch *B = new (std::nothrow) Batch();
+    if (!B) return fail(ARKCOS_ENOMEM, "host allocation failed");
+    std::vector<DevPlanView> views;
+    std::vector<double> cost;
+    for (int k = 0; k < nmaps; ++k) {
+        Plan *P = reinterpret_cast<Plan *>(plans[k]);
+        if (!P) { delete B; return fail(ARKCOS_EINVAL, "NULL plan in batch"); }
+        if (P->host_only) { delete B; return fail(ARKCOS_ESTATE, "host-only plan in batch"); }
+        if (B->device < 0) B->device = P->device;
+        if (P->device != B->device) { delete B; return fail(ARKCOS_EINVAL, "plans on different devices"); }
+        B->plans.push_back(P);
+        B->max_ntab = std::max(B->max_ntab, P->desc.ntab);
+        views.push_back(P->view());
+        // per-tile cost: candidates of its ring times its length
+        for (int t = 0; t < (int)P->tiles.size(); ++t) {
+            const DevTile &T = P->tiles[t];
+            const DevRing &R = P->dev_rings[T.r];
+            double c = 0.0;
+            for (int q = R.pair_begin; q < R.pair_end; ++q) {
+                const DevPair &pp = P->pairs[q];
+                c += pp.whole ? (double)P->dev_rings[pp.s].n : 2.0 * pp.w + 1.0;
+            }
+            B->tile_map.push_back(k);
+            B->tile_local.push_back(t);
+            cost.push_back(c * T.len);
+        }
+    }
+    std::vector<size_t> order(cost.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    std::vector<int> tm(order.size()), tl(order.size());
+    for (size_t i = 0; i < order.size(); ++i) {
+        tm[i] = B->tile_map[order[i]];
+        tl[i] = B->tile_local[order[i]];
+    }
+    B->tile_map.swap(tm);
+    B->tile_local.swap(tl);
+    B->ntiles = (int)B->tile_map.size();
+
+    DeviceGuard g(B->device);
+    auto bail = [&](int rc) {
+        (void)hipFree(B->d_tile_map);
+        (void)hipFree(B->d_tile_local);
+        (void)hipFree(B->d_views);
+        (void)hipFree(B->d_counter);
+        delete B;
+        return rc;
+    };
+    if (hipMalloc((void **)&B->d_tile_map, sizeof(int) * B->ntiles) != hipSuccess ||
+        hipMalloc((void **)&B->d_tile_local, sizeof(int) * B->ntiles) != hipSuccess ||
+        hipMalloc((void **)&B->d_views, sizeof(DevPlanView) * nmaps) != hipSuccess ||
+        hipMalloc((void **)&B->d_counter, sizeof(unsigned int) * 4) != hipSuccess) {
+        (void)hipGetLastError();
+        return bail(fail(ARKCOS_ENOMEM, "hipMalloc failed for the batch queue"));
+    }
+    if (hipMemcpy(B->d_tile_map, B->tile_map.data(), sizeof(int) * B->ntiles, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(B->d_tile_local, B->tile_local.data(), sizeof(int) * B->ntiles, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(B->d_views, views.data(), sizeof(DevPlanView) * nmaps, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(B->d_counter, 0, sizeof(unsigned int) * 4) != hipSuccess)
+        return bail(fail(ARKCOS_EDEVICE, "copy of the batch queue failed"));
+    int rc = prepare_batch(*B);
+    if (rc) return bail(rc);
+    *out = reinterpret_cast<arkcos_batch_t>(B);
+    return ARKCOS_OK;
+}
+
+int arkcos_batch_convolve(arkcos_batch_t batch, const float *const *d_in, float *const *d_out,
+                          void *stream)
+{
+    clear_error();
+    if (!batch || !d_in || !d_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Batch *B = reinterpret_cast<const Batch *>(batch);
+    const int n = (int)B->plans.size();
+    for (int k = 0; k < n; ++k) {
+        if (!d_in[k] || !d_out[k]) return fail(ARKCOS_EINVAL, "NULL map pointer");
+        if (!B->plans[k]->knots_set) return fail(ARKCOS_ESTATE, "node table not set");
+    }
+    for (int k = 0; k < n; ++k) {
+        const size_t bk = (size_t)B->plans[k]->npix * sizeof(float);
+        for (int l = 0; l < n; ++l) {
+            const size_t bl = (size_t)B->plans[l]->npix * sizeof(float);
+            if (overlaps(d_out[k], bk, d_in[l], bl))
+                return fail(ARKCOS_EINVAL, "an output map overlaps an input map");
+            if (l != k && overlaps(d_out[k], bk, d_out[l], bl))
+                return fail(ARKCOS_EINVAL, "output maps overlap");
+        }
+    }
+    DeviceGuard g(B->device);
+    return launch_batch(*B, d_in, d_out, (hipStream_t)stream);
+}
+
+int arkcos_batch_destroy(arkcos_batch_t batch)
+{
+    clear_error();
+    if (!batch) return ARKCOS_OK;
+    Batch *B = reinterpret_cast<Batch *>(batch);
+    {
+        DeviceGuard g(B->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(B->d_tile_map);
+        (void)hipFree(B->d_tile_local);
+        (void)hipFree(B->d_views);
+        (void)hipFree(B->d_counter);
+    }
+    delete B;
+    return ARKCOS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,510 @@
+// Host plan of the real-space convolution: HEALPix ring geometry, the node
+// table, per-ring source lists with longitude windows, tiles and exact pair
+// counts (Sutter, Wandelt & Elsner 2012, Sec. 2: the real-space part K_theta
+// of the split kernel, truncated at theta_cut; Sec. 3: interpolated node
+// table).  Everything here runs once per plan, in FP64 on the host.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+
+#include "arkcos_internal.hpp"
+
+namespace arkcos {
+
+static thread_local std::string g_last_error;
+
+int fail(int status, const std::string &msg)
+{
+    g_last_error = msg;
+    return status;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+// HEALPix RING geometry of ring i (1-based) at resolution N (Gorski et al.
+// 2005, the map format of Sec. 2).  Polar rings use the cancellation-free
+// sin(theta) = sqrt(a (2 - a)) with a = 1 - |z| = i^2 / (3 N^2).
+static HostRing ring_geometry(int N, int i)
+{
+    HostRing g{};
+    const double dN = N;
+    const long long LN = N;
+    if (i < N || i > 3 * N) {
+        const int k = (i < N) ? i : 4 * N - i;                 // rings from the nearer pole
+        const double a = (double)k * (double)k / (3.0 * dN * dN);
+        g.z = (i < N) ? 1.0 - a : a - 1.0;
+        g.s = std::sqrt(a * (2.0 - a));
+        g.n = 4 * k;
+        g.first = (i < N) ? 2LL * k * (k - 1) : 12LL * LN * LN - 2LL * k * (k + 1);
+        g.two_o = 1;
+    } else {
+        g.z = 2.0 * (2.0 * dN - (double)i) / (3.0 * dN);
+        g.s = std::sqrt((1.0 - g.z) * (1.0 + g.z));
+        g.n = 4 * N;
+        g.first = 2LL * LN * (LN - 1) + 4LL * LN * (i - N);
+        g.two_o = ((i - N) % 2 == 0) ? 1 : 0;
+    }
+    g.theta = std::atan2(g.s, g.z);
+    g.phi0 = g.two_o * M_PI / (double)g.n;
+    return g;
+}
+
+DevPlanView Plan::view() const
+{
+    DevPlanView v{};
+    v.rings = d_rings;
+    v.pairs = d_pairs;
+    v.tiles = d_tiles;
+    v.table = d_table;
+    v.ntiles = (int)tiles.size();
+    v.ntab = desc.ntab;
+    v.npix = (int)npix;
+    v.large_angle = large_angle ? 1 : 0;
+    v.inv_h = (float)((desc.ntab - 1) / desc.theta_cut);
+    v.u_max = (float)(desc.ntab - 1);
+    return v;
+}
+
+// Longitude half-width (radians) of the disc on ring s around a pixel of
+// ring r, from the haversine identity
+//   sin^2(theta/2) = sin^2(dtheta/2) + sin_r sin_s sin^2(dphi/2);
+// returns < 0 if the whole ring lies inside, and R < 0 means no pixel.
+static double half_width(const HostRing &r, const HostRing &s, double theta_cut, bool *whole)
+{
+    const double hc = std::sin(0.5 * theta_cut);
+    const double hd = std::sin(0.5 * (r.theta - s.theta));
+    const double R = (hc * hc - hd * hd) / (r.s * s.s);
+    *whole = false;
+    if (R >= 1.0) {
+        *whole = true;
+        return M_PI;
+    }
+    if (R <= 0.0) return 0.0;
+    return 2.0 * std::asin(std::sqrt(R));
+}
+
+static int build_plan(Plan &P)
+{
+    const int N = P.nside;
+    const double tc = P.desc.theta_cut;
+    P.rings.resize(P.nrings);
+    P.dev_rings.resize(P.nrings);
+    for (int i = 1; i <= P.nrings; ++i) P.rings[i - 1] = ring_geometry(N, i);
+
+    // Source rings of each output ring: a contiguous run, since colatitude
+    // grows with the ring index.  A small slack admits rings whose nearest
+    // pixel sits on the cut; the per-pair test on the device decides.
+    const double slack = 1e-12 + 1e-9 * tc;
+    P.pairs.clear();
+    P.candidates = 0;
+    std::vector<double> ring_cost(P.nrings, 0.0);
+    for (int r = 0; r < P.nrings; ++r) {
+        const HostRing &R = P.rings[r];
+        DevRing &dr = P.dev_rings[r];
+        dr.n = R.n;
+        dr.first = (int)R.first;
+        dr.two_o = R.two_o;
+        dr.pair_begin = (int)P.pairs.size();
+        int lo = r, hi = r;
+        while (lo > 0 && std::fabs(P.rings[lo - 1].theta - R.theta) < tc + slack) --lo;
+        while (hi < P.nrings - 1 && std::fabs(P.rings[hi + 1].theta - R.theta) < tc + slack) ++hi;
+        double per_pixel = 0.0;
+        for (int s = lo; s <= hi; ++s) {
+            const HostRing &S = P.rings[s];
+            bool whole = false;
+            const double dphi = half_width(R, S, tc, &whole);
+            DevPair p{};
+            const double dA = 2.0 * std::sin(0.5 * (R.theta - S.theta));
+            p.A = (float)(dA * dA);
+            p.B = (float)(4.0 * R.s * S.s);
+            p.xscale = (float)(M_PI / (2.0 * (double)R.n * (double)S.n));
+            p.a = (float)((double)S.n / (double)R.n);
+            p.b = (float)(0.5 * R.two_o * (double)S.n / (double)R.n - 0.5 * S.two_o);
+            // window half-width in source pixels, widened to cover FP32 rounding
+            // of the centre and of the separation near the cut
+            double w = dphi * S.n / (2.0 * M_PI);
+            w = w * (1.0 + 1e-5) + 0.02;
+            if (whole || 2.0 * w + 1.0 >= (double)S.n) {
+                p.whole = 1;
+                p.w = 0.0f;
+                per_pixel += S.n;
+            } else {
+                p.whole = 0;
+                p.w = (float)w;
+                per_pixel += std::floor(2.0 * w) + 1.0;
+            }
+            p.s = s;
+            P.pairs.push_back(p);
+        }
+        dr.pair_end = (int)P.pairs.size();
+        ring_cost[r] = per_pixel;
+        P.candidates += (long long)std::llround(per_pixel * R.n);
+    }
+
+    // Tiles of `tile` consecutive pixels of one output ring, longest first.
+    P.tiles.clear();
+    std::vector<double> cost;
+    for (int r = 0; r < P.nrings; ++r) {
+        const int n = P.rings[r].n;
+        for (int j0 = 0; j0 < n; j0 += P.tile) {
+            DevTile t{};
+            t.r = r;
+            t.j0 = j0;
+            t.len = std::min(P.tile, n - j0);
+            P.tiles.push_back(t);
+            cost.push_back(ring_cost[r] * t.len);
+        }
+    }
+    std::vector<size_t> order(P.tiles.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<DevTile> sorted(P.tiles.size());
+    for (size_t k = 0; k < order.size(); ++k) sorted[k] = P.tiles[order[k]];
+    P.tiles.swap(sorted);
+    return ARKCOS_OK;
+}
+
+// Exact in-disc pair count of one map.  For output pixel j of ring r and
+// source ring s the pixels inside the disc are the integers j' in the open
+// interval (c - W, c + W), c = ((2j + 2o_r) n_s / n_r - 2o_s) / 2, with
+// W = dphi_max n_s / (2 pi).  A rotation by a quarter turn maps pixel j to
+// j + n_r/4 and shifts c by n_s/4, so a quarter of each ring is counted.
+static unsigned long long count_pairs(const Plan &P)
+{
+    const double tc = P.desc.theta_cut;
+    unsigned long long total = 0;
+    for (int r = 0; r < P.nrings; ++r) {
+        const HostRing &R = P.rings[r];
+        const DevRing &dr = P.dev_rings[r];
+        unsigned long long ring_total = 0;
+        for (int k = dr.pair_begin; k < dr.pair_end; ++k) {
+            const HostRing &S = P.rings[P.pairs[k].s];
+            bool whole = false;
+            const double dphi = half_width(R, S, tc, &whole);
+            if (whole) {
+                ring_total += (unsigned long long)S.n * (unsigned long long)R.n;
+                continue;
+            }
+            const double W = dphi * S.n / (2.0 * M_PI);
+            const int quarter = R.n / 4;
+            const bool circulant = (R.n == S.n);
+            const int jn = circulant ? 1 : quarter;
+            unsigned long long part = 0;
+            for (int j = 0; j < jn; ++j) {
+                const double c = 0.5 * ((2.0 * j + R.two_o) * (double)S.n / (double)R.n - S.two_o);
+                long long cnt = (long long)std::ceil(c + W) - (long long)std::floor(c - W) - 1;
+                if (cnt < 0) cnt = 0;
+                if (cnt > S.n) cnt = S.n;
+                part += (unsigned long long)cnt;
+            }
+            ring_total += circulant ? part * (unsigned long long)R.n : 4ULL * part;
+        }
+        total += ring_total;
+    }
+    return total;
+}
+
+// Node table by Clenshaw's backward recurrence for sum_l c_l P_l(x) with
+// c_l = (2l+1) b_l / (4 pi): with alpha_k = (2k+1) x / (k+1) and
+// beta_k = -k / (k+1), y_k = c_k + alpha_k y_{k+1} + beta_{k+1} y_{k+2},
+// y_{L+1} = y_{L+2} = 0, and the sum is y_0.
+static void tabulate(const double *bl, int lmax, double theta_cut, int ntab, double *out)
+{
+    const double h = theta_cut / (double)(ntab - 1);
+    const double inv4pi = 1.0 / (4.0 * M_PI);
+    for (int k = 0; k < ntab; ++k) {
+        const double x = std::cos(k * h);
+        double y1 = 0.0, y2 = 0.0;  // y_{l+1}, y_{l+2}
+        for (int l = lmax; l >= 0; --l) {
+            const double alpha = (2.0 * l + 1.0) * x / (l + 1.0);
+            const double beta_next = -(l + 1.0) / (l + 2.0);
+            const double y = (2.0 * l + 1.0) * bl[l] * inv4pi + alpha * y1 + beta_next * y2;
+            y2 = y1;
+            y1 = y;
+        }
+        out[k] = y1;
+    }
+}
+
+static void free_device(Plan &P)
+{
+    if (P.device >= 0) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(P.device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(P.d_rings);
+        (void)hipFree(P.d_pairs);
+        (void)hipFree(P.d_tiles);
+        (void)hipFree(P.d_table);
+        (void)hipFree(P.d_counter);
+        (void)hipFree(P.d_kpart);
+        (void)hipSetDevice(cur);
+    }
+    P.d_rings = nullptr;
+    P.d_pairs = nullptr;
+    P.d_tiles = nullptr;
+    P.d_table = nullptr;
+    P.d_counter = nullptr;
+    P.d_kpart = nullptr;
+}
+
+template <class T>
+static int upload(T **dst, const std::vector<T> &src, long long *bytes)
+{
+    const size_t n = std::max<size_t>(src.size(), 1) * sizeof(T);
+    if (hipMalloc((void **)dst, n) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ARKCOS_ENOMEM, "hipMalloc of " + std::to_string(n) + " bytes failed");
+    }
+    *bytes += (long long)n;
+    if (!src.empty()) ARKCOS_HIP_CHECK(hipMemcpy(*dst, src.data(), src.size() * sizeof(T),
+                                                 hipMemcpyHostToDevice));
+    return ARKCOS_OK;
+}
+
+static int write_table_host(Plan &P)
+{
+    std::vector<float> t(P.desc.ntab);
+    for (int k = 0; k < P.desc.ntab; ++k) t[k] = (float)(P.omega * P.ktab[k]);
+    ARKCOS_HIP_CHECK(hipMemcpy(P.d_table, t.data(), t.size() * sizeof(float),
+                               hipMemcpyHostToDevice));
+    return ARKCOS_OK;
+}
+
+static int to_device(Plan &P)
+{
+    if (getenv("ARKCOS_FAULT") && std::string(getenv("ARKCOS_FAULT")) == "alloc")
+        return fail(ARKCOS_ENOMEM, "allocation failure forced by ARKCOS_FAULT=alloc");
+    ARKCOS_HIP_CHECK(hipGetDevice(&P.device));
+    size_t lds = 0;
+    int rc = device_lds_limit(P.device, &lds);
+    if (rc) return rc;
+    if ((size_t)P.desc.ntab * sizeof(float) > lds)
+        return fail(ARKCOS_EUNSUPPORTED, "node table of " + std::to_string(P.desc.ntab) +
+                                             " FP32 values exceeds the workgroup LDS limit of " +
+                                             std::to_string(lds) + " bytes");
+    P.device_bytes = 0;
+    if ((rc = upload(&P.d_rings, P.dev_rings, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_pairs, P.pairs, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_tiles, P.tiles, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_table, std::vector<float>(P.desc.ntab, 0.0f), &P.device_bytes)))
+        return rc;
+    if ((rc = upload(&P.d_counter, std::vector<unsigned int>(4, 0u), &P.device_bytes))) return rc;
+    if ((rc = prepare_launches(P))) return rc;
+    if ((P.desc.flags & ARKCOS_PLAN_LEARNABLE) && P.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
+        std::vector<double> z((size_t)P.grid * P.desc.ntab, 0.0);
+        if ((rc = upload(&P.d_kpart, z, &P.device_bytes))) return rc;
+    }
+    if (!P.ktab.empty()) {
+        if ((rc = write_table_host(P))) return rc;
+        P.knots_set = true;
+    }
+    return ARKCOS_OK;
+}
+
+}  // namespace arkcos
+
+using namespace arkcos;
+
+extern "C" {
+
+const char *arkcos_last_error(void) { return arkcos::g_last_error.c_str(); }
+
+const char *arkcos_status_string(int status)
+{
+    switch (status) {
+        case ARKCOS_OK: return "ARKCOS_OK";
+        case ARKCOS_EINVAL: return "ARKCOS_EINVAL: invalid argument";
+        case ARKCOS_ENOMEM: return "ARKCOS_ENOMEM: out of memory";
+        case ARKCOS_EDEVICE: return "ARKCOS_EDEVICE: HIP device error";
+        case ARKCOS_EUNSUPPORTED: return "ARKCOS_EUNSUPPORTED: unsupported configuration";
+        case ARKCOS_ESTATE: return "ARKCOS_ESTATE: object not in the required state";
+        default: return "ARKCOS: unknown status";
+    }
+}
+
+int arkcos_version(void) { return 10000; }
+
+int arkcos_tabulate_legendre(const double *b_l, int lmax, double theta_cut, int ntab,
+                             double *ktab_out)
+{
+    clear_error();
+    if (!b_l || !ktab_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    if (lmax < 0) return fail(ARKCOS_EINVAL, "lmax must be >= 0");
+    if (ntab < 2) return fail(ARKCOS_EINVAL, "ntab must be >= 2");
+    if (!(theta_cut > 0.0) || theta_cut > M_PI)
+        return fail(ARKCOS_EINVAL, "theta_cut must lie in (0, pi]");
+    tabulate(b_l, lmax, theta_cut, ntab, ktab_out);
+    return ARKCOS_OK;
+}
+
+int arkcos_ring_info(int nside, int ring, double *z, double *sin_theta, int *npix_ring,
+                     long long *first_pixel, double *phi0)
+{
+    clear_error();
+    if (nside < 1 || nside > ARKCOS_MAX_NSIDE)
+        return fail(ARKCOS_EINVAL, "nside out of range");
+    if (ring < 1 || ring > 4 * nside - 1) return fail(ARKCOS_EINVAL, "ring out of range");
+    const HostRing g = ring_geometry(nside, ring);
+    if (z) *z = g.z;
+    if (sin_theta) *sin_theta = g.s;
+    if (npix_ring) *npix_ring = g.n;
+    if (first_pixel) *first_pixel = g.first;
+    if (phi0) *phi0 = g.phi0;
+    return ARKCOS_OK;
+}
+
+int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
+{
+    clear_error();
+    if (!out) return fail(ARKCOS_EINVAL, "NULL output pointer");
+    *out = nullptr;
+    if (!desc) return fail(ARKCOS_EINVAL, "NULL descriptor");
+    if (desc->nside < 1 || desc->nside > ARKCOS_MAX_NSIDE)
+        return fail(ARKCOS_EINVAL, "nside must lie in 1.." + std::to_string(ARKCOS_MAX_NSIDE));
+    if (!(desc->theta_cut > 0.0) || desc->theta_cut > M_PI)
+        return fail(ARKCOS_EINVAL, "theta_cut must lie in (0, pi]");
+    if (desc->ntab < 2) return fail(ARKCOS_EINVAL, "ntab must be >= 2");
+    if (desc->max_batch < 1) return fail(ARKCOS_EINVAL, "max_batch must be >= 1");
+    if (desc->tile != 0 && (desc->tile < 64 || desc->tile > 4096 || desc->tile % 64 != 0))
+        return fail(ARKCOS_EINVAL, "tile must be 0 or a multiple of 64 in 64..4096");
+    if (!desc->ktab && !(desc->flags & ARKCOS_PLAN_LEARNABLE))
+        return fail(ARKCOS_EINVAL, "ktab may be NULL only for a learnable plan");
+    if (desc->flags & ~(ARKCOS_PLAN_HOST_ONLY | ARKCOS_PLAN_LEARNABLE))
+        return fail(ARKCOS_EINVAL, "unknown flag bits");
+    const long long npix = 12LL * desc->nside * desc->nside;
+    if ((long long)desc->max_batch * npix > 0x7fffffffLL * 4)
+        return fail(ARKCOS_EUNSUPPORTED, "max_batch * Npix too large");
+
+    Plan *P = new (std::nothrow) Plan();
+    if (!P) return fail(ARKCOS_ENOMEM, "host allocation failed");
+    P->desc = *desc;
+    P->desc.ktab = nullptr;
+    P->nside = desc->nside;
+    P->nrings = 4 * desc->nside - 1;
+    P->npix = npix;
+    P->omega = 4.0 * M_PI / (double)npix;
+    P->tile = desc->tile ? desc->tile : 256;
+    P->threads = forward_threads();
+    P->host_only = (desc->flags & ARKCOS_PLAN_HOST_ONLY) != 0;
+    P->large_angle = desc->theta_cut > 0.5;
+    if (desc->ktab) P->ktab.assign(desc->ktab, desc->ktab + desc->ntab);
+    int rc;
+    try {
+        rc = build_plan(*P);
+    } catch (const std::bad_alloc &) {
+        rc = fail(ARKCOS_ENOMEM, "host allocation failed while building the plan");
+    }
+    if (rc == ARKCOS_OK && !P->host_only) rc = to_device(*P);
+    if (rc != ARKCOS_OK) {
+        free_device(*P);
+        delete P;
+        return rc;
+    }
+    *out = reinterpret_cast<arkcos_plan_t>(P);
+    return ARKCOS_OK;
+}
+
+int arkcos_plan_destroy(arkcos_plan_t plan)
+{
+    clear_error();
+    if (!plan) return ARKCOS_OK;
+    Plan *P = reinterpret_cast<Plan *>(plan);
+    free_device(*P);
+    delete P;
+    return ARKCOS_OK;
+}
+
+int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info)
+{
+    clear_error();
+    if (!plan || !info) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    info->nside = P->nside;
+    info->nrings = P->nrings;
+    info->npix = P->npix;
+    info->ring_pairs = (long long)P->pairs.size();
+    info->tiles = (long long)P->tiles.size();
+    info->candidates = P->candidates;
+    info->omega = P->omega;
+    info->ntab = P->desc.ntab;
+    info->tile = P->tile;
+    info->flags = P->desc.flags;
+    info->threads_per_block = P->threads;
+    info->device_bytes = P->device_bytes;
+    return ARKCOS_OK;
+}
+
+int arkcos_plan_pair_count(arkcos_plan_t plan, unsigned long long *pairs)
+{
+    clear_error();
+    if (!plan || !pairs) return fail(ARKCOS_EINVAL, "NULL pointer");
+    Plan *P = reinterpret_cast<Plan *>(plan);
+    if (!P->pairs_counted) {
+        P->pair_count = count_pairs(*P);
+        P->pairs_counted = true;
+    }
+    *pairs = P->pair_count;
+    return ARKCOS_OK;
+}
+
+int arkcos_plan_window(arkcos_plan_t plan, int ring_out, int ring_src, int j, int *lo, int *hi,
+                       int *covered)
+{
+    clear_error();
+    if (!plan || !lo || !hi || !covered) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    if (ring_out < 1 || ring_out > P->nrings || ring_src < 1 || ring_src > P->nrings)
+        return fail(ARKCOS_EINVAL, "ring out of range");
+    const DevRing &dr = P->dev_rings[ring_out - 1];
+    if (j < 0 || j >= dr.n) return fail(ARKCOS_EINVAL, "pixel index out of range");
+    *covered = 0;
+    *lo = 1;
+    *hi = 0;
+    for (int k = dr.pair_begin; k < dr.pair_end; ++k) {
+        if (P->pairs[k].s != ring_src - 1) continue;
+        pair_window(P->pairs[k], P->dev_rings[ring_src - 1].n, j, *lo, *hi);
+        *covered = 1;
+    }
+    return ARKCOS_OK;
+}
+
+int arkcos_plan_set_kernel_host(arkcos_plan_t plan, const double *ktab)
+{
+    clear_error();
+    if (!plan || !ktab) return fail(ARKCOS_EINVAL, "NULL pointer");
+    Plan *P = reinterpret_cast<Plan *>(plan);
+    if (P->host_only) return fail(ARKCOS_ESTATE, "host-only plan has no device table");
+    P->ktab.assign(ktab, ktab + P->desc.ntab);
+    int cur = 0;
+    ARKCOS_HIP_CHECK(hipGetDevice(&cur));
+    ARKCOS_HIP_CHECK(hipSetDevice(P->device));
+    int rc = write_table_host(*P);
+    (void)hipSetDevice(cur);
+    if (rc == ARKCOS_OK) P->knots_set = true;
+    return rc;
+}
+
+int arkcos_plan_set_kernel(arkcos_plan_t plan, const float *d_knots, void *stream)
+{
+    clear_error();
+    if (!plan || !d_knots) return fail(ARKCOS_EINVAL, "NULL pointer");
+    Plan *P = reinterpret_cast<Plan *>(plan);
+    if (P->host_only) return fail(ARKCOS_ESTATE, "host-only plan has no device table");
+    if (!(P->desc.flags & ARKCOS_PLAN_LEARNABLE))
+        return fail(ARKCOS_ESTATE, "plan was not created with ARKCOS_PLAN_LEARNABLE");
+    int rc = launch_set_table(*P, d_knots, (hipStream_t)stream);
+    if (rc == ARKCOS_OK) {
+        P->knots_set = true;
+        P->ktab.clear();
+    }
+    return rc;
+}
+
+}  // extern "C"

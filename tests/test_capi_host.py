@@ -1,0 +1,198 @@
+"""Host-side checks of libarkcos (no GPU needed): exported symbols, status
+codes, and the plan's FP64 geometry, node table, longitude windows and exact
+pair counts against the independent oracle."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1211_3556_amd as A
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "arkcos.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(arkcos_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = A.load_library()
+    names = _declared_functions()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+    # and nothing outside the header is exported with the prefix
+    out = os.popen("nm -D --defined-only %s" % A.library_path()).read()
+    exported = set(re.findall(r"\bT (arkcos_\w+)", out))
+    assert exported == set(names)
+
+
+def test_status_strings_and_version():
+    lib = A.load_library()
+    for code in (0, -1, -2, -3, -4, -5):
+        assert lib.arkcos_status_string(code).startswith(b"ARKCOS")
+    assert lib.arkcos_version() == 10000
+
+
+@pytest.mark.parametrize("kw,msg", [
+    (dict(nside=0), "nside"), (dict(nside=8193), "nside"),
+    (dict(theta_cut=0.0), "theta_cut"), (dict(theta_cut=3.2), "theta_cut"),
+    (dict(ntab=1, ktab=None), "ntab"), (dict(max_batch=0), "max_batch"),
+    (dict(tile=100), "tile"), (dict(tile=8192), "tile"),
+])
+def test_plan_argument_errors(kw, msg):
+    args = dict(nside=8, theta_cut=0.1, ktab=np.ones(16), max_batch=1, tile=0, host_only=True)
+    args.update(kw)
+    if "ntab" in kw:
+        args["ktab"] = np.ones(kw["ntab"])
+        del args["ntab"]
+    with pytest.raises(A.ArkcosError) as e:
+        A.Plan(**args)
+    assert e.value.status == -1 and msg in str(e.value)
+
+
+def test_null_knots_need_learnable_and_bad_flags():
+    lib = A.load_library()
+    desc = A._PlanDesc(8, 0.1, 16, None, 1, 0, 1)
+    h = ctypes.c_void_p()
+    assert lib.arkcos_plan_create(ctypes.byref(desc), ctypes.byref(h)) == -1
+    assert b"learnable" in lib.arkcos_last_error()
+    assert not h.value
+    desc = A._PlanDesc(8, 0.1, 16, None, 1, 0, 1 | 2 | 64)
+    assert lib.arkcos_plan_create(ctypes.byref(desc), ctypes.byref(h)) == -1
+    assert lib.arkcos_plan_create(None, ctypes.byref(h)) == -1
+    assert lib.arkcos_plan_create(ctypes.byref(desc), None) == -1
+
+
+def test_compute_calls_on_host_only_plan_are_rejected():
+    lib = A.load_library()
+    p = A.Plan(8, 0.2, np.ones(16), host_only=True, learnable=True)
+    buf = ctypes.c_void_p(0x1000)
+    out = ctypes.c_void_p(0x100000)
+    assert lib.arkcos_convolve(p.handle, buf, out, 1, None) == -5
+    assert lib.arkcos_convolve(p.handle, None, out, 1, None) == -1
+    assert lib.arkcos_convolve_backward(p.handle, buf, None, None, None, 1, None) == -1
+    assert lib.arkcos_plan_set_kernel(p.handle, buf, None) == -5
+    assert lib.arkcos_plan_set_kernel_host(p.handle, np.ones(16).ctypes.data_as(A._dp)) == -5
+    assert lib.arkcos_batch_create(None, 0, ctypes.byref(ctypes.c_void_p())) == -1
+    arr = (ctypes.c_void_p * 1)(p.handle)
+    assert lib.arkcos_batch_create(arr, 1, ctypes.byref(ctypes.c_void_p())) == -5
+    # destroying NULL objects is a no-op
+    assert lib.arkcos_plan_destroy(None) == 0
+    assert lib.arkcos_batch_destroy(None) == 0
+
+
+def test_forced_allocation_failure(monkeypatch):
+    monkeypatch.setenv("ARKCOS_FAULT", "alloc")
+    with pytest.raises(A.ArkcosError) as e:
+        A.Plan(8, 0.2, np.ones(16))
+    assert e.value.status == -2
+
+
+def test_tabulate_argument_errors():
+    lib = A.load_library()
+    b = np.ones(4)
+    out = np.empty(4)
+    f = lib.arkcos_tabulate_legendre
+    assert f(b.ctypes.data_as(A._dp), -1, 0.1, 4, out.ctypes.data_as(A._dp)) == -1
+    assert f(b.ctypes.data_as(A._dp), 3, 0.0, 4, out.ctypes.data_as(A._dp)) == -1
+    assert f(b.ctypes.data_as(A._dp), 3, 0.1, 1, out.ctypes.data_as(A._dp)) == -1
+    assert f(None, 3, 0.1, 4, out.ctypes.data_as(A._dp)) == -1
+
+
+@pytest.mark.parametrize("nside", [1, 2, 3, 7, 64, 2048])
+def test_ring_geometry_matches_oracle(nside):
+    g = O.ring_geometry(nside)
+    rings = range(1, 4 * nside) if nside < 100 else list(range(1, 40)) + list(
+        range(nside - 5, nside + 6)) + list(range(2 * nside - 3, 2 * nside + 4)) + list(
+        range(4 * nside - 40, 4 * nside))
+    for i in rings:
+        r = A.ring_info(nside, i)
+        assert r["n"] == g["n"][i - 1] and r["first"] == g["first"][i - 1]
+        assert abs(r["z"] - g["z"][i - 1]) < 5e-16
+        assert abs(r["sin_theta"] - g["s"][i - 1]) < 5e-16
+        assert abs(r["phi0"] - g["phi0"][i - 1]) < 1e-15
+
+
+@pytest.mark.parametrize("fwhm_arcmin,lmax,tc_arcmin,ntab", [
+    (120.0, 191, 360.0, 4096), (30.0, 1535, 90.0, 8192), (5.0, 6143, 20.0, 2049),
+])
+def test_tabulation_matches_oracle(fwhm_arcmin, lmax, tc_arcmin, ntab):
+    am = np.pi / 180 / 60
+    bl = O.gaussian_bl(fwhm_arcmin * am, lmax)
+    np.testing.assert_allclose(A.gaussian_bl(fwhm_arcmin * am, lmax), bl, rtol=1e-15)
+    ko = O.tabulate(bl, tc_arcmin * am, ntab)
+    ka = A.tabulate_legendre(bl, tc_arcmin * am, ntab)
+    # two different FP64 summation algorithms (forward recurrence in the oracle,
+    # Clenshaw in the plan); rounding grows like lmax * eps * max|K|
+    assert np.max(np.abs(ka - ko)) < max(1e-13, 2e-14 * lmax) * np.abs(ko).max()
+
+
+@pytest.mark.parametrize("nside,tc_deg", [
+    (1, 30.0), (1, 179.0), (2, 50.0), (4, 1.0), (4, 89.7), (8, 20.0), (8, 179.3),
+    (16, 6.0), (16, 44.9), (16, 71.7), (32, 17.3), (64, 6.0), (64, 2.5), (128, 1.5),
+])
+def test_exact_pair_count_matches_oracle(nside, tc_deg):
+    """Cut-offs are chosen off lattice ties: at e.g. 45 or 90 degrees whole
+    families of HEALPix pairs sit exactly on the cut, where the strict test
+    theta < theta_cut is decided by the last bit of either computation."""
+    tc = np.radians(tc_deg)
+    p = A.Plan(nside, tc, np.ones(8), host_only=True)
+    assert p.pair_count() == int(O.pair_counts(nside, tc).sum())
+
+
+def _in_disc_pairs(nside, tc):
+    v = O.pix2vec(nside)
+    d = np.linalg.norm(v[:, None, :] - v[None, :, :], axis=2)
+    th = 2 * np.arcsin(np.minimum(1.0, d / 2))
+    return np.nonzero(th < tc)
+
+
+def _ring_index(nside):
+    g = O.ring_geometry(nside)
+    ring = np.repeat(np.arange(1, 4 * nside), g["n"])
+    j = np.arange(12 * nside * nside) - np.repeat(g["first"], g["n"])
+    return ring, j, g
+
+
+@pytest.mark.parametrize("nside,tc_deg", [(4, 40.0), (8, 12.0), (8, 100.0), (16, 7.0),
+                                          (16, 160.0), (24, 5.0)])
+def test_windows_cover_every_in_disc_pair(nside, tc_deg):
+    """Every pair the oracle finds inside the disc lies in a window the kernels
+    scan, and every window stays within one wrap of its ring."""
+    tc = np.radians(tc_deg)
+    plan = A.Plan(nside, tc, np.ones(8), host_only=True)
+    ring, jj, g = _ring_index(nside)
+    P, Q = _in_disc_pairs(nside, tc)
+    win = {}
+    for r in range(1, 4 * nside):
+        for s in range(1, 4 * nside):
+            w0 = plan.window(r, s, 0)
+            if w0 is None:
+                continue
+            n_s = g["n"][s - 1]
+            for j in range(g["n"][r - 1]):
+                lo, hi = plan.window(r, s, j)
+                assert -n_s < lo and hi < 2 * n_s and hi - lo + 1 <= n_s
+                win[(r, s, j)] = (lo, hi)
+    for p, q in zip(P, Q):
+        r, j, s, jq = ring[p], jj[p], ring[q], jj[q]
+        lo, hi = win[(r, s, j)]
+        n_s = g["n"][s - 1]
+        assert any(lo <= jq + k * n_s <= hi for k in (-1, 0, 1)), (r, j, s, jq, lo, hi)
+
+
+def test_plan_info_is_consistent():
+    p = A.Plan(32, np.radians(5.0), np.ones(100), host_only=True, tile=128)
+    inf = p.info()
+    assert inf["nside"] == 32 and inf["nrings"] == 127 and inf["npix"] == 12288
+    assert inf["tile"] == 128 and inf["ntab"] == 100 and inf["device_bytes"] == 0
+    assert abs(inf["omega"] - 4 * np.pi / 12288) < 1e-18
+    assert inf["tiles"] == sum(-(-n // 128) for n in O.ring_geometry(32)["n"])
+    assert inf["candidates"] >= p.pair_count()

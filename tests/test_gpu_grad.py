@@ -1,0 +1,126 @@
+"""GPU parity of the adjoint (d/dmap, the transposed gather) and of the knot
+gradient (hat-basis gather) against the FP64 oracle's gradients, whose own
+correctness is pinned by exact central differences in the CPU suite."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from gpu_util import REL_RMS_TOL, assert_tie_free, log, rel_rms, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+
+def _A():
+    import paper_1211_3556_amd as A
+    return A
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("nside,nb,tc_deg,nk", [(32, 3, 10.3, 64), (24, 1, 40.3, 200),
+                                                 (16, 8, 99.3, 33)])
+def test_gradients_full_maps(nside, nb, tc_deg, nk):
+    tc = np.radians(tc_deg)
+    assert_tie_free(nside, tc)
+    knots = W.gaussian_profile_knots(tc / 3, tc, nk)
+    x = W.white_noise(nside, 600, nbatch=nb)
+    g = W.white_noise(nside, 700, nbatch=nb)
+    A = _A()
+    plan = A.Plan(nside, tc, ntab=nk, max_batch=nb, learnable=True)
+    plan.set_knots(to_dev(knots))
+    log("gradients Nside %d batch %d" % (nside, nb))
+    gx, gk = plan.backward(to_dev(g), to_dev(x), want_map=True, want_knots=True)
+    _sync()
+    gx, gk = to_host(gx), to_host(gk)
+    gk_ref = sum(O.knot_grad(nside, tc, nk, x[b], g[b]) for b in range(nb))
+    for b in range(nb):
+        assert rel_rms(gx[b], O.map_grad(nside, tc, knots, g[b])) <= REL_RMS_TOL
+    assert np.max(np.abs(gk - gk_ref)) <= 1e-5 * np.abs(gk_ref).max()
+    assert rel_rms(gk, gk_ref) <= 1e-6
+    # knot gradient alone, and map gradient alone, agree with the fused call
+    _, gk2 = plan.backward(to_dev(g), to_dev(x), want_map=False, want_knots=True)
+    gx2, _ = plan.backward(to_dev(g), None, want_map=True, want_knots=False)
+    _sync()
+    assert rel_rms(to_host(gk2), gk_ref) <= 1e-6
+    assert np.array_equal(to_host(gx2), gx)
+
+
+def test_autograd_function_and_loss():
+    """The torch.autograd.Function path on the c5 loss L = sum (conv(x) - t)^2 at
+    a reduced Nside: gradients match the oracle's."""
+    import torch
+    A = _A()
+    spec = W.C5
+    nside, nb = 128, 2
+    tc = spec.theta_cut * 8     # same number of pixels per disc radius as at Nside 1024
+    knots = W.gaussian_profile_knots(spec.fwhm * 8, tc, spec.nknots)
+    target_knots = W.gaussian_profile_knots(spec.target_fwhm * 8, tc, spec.nknots)
+    x = W.white_noise(nside, spec.seed0, nbatch=nb)
+    t = np.stack([O.convolve(nside, tc, target_knots, x[b]) for b in range(nb)])
+    y_ref = np.stack([O.convolve(nside, tc, knots, x[b]) for b in range(nb)])
+    g_ref = 2.0 * (y_ref - t)
+    gx_ref = np.stack([O.map_grad(nside, tc, knots, g_ref[b]) for b in range(nb)])
+    gk_ref = sum(O.knot_grad(nside, tc, spec.nknots, x[b], g_ref[b]) for b in range(nb))
+
+    plan = A.Plan(nside, tc, ntab=spec.nknots, max_batch=nb, learnable=True)
+    xd = to_dev(x).requires_grad_(True)
+    kd = to_dev(knots).requires_grad_(True)
+    log("autograd loss")
+    y = A.conv(xd, plan, kd)
+    loss = torch.sum((y.double() - torch.from_numpy(t).cuda()) ** 2)
+    loss.backward()
+    _sync()
+    assert rel_rms(to_host(y), y_ref) <= REL_RMS_TOL
+    # g = 2 (y - t) carries the FP32 forward error into both gradients
+    assert rel_rms(to_host(xd.grad), gx_ref) <= 1e-5
+    assert np.max(np.abs(to_host(kd.grad) - gk_ref)) <= 1e-4 * np.abs(gk_ref).max()
+
+
+def test_c5_full_size_sampled_and_identities():
+    """Nside 1024, 8 maps, 256 learnable knots, theta_cut 30 arcmin, in the
+    benchmark's launch configuration: the adjoint at sampled pixels against
+    the oracle, and the Euler identities <K, dL/dK> = <g, y> = <x, A g>,
+    which hold at any size, for the knot gradient."""
+    spec = W.C5
+    A = _A()
+    knots = W.gaussian_profile_knots(spec.fwhm, spec.theta_cut, spec.nknots)
+    x = W.white_noise(spec.nside, spec.seed0, nbatch=spec.nbatch)
+    g = W.white_noise(spec.nside, spec.seed0 + 50, nbatch=spec.nbatch)
+    plan = A.Plan(spec.nside, spec.theta_cut, ntab=spec.nknots, max_batch=spec.nbatch,
+                  learnable=True)
+    plan.set_knots(to_dev(knots))
+    log("c5 full size backward")
+    xd, gd = to_dev(x), to_dev(g)
+    y = plan.convolve(xd)
+    gx, gk = plan.backward(gd, xd, want_map=True, want_knots=True)
+    _sync()
+    pix = W.eval_pixels(spec.nside, 512, spec.seed0, max_strata_ring_pixels=128)
+    for b in (0, spec.nbatch - 1):
+        # (A^T g)_q = (A g)_q: the operator is symmetric, so the oracle's direct
+        # sum of g at the sampled pixels is the adjoint there
+        ref = O.convolve(spec.nside, spec.theta_cut, knots, g[b], pixels=pix)
+        assert rel_rms(to_host(gx[b])[pix], ref) <= REL_RMS_TOL
+    gy = float(np.sum(to_host(gd) * to_host(y)))
+    kg = float(np.dot(knots, to_host(gk)))
+    xg = float(np.sum(to_host(xd) * to_host(gx)))
+    scale = float(np.sqrt(np.sum(to_host(gd) ** 2) * np.sum(to_host(y) ** 2)))
+    assert abs(kg - gy) <= 1e-5 * scale
+    assert abs(xg - gy) <= 1e-5 * scale
+
+
+def test_knot_gradient_limits():
+    import torch
+    A = _A()
+    plan = A.Plan(8, 0.3, ntab=A.MAX_GRAD_NTAB + 1, learnable=True)
+    plan.set_knots(torch.ones(A.MAX_GRAD_NTAB + 1, device="cuda"))
+    z = torch.zeros(768, device="cuda")
+    with pytest.raises(A.ArkcosError) as e:
+        plan.backward(z, z.clone(), want_map=False, want_knots=True)
+    assert e.value.status == -4
+    gx, _ = plan.backward(z, None, want_map=True)
+    _sync()
+    assert float(gx.abs().max()) == 0.0
