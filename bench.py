@@ -73,7 +73,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain-compare", action="store_true",
                     help="skip the 16 plain launches the batch is compared with")
-    ap.add_argument("--cpu-sample", type=int, default=600_000,
+    ap.add_argument("--cpu-sample", type=int, default=6_000_000,
                     help="output pixels of the Nside-2048 oracle sample")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))

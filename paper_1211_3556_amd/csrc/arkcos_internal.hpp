@@ -56,6 +56,16 @@ struct DevPair {
 };
 static_assert(sizeof(DevPair) == 32, "DevPair layout");
 
+// FP64 copy of the chord constants of a ring pair, used where the node index
+// and fraction must be exact to ~1e-9 (the knot gradient: the hat basis has
+// slope 1/h, so an FP32 angle moves node fractions by ~1e-7 u).
+struct DevPairD {
+    double A;
+    double B;
+    double xscale;
+    double pad;
+};
+
 // One work item: pixels j0 .. j0 + len - 1 of output ring r.
 struct DevTile {
     int r;
@@ -70,6 +80,8 @@ struct DevPlanView {
     const DevPair *pairs;
     const DevTile *tiles;
     const float *table;      // ntab FP32 values Omega * K_k
+    const DevPairD *pairs_d; // FP64 chord constants (learnable plans), else NULL
+    double inv_h_d;          // (ntab - 1) / theta_cut in FP64
     int ntiles;
     int ntab;
     int npix;
@@ -120,6 +132,7 @@ struct Plan {
     std::vector<HostRing> rings;      // 0-based
     std::vector<DevRing> dev_rings;
     std::vector<DevPair> pairs;
+    std::vector<DevPairD> pairs_d;    // same order as pairs
     std::vector<DevTile> tiles;       // sorted by decreasing cost
     std::vector<double> ktab;         // current host copy (FP64), if known
     long long candidates = 0;
@@ -130,6 +143,7 @@ struct Plan {
     int device = -1;
     DevRing *d_rings = nullptr;
     DevPair *d_pairs = nullptr;
+    DevPairD *d_pairs_d = nullptr;
     DevTile *d_tiles = nullptr;
     float *d_table = nullptr;
     unsigned int *d_counter = nullptr;  // persistent-queue counter (+ 1 spare)

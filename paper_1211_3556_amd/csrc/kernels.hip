@@ -103,6 +103,22 @@ __device__ __forceinline__ float pair_weight(const DevPlanView &P, const DevPair
     return inside ? fmaf(frac, k1 - k0, k0) : 0.0f;
 }
 
+// Node index and fraction of one pair from FP64 geometry (same chord, angle
+// and table coordinate as pair_weight, through the device math library).
+// Returns false at or beyond the cut.
+__device__ __forceinline__ bool pair_node_fp64(const DevPlanView &P, const DevPairD &pd, int m,
+                                               int &node, double &frac)
+{
+    const double sx = sin((double)m * pd.xscale);
+    const double d2 = fma(pd.B, sx * sx, pd.A);
+    const double th = 2.0 * asin(fmin(1.0, 0.5 * sqrt(d2)));
+    const double u = th * P.inv_h_d;
+    if (!(u < (double)(P.ntab - 1))) return false;
+    node = (int)u;
+    frac = u - (double)node;
+    return true;
+}
+
 __device__ __forceinline__ int wrap_index(int jq, int n)
 {
     jq = (jq < 0) ? jq + n : jq;
@@ -213,9 +229,11 @@ __global__ void k_set_table(float *table, const float *knots, int ntab, float om
 }
 
 // -------------------------------------------------------------- backward --
-// Fused adjoint: gx[q'] over the batch (the same gather applied to g) and the
-// knot gradient sum_b g_b[p] x_b[q] hat_k(theta_pq), accumulated per
-// workgroup in an FP64 LDS histogram and written to partials[block][ntab].
+// Fused adjoint: gx[q'] over the batch (the same gather applied to g, with the
+// forward's FP32 weights, so it is the exact transpose of the forward) and the
+// knot gradient sum_b g_b[p] x_b[q] hat_k(theta_pq), with node and fraction
+// from FP64 geometry, accumulated per workgroup in an FP64 LDS histogram and
+// written to partials[block][ntab].
 template <int NB, bool WANT_GX, bool WANT_GK>
 __global__ __launch_bounds__(kThreads) void k_backward(DevPlanView P,
                                                        const float *__restrict__ g,
@@ -262,6 +280,8 @@ __global__ __launch_bounds__(kThreads) void k_backward(DevPlanView P,
                 int lo, hi;
                 pair_window(pp, S.n, j, lo, hi);
                 const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+                DevPairD pd{};
+                if (WANT_GK) pd = P.pairs_d[k];
                 float row[NB];
 #pragma unroll
                 for (int b = 0; b < NB; ++b) row[b] = 0.0f;
@@ -269,9 +289,9 @@ __global__ __launch_bounds__(kThreads) void k_backward(DevPlanView P,
                     int node;
                     float frac;
                     bool inside;
-                    const float w = pair_weight(P, pp, lds_tab,
-                                                lon_numerator(mbase, jq, S.two_o, R.n), node,
-                                                frac, inside);
+                    const int m = lon_numerator(mbase, jq, S.two_o, R.n);
+                    const float w = WANT_GX ? pair_weight(P, pp, lds_tab, m, node, frac, inside)
+                                            : 0.0f;
                     const size_t q = (size_t)(S.first + wrap_index(jq, S.n));
                     float c = 0.0f;
 #pragma unroll
@@ -282,9 +302,13 @@ __global__ __launch_bounds__(kThreads) void k_backward(DevPlanView P,
                             if (WANT_GK) c = fmaf(gp[b], x[off + q], c);
                         }
                     }
-                    if (WANT_GK && inside) {
-                        atomicAdd(&hist[node], (double)((1.0f - frac) * c));
-                        atomicAdd(&hist[node + 1], (double)(frac * c));
+                    if (WANT_GK) {
+                        int nd;
+                        double fd;
+                        if (pair_node_fp64(P, pd, m, nd, fd)) {
+                            atomicAdd(&hist[nd], (1.0 - fd) * (double)c);
+                            atomicAdd(&hist[nd + 1], fd * (double)c);
+                        }
                     }
                 }
                 if (WANT_GX) {

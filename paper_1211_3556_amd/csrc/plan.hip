@@ -60,6 +60,8 @@ DevPlanView Plan::view() const
     v.pairs = d_pairs;
     v.tiles = d_tiles;
     v.table = d_table;
+    v.pairs_d = d_pairs_d;
+    v.inv_h_d = (desc.ntab - 1) / desc.theta_cut;
     v.ntiles = (int)tiles.size();
     v.ntab = desc.ntab;
     v.npix = (int)npix;
@@ -100,6 +102,7 @@ static int build_plan(Plan &P)
     // pixel sits on the cut; the per-pair test on the device decides.
     const double slack = 1e-12 + 1e-9 * tc;
     P.pairs.clear();
+    P.pairs_d.clear();
     P.candidates = 0;
     std::vector<double> ring_cost(P.nrings, 0.0);
     for (int r = 0; r < P.nrings; ++r) {
@@ -118,10 +121,14 @@ static int build_plan(Plan &P)
             bool whole = false;
             const double dphi = half_width(R, S, tc, &whole);
             DevPair p{};
+            DevPairD pd{};
             const double dA = 2.0 * std::sin(0.5 * (R.theta - S.theta));
-            p.A = (float)(dA * dA);
-            p.B = (float)(4.0 * R.s * S.s);
-            p.xscale = (float)(M_PI / (2.0 * (double)R.n * (double)S.n));
+            pd.A = dA * dA;
+            pd.B = 4.0 * R.s * S.s;
+            pd.xscale = M_PI / (2.0 * (double)R.n * (double)S.n);
+            p.A = (float)pd.A;
+            p.B = (float)pd.B;
+            p.xscale = (float)pd.xscale;
             p.a = (float)((double)S.n / (double)R.n);
             p.b = (float)(0.5 * R.two_o * (double)S.n / (double)R.n - 0.5 * S.two_o);
             // window half-width in source pixels, widened to cover FP32 rounding
@@ -139,6 +146,7 @@ static int build_plan(Plan &P)
             }
             p.s = s;
             P.pairs.push_back(p);
+            P.pairs_d.push_back(pd);
         }
         dr.pair_end = (int)P.pairs.size();
         ring_cost[r] = per_pixel;
@@ -240,6 +248,7 @@ static void free_device(Plan &P)
         (void)hipDeviceSynchronize();
         (void)hipFree(P.d_rings);
         (void)hipFree(P.d_pairs);
+        (void)hipFree(P.d_pairs_d);
         (void)hipFree(P.d_tiles);
         (void)hipFree(P.d_table);
         (void)hipFree(P.d_counter);
@@ -248,6 +257,7 @@ static void free_device(Plan &P)
     }
     P.d_rings = nullptr;
     P.d_pairs = nullptr;
+    P.d_pairs_d = nullptr;
     P.d_tiles = nullptr;
     P.d_table = nullptr;
     P.d_counter = nullptr;
@@ -300,6 +310,7 @@ static int to_device(Plan &P)
     if ((P.desc.flags & ARKCOS_PLAN_LEARNABLE) && P.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
         std::vector<double> z((size_t)P.grid * P.desc.ntab, 0.0);
         if ((rc = upload(&P.d_kpart, z, &P.device_bytes))) return rc;
+        if ((rc = upload(&P.d_pairs_d, P.pairs_d, &P.device_bytes))) return rc;
     }
     if (!P.ktab.empty()) {
         if ((rc = write_table_host(P))) return rc;
