@@ -83,6 +83,11 @@ typedef struct {
     unsigned flags;
     int threads_per_block;
     long long device_bytes;        /* device memory the plan holds                      */
+    int circulant_rings;           /* rings gathered with precomputed weight rows       */
+    int general_rings;             /* rings gathered with per-pair weights              */
+    long long circulant_tiles;     /* work items of the two gathers per map             */
+    long long general_tiles;
+    long long weights;             /* FP32 entries of the circulant weight rows         */
 } arkcos_plan_info;
 
 /* ----------------------------------------------------------------- host -- */

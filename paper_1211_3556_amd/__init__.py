@@ -56,7 +56,10 @@ class _PlanInfo(ctypes.Structure):
                 ("ring_pairs", ctypes.c_longlong), ("tiles", ctypes.c_longlong),
                 ("candidates", ctypes.c_longlong), ("omega", ctypes.c_double),
                 ("ntab", ctypes.c_int), ("tile", ctypes.c_int), ("flags", ctypes.c_uint),
-                ("threads_per_block", ctypes.c_int), ("device_bytes", ctypes.c_longlong)]
+                ("threads_per_block", ctypes.c_int), ("device_bytes", ctypes.c_longlong),
+                ("circulant_rings", ctypes.c_int), ("general_rings", ctypes.c_int),
+                ("circulant_tiles", ctypes.c_longlong), ("general_tiles", ctypes.c_longlong),
+                ("weights", ctypes.c_longlong)]
 
 
 _lib = None

@@ -66,12 +66,45 @@ struct DevPairD {
     double pad;
 };
 
-// One work item: pixels j0 .. j0 + len - 1 of output ring r.
+// One work item: pixels j0 .. j0 + len - 1 of output ring r (or of the rings
+// of group r, for the circulant kernel).
 struct DevTile {
     int r;
     int j0;
     int len;
     int pad;
+};
+
+// Rings per group and outputs per lane of the circulant kernel, and the
+// source pixels one pass of the general kernel stages per image.
+constexpr int kThreads = 256;
+constexpr int kGroupRings = 4;
+constexpr int kCircPix = 4;
+constexpr int kCircSeg = kThreads * kCircPix;
+constexpr int kCircMaxTaps = 256;   // wider rows make their rings general
+constexpr int kGenChunk = 320;
+constexpr int kMaxMaps = 32;
+
+// A group of up to kGroupRings consecutive belt rings r0 .. r0+nr-1 whose
+// source rings all have the ring's own pixel count: the weight of a pair then
+// depends only on (r, s, j' - j), so each (r, s) has one weight row.
+struct DevGroup {
+    int r0;
+    int nr;
+    int row_begin;
+    int row_end;
+};
+
+// One source ring s of a group: taps k = k_lo .. k_lo+ntaps-1 (source pixel
+// j + k for output pixel j); the weight of tap t for ring r0+i is
+// wts[w_off + t * kGroupRings + i] (zero where (r0+i, s, k) is not a candidate).
+struct DevRow {
+    int s;
+    int k_lo;
+    int ntaps;
+    int w_off;
+    int g;
+    int pad0, pad1, pad2;
 };
 
 // Kernel-argument view of a plan (passed by value).
@@ -82,6 +115,15 @@ struct DevPlanView {
     const float *table;      // ntab FP32 values Omega * K_k
     const DevPairD *pairs_d; // FP64 chord constants (learnable plans), else NULL
     double inv_h_d;          // (ntab - 1) / theta_cut in FP64
+    const DevGroup *groups;  // circulant ring groups
+    const DevRow *rows;      // their source rows
+    float *wts;              // their weight rows (written by the weight-build kernel)
+    const DevTile *ctiles;   // circulant tiles: (group, j0, len)
+    const DevTile *gtiles;   // general tiles: (north ring, j0, len) inside quadrant 0
+    int nctiles;
+    int ngtiles;
+    int nrows;
+    int nrings;
     int ntiles;
     int ntab;
     int npix;
@@ -133,7 +175,14 @@ struct Plan {
     std::vector<DevRing> dev_rings;
     std::vector<DevPair> pairs;
     std::vector<DevPairD> pairs_d;    // same order as pairs
-    std::vector<DevTile> tiles;       // sorted by decreasing cost
+    std::vector<DevTile> tiles;       // per-ring tiles (knot gradient), longest first
+    std::vector<DevGroup> groups;
+    std::vector<DevRow> rows;
+    std::vector<DevTile> ctiles;      // circulant tiles, longest first
+    std::vector<DevTile> gtiles;      // general tiles, longest first
+    std::vector<double> ctile_cost, gtile_cost;
+    long long nweights = 0;
+    int max_taps = 0;
     std::vector<double> ktab;         // current host copy (FP64), if known
     long long candidates = 0;
     bool pairs_counted = false;
@@ -145,12 +194,20 @@ struct Plan {
     DevPair *d_pairs = nullptr;
     DevPairD *d_pairs_d = nullptr;
     DevTile *d_tiles = nullptr;
+    DevGroup *d_groups = nullptr;
+    DevRow *d_rows = nullptr;
+    float *d_wts = nullptr;
+    DevTile *d_ctiles = nullptr;
+    DevTile *d_gtiles = nullptr;
+    DevPlanView *d_view = nullptr;      // device copy of view() (a batch of one plan)
     float *d_table = nullptr;
     unsigned int *d_counter = nullptr;  // persistent-queue counter (+ 1 spare)
     double *d_kpart = nullptr;          // knot-gradient partials [grid][ntab] (learnable)
     int grid = 0;                       // rows of d_kpart: most resident backward workgroups
     int cus = 0;                        // compute units of the device
-    int occ_fwd[4] = {0, 0, 0, 0};      // resident workgroups per CU, NB = 1, 2, 4, 8
+    int occ_circ = 0;                   // resident workgroups per CU of the two gathers
+    int occ_gen = 0;
+    int occ_fwd[4] = {0, 0, 0, 0};      // unused slots kept zero
     int occ_bwd_gxgk[4] = {0, 0, 0, 0};
     int occ_bwd_gk[4] = {0, 0, 0, 0};
     long long device_bytes = 0;
@@ -160,16 +217,17 @@ struct Plan {
 
 struct Batch {
     std::vector<Plan *> plans;
-    std::vector<int> tile_map;          // global tile -> plan (sorted, longest first)
-    std::vector<int> tile_local;        // global tile -> tile index inside its plan
-    int *d_tile_map = nullptr;          // device copies of the two arrays above
-    int *d_tile_local = nullptr;
+    std::vector<int2> cmap;             // circulant tiles of all plans: (plan, tile), longest first
+    std::vector<int2> gmap;             // general tiles of all plans
+    int2 *d_cmap = nullptr;
+    int2 *d_gmap = nullptr;
     DevPlanView *d_views = nullptr;
     unsigned int *d_counter = nullptr;
-    int ntiles = 0;
-    int grid = 0;
+    int grid_circ = 0;
+    int grid_gen = 0;
     int cus = 0;
     int max_ntab = 0;
+    int max_taps = 0;
     int device = -1;
 };
 
@@ -180,6 +238,7 @@ int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipSt
 int launch_backward(const Plan &p, const float *g, const float *x, float *gx, float *gk,
                     int nbatch, hipStream_t s);
 int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s);
+int launch_build_weights(const Plan &p, hipStream_t s);
 int device_lds_limit(int device, size_t *bytes);
 int prepare_launches(Plan &p);   // occupancy of every kernel variant, grid sizes
 int prepare_batch(Batch &b);

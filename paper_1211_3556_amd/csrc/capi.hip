@@ -104,7 +104,7 @@ int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *o
     Batch *B = new (std::nothrow) Batch();
     if (!B) return fail(ARKCOS_ENOMEM, "host allocation failed");
     std::vector<DevPlanView> views;
-    std::vector<double> cost;
+    std::vector<double> ccost, gcost;
     for (int k = 0; k < nmaps; ++k) {
         Plan *P = reinterpret_cast<Plan *>(plans[k]);
         if (!P) { delete B; return fail(ARKCOS_EINVAL, "NULL plan in batch"); }
@@ -113,54 +113,53 @@ int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *o
         if (P->device != B->device) { delete B; return fail(ARKCOS_EINVAL, "plans on different devices"); }
         B->plans.push_back(P);
         B->max_ntab = std::max(B->max_ntab, P->desc.ntab);
+        B->max_taps = std::max(B->max_taps, P->max_taps);
         views.push_back(P->view());
-        // per-tile cost: candidates of its ring times its length
-        for (int t = 0; t < (int)P->tiles.size(); ++t) {
-            const DevTile &T = P->tiles[t];
-            const DevRing &R = P->dev_rings[T.r];
-            double c = 0.0;
-            for (int q = R.pair_begin; q < R.pair_end; ++q) {
-                const DevPair &pp = P->pairs[q];
-                c += pp.whole ? (double)P->dev_rings[pp.s].n : 2.0 * pp.w + 1.0;
-            }
-            B->tile_map.push_back(k);
-            B->tile_local.push_back(t);
-            cost.push_back(c * T.len);
+        for (int t = 0; t < (int)P->ctiles.size(); ++t) {
+            B->cmap.push_back(make_int2(k, t));
+            ccost.push_back(P->ctile_cost[t]);
+        }
+        for (int t = 0; t < (int)P->gtiles.size(); ++t) {
+            B->gmap.push_back(make_int2(k, t));
+            gcost.push_back(P->gtile_cost[t]);
         }
     }
-    std::vector<size_t> order(cost.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return cost[a] > cost[b]; });
-    std::vector<int> tm(order.size()), tl(order.size());
-    for (size_t i = 0; i < order.size(); ++i) {
-        tm[i] = B->tile_map[order[i]];
-        tl[i] = B->tile_local[order[i]];
-    }
-    B->tile_map.swap(tm);
-    B->tile_local.swap(tl);
-    B->ntiles = (int)B->tile_map.size();
+    // one queue per kernel over the tiles of every plan, longest first
+    auto sort_map = [](std::vector<int2> &m, const std::vector<double> &c) {
+        std::vector<size_t> order(m.size());
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return c[a] > c[b]; });
+        std::vector<int2> m2(m.size());
+        for (size_t i = 0; i < order.size(); ++i) m2[i] = m[order[i]];
+        m.swap(m2);
+    };
+    sort_map(B->cmap, ccost);
+    sort_map(B->gmap, gcost);
 
     DeviceGuard g(B->device);
     auto bail = [&](int rc) {
-        (void)hipFree(B->d_tile_map);
-        (void)hipFree(B->d_tile_local);
+        (void)hipFree(B->d_cmap);
+        (void)hipFree(B->d_gmap);
         (void)hipFree(B->d_views);
         (void)hipFree(B->d_counter);
         delete B;
         return rc;
     };
-    if (hipMalloc((void **)&B->d_tile_map, sizeof(int) * B->ntiles) != hipSuccess ||
-        hipMalloc((void **)&B->d_tile_local, sizeof(int) * B->ntiles) != hipSuccess ||
+    const size_t nc = std::max<size_t>(B->cmap.size(), 1), ng = std::max<size_t>(B->gmap.size(), 1);
+    if (hipMalloc((void **)&B->d_cmap, sizeof(int2) * nc) != hipSuccess ||
+        hipMalloc((void **)&B->d_gmap, sizeof(int2) * ng) != hipSuccess ||
         hipMalloc((void **)&B->d_views, sizeof(DevPlanView) * nmaps) != hipSuccess ||
         hipMalloc((void **)&B->d_counter, sizeof(unsigned int) * 4) != hipSuccess) {
         (void)hipGetLastError();
-        return bail(fail(ARKCOS_ENOMEM, "hipMalloc failed for the batch queue"));
+        return bail(fail(ARKCOS_ENOMEM, "hipMalloc failed for the batch queues"));
     }
-    if (hipMemcpy(B->d_tile_map, B->tile_map.data(), sizeof(int) * B->ntiles, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(B->d_tile_local, B->tile_local.data(), sizeof(int) * B->ntiles, hipMemcpyHostToDevice) != hipSuccess ||
+    if ((!B->cmap.empty() && hipMemcpy(B->d_cmap, B->cmap.data(), sizeof(int2) * B->cmap.size(),
+                                       hipMemcpyHostToDevice) != hipSuccess) ||
+        (!B->gmap.empty() && hipMemcpy(B->d_gmap, B->gmap.data(), sizeof(int2) * B->gmap.size(),
+                                       hipMemcpyHostToDevice) != hipSuccess) ||
         hipMemcpy(B->d_views, views.data(), sizeof(DevPlanView) * nmaps, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(B->d_counter, 0, sizeof(unsigned int) * 4) != hipSuccess)
-        return bail(fail(ARKCOS_EDEVICE, "copy of the batch queue failed"));
+        return bail(fail(ARKCOS_EDEVICE, "copy of the batch queues failed"));
     int rc = prepare_batch(*B);
     if (rc) return bail(rc);
     *out = reinterpret_cast<arkcos_batch_t>(B);
@@ -200,8 +199,8 @@ int arkcos_batch_destroy(arkcos_batch_t batch)
     {
         DeviceGuard g(B->device);
         (void)hipDeviceSynchronize();
-        (void)hipFree(B->d_tile_map);
-        (void)hipFree(B->d_tile_local);
+        (void)hipFree(B->d_cmap);
+        (void)hipFree(B->d_gmap);
         (void)hipFree(B->d_views);
         (void)hipFree(B->d_counter);
     }

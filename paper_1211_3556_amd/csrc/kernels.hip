@@ -2,17 +2,32 @@
 // Sec. 2: the real-space part of the split kernel applied by direct summation
 // on the GPU; Sec. 3: radial kernel interpolated from a node table).
 //
-// Work decomposition: a tile is a run of consecutive pixels of one output
-// ring.  Persistent workgroups pull tiles from a queue (longest first), keep
-// the node table in LDS and give each lane one output pixel; the lane walks
-// the source rings of its ring and the longitude window on each, computes the
-// chord from small, exactly known ring-pair constants, converts it to an
-// angle, interpolates the table and accumulates (FP32 per source-ring row,
-// FP64 across rows).  One weight serves
-// every map of the batch.  This is a gather with a per-pair kernel
-// evaluation, so it runs on the vector ALUs, not on matrix cores.
+// Every output ring is gathered by one of two kernels, which write disjoint
+// rings:
+//
+//  * k_circ (circulant rings: belt rings whose whole disc lies in the belt).
+//    All their source rings have 4N pixels, so the weight of (r, j; s, j')
+//    depends on j' - j only.  Each (r, s) has one weight row, evaluated once
+//    per node table by k_build_weights with exactly the per-pair arithmetic.
+//    The gather is then a correlation: a workgroup owns kGroupRings
+//    consecutive output rings and kCircSeg pixels of each, stages one source
+//    row at a time in LDS, and every LDS read feeds kGroupRings FMAs whose
+//    weights are wave-uniform scalar operands.
+//
+//  * k_general (polar caps and belt rings whose disc reaches a cap).  Weights
+//    are evaluated per pair from exact ring-pair constants: chord from
+//    d^2 = A + B sin^2(dphi/2), angle by series, node table in LDS with
+//    linear interpolation.  A quarter turn maps pixel j of a ring to
+//    j + n/4 and the N-S mirror maps ring i to ring 4N - i, so one weight
+//    serves eight pairs; source rows are staged in LDS as [pixel][8 images].
+//
+// Sums are FP32 within a source-ring row and FP64 across rows.  No atomics
+// touch the outputs: results are bitwise reproducible.  This is a gather with
+// a per-pair kernel evaluation, so it runs on the vector ALUs, not on matrix
+// cores.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
 
@@ -20,8 +35,22 @@
 
 namespace arkcos {
 
-constexpr int kThreads = 256;
-constexpr int kMaxBatchMaps = 32;
+// Plan data is read-only while a gather runs.  Reading it through the
+// constant address space lets wave-uniform loads (ring and pair records,
+// weight rows) become scalar loads.  (The host pass of the compiler, which
+// never runs these bodies, sees an ordinary pointer.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using cptr = const __attribute__((address_space(4))) T *;
+#else
+template <class T>
+using cptr = const T *;
+#endif
+template <class T>
+__device__ __forceinline__ cptr<T> cst(const T *p)
+{
+    return (cptr<T>)(p);
+}
 
 // ------------------------------------------------------------ FP32 math --
 // sin(x) for |x| <= 2 by its Taylor series through x^13 (truncation below
@@ -84,20 +113,18 @@ __device__ __forceinline__ float theta_large(float d2)
 }
 
 // Interpolated, Omega-scaled weight of one pair (0 at or beyond theta_cut).
-// Also returns the node index and fraction for the knot gradient.
 __device__ __forceinline__ float pair_weight(const DevPlanView &P, const DevPair &pp,
-                                             const float *tab, int m, int &node, float &frac,
-                                             bool &inside)
+                                             const float *tab, int m)
 {
     const float x = (float)m * pp.xscale;          // half the longitude difference
     const float sx = sin_series(x);
     const float d2 = fmaf(pp.B, sx * sx, pp.A);      // squared chord
     const float th = P.large_angle ? theta_large(d2) : theta_small(d2);
     const float u = th * P.inv_h;
-    inside = u < P.u_max;
+    const bool inside = u < P.u_max;
     const float uc = inside ? u : 0.0f;
-    node = (int)uc;
-    frac = uc - (float)node;
+    const int node = (int)uc;
+    const float frac = uc - (float)node;
     const float k0 = tab[node];
     const float k1 = tab[node + 1];
     return inside ? fmaf(frac, k1 - k0, k0) : 0.0f;
@@ -125,6 +152,14 @@ __device__ __forceinline__ int wrap_index(int jq, int n)
     return (jq >= n) ? jq - n : jq;
 }
 
+// j mod n for -n <= j < 3n.
+__device__ __forceinline__ int wrap3(int j, int n)
+{
+    j = (j < 0) ? j + n : j;
+    j = (j >= n) ? j - n : j;
+    return (j >= n) ? j - n : j;
+}
+
 // Exact longitude numerator m = (2j + 2o_r) n_s - (2j' + 2o_s) n_r; the
 // product terms may exceed 2^31 but the difference does not, so unsigned
 // wrap-around arithmetic gives it exactly.
@@ -133,93 +168,271 @@ __device__ __forceinline__ int lon_numerator(unsigned mbase, int jq, int two_o_s
     return (int)(mbase - (unsigned)(2 * jq + two_o_s) * (unsigned)n_r);
 }
 
-// Offset (in floats) of the knot-gradient histogram after an ntab-entry FP32
-// table: rounded up to 16 bytes.
-__host__ __device__ constexpr int hist_offset_floats(int ntab) { return (ntab + 3) & ~3; }
-
-// --------------------------------------------------------------- forward --
-// Accumulate the outputs of pixel j of ring R for maps map0 .. map0+NB-1.
-// Each source-ring row is summed in FP32 (at most a few hundred terms) and
-// the row sums in FP64, which keeps the rounding of long sums (wide discs,
-// thousands of pairs) well below the FP32 weight error.
-template <int NB>
-__device__ __forceinline__ void gather_pixel(const DevPlanView &P, const float *tab,
-                                             const DevRing &R, int j,
-                                             const float *__restrict__ in, int map0,
-                                             int nmaps, float out[NB])
-{
-    double acc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = 0.0;
-    for (int k = R.pair_begin; k < R.pair_end; ++k) {
-        const DevPair pp = P.pairs[k];
-        const DevRing S = P.rings[pp.s];
-        int lo, hi;
-        pair_window(pp, S.n, j, lo, hi);
-        const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
-        float row[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) row[b] = 0.0f;
-        for (int jq = lo; jq <= hi; ++jq) {
-            int node;
-            float frac;
-            bool inside;
-            const float w = pair_weight(P, pp, tab, lon_numerator(mbase, jq, S.two_o, R.n),
-                                        node, frac, inside);
-            const size_t q = (size_t)(S.first + wrap_index(jq, S.n));
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-                if (b < nmaps) row[b] = fmaf(w, in[(size_t)(map0 + b) * P.npix + q], row[b]);
-        }
-#pragma unroll
-        for (int b = 0; b < NB; ++b) acc[b] += (double)row[b];
-    }
-#pragma unroll
-    for (int b = 0; b < NB; ++b) out[b] = (float)acc[b];
-}
-
 __device__ __forceinline__ void load_table(float *lds, const float *table, int ntab)
 {
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) lds[i] = table[i];
 }
 
-// Persistent forward kernel: work item = (tile, group of NB maps), tiles in
-// the plan's longest-first order.
-template <int NB>
-__global__ __launch_bounds__(kThreads) void k_forward(DevPlanView P,
-                                                      const float *__restrict__ in,
-                                                      float *__restrict__ out, int nbatch,
-                                                      unsigned int *counter)
+// Work item of a persistent kernel, made wave-uniform.
+__device__ __forceinline__ int next_item(unsigned int *counter, int *s_item)
 {
-    extern __shared__ __align__(16) float lds_tab[];
-    __shared__ int s_item;
-    load_table(lds_tab, P.table, P.ntab);
-    const int ngroups = (nbatch + NB - 1) / NB;
-    const int nitems = P.ntiles * ngroups;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int item = s_item;
-        if (item >= nitems) break;
-        const int ti = item / ngroups;
-        const int map0 = (item - ti * ngroups) * NB;
-        const int nmaps = min(NB, nbatch - map0);
-        const DevTile T = P.tiles[ti];
-        const DevRing R = P.rings[T.r];
-        for (int jj = threadIdx.x; jj < T.len; jj += blockDim.x) {
-            const int j = T.j0 + jj;
-            float acc[NB];
-            gather_pixel<NB>(P, lds_tab, R, j, in, map0, nmaps, acc);
-            const size_t p = (size_t)(R.first + j);
+    __syncthreads();
+    if (threadIdx.x == 0) *s_item = (int)atomicAdd(counter, 1u);
+    __syncthreads();
+    return __builtin_amdgcn_readfirstlane(*s_item);
+}
+
+// Input and output maps of a launch: plan p reads in[p] and writes out[p]
+// (nmaps consecutive maps of Npix pixels each).
+struct MapIO {
+    const float *in[kMaxMaps];
+    float *out[kMaxMaps];
+};
+
+// ------------------------------------------------------- circulant gather --
+// Weight rows of the circulant groups, one workgroup per row: tap k of ring r
+// is the per-pair weight at the exact longitude numerator
+// m = n (2o_r - 2o_s - 2k), zero where k is outside the (r, s) window.
+__global__ __launch_bounds__(kThreads) void k_build_weights(DevPlanView P)
+{
+    const int row = blockIdx.x;
+    if (row >= P.nrows) return;
+    const DevRow W = P.rows[row];
+    const DevGroup G = P.groups[W.g];
+    const int n = P.rings[G.r0].n;
+    const int two_o_s = P.rings[W.s].two_o;
+    for (int e = threadIdx.x; e < W.ntaps * kGroupRings; e += blockDim.x) {
+        const int t = e / kGroupRings;
+        const int i = e - t * kGroupRings;
+        const int k = W.k_lo + t;
+        float w = 0.0f;
+        if (i < G.nr) {
+            const DevRing R = P.rings[G.r0 + i];
+            const int kk = R.pair_begin + (W.s - P.pairs[R.pair_begin].s);
+            if (kk >= R.pair_begin && kk < R.pair_end) {
+                const DevPair pp = P.pairs[kk];
+                int lo, hi;
+                pair_window(pp, n, 0, lo, hi);
+                if (k >= lo && k <= hi)
+                    w = pair_weight(P, pp, P.table, n * (R.two_o - two_o_s - 2 * k));
+            }
+        }
+        P.wts[W.w_off + e] = w;
+    }
+}
+
+// Source pixels each lane prefetches per row: a row spans at most
+// kCircSeg + kCircMaxTaps - 1 pixels.
+constexpr int kStageRegs = (kCircSeg + kCircMaxTaps + kThreads - 1) / kThreads;
+
+// Issue the global loads of one staged row (pixels base .. base+nstage-1 of a
+// ring of n pixels, wrapped) into registers.
+__device__ __forceinline__ void prefetch_row(const float *src, int base, int nstage, int n,
+                                             float v[kStageRegs])
+{
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                if (b < nmaps) out[(size_t)(map0 + b) * P.npix + p] = acc[b];
+    for (int u = 0; u < kStageRegs; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        v[u] = (e < nstage) ? src[wrap_index(base + e, n)] : 0.0f;
+    }
+}
+
+// Persistent circulant gather over tiles (plan, group, segment) x maps.  Rows
+// are double-buffered: the loads of row t+1 are in flight while row t is
+// multiplied, and one barrier per row separates the buffers.
+__global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict__ views,
+                                                   const int2 *__restrict__ tile_map,
+                                                   int ntiles, MapIO io, int nmaps,
+                                                   int buf_floats, unsigned int *counter)
+{
+    extern __shared__ __align__(16) float xs[];
+    __shared__ int s_item;
+    const int nitems = ntiles * nmaps;
+    for (;;) {
+        const int item = next_item(counter, &s_item);
+        if (item >= nitems) break;
+        const int ti = item / nmaps;
+        const int map = item - ti * nmaps;
+        const int pi = tile_map ? cst(tile_map)[ti].x : 0;
+        const int lt = tile_map ? cst(tile_map)[ti].y : ti;
+        const DevPlanView P = cst(views)[pi];
+        const DevTile T = cst(P.ctiles)[lt];
+        const DevGroup G = cst(P.groups)[T.r];
+        const int n = cst(P.rings)[G.r0].n;
+        const float *in = io.in[pi] + (size_t)map * P.npix;
+        double acc[kGroupRings][kCircPix];
+#pragma unroll
+        for (int r = 0; r < kGroupRings; ++r)
+#pragma unroll
+            for (int i = 0; i < kCircPix; ++i) acc[r][i] = 0.0;
+        float v[kStageRegs];
+        {
+            const DevRow W = cst(P.rows)[G.row_begin];
+            prefetch_row(in + cst(P.rings)[W.s].first, T.j0 + W.k_lo, T.len + W.ntaps - 1, n, v);
+        }
+        int buf = 0;
+        for (int row = G.row_begin; row < G.row_end; ++row) {
+            const DevRow W = cst(P.rows)[row];
+            float *xb = xs + buf * buf_floats;
+#pragma unroll
+            for (int u = 0; u < kStageRegs; ++u) xb[threadIdx.x + u * kThreads] = v[u];
+            __syncthreads();
+            if (row + 1 < G.row_end) {
+                const DevRow W1 = cst(P.rows)[row + 1];
+                prefetch_row(in + cst(P.rings)[W1.s].first, T.j0 + W1.k_lo,
+                             T.len + W1.ntaps - 1, n, v);
+            }
+            float racc[kGroupRings][kCircPix];
+#pragma unroll
+            for (int r = 0; r < kGroupRings; ++r)
+#pragma unroll
+                for (int i = 0; i < kCircPix; ++i) racc[r][i] = 0.0f;
+            cptr<float> w = cst(P.wts + W.w_off);
+            const float *x0 = xb + threadIdx.x;
+#pragma unroll 2
+            for (int t = 0; t < W.ntaps; ++t) {
+                float wr[kGroupRings];
+#pragma unroll
+                for (int r = 0; r < kGroupRings; ++r) wr[r] = w[t * kGroupRings + r];
+#pragma unroll
+                for (int i = 0; i < kCircPix; ++i) {
+                    const float x = x0[i * kThreads + t];
+#pragma unroll
+                    for (int r = 0; r < kGroupRings; ++r) racc[r][i] = fmaf(wr[r], x, racc[r][i]);
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kGroupRings; ++r)
+#pragma unroll
+                for (int i = 0; i < kCircPix; ++i) acc[r][i] += (double)racc[r][i];
+            buf ^= 1;
+        }
+        float *out = io.out[pi] + (size_t)map * P.npix;
+#pragma unroll
+        for (int r = 0; r < kGroupRings; ++r) {
+            if (r >= G.nr) break;
+            float *o = out + cst(P.rings)[G.r0 + r].first + T.j0;
+#pragma unroll
+            for (int i = 0; i < kCircPix; ++i) {
+                const int jj = threadIdx.x + i * kThreads;
+                if (jj < T.len) o[jj] = (float)acc[r][i];
+            }
         }
     }
 }
 
-__global__ void k_reset_counter(unsigned int *counter) { counter[0] = 0u; }
+// --------------------------------------------------------- general gather --
+// Persistent general gather over tiles (plan, north ring, quadrant segment) x
+// maps.  LDS: the node table of the current plan, then the staged source row
+// as [pixel][8] = 4 quarter-turn images of ring s, then 4 of its mirror.
+__global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restrict__ views,
+                                                      const int2 *__restrict__ tile_map,
+                                                      int ntiles, MapIO io, int nmaps,
+                                                      int tab_floats, unsigned int *counter)
+{
+    extern __shared__ __align__(16) float lds[];
+    float *tab = lds;
+    float4 *stage = reinterpret_cast<float4 *>(lds + tab_floats);
+    __shared__ int s_item;
+    const int nitems = ntiles * nmaps;
+    int cur = -1;
+    for (;;) {
+        const int item = next_item(counter, &s_item);
+        if (item >= nitems) break;
+        const int ti = item / nmaps;
+        const int map = item - ti * nmaps;
+        const int pi = tile_map ? cst(tile_map)[ti].x : 0;
+        const int lt = tile_map ? cst(tile_map)[ti].y : ti;
+        const DevPlanView P = cst(views)[pi];
+        if (pi != cur) {
+            load_table(tab, P.table, P.ntab);
+            cur = pi;
+            __syncthreads();
+        }
+        const DevTile T = cst(P.gtiles)[lt];
+        const int rn = T.r;
+        const int rs = P.nrings - 1 - rn;           // mirror ring
+        const bool mirror = rs != rn;
+        const DevRing R = cst(P.rings)[rn];
+        const int qr = R.n >> 2;
+        const bool active = (int)threadIdx.x < T.len;
+        const int j = T.j0 + min((int)threadIdx.x, T.len - 1);
+        const float *in = io.in[pi] + (size_t)map * P.npix;
+        double acc[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+        for (int k = R.pair_begin; k < R.pair_end; ++k) {
+            const DevPair pp = cst(P.pairs)[k];
+            const DevRing S = cst(P.rings)[pp.s];
+            const float *src = in + S.first;
+            const float *srcm = in + cst(P.rings)[P.nrings - 1 - pp.s].first;
+            const int qs = S.n >> 2;
+            int lo_min, hi_max, lo, hi, dummy;
+            pair_window(pp, S.n, T.j0, lo_min, dummy);
+            pair_window(pp, S.n, T.j0 + T.len - 1, dummy, hi_max);
+            pair_window(pp, S.n, j, lo, hi);
+            const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+            float row[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) row[q] = 0.0f;
+            for (int c0 = lo_min; c0 <= hi_max; c0 += kGenChunk) {
+                const int cn = min(kGenChunk, hi_max - c0 + 1);
+                __syncthreads();
+                for (int e = threadIdx.x; e < cn; e += kThreads) {
+                    float4 a, b;
+                    a.x = src[wrap3(c0 + e, S.n)];
+                    a.y = src[wrap3(c0 + e + qs, S.n)];
+                    a.z = src[wrap3(c0 + e + 2 * qs, S.n)];
+                    a.w = src[wrap3(c0 + e + 3 * qs, S.n)];
+                    if (mirror) {
+                        b.x = srcm[wrap3(c0 + e, S.n)];
+                        b.y = srcm[wrap3(c0 + e + qs, S.n)];
+                        b.z = srcm[wrap3(c0 + e + 2 * qs, S.n)];
+                        b.w = srcm[wrap3(c0 + e + 3 * qs, S.n)];
+                    } else {
+                        b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+                    }
+                    stage[2 * e] = a;
+                    stage[2 * e + 1] = b;
+                }
+                __syncthreads();
+                const int a0 = max(lo, c0);
+                const int a1 = min(hi, c0 + cn - 1);
+                for (int jq = a0; jq <= a1; ++jq) {
+                    const float w = pair_weight(P, pp, tab, lon_numerator(mbase, jq, S.two_o, R.n));
+                    const float4 v0 = stage[2 * (jq - c0)];
+                    const float4 v1 = stage[2 * (jq - c0) + 1];
+                    row[0] = fmaf(w, v0.x, row[0]);
+                    row[1] = fmaf(w, v0.y, row[1]);
+                    row[2] = fmaf(w, v0.z, row[2]);
+                    row[3] = fmaf(w, v0.w, row[3]);
+                    row[4] = fmaf(w, v1.x, row[4]);
+                    row[5] = fmaf(w, v1.y, row[5]);
+                    row[6] = fmaf(w, v1.z, row[6]);
+                    row[7] = fmaf(w, v1.w, row[7]);
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] += (double)row[q];
+        }
+        if (active) {
+            float *out = io.out[pi] + (size_t)map * P.npix;
+            float *o = out + R.first + j;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q * qr] = (float)acc[q];
+            if (mirror) {
+                float *om = out + cst(P.rings)[rs].first + j;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) om[q * qr] = (float)acc[4 + q];
+            }
+        }
+    }
+}
+
+__global__ void k_reset_counters(unsigned int *counter)
+{
+    if (threadIdx.x < 2) counter[threadIdx.x] = 0u;
+}
 
 // Omega-scaled FP32 table from device knots.
 __global__ void k_set_table(float *table, const float *knots, int ntab, float omega)
@@ -228,106 +441,70 @@ __global__ void k_set_table(float *table, const float *knots, int ntab, float om
     if (i < ntab) table[i] = omega * knots[i];
 }
 
-// -------------------------------------------------------------- backward --
-// Fused adjoint: gx[q'] over the batch (the same gather applied to g, with the
-// forward's FP32 weights, so it is the exact transpose of the forward) and the
-// knot gradient sum_b g_b[p] x_b[q] hat_k(theta_pq), with node and fraction
-// from FP64 geometry, accumulated per workgroup in an FP64 LDS histogram and
-// written to partials[block][ntab].
-template <int NB, bool WANT_GX, bool WANT_GK>
-__global__ __launch_bounds__(kThreads) void k_backward(DevPlanView P,
-                                                       const float *__restrict__ g,
-                                                       const float *__restrict__ x,
-                                                       float *__restrict__ gx, int nbatch,
-                                                       unsigned int *counter,
-                                                       double *__restrict__ partials)
+// ---------------------------------------------------------- knot gradient --
+// Offset (in floats) of the knot-gradient histogram after an ntab-entry FP32
+// table: rounded up to 16 bytes.
+__host__ __device__ constexpr int hist_offset_floats(int ntab) { return (ntab + 3) & ~3; }
+
+// Knot gradient sum_b g_b[p] x_b[q] hat_k(theta_pq) over all pairs, node and
+// fraction from FP64 geometry, accumulated per workgroup in an FP64 LDS
+// histogram and written to partials[block][ntab].  One pass serves NB maps.
+template <int NB>
+__global__ __launch_bounds__(kThreads) void k_knot_grad(DevPlanView P,
+                                                        const float *__restrict__ g,
+                                                        const float *__restrict__ x,
+                                                        int nbatch, unsigned int *counter,
+                                                        double *__restrict__ partials)
 {
     // The dynamic LDS base is 16-byte aligned and the FP64 histogram starts at
-    // a 16-byte boundary after the table: 64-bit LDS atomics need natural
-    // alignment.
+    // a 16-byte boundary: 64-bit LDS atomics need natural alignment.
     extern __shared__ __align__(16) float lds_tab[];
     double *hist = reinterpret_cast<double *>(lds_tab + hist_offset_floats(P.ntab));
     __shared__ int s_item;
-    load_table(lds_tab, P.table, P.ntab);
-    if (WANT_GK)
-        for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) hist[i] = 0.0;
+    for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) hist[i] = 0.0;
     const int ngroups = (nbatch + NB - 1) / NB;
     const int nitems = P.ntiles * ngroups;
     for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int item = s_item;
+        const int item = next_item(counter, &s_item);
         if (item >= nitems) break;
         const int ti = item / ngroups;
         const int map0 = (item - ti * ngroups) * NB;
-        const int nmaps = min(NB, nbatch - map0);
+        const int nm = min(NB, nbatch - map0);
         const DevTile T = P.tiles[ti];
         const DevRing R = P.rings[T.r];
         for (int jj = threadIdx.x; jj < T.len; jj += blockDim.x) {
             const int j = T.j0 + jj;
             const size_t p = (size_t)(R.first + j);
             float gp[NB];
-            double acc[NB];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-                acc[b] = 0.0;
-                gp[b] = (WANT_GK && b < nmaps) ? g[(size_t)(map0 + b) * P.npix + p] : 0.0f;
-            }
+            for (int b = 0; b < NB; ++b)
+                gp[b] = (b < nm) ? g[(size_t)(map0 + b) * P.npix + p] : 0.0f;
             for (int k = R.pair_begin; k < R.pair_end; ++k) {
                 const DevPair pp = P.pairs[k];
+                const DevPairD pd = P.pairs_d[k];
                 const DevRing S = P.rings[pp.s];
                 int lo, hi;
                 pair_window(pp, S.n, j, lo, hi);
                 const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
-                DevPairD pd{};
-                if (WANT_GK) pd = P.pairs_d[k];
-                float row[NB];
-#pragma unroll
-                for (int b = 0; b < NB; ++b) row[b] = 0.0f;
                 for (int jq = lo; jq <= hi; ++jq) {
-                    int node;
-                    float frac;
-                    bool inside;
-                    const int m = lon_numerator(mbase, jq, S.two_o, R.n);
-                    const float w = WANT_GX ? pair_weight(P, pp, lds_tab, m, node, frac, inside)
-                                            : 0.0f;
+                    int nd;
+                    double fd;
+                    if (!pair_node_fp64(P, pd, lon_numerator(mbase, jq, S.two_o, R.n), nd, fd))
+                        continue;
                     const size_t q = (size_t)(S.first + wrap_index(jq, S.n));
                     float c = 0.0f;
 #pragma unroll
-                    for (int b = 0; b < NB; ++b) {
-                        if (b < nmaps) {
-                            const size_t off = (size_t)(map0 + b) * P.npix;
-                            if (WANT_GX) row[b] = fmaf(w, g[off + q], row[b]);
-                            if (WANT_GK) c = fmaf(gp[b], x[off + q], c);
-                        }
-                    }
-                    if (WANT_GK) {
-                        int nd;
-                        double fd;
-                        if (pair_node_fp64(P, pd, m, nd, fd)) {
-                            atomicAdd(&hist[nd], (1.0 - fd) * (double)c);
-                            atomicAdd(&hist[nd + 1], fd * (double)c);
-                        }
-                    }
+                    for (int b = 0; b < NB; ++b)
+                        if (b < nm) c = fmaf(gp[b], x[(size_t)(map0 + b) * P.npix + q], c);
+                    atomicAdd(&hist[nd], (1.0 - fd) * (double)c);
+                    atomicAdd(&hist[nd + 1], fd * (double)c);
                 }
-                if (WANT_GX) {
-#pragma unroll
-                    for (int b = 0; b < NB; ++b) acc[b] += (double)row[b];
-                }
-            }
-            if (WANT_GX) {
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                    if (b < nmaps) gx[(size_t)(map0 + b) * P.npix + p] = (float)acc[b];
             }
         }
     }
-    if (WANT_GK) {
-        __syncthreads();
-        double *dst = partials + (size_t)blockIdx.x * P.ntab;
-        for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) dst[i] = hist[i];
-    }
+    __syncthreads();
+    double *dst = partials + (size_t)blockIdx.x * P.ntab;
+    for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) dst[i] = hist[i];
 }
 
 // Fixed-order reduction of the per-workgroup partials, scaled by Omega.
@@ -341,51 +518,9 @@ __global__ void k_knot_reduce(const double *__restrict__ partials, int nblocks, 
     gk[k] = (float)(omega * s);
 }
 
-// --------------------------------------------------------------- batched --
-struct BatchArgs {
-    const float *in[kMaxBatchMaps];
-    float *out[kMaxBatchMaps];
-};
-
-// One persistent launch over the tiles of several plans (one map each).  A
-// workgroup reloads the LDS table only when the plan of its next tile differs.
-__global__ __launch_bounds__(kThreads) void k_batch(const DevPlanView *__restrict__ views,
-                                                    const int *__restrict__ tile_plan,
-                                                    const int *__restrict__ tile_local,
-                                                    int ntiles, BatchArgs args,
-                                                    unsigned int *counter)
-{
-    extern __shared__ __align__(16) float lds_tab[];
-    __shared__ int s_item;
-    int cur = -1;
-    for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int item = s_item;
-        if (item >= ntiles) break;
-        const int pi = tile_plan[item];
-        const DevPlanView P = views[pi];
-        if (pi != cur) {
-            load_table(lds_tab, P.table, P.ntab);
-            cur = pi;
-            __syncthreads();
-        }
-        const DevTile T = P.tiles[tile_local[item]];
-        const DevRing R = P.rings[T.r];
-        const float *in = args.in[pi];
-        float *out = args.out[pi];
-        for (int jj = threadIdx.x; jj < T.len; jj += blockDim.x) {
-            const int j = T.j0 + jj;
-            float acc[1];
-            gather_pixel<1>(P, lds_tab, R, j, in, 0, 1, acc);
-            out[R.first + j] = acc[0];
-        }
-    }
-}
-
 // ---------------------------------------------------------------- launch --
 int forward_threads() { return kThreads; }
+int batch_max_maps() { return kMaxMaps; }
 
 int device_lds_limit(int device, size_t *bytes)
 {
@@ -412,30 +547,25 @@ static int occupancy(K kernel, size_t lds, int *per_cu)
     return ARKCOS_OK;
 }
 
-static size_t forward_lds(int ntab) { return (size_t)ntab * sizeof(float); }
-static size_t backward_lds(int ntab, bool gk)
+// Two row buffers of kStageRegs * kThreads floats each.
+static int circ_buf_floats() { return kStageRegs * kThreads; }
+static size_t circ_lds() { return (size_t)2 * circ_buf_floats() * sizeof(float); }
+static int gen_tab_floats(int ntab) { return hist_offset_floats(ntab); }
+static size_t gen_lds(int ntab)
 {
-    return (size_t)hist_offset_floats(ntab) * sizeof(float) +
-           (gk ? (size_t)ntab * sizeof(double) : 0);
+    return (size_t)(gen_tab_floats(ntab) + 8 * kGenChunk) * sizeof(float);
+}
+static size_t knot_lds(int ntab)
+{
+    return (size_t)hist_offset_floats(ntab) * sizeof(float) + (size_t)ntab * sizeof(double);
 }
 
-// Variant index of the batch-width templates: NB = 1, 2, 4, 8.
 static int nb_index(int nbatch) { return nbatch >= 8 ? 3 : nbatch >= 4 ? 2 : nbatch >= 2 ? 1 : 0; }
 
 template <int NB>
-static int prepare_nb(Plan &p, int vi)
+static int prepare_knot(Plan &p, int vi)
 {
-    int rc = occupancy(k_forward<NB>, forward_lds(p.desc.ntab), &p.occ_fwd[vi]);
-    if (rc) return rc;
-    if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
-        if ((rc = occupancy(k_backward<NB, true, true>, backward_lds(p.desc.ntab, true),
-                            &p.occ_bwd_gxgk[vi])))
-            return rc;
-        if ((rc = occupancy(k_backward<NB, false, true>, backward_lds(p.desc.ntab, true),
-                            &p.occ_bwd_gk[vi])))
-            return rc;
-    }
-    return ARKCOS_OK;
+    return occupancy(k_knot_grad<NB>, knot_lds(p.desc.ntab), &p.occ_bwd_gk[vi]);
 }
 
 int prepare_launches(Plan &p)
@@ -443,12 +573,15 @@ int prepare_launches(Plan &p)
     ARKCOS_HIP_CHECK(hipDeviceGetAttribute(&p.cus, hipDeviceAttributeMultiprocessorCount,
                                            p.device));
     int rc;
-    if ((rc = prepare_nb<1>(p, 0))) return rc;
-    if ((rc = prepare_nb<2>(p, 1))) return rc;
-    if ((rc = prepare_nb<4>(p, 2))) return rc;
-    if ((rc = prepare_nb<8>(p, 3))) return rc;
+    if ((rc = occupancy(k_circ, circ_lds(), &p.occ_circ))) return rc;
+    if ((rc = occupancy(k_general, gen_lds(p.desc.ntab), &p.occ_gen))) return rc;
     int most = 1;
-    for (int v = 0; v < 4; ++v) most = std::max({most, p.occ_bwd_gxgk[v], p.occ_bwd_gk[v]});
+    if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
+        if ((rc = prepare_knot<1>(p, 0)) || (rc = prepare_knot<2>(p, 1)) ||
+            (rc = prepare_knot<4>(p, 2)) || (rc = prepare_knot<8>(p, 3)))
+            return rc;
+        for (int v = 0; v < 4; ++v) most = std::max(most, p.occ_bwd_gk[v]);
+    }
     p.grid = most * p.cus;  // rows of the knot-gradient partials
     return ARKCOS_OK;
 }
@@ -457,10 +590,11 @@ int prepare_batch(Batch &b)
 {
     ARKCOS_HIP_CHECK(hipDeviceGetAttribute(&b.cus, hipDeviceAttributeMultiprocessorCount,
                                            b.device));
-    int per_cu = 0;
-    int rc = occupancy(k_batch, forward_lds(b.max_ntab), &per_cu);
-    if (rc) return rc;
-    b.grid = std::max(1, std::min(b.ntiles, per_cu * b.cus));
+    int occ_c = 0, occ_g = 0, rc;
+    if ((rc = occupancy(k_circ, circ_lds(), &occ_c))) return rc;
+    if ((rc = occupancy(k_general, gen_lds(b.max_ntab), &occ_g))) return rc;
+    b.grid_circ = std::max(1, std::min((int)b.cmap.size(), occ_c * b.cus));
+    b.grid_gen = std::max(1, std::min((int)b.gmap.size(), occ_g * b.cus));
     return ARKCOS_OK;
 }
 
@@ -473,84 +607,93 @@ int launch_set_table(const Plan &p, const float *d_knots, hipStream_t s)
     return ARKCOS_OK;
 }
 
-template <int NB>
-static int forward_nb(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s)
+int launch_build_weights(const Plan &p, hipStream_t s)
 {
-    const size_t lds = forward_lds(p.desc.ntab);
-    const int items = (int)p.tiles.size() * ((nbatch + NB - 1) / NB);
-    const int grid = std::max(1, std::min(items, p.occ_fwd[nb_index(NB)] * p.cus));
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, p.d_counter);
-    hipLaunchKernelGGL(k_forward<NB>, dim3(grid), dim3(kThreads), lds, s, p.view(), in, out,
-                       nbatch, p.d_counter);
+    if (p.rows.empty()) return ARKCOS_OK;
+    hipLaunchKernelGGL(k_build_weights, dim3((unsigned)p.rows.size()), dim3(kThreads), 0, s,
+                       p.view());
     ARKCOS_HIP_CHECK(hipGetLastError());
     return ARKCOS_OK;
 }
 
+// The two gathers of one plan over nbatch maps; they write disjoint rings.
 int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s)
 {
-    if (nbatch >= 8) return forward_nb<8>(p, in, out, nbatch, s);
-    if (nbatch >= 4) return forward_nb<4>(p, in, out, nbatch, s);
-    if (nbatch >= 2) return forward_nb<2>(p, in, out, nbatch, s);
-    return forward_nb<1>(p, in, out, nbatch, s);
-}
-
-template <int NB, bool GX, bool GK>
-static int backward_nb(const Plan &p, const float *g, const float *x, float *gx, float *gk,
-                       int nbatch, hipStream_t s)
-{
-    const int ntab = p.desc.ntab;
-    const size_t lds = backward_lds(ntab, GK);
-    const int items = (int)p.tiles.size() * ((nbatch + NB - 1) / NB);
-    const int occ = GX ? p.occ_bwd_gxgk[nb_index(NB)] : p.occ_bwd_gk[nb_index(NB)];
-    const int grid = std::max(1, std::min({items, occ * p.cus, p.grid}));
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, p.d_counter);
-    hipLaunchKernelGGL((k_backward<NB, GX, GK>), dim3(grid), dim3(kThreads), lds, s, p.view(),
-                       g, x, gx, nbatch, p.d_counter, p.d_kpart);
-    ARKCOS_HIP_CHECK(hipGetLastError());
-    if (GK) {
-        hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 255) / 256), dim3(256), 0, s, p.d_kpart,
-                           grid, ntab, p.omega, gk);
-        ARKCOS_HIP_CHECK(hipGetLastError());
+    MapIO io{};
+    io.in[0] = in;
+    io.out[0] = out;
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, p.d_counter);
+    const int nct = (int)p.ctiles.size(), ngt = (int)p.gtiles.size();
+    if (nct > 0) {
+        const int grid = std::max(1, std::min(nct * nbatch, p.occ_circ * p.cus));
+        hipLaunchKernelGGL(k_circ, dim3(grid), dim3(kThreads), circ_lds(), s,
+                           (const DevPlanView *)p.d_view, (const int2 *)nullptr, nct, io, nbatch,
+                           circ_buf_floats(), p.d_counter);
     }
+    if (ngt > 0) {
+        const int grid = std::max(1, std::min(ngt * nbatch, p.occ_gen * p.cus));
+        hipLaunchKernelGGL(k_general, dim3(grid), dim3(kThreads), gen_lds(p.desc.ntab), s,
+                           (const DevPlanView *)p.d_view, (const int2 *)nullptr, ngt, io, nbatch,
+                           gen_tab_floats(p.desc.ntab), p.d_counter + 1);
+    }
+    ARKCOS_HIP_CHECK(hipGetLastError());
     return ARKCOS_OK;
 }
 
-template <bool GX, bool GK>
-static int backward_dispatch(const Plan &p, const float *g, const float *x, float *gx,
-                             float *gk, int nbatch, hipStream_t s)
+template <int NB>
+static int knot_nb(const Plan &p, const float *g, const float *x, float *gk, int nbatch,
+                   hipStream_t s)
 {
-    if (nbatch >= 8) return backward_nb<8, GX, GK>(p, g, x, gx, gk, nbatch, s);
-    if (nbatch >= 4) return backward_nb<4, GX, GK>(p, g, x, gx, gk, nbatch, s);
-    if (nbatch >= 2) return backward_nb<2, GX, GK>(p, g, x, gx, gk, nbatch, s);
-    return backward_nb<1, GX, GK>(p, g, x, gx, gk, nbatch, s);
+    const int ntab = p.desc.ntab;
+    const int items = (int)p.tiles.size() * ((nbatch + NB - 1) / NB);
+    const int grid = std::max(1, std::min({items, p.occ_bwd_gk[nb_index(NB)] * p.cus, p.grid}));
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, p.d_counter + 2);
+    hipLaunchKernelGGL(k_knot_grad<NB>, dim3(grid), dim3(kThreads), knot_lds(ntab), s, p.view(),
+                       g, x, nbatch, p.d_counter + 2, p.d_kpart);
+    ARKCOS_HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 255) / 256), dim3(256), 0, s, p.d_kpart, grid,
+                       ntab, p.omega, gk);
+    ARKCOS_HIP_CHECK(hipGetLastError());
+    return ARKCOS_OK;
 }
 
 int launch_backward(const Plan &p, const float *g, const float *x, float *gx, float *gk,
                     int nbatch, hipStream_t s)
 {
-    if (gx && gk) return backward_dispatch<true, true>(p, g, x, gx, gk, nbatch, s);
-    if (gk) return backward_dispatch<false, true>(p, g, x, gx, gk, nbatch, s);
-    return launch_forward(p, g, gx, nbatch, s);
+    // The operator is symmetric, so d/dmap is the same gather applied to g.
+    if (gx) {
+        int rc = launch_forward(p, g, gx, nbatch, s);
+        if (rc) return rc;
+    }
+    if (gk) {
+        if (nbatch >= 8) return knot_nb<8>(p, g, x, gk, nbatch, s);
+        if (nbatch >= 4) return knot_nb<4>(p, g, x, gk, nbatch, s);
+        if (nbatch >= 2) return knot_nb<2>(p, g, x, gk, nbatch, s);
+        return knot_nb<1>(p, g, x, gk, nbatch, s);
+    }
+    return ARKCOS_OK;
 }
 
 int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s)
 {
-    if ((int)b.plans.size() > kMaxBatchMaps)
-        return fail(ARKCOS_EUNSUPPORTED, "at most " + std::to_string(kMaxBatchMaps) +
-                                             " maps per batch");
-    BatchArgs args{};
+    if ((int)b.plans.size() > kMaxMaps)
+        return fail(ARKCOS_EUNSUPPORTED, "at most " + std::to_string(kMaxMaps) + " maps per batch");
+    MapIO io{};
     for (size_t k = 0; k < b.plans.size(); ++k) {
-        args.in[k] = in[k];
-        args.out[k] = out[k];
+        io.in[k] = in[k];
+        io.out[k] = out[k];
     }
-    const size_t lds = forward_lds(b.max_ntab);
-    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, s, b.d_counter);
-    hipLaunchKernelGGL(k_batch, dim3(b.grid), dim3(kThreads), lds, s, b.d_views, b.d_tile_map,
-                       b.d_tile_local, b.ntiles, args, b.d_counter);
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.d_counter);
+    if (!b.cmap.empty())
+        hipLaunchKernelGGL(k_circ, dim3(b.grid_circ), dim3(kThreads), circ_lds(), s,
+                           (const DevPlanView *)b.d_views, (const int2 *)b.d_cmap,
+                           (int)b.cmap.size(), io, 1, circ_buf_floats(), b.d_counter);
+    if (!b.gmap.empty())
+        hipLaunchKernelGGL(k_general, dim3(b.grid_gen), dim3(kThreads), gen_lds(b.max_ntab), s,
+                           (const DevPlanView *)b.d_views, (const int2 *)b.d_gmap,
+                           (int)b.gmap.size(), io, 1, gen_tab_floats(b.max_ntab), b.d_counter + 1);
     ARKCOS_HIP_CHECK(hipGetLastError());
     return ARKCOS_OK;
 }
-
-int batch_max_maps() { return kMaxBatchMaps; }
 
 }  // namespace arkcos

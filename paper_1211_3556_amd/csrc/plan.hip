@@ -62,6 +62,15 @@ DevPlanView Plan::view() const
     v.table = d_table;
     v.pairs_d = d_pairs_d;
     v.inv_h_d = (desc.ntab - 1) / desc.theta_cut;
+    v.groups = d_groups;
+    v.rows = d_rows;
+    v.wts = d_wts;
+    v.ctiles = d_ctiles;
+    v.gtiles = d_gtiles;
+    v.nctiles = (int)ctiles.size();
+    v.ngtiles = (int)gtiles.size();
+    v.nrows = (int)rows.size();
+    v.nrings = nrings;
     v.ntiles = (int)tiles.size();
     v.ntab = desc.ntab;
     v.npix = (int)npix;
@@ -87,6 +96,23 @@ static double half_width(const HostRing &r, const HostRing &s, double theta_cut,
     }
     if (R <= 0.0) return 0.0;
     return 2.0 * std::asin(std::sqrt(R));
+}
+
+// Reorder tiles (and their costs) by decreasing cost; ties keep their order.
+static void sort_by_cost(std::vector<DevTile> &tiles, std::vector<double> &cost)
+{
+    std::vector<size_t> order(tiles.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+    std::vector<DevTile> t2(tiles.size());
+    std::vector<double> c2(cost.size());
+    for (size_t k = 0; k < order.size(); ++k) {
+        t2[k] = tiles[order[k]];
+        c2[k] = cost[order[k]];
+    }
+    tiles.swap(t2);
+    cost.swap(c2);
 }
 
 static int build_plan(Plan &P)
@@ -153,7 +179,7 @@ static int build_plan(Plan &P)
         P.candidates += (long long)std::llround(per_pixel * R.n);
     }
 
-    // Tiles of `tile` consecutive pixels of one output ring, longest first.
+    // Per-ring tiles of `tile` pixels, longest first (knot-gradient kernel).
     P.tiles.clear();
     std::vector<double> cost;
     for (int r = 0; r < P.nrings; ++r) {
@@ -167,13 +193,118 @@ static int build_plan(Plan &P)
             cost.push_back(ring_cost[r] * t.len);
         }
     }
-    std::vector<size_t> order(P.tiles.size());
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-    std::vector<DevTile> sorted(P.tiles.size());
-    for (size_t k = 0; k < order.size(); ++k) sorted[k] = P.tiles[order[k]];
-    P.tiles.swap(sorted);
+    sort_by_cost(P.tiles, cost);
+
+    // Ring classes.  A belt ring whose source rings are all belt rings (4N
+    // pixels each, windows narrower than a ring) is circulant: the weight of
+    // (r, j; s, j') depends on j' - j only.  Every other ring (polar caps and
+    // belt rings whose disc reaches a cap) is general.  The classes are kept
+    // mirror-symmetric (ring i and ring 4N - i), since the general kernel
+    // evaluates each weight for a ring and its mirror image together.
+    const int nbelt = 4 * N;
+    std::vector<char> general(P.nrings, 1);
+    for (int r = 0; r < P.nrings; ++r) {
+        if (P.rings[r].n != nbelt || r < N - 1 || r > 3 * N - 1) continue;
+        bool circ = true;
+        for (int k = P.dev_rings[r].pair_begin; k < P.dev_rings[r].pair_end; ++k) {
+            const DevPair &pp = P.pairs[k];
+            if (pp.whole || P.rings[pp.s].n != nbelt) circ = false;
+            // a group row spans the union of up to kGroupRings windows
+            if (!pp.whole && 2.0 * pp.w + 3.0 + kGroupRings > kCircMaxTaps) circ = false;
+        }
+        general[r] = circ ? 0 : 1;
+    }
+    for (int r = 0; r < P.nrings; ++r) {
+        const int rm = P.nrings - 1 - r;
+        const char g = general[r] | general[rm];
+        general[r] = general[rm] = g;
+    }
+
+    // Circulant groups of up to kGroupRings consecutive circulant rings, each
+    // with the union of its rings' source rows and tap ranges.
+    P.groups.clear();
+    P.rows.clear();
+    P.nweights = 0;
+    P.max_taps = 0;
+    for (int r = 0; r < P.nrings;) {
+        if (general[r]) { ++r; continue; }
+        DevGroup G{};
+        G.r0 = r;
+        G.nr = 0;
+        while (r < P.nrings && !general[r] && G.nr < kGroupRings) { ++G.nr; ++r; }
+        G.row_begin = (int)P.rows.size();
+        int s_lo = 1 << 30, s_hi = -1;
+        for (int i = 0; i < G.nr; ++i) {
+            const DevRing &dr = P.dev_rings[G.r0 + i];
+            s_lo = std::min(s_lo, P.pairs[dr.pair_begin].s);
+            s_hi = std::max(s_hi, P.pairs[dr.pair_end - 1].s);
+        }
+        for (int sr = s_lo; sr <= s_hi; ++sr) {
+            int k_lo = 1 << 30, k_hi = -(1 << 30);
+            for (int i = 0; i < G.nr; ++i) {
+                const DevRing &dr = P.dev_rings[G.r0 + i];
+                const int kk = dr.pair_begin + (sr - P.pairs[dr.pair_begin].s);
+                if (kk < dr.pair_begin || kk >= dr.pair_end) continue;
+                int lo, hi;
+                pair_window(P.pairs[kk], nbelt, 0, lo, hi);
+                k_lo = std::min(k_lo, lo);
+                k_hi = std::max(k_hi, hi);
+            }
+            if (k_hi < k_lo) continue;
+            if (k_hi - k_lo + 1 > kCircMaxTaps)
+                return fail(ARKCOS_EUNSUPPORTED, "circulant row wider than the staging limit");
+            DevRow row{};
+            row.s = sr;
+            row.k_lo = k_lo;
+            row.ntaps = k_hi - k_lo + 1;
+            row.w_off = (int)P.nweights;
+            row.g = (int)P.groups.size();
+            P.nweights += (long long)row.ntaps * kGroupRings;
+            P.max_taps = std::max(P.max_taps, row.ntaps);
+            P.rows.push_back(row);
+        }
+        G.row_end = (int)P.rows.size();
+        P.groups.push_back(G);
+    }
+    if (P.nweights > 0x7fffffffLL) return fail(ARKCOS_EUNSUPPORTED, "circulant weight table too large");
+
+    // Circulant tiles: kCircSeg consecutive pixels of every ring of a group.
+    P.ctiles.clear();
+    cost.clear();
+    for (int g = 0; g < (int)P.groups.size(); ++g) {
+        double taps = 0.0;
+        for (int q = P.groups[g].row_begin; q < P.groups[g].row_end; ++q) taps += P.rows[q].ntaps;
+        for (int j0 = 0; j0 < nbelt; j0 += kCircSeg) {
+            DevTile t{};
+            t.r = g;
+            t.j0 = j0;
+            t.len = std::min(kCircSeg, nbelt - j0);
+            P.ctiles.push_back(t);
+            cost.push_back(taps * kGroupRings * t.len);
+        }
+    }
+    sort_by_cost(P.ctiles, cost);
+    P.ctile_cost = cost;
+
+    // General tiles: up to kThreads pixels of the first quadrant of a general
+    // ring of the northern half (equator included); each lane produces the
+    // four quarter-turn images on the ring and on its mirror ring.
+    P.gtiles.clear();
+    cost.clear();
+    for (int r = 0; r <= P.nrings - 1 - r; ++r) {
+        if (!general[r]) continue;
+        const int quarter = P.rings[r].n / 4;
+        for (int j0 = 0; j0 < quarter; j0 += kThreads) {
+            DevTile t{};
+            t.r = r;
+            t.j0 = j0;
+            t.len = std::min(kThreads, quarter - j0);
+            P.gtiles.push_back(t);
+            cost.push_back(ring_cost[r] * t.len + 1.0);
+        }
+    }
+    sort_by_cost(P.gtiles, cost);
+    P.gtile_cost = cost;
     return ARKCOS_OK;
 }
 
@@ -250,6 +381,12 @@ static void free_device(Plan &P)
         (void)hipFree(P.d_pairs);
         (void)hipFree(P.d_pairs_d);
         (void)hipFree(P.d_tiles);
+        (void)hipFree(P.d_groups);
+        (void)hipFree(P.d_rows);
+        (void)hipFree(P.d_wts);
+        (void)hipFree(P.d_ctiles);
+        (void)hipFree(P.d_gtiles);
+        (void)hipFree(P.d_view);
         (void)hipFree(P.d_table);
         (void)hipFree(P.d_counter);
         (void)hipFree(P.d_kpart);
@@ -259,6 +396,12 @@ static void free_device(Plan &P)
     P.d_pairs = nullptr;
     P.d_pairs_d = nullptr;
     P.d_tiles = nullptr;
+    P.d_groups = nullptr;
+    P.d_rows = nullptr;
+    P.d_wts = nullptr;
+    P.d_ctiles = nullptr;
+    P.d_gtiles = nullptr;
+    P.d_view = nullptr;
     P.d_table = nullptr;
     P.d_counter = nullptr;
     P.d_kpart = nullptr;
@@ -284,6 +427,9 @@ static int write_table_host(Plan &P)
     for (int k = 0; k < P.desc.ntab; ++k) t[k] = (float)(P.omega * P.ktab[k]);
     ARKCOS_HIP_CHECK(hipMemcpy(P.d_table, t.data(), t.size() * sizeof(float),
                                hipMemcpyHostToDevice));
+    int rc = launch_build_weights(P, nullptr);
+    if (rc) return rc;
+    ARKCOS_HIP_CHECK(hipStreamSynchronize(nullptr));
     return ARKCOS_OK;
 }
 
@@ -303,6 +449,13 @@ static int to_device(Plan &P)
     if ((rc = upload(&P.d_rings, P.dev_rings, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_pairs, P.pairs, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_tiles, P.tiles, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_groups, P.groups, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_rows, P.rows, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_ctiles, P.ctiles, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_gtiles, P.gtiles, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_wts, std::vector<float>((size_t)std::max<long long>(P.nweights, 1), 0.0f),
+                     &P.device_bytes)))
+        return rc;
     if ((rc = upload(&P.d_table, std::vector<float>(P.desc.ntab, 0.0f), &P.device_bytes)))
         return rc;
     if ((rc = upload(&P.d_counter, std::vector<unsigned int>(4, 0u), &P.device_bytes))) return rc;
@@ -311,6 +464,10 @@ static int to_device(Plan &P)
         std::vector<double> z((size_t)P.grid * P.desc.ntab, 0.0);
         if ((rc = upload(&P.d_kpart, z, &P.device_bytes))) return rc;
         if ((rc = upload(&P.d_pairs_d, P.pairs_d, &P.device_bytes))) return rc;
+    }
+    {
+        std::vector<DevPlanView> v(1, P.view());
+        if ((rc = upload(&P.d_view, v, &P.device_bytes))) return rc;
     }
     if (!P.ktab.empty()) {
         if ((rc = write_table_host(P))) return rc;
@@ -449,6 +606,13 @@ int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info)
     info->flags = P->desc.flags;
     info->threads_per_block = P->threads;
     info->device_bytes = P->device_bytes;
+    int circ = 0;
+    for (const DevGroup &g : P->groups) circ += g.nr;
+    info->circulant_rings = circ;
+    info->general_rings = P->nrings - circ;
+    info->circulant_tiles = (long long)P->ctiles.size();
+    info->general_tiles = (long long)P->gtiles.size();
+    info->weights = P->nweights;
     return ARKCOS_OK;
 }
 
@@ -511,6 +675,7 @@ int arkcos_plan_set_kernel(arkcos_plan_t plan, const float *d_knots, void *strea
     if (!(P->desc.flags & ARKCOS_PLAN_LEARNABLE))
         return fail(ARKCOS_ESTATE, "plan was not created with ARKCOS_PLAN_LEARNABLE");
     int rc = launch_set_table(*P, d_knots, (hipStream_t)stream);
+    if (rc == ARKCOS_OK) rc = launch_build_weights(*P, (hipStream_t)stream);
     if (rc == ARKCOS_OK) {
         P->knots_set = true;
         P->ktab.clear();
