@@ -8,15 +8,18 @@ resident in HBM (white-noise maps, the flat-spectrum inputs of the paper's
 Sec. 3):
 
   fwd      Nside 2048, one map, Gaussian beam FWHM 5 arcmin, 16384-node table,
-           theta_cut swept over 10, 15 and 20 arcmin (three plain launches);
+           theta_cut swept over 10, 15 and 20 arcmin;
   fwdbwd   Nside 2048, theta_cut 15 arcmin, 256 learnable knots: forward, then
-           the fused adjoint (d/dmap and d/dknots);
-  batch    16 maps of Nside 256..2048 and FWHM 5..30 arcmin (cut 3 FWHM) in one
-           persistent launch, replayed from a captured graph.
+           the adjoint (d/dmap: the same gathers on g) and the knot gradient;
+  batch    16 maps of Nside 256..2048 and FWHM 5..30 arcmin (cut 3 FWHM) as one
+           batch, each of its two gathers one persistent launch replayed from
+           a captured graph.
 
-The unit of work is one in-disc pair term (theta_pq < theta_cut), counted
-exactly by the plan; `value` is total pairs / total step time, in
-GPair-evals/s.  Rank 0 prints one JSON line.
+Every gather launch is bracketed by HIP events on the stream it runs on, so
+each kernel's launch time is measured inside the timed region.  The unit of
+work is one in-disc pair term (theta_pq < theta_cut), counted exactly by the
+plan; `value` is total pairs / total step time, in GPair-evals/s.  One JSON
+line is printed.
 """
 from __future__ import annotations
 
@@ -34,11 +37,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GPair-evals/s and maps/s at Nside 2048 (fwd, fwd+bwd, batched) vs plain kernel"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-HBM_PEAK_GBS = 8000.0
-# Algorithmic FP32 work of one pair term of the per-pair gather: longitude
-# difference, sine series, chord, angle series, table index, interpolation
-# and the accumulating FMA.
-FLOP_PER_PAIR = 24.0
+# Algorithmic FP32 work per in-disc pair term of each kernel:
+#   k_circ     one FMA with a precomputed weight;
+#   k_general  one FMA, plus a 24-FLOP weight evaluation (longitude, sine
+#              series, chord, angle series, table index, interpolation) shared
+#              by the 8 quarter-turn and mirror images;
+#   k_knot     8 FMAs of g x per candidate plus ~40 FLOP of FP64 geometry, per
+#              8 images.
+FLOP_PER_PAIR = {"k_circ": 2.0, "k_general": 2.0 + 24.0 / 8.0, "k_knot": (16.0 + 40.0) / 8.0}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -92,21 +98,25 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream()
+    CIRC, GEN = A.PART_CIRCULANT, A.PART_GENERAL
 
     def log(msg):
         print("[bench] " + msg, file=sys.stderr, flush=True)
 
-    # ---------------------------------------------------------------- setup --
     def table(spec):
         return A.tabulate_legendre(A.gaussian_bl(spec.fwhm, spec.ell_max), spec.theta_cut,
                                    spec.ntab)
 
+    def dev_map(nside, seed):
+        return torch.from_numpy(W.white_noise(nside, seed).astype(np.float32)).to(dev)
+
+    # ---------------------------------------------------------------- setup --
     log("building plans")
     fwd_specs = list(W.C3)
     fwd_plans = [A.Plan(s.nside, s.theta_cut, table(s)) for s in fwd_specs]
-    x2048 = torch.from_numpy(W.white_noise(2048, fwd_specs[0].seed).astype(np.float32)).to(dev)
+    x2048 = dev_map(2048, fwd_specs[0].seed)
     fwd_out = [torch.empty_like(x2048) for _ in fwd_plans]
-    fwd_pairs = [p.pair_count() for p in fwd_plans]
+    fwd_parts = [p.pair_count_parts() for p in fwd_plans]
 
     gspec = W.MapSpec(nside=2048, fwhm=5.0 * W.ARCMIN, theta_cut=15.0 * W.ARCMIN, ntab=256,
                       seed=3)
@@ -114,57 +124,60 @@ def main() -> int:
     knots = torch.from_numpy(W.gaussian_profile_knots(gspec.fwhm, gspec.theta_cut,
                                                       gspec.ntab).astype(np.float32)).to(dev)
     gplan.set_knots(knots)
-    gin = torch.from_numpy(W.white_noise(2048, 13).astype(np.float32)).to(dev)
+    gin = dev_map(2048, 13)
     g_out = torch.empty_like(x2048)
-    g_pairs = gplan.pair_count()
+    g_gx = torch.empty_like(x2048)
+    g_parts = gplan.pair_count_parts()
+    g_pairs = sum(g_parts)
 
     bspecs = W.batch_specs()
     bplans = [A.Plan(s.nside, s.theta_cut, table(s)) for s in bspecs]
-    bx = [torch.from_numpy(W.white_noise(s.nside, s.seed).astype(np.float32)).to(dev)
-          for s in bspecs]
+    bx = [dev_map(s.nside, s.seed) for s in bspecs]
     by = [torch.empty_like(x) for x in bx]
     batch = A.Batch(bplans)
-    b_pairs = sum(p.pair_count() for p in bplans)
+    b_parts = [p.pair_count_parts() for p in bplans]
+    b_circ, b_gen = sum(c for c, _ in b_parts), sum(g for _, g in b_parts)
     torch.cuda.synchronize()
 
-    # capture the batched launch in a graph (replayed each step)
+    # each gather of the batch as one captured graph, replayed every step
     side = torch.cuda.Stream()
     side.wait_stream(stream)
     with torch.cuda.stream(side):
         batch.convolve(bx, by)
     stream.wait_stream(side)
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        batch.convolve(bx, by)
+    graphs = {}
+    for part in (CIRC, GEN):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            batch.convolve(bx, by, part=part)
+        graphs[part] = g
     torch.cuda.synchronize()
 
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
-    times = {"fwd": [], "fwdbwd_fwd": [], "fwdbwd_bwd": [], "batch": []}
-    fwd_launch_ms = []
+    launches = []   # (part of the step, kernel, algorithmic FLOP, start event, end event)
 
-    def step(record: bool):
-        for p, o, np_ in zip(fwd_plans, fwd_out, fwd_pairs):
-            e0, e1 = ev(), ev()
-            e0.record(stream)
-            p.convolve(x2048, o)
-            e1.record(stream)
-            if record:
-                times["fwd"].append((e0, e1))
-        e0, e1, e2 = ev(), ev(), ev()
-        e0.record(stream)
-        gplan.convolve(x2048, g_out)
-        e1.record(stream)
-        gplan.backward(gin, x2048, want_map=True, want_knots=True)
-        e2.record(stream)
-        if record:
-            times["fwdbwd_fwd"].append((e0, e1))
-            times["fwdbwd_bwd"].append((e1, e2))
+    def timed(record, part, kernel, pairs, fn):
         e0, e1 = ev(), ev()
         e0.record(stream)
-        graph.replay()
+        fn()
         e1.record(stream)
         if record:
-            times["batch"].append((e0, e1))
+            launches.append((part, kernel, FLOP_PER_PAIR[kernel] * pairs, e0, e1))
+
+    def step(record: bool):
+        for i, (p, o, (pc, pg)) in enumerate(zip(fwd_plans, fwd_out, fwd_parts)):
+            timed(record, "fwd%d" % i, "k_circ", pc, lambda: p.convolve_part(x2048, o, CIRC))
+            timed(record, "fwd%d" % i, "k_general", pg, lambda: p.convolve_part(x2048, o, GEN))
+        pc, pg = g_parts
+        timed(record, "fwdbwd", "k_circ", pc, lambda: gplan.convolve_part(x2048, g_out, CIRC))
+        timed(record, "fwdbwd", "k_general", pg, lambda: gplan.convolve_part(x2048, g_out, GEN))
+        # adjoint: the operator is symmetric, so d/dmap is the same two gathers on g
+        timed(record, "fwdbwd", "k_circ", pc, lambda: gplan.convolve_part(gin, g_gx, CIRC))
+        timed(record, "fwdbwd", "k_general", pg, lambda: gplan.convolve_part(gin, g_gx, GEN))
+        timed(record, "fwdbwd", "k_knot", g_pairs,
+              lambda: gplan.backward(gin, x2048, want_map=False, want_knots=True))
+        timed(record, "batch", "k_circ", b_circ, graphs[CIRC].replay)
+        timed(record, "batch", "k_general", b_gen, graphs[GEN].replay)
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
@@ -177,15 +190,31 @@ def main() -> int:
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
 
-    def mean_ms(key):
-        return float(np.mean([a.elapsed_time(b) for a, b in times[key]]))
+    ms = [(part, k, fl, a.elapsed_time(b)) for part, k, fl, a, b in launches]
 
-    fwd_ms = [float(np.mean([a.elapsed_time(b) for a, b in times["fwd"][i::3]]))
-              for i in range(3)]
-    fb_f, fb_b, b_ms = mean_ms("fwdbwd_fwd"), mean_ms("fwdbwd_bwd"), mean_ms("batch")
-    step_pairs = sum(fwd_pairs) + 2 * g_pairs + b_pairs
+    def part_ms(name):
+        return sum(m for part, _, _, m in ms if part == name) / args.steps
+
+    fwd_ms = [part_ms("fwd%d" % i) for i in range(3)]
+    fb_ms, b_ms = part_ms("fwdbwd"), part_ms("batch")
+    fwd_pairs = [c + g for c, g in fwd_parts]
+    step_pairs = sum(fwd_pairs) + 2 * g_pairs + b_circ + b_gen
     ms_per_step = 1e3 * wall / args.steps
     value = step_pairs / (wall / args.steps) / 1e9
+
+    # per-kernel totals; the dominant kernel is the one with the most time
+    kern = {}
+    for _, k, fl, m in ms:
+        t = kern.setdefault(k, [0.0, 0.0, 0])
+        t[0] += fl
+        t[1] += m
+        t[2] += 1
+    dom = max(kern, key=lambda k: kern[k][1])
+    flops, total_ms, nl = kern[dom]
+    achieved = flops / (total_ms * 1e-3) / 1e12
+    kernels = {k: {"launches_per_step": v[2] // args.steps,
+                   "avg_launch_ms": round(v[1] / v[2], 4),
+                   "tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 2)} for k, v in kern.items()}
 
     plain16_ms = None
     if not args.no_plain_compare:
@@ -197,18 +226,6 @@ def main() -> int:
         e1.record(stream)
         torch.cuda.synchronize()
         plain16_ms = e0.elapsed_time(e1)
-
-    # dominant kernel of the step: the batched gather
-    parts_ms = {"fwd": sum(fwd_ms), "fwdbwd": fb_f + fb_b, "batch": b_ms}
-    dom = max(parts_ms, key=parts_ms.get)
-    if dom == "batch":
-        kname, dom_pairs, dom_ms = "k_batch", b_pairs, b_ms
-    elif dom == "fwd":
-        kname, dom_pairs, dom_ms = "k_forward<1>", sum(fwd_pairs) / 3, sum(fwd_ms) / 3
-    else:
-        kname, dom_pairs, dom_ms = "k_backward<1,1,1>", g_pairs, fb_b
-    achieved = FLOP_PER_PAIR * dom_pairs / (dom_ms * 1e-3) / 1e12
-    traffic = _traffic(kname)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -222,12 +239,11 @@ def main() -> int:
         t = time.perf_counter()
         _, pairs = O.convolve(s.nside, s.theta_cut, k64, x64, pixels=pix, return_pairs=True)
         dt = time.perf_counter() - t
-        cpu = {"value": float(pairs.sum()) / dt / 1e9, "unit": "GPair-evals/s",
+        cpu = {"value": round(float(pairs.sum()) / dt / 1e9, 4), "unit": "GPair-evals/s",
                "cores": O.threads(), "kind": "oracle",
                "sample": "Nside 2048, FWHM 5', theta_cut 20', %d random output pixels "
                          "(%d pairs, %.1f s); FP64 C/OpenMP" % (pix.size, int(pairs.sum()), dt)}
 
-    maps_per_step = len(fwd_plans) + 1 + len(bplans)
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -244,35 +260,35 @@ def main() -> int:
         "config": {
             "workload": "step = Nside-2048 fwd at theta_cut 10/15/20' + Nside-2048 fwd+bwd "
                         "(15', 256 knots) + 16-map batch (Nside 256-2048, FWHM 5-30', 3 FWHM "
-                        "cut) in one graph-replayed launch; white-noise FP32 maps",
+                        "cut) replayed from captured graphs; white-noise FP32 maps",
             "pairs_per_step": int(step_pairs),
-            "maps_per_step": maps_per_step,
+            "maps_per_step": len(fwd_plans) + 1 + len(bplans),
         },
         "breakdown": {
             "fwd": {"theta_cut_arcmin": [10, 15, 20], "ms": [round(m, 4) for m in fwd_ms],
                     "pairs": fwd_pairs,
                     "gpair_per_s": [round(p / (m * 1e-3) / 1e9, 2) for p, m in zip(fwd_pairs, fwd_ms)],
                     "maps_per_s": [round(1e3 / m, 1) for m in fwd_ms]},
-            "fwdbwd": {"ms_fwd": round(fb_f, 4), "ms_bwd": round(fb_b, 4),
-                       "pairs": 2 * g_pairs,
-                       "gpair_per_s": round(2 * g_pairs / ((fb_f + fb_b) * 1e-3) / 1e9, 2),
-                       "maps_per_s": round(1e3 / (fb_f + fb_b), 1)},
-            "batch": {"ms": round(b_ms, 4), "pairs": int(b_pairs),
-                      "gpair_per_s": round(b_pairs / (b_ms * 1e-3) / 1e9, 2),
+            "fwdbwd": {"ms": round(fb_ms, 4), "pairs": 2 * g_pairs,
+                       "gpair_per_s": round(2 * g_pairs / (fb_ms * 1e-3) / 1e9, 2),
+                       "maps_per_s": round(1e3 / fb_ms, 1)},
+            "batch": {"ms": round(b_ms, 4), "pairs": int(b_circ + b_gen),
+                      "gpair_per_s": round((b_circ + b_gen) / (b_ms * 1e-3) / 1e9, 2),
                       "maps_per_s": round(16e3 / b_ms, 1),
                       "plain16_ms": None if plain16_ms is None else round(plain16_ms, 4),
                       "speedup_vs_plain16": None if plain16_ms is None else round(plain16_ms / b_ms, 3)},
+            "kernels": kernels,
         },
         "roofline": {
-            "kernel": kname,
+            "kernel": dom,
             "bound": "alu",
             "achieved": round(achieved, 3),
             "peak": FP32_VECTOR_PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
-            "traffic": traffic,
-            "flop_per_pair": FLOP_PER_PAIR,
-            "avg_launch_ms": round(dom_ms, 4),
+            "traffic": _traffic(dom),
+            "flop_per_pair": FLOP_PER_PAIR[dom],
+            "avg_launch_ms": round(total_ms / nl, 4),
         },
         "cpu_baseline": cpu,
     }

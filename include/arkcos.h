@@ -90,6 +90,11 @@ typedef struct {
     long long weights;             /* FP32 entries of the circulant weight rows         */
 } arkcos_plan_info;
 
+/* The two gathers of a forward convolution (they write disjoint rings). */
+#define ARKCOS_PART_CIRCULANT 1   /* belt rings whose discs stay in the belt */
+#define ARKCOS_PART_GENERAL 2     /* polar caps and belt rings near them     */
+#define ARKCOS_PART_ALL 3
+
 /* ----------------------------------------------------------------- host -- */
 
 /*
@@ -145,6 +150,14 @@ int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info);
 int arkcos_plan_pair_count(arkcos_plan_t plan, unsigned long long *pairs);
 
 /*
+ * The same exact count split by the gather that evaluates the pairs: output
+ * rings of ARKCOS_PART_CIRCULANT or ARKCOS_PART_GENERAL (either pointer may be
+ * NULL).  Host only.
+ */
+int arkcos_plan_pair_count_parts(arkcos_plan_t plan, unsigned long long *circulant,
+                                 unsigned long long *general);
+
+/*
  * Longitude window the device kernels scan for output pixel j of ring
  * `ring_out` on source ring `ring_src` (rings 1-based): unwrapped source
  * indices lo..hi (hi - lo + 1 <= pixels of the source ring; indices are taken
@@ -182,6 +195,16 @@ int arkcos_plan_set_kernel(arkcos_plan_t plan, const float *d_knots, void *strea
  */
 int arkcos_convolve(arkcos_plan_t plan, const float *d_in, float *d_out, int nbatch,
                     void *stream);
+
+/*
+ * One or both gathers of arkcos_convolve (part = ARKCOS_PART_*): the rings of
+ * the other gather are left untouched in d_out.  Running both parts, in either
+ * order, equals arkcos_convolve bit for bit.  For timing and testing the two
+ * kernels separately; arguments and errors as arkcos_convolve, plus EINVAL for
+ * an unknown part.
+ */
+int arkcos_convolve_part(arkcos_plan_t plan, const float *d_in, float *d_out, int nbatch, int part,
+                         void *stream);
 
 /*
  * Adjoint of arkcos_convolve for a loss L with d_grad_out = dL/d(out):
@@ -223,6 +246,14 @@ int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *o
  */
 int arkcos_batch_convolve(arkcos_batch_t batch, const float *const *d_in, float *const *d_out,
                           void *stream);
+
+/*
+ * One or both gathers of arkcos_batch_convolve (part = ARKCOS_PART_*), one
+ * persistent launch each; the rings of the other gather are left untouched.
+ * Both parts, in either order, equal arkcos_batch_convolve bit for bit.
+ */
+int arkcos_batch_convolve_part(arkcos_batch_t batch, const float *const *d_in,
+                               float *const *d_out, int part, void *stream);
 
 /* Release a batch (not its plans).  NULL is accepted. */
 int arkcos_batch_destroy(arkcos_batch_t batch);

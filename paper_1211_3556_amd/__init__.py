@@ -23,13 +23,17 @@ import numpy as np
 
 __all__ = ["ArkcosError", "Plan", "Batch", "ArkcosConvFn", "conv", "tabulate_legendre",
            "ring_info", "gaussian_bl", "library_path", "load_library", "PLAN_HOST_ONLY",
-           "PLAN_LEARNABLE", "MAX_GRAD_NTAB", "MAX_NSIDE"]
+           "PLAN_LEARNABLE", "PART_CIRCULANT", "PART_GENERAL", "PART_ALL", "MAX_GRAD_NTAB",
+           "MAX_NSIDE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libarkcos.so")
 
 PLAN_HOST_ONLY = 1
 PLAN_LEARNABLE = 2
+PART_CIRCULANT = 1
+PART_GENERAL = 2
+PART_ALL = 3
 MAX_NSIDE = 8192
 MAX_GRAD_NTAB = 8192
 
@@ -93,9 +97,14 @@ def load_library():
         "arkcos_plan_set_kernel_host": [_vp, _dp],
         "arkcos_plan_set_kernel": [_vp, _vp, _vp],
         "arkcos_convolve": [_vp, _vp, _vp, ctypes.c_int, _vp],
+        "arkcos_convolve_part": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
+        "arkcos_plan_pair_count_parts": [_vp, ctypes.POINTER(ctypes.c_ulonglong),
+                                         ctypes.POINTER(ctypes.c_ulonglong)],
         "arkcos_convolve_backward": [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp],
         "arkcos_batch_create": [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)],
         "arkcos_batch_convolve": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
+        "arkcos_batch_convolve_part": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int,
+                                       _vp],
         "arkcos_batch_destroy": [_vp],
         "arkcos_status_string": [ctypes.c_int],
         "arkcos_last_error": [],
@@ -220,6 +229,12 @@ class Plan:
         _call("arkcos_plan_pair_count", self._h, ctypes.byref(c))
         return int(c.value)
 
+    def pair_count_parts(self):
+        """(pairs of circulant output rings, pairs of general output rings)."""
+        c, g = ctypes.c_ulonglong(), ctypes.c_ulonglong()
+        _call("arkcos_plan_pair_count_parts", self._h, ctypes.byref(c), ctypes.byref(g))
+        return int(c.value), int(g.value)
+
     def window(self, ring_out: int, ring_src: int, j: int):
         lo, hi, cov = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
         _call("arkcos_plan_window", self._h, ring_out, ring_src, j, ctypes.byref(lo),
@@ -261,6 +276,18 @@ class Plan:
                 raise ValueError("out must have the shape of x")
         _call("arkcos_convolve", self._h, _vp(x.data_ptr()), _vp(out.data_ptr()), nb,
               _stream_ptr(stream))
+        return out
+
+    def convolve_part(self, x, out, part: int, stream=None):
+        """Run one gather (PART_CIRCULANT or PART_GENERAL) into `out`; the other
+        gather's rings are left as they are."""
+        x = _dev_f32(x, "x")
+        nb = self._shape(x)
+        _dev_f32(out, "out")
+        if out.shape != x.shape:
+            raise ValueError("out must have the shape of x")
+        _call("arkcos_convolve_part", self._h, _vp(x.data_ptr()), _vp(out.data_ptr()), nb,
+              int(part), _stream_ptr(stream))
         return out
 
     def backward(self, grad_out, x=None, want_map: bool = True, want_knots: bool = False,
@@ -354,7 +381,8 @@ class Batch:
         except Exception:
             pass
 
-    def convolve(self, xs, outs=None, stream=None):
+    def convolve(self, xs, outs=None, stream=None, part: int = PART_ALL):
+        """Convolve map k with plan k; `part` selects one of the two gathers."""
         import torch
         if len(xs) != len(self.plans):
             raise ValueError("need one map per plan")
@@ -368,5 +396,5 @@ class Batch:
         n = len(self.plans)
         ins = (_vp * n)(*[x.data_ptr() for x in xs])
         ous = (_vp * n)(*[o.data_ptr() for o in outs])
-        _call("arkcos_batch_convolve", self._h, ins, ous, _stream_ptr(stream))
+        _call("arkcos_batch_convolve_part", self._h, ins, ous, int(part), _stream_ptr(stream))
         return outs

@@ -43,7 +43,8 @@ struct DevRing {
 // with dphi/2 = m * xscale and m = (2j + 2o_r) n_s - (2j' + 2o_s) n_r an exact
 // integer.  The longitude window of output pixel j is centred at source index
 // c = j * a + b (a = n_s/n_r, b = o_r n_s/n_r - o_s) with half-width w source
-// pixels (margin included); whole != 0 means every pixel of ring s.
+// pixels (margin included).  mode bit 0: the window is every pixel of ring s;
+// bit 1: |dphi/2| may exceed 0.35 rad, so the sine needs its long series.
 struct DevPair {
     float A;
     float B;
@@ -52,8 +53,10 @@ struct DevPair {
     float b;
     float w;
     int s;       // 0-based source ring
-    int whole;
+    int mode;
 };
+constexpr int kPairWhole = 1;
+constexpr int kPairLongSin = 2;
 static_assert(sizeof(DevPair) == 32, "DevPair layout");
 
 // FP64 copy of the chord constants of a ring pair, used where the node index
@@ -120,14 +123,16 @@ struct DevPlanView {
     float *wts;              // their weight rows (written by the weight-build kernel)
     const DevTile *ctiles;   // circulant tiles: (group, j0, len)
     const DevTile *gtiles;   // general tiles: (north ring, j0, len) inside quadrant 0
+    const DevTile *ktiles;   // knot-gradient tiles: every northern ring, quadrant 0
     int nctiles;
     int ngtiles;
+    int nktiles;
     int nrows;
     int nrings;
     int ntiles;
     int ntab;
     int npix;
-    int large_angle;         // 1: theta_cut > 0.5 rad, full-range asin
+    int angle_mode;          // angle series: 0 (theta_cut <= 0.1), 1 (<= 0.5), 2 full range
     float inv_h;             // (ntab - 1) / theta_cut
     float u_max;             // ntab - 1 (strict upper bound of u = theta / h)
 };
@@ -141,7 +146,7 @@ __host__ __device__ inline void pair_window(const DevPair &p, int n_s, int j, in
                                             int &hi)
 {
     float c = fmaf((float)j, p.a, p.b);
-    if (p.whole) {
+    if (p.mode & kPairWhole) {
         // n_s consecutive pixels centred on c: |dphi| <= pi + pi/n_s
         lo = (int)floorf(c + 0.5f) - (n_s >> 1);
         hi = lo + n_s - 1;
@@ -169,7 +174,7 @@ struct Plan {
     int threads = 0;
     bool host_only = false;
     bool knots_set = false;
-    bool large_angle = false;
+    int angle_mode = 0;
 
     std::vector<HostRing> rings;      // 0-based
     std::vector<DevRing> dev_rings;
@@ -180,6 +185,7 @@ struct Plan {
     std::vector<DevRow> rows;
     std::vector<DevTile> ctiles;      // circulant tiles, longest first
     std::vector<DevTile> gtiles;      // general tiles, longest first
+    std::vector<DevTile> ktiles;      // knot-gradient tiles, longest first
     std::vector<double> ctile_cost, gtile_cost;
     long long nweights = 0;
     int max_taps = 0;
@@ -187,6 +193,8 @@ struct Plan {
     long long candidates = 0;
     bool pairs_counted = false;
     unsigned long long pair_count = 0;
+    unsigned long long pair_count_circ = 0;   // pairs of circulant output rings
+    std::vector<char> general_ring;           // ring class (1: general)
 
     // device memory
     int device = -1;
@@ -199,6 +207,7 @@ struct Plan {
     float *d_wts = nullptr;
     DevTile *d_ctiles = nullptr;
     DevTile *d_gtiles = nullptr;
+    DevTile *d_ktiles = nullptr;
     DevPlanView *d_view = nullptr;      // device copy of view() (a batch of one plan)
     float *d_table = nullptr;
     unsigned int *d_counter = nullptr;  // persistent-queue counter (+ 1 spare)
@@ -207,6 +216,7 @@ struct Plan {
     int cus = 0;                        // compute units of the device
     int occ_circ = 0;                   // resident workgroups per CU of the two gathers
     int occ_gen = 0;
+    int occ_knot = 0;                   // and of the knot-gradient kernel
     int occ_fwd[4] = {0, 0, 0, 0};      // unused slots kept zero
     int occ_bwd_gxgk[4] = {0, 0, 0, 0};
     int occ_bwd_gk[4] = {0, 0, 0, 0};
@@ -234,10 +244,12 @@ struct Batch {
 // ----------------------------------------------------------------- launch --
 // Implemented in kernels.hip.
 int launch_set_table(const Plan &p, const float *d_knots, hipStream_t s);
-int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s);
+int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s,
+                   int parts = ARKCOS_PART_ALL);
 int launch_backward(const Plan &p, const float *g, const float *x, float *gx, float *gk,
                     int nbatch, hipStream_t s);
-int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s);
+int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s,
+                 int parts = ARKCOS_PART_ALL);
 int launch_build_weights(const Plan &p, hipStream_t s);
 int device_lds_limit(int device, size_t *bytes);
 int prepare_launches(Plan &p);   // occupancy of every kernel variant, grid sizes

@@ -45,18 +45,25 @@ struct DeviceGuard {
 
 extern "C" {
 
-int arkcos_convolve(arkcos_plan_t plan, const float *d_in, float *d_out, int nbatch,
-                    void *stream)
+int arkcos_convolve_part(arkcos_plan_t plan, const float *d_in, float *d_out, int nbatch, int part,
+                         void *stream)
 {
     clear_error();
     if (!plan || !d_in || !d_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    if (part < 1 || part > ARKCOS_PART_ALL) return fail(ARKCOS_EINVAL, "unknown part");
     const Plan *P = reinterpret_cast<const Plan *>(plan);
     int rc = check_compute(P, nbatch);
     if (rc) return rc;
     const size_t bytes = (size_t)nbatch * (size_t)P->npix * sizeof(float);
     if (overlaps(d_in, bytes, d_out, bytes)) return fail(ARKCOS_EINVAL, "d_in and d_out overlap");
     DeviceGuard g(P->device);
-    return launch_forward(*P, d_in, d_out, nbatch, (hipStream_t)stream);
+    return launch_forward(*P, d_in, d_out, nbatch, (hipStream_t)stream, part);
+}
+
+int arkcos_convolve(arkcos_plan_t plan, const float *d_in, float *d_out, int nbatch,
+                    void *stream)
+{
+    return arkcos_convolve_part(plan, d_in, d_out, nbatch, ARKCOS_PART_ALL, stream);
 }
 
 int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const float *d_in,
@@ -169,8 +176,15 @@ int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *o
 int arkcos_batch_convolve(arkcos_batch_t batch, const float *const *d_in, float *const *d_out,
                           void *stream)
 {
+    return arkcos_batch_convolve_part(batch, d_in, d_out, ARKCOS_PART_ALL, stream);
+}
+
+int arkcos_batch_convolve_part(arkcos_batch_t batch, const float *const *d_in,
+                               float *const *d_out, int part, void *stream)
+{
     clear_error();
     if (!batch || !d_in || !d_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    if (part < 1 || part > ARKCOS_PART_ALL) return fail(ARKCOS_EINVAL, "unknown part");
     const Batch *B = reinterpret_cast<const Batch *>(batch);
     const int n = (int)B->plans.size();
     for (int k = 0; k < n; ++k) {
@@ -188,7 +202,7 @@ int arkcos_batch_convolve(arkcos_batch_t batch, const float *const *d_in, float 
         }
     }
     DeviceGuard g(B->device);
-    return launch_batch(*B, d_in, d_out, (hipStream_t)stream);
+    return launch_batch(*B, d_in, d_out, (hipStream_t)stream, part);
 }
 
 int arkcos_batch_destroy(arkcos_batch_t batch)

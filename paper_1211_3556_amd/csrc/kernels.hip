@@ -53,34 +53,25 @@ __device__ __forceinline__ cptr<T> cst(const T *p)
 }
 
 // ------------------------------------------------------------ FP32 math --
-// sin(x) for |x| <= 2 by its Taylor series through x^13 (truncation below
-// 2e-8 relative on that range).
+// sin(x) by its Taylor series: LONG through x^13 for |x| <= 2 (truncation
+// below 2e-8 relative), otherwise through x^7 for |x| <= 0.35 (below 1e-9).
+template <bool LONG>
 __device__ __forceinline__ float sin_series(float x)
 {
     const float x2 = x * x;
-    float p = 1.0f / 6227020800.0f;           // 1/13!
-    p = fmaf(p, x2, -1.0f / 39916800.0f);     // 1/11!
-    p = fmaf(p, x2, 1.0f / 362880.0f);        // 1/9!
-    p = fmaf(p, x2, -1.0f / 5040.0f);         // 1/7!
+    float p;
+    if (LONG) {
+        p = 1.0f / 6227020800.0f;             // 1/13!
+        p = fmaf(p, x2, -1.0f / 39916800.0f); // 1/11!
+        p = fmaf(p, x2, 1.0f / 362880.0f);    // 1/9!
+        p = fmaf(p, x2, -1.0f / 5040.0f);     // 1/7!
+    } else {
+        p = -1.0f / 5040.0f;
+    }
     p = fmaf(p, x2, 1.0f / 120.0f);           // 1/5!
     p = fmaf(p, x2, -1.0f / 6.0f);            // 1/3!
     p = fmaf(p, x2, 1.0f);
     return x * p;
-}
-
-// theta = 2 asin(d/2) from the squared chord d^2 <= 0.245 (theta <= 0.5 rad):
-// theta = d (1 + d^2/24 + 3 d^4/640 + 5 d^6/7168 + 35 d^8/294912
-//            + 63 d^10/2883584), truncation below 1e-9 relative.
-__device__ __forceinline__ float theta_small(float d2)
-{
-    const float d = sqrtf(d2);
-    float p = 63.0f / 2883584.0f;
-    p = fmaf(p, d2, 35.0f / 294912.0f);
-    p = fmaf(p, d2, 5.0f / 7168.0f);
-    p = fmaf(p, d2, 3.0f / 640.0f);
-    p = fmaf(p, d2, 1.0f / 24.0f);
-    p = fmaf(p, d2, 1.0f);
-    return d * p;
 }
 
 // asin(y) for 0 <= y <= 0.5 by its Maclaurin series
@@ -101,49 +92,72 @@ __device__ __forceinline__ float asin_series(float y)
     return y * p;
 }
 
-// theta = 2 asin(d/2) for any chord 0 <= d <= 2; above y = 1/2 the half-angle
-// identity asin(y) = pi/2 - 2 asin(sqrt((1 - y)/2)) keeps the series argument
-// below 1/2.
-__device__ __forceinline__ float theta_large(float d2)
+// theta = 2 asin(d/2) from the squared chord d^2.
+//  AM 0 (theta_cut <= 0.1 rad): d (1 + d^2/24 + 3 d^4/640), truncation below
+//       1e-9 relative for d <= 0.1;
+//  AM 1 (theta_cut <= 0.5 rad): d (1 + d^2/24 + 3 d^4/640 + 5 d^6/7168
+//       + 35 d^8/294912 + 63 d^10/2883584), below 1e-9 for d^2 <= 0.245;
+//  AM 2 (any cut): asin series, with asin(y) = pi/2 - 2 asin(sqrt((1 - y)/2))
+//       above y = 1/2 to keep the series argument below 1/2.
+// The series have positive coefficients, so the computed angle grows with d
+// and a candidate beyond the cut never lands inside it.  The square roots are
+// the hardware instruction (1 ulp).
+template <int AM>
+__device__ __forceinline__ float theta_of(float d2)
 {
-    const float y = fminf(0.5f * sqrtf(d2), 1.0f);
-    if (y <= 0.5f) return 2.0f * asin_series(y);
-    const float w = sqrtf(0.5f * (1.0f - y));
-    return 2.0f * (1.5707963267948966f - 2.0f * asin_series(w));
+    if (AM == 2) {
+        const float y = fminf(0.5f * __builtin_amdgcn_sqrtf(d2), 1.0f);
+        if (y <= 0.5f) return 2.0f * asin_series(y);
+        const float w = __builtin_amdgcn_sqrtf(0.5f * (1.0f - y));
+        return 2.0f * (1.5707963267948966f - 2.0f * asin_series(w));
+    }
+    const float d = __builtin_amdgcn_sqrtf(d2);
+    float p;
+    if (AM == 1) {
+        p = 63.0f / 2883584.0f;
+        p = fmaf(p, d2, 35.0f / 294912.0f);
+        p = fmaf(p, d2, 5.0f / 7168.0f);
+        p = fmaf(p, d2, 3.0f / 640.0f);
+    } else {
+        p = 3.0f / 640.0f;
+    }
+    p = fmaf(p, d2, 1.0f / 24.0f);
+    p = fmaf(p, d2, 1.0f);
+    return d * p;
 }
 
 // Interpolated, Omega-scaled weight of one pair (0 at or beyond theta_cut).
-__device__ __forceinline__ float pair_weight(const DevPlanView &P, const DevPair &pp,
-                                             const float *tab, int m)
+// Branch-free: the node index is clamped into the table and the weight masked.
+template <bool LONG, int AM>
+__device__ __forceinline__ float pair_weight_t(const DevPair &pp, const float *tab, float inv_h,
+                                               float u_max, int m)
 {
     const float x = (float)m * pp.xscale;          // half the longitude difference
-    const float sx = sin_series(x);
+    const float sx = sin_series<LONG>(x);
     const float d2 = fmaf(pp.B, sx * sx, pp.A);      // squared chord
-    const float th = P.large_angle ? theta_large(d2) : theta_small(d2);
-    const float u = th * P.inv_h;
-    const bool inside = u < P.u_max;
-    const float uc = inside ? u : 0.0f;
-    const int node = (int)uc;
+    const float u = theta_of<AM>(d2) * inv_h;
+    const float uc = fminf(u, u_max);
+    const int node = min((int)uc, (int)u_max - 1);
     const float frac = uc - (float)node;
     const float k0 = tab[node];
     const float k1 = tab[node + 1];
-    return inside ? fmaf(frac, k1 - k0, k0) : 0.0f;
+    const float w = fmaf(frac, k1 - k0, k0);
+    return (u < u_max) ? w : 0.0f;
 }
 
-// Node index and fraction of one pair from FP64 geometry (same chord, angle
-// and table coordinate as pair_weight, through the device math library).
-// Returns false at or beyond the cut.
-__device__ __forceinline__ bool pair_node_fp64(const DevPlanView &P, const DevPairD &pd, int m,
-                                               int &node, double &frac)
+// The same weight with the series chosen at run time from the pair and plan.
+__device__ __forceinline__ float pair_weight(const DevPlanView &P, const DevPair &pp,
+                                             const float *tab, int m)
 {
-    const double sx = sin((double)m * pd.xscale);
-    const double d2 = fma(pd.B, sx * sx, pd.A);
-    const double th = 2.0 * asin(fmin(1.0, 0.5 * sqrt(d2)));
-    const double u = th * P.inv_h_d;
-    if (!(u < (double)(P.ntab - 1))) return false;
-    node = (int)u;
-    frac = u - (double)node;
-    return true;
+    const bool lg = (pp.mode & kPairLongSin) != 0;
+    switch (P.angle_mode) {
+        case 0: return lg ? pair_weight_t<true, 0>(pp, tab, P.inv_h, P.u_max, m)
+                          : pair_weight_t<false, 0>(pp, tab, P.inv_h, P.u_max, m);
+        case 1: return lg ? pair_weight_t<true, 1>(pp, tab, P.inv_h, P.u_max, m)
+                          : pair_weight_t<false, 1>(pp, tab, P.inv_h, P.u_max, m);
+        default: return lg ? pair_weight_t<true, 2>(pp, tab, P.inv_h, P.u_max, m)
+                           : pair_weight_t<false, 2>(pp, tab, P.inv_h, P.u_max, m);
+    }
 }
 
 __device__ __forceinline__ int wrap_index(int jq, int n)
@@ -322,9 +336,76 @@ __global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict
 }
 
 // --------------------------------------------------------- general gather --
+// Source pixels each lane prefetches per staged chunk.
+constexpr int kGenRegs = (kGenChunk + kThreads - 1) / kThreads;
+
+// One staged chunk of one source row of a general tile: row k of the output
+// ring's pair list, unwrapped source pixels c0 .. c0+cn-1.
+struct GenChunk {
+    int k;
+    int c0;
+    int cn;
+};
+
+// Window bounds of a tile's first and last pixel on the row of pair pp.
+__device__ __forceinline__ void tile_window(const DevPair &pp, int n_s, const DevTile &T,
+                                            int &lo_min, int &hi_max)
+{
+    int dummy;
+    pair_window(pp, n_s, T.j0, lo_min, dummy);
+    pair_window(pp, n_s, T.j0 + T.len - 1, dummy, hi_max);
+}
+
+// Issue the loads of the 8 images of a chunk: the four quarter turns of ring s
+// and of its mirror ring.
+__device__ __forceinline__ void prefetch_chunk(const float *src, const float *srcm, bool mirror,
+                                               int n_s, int c0, int cn, float4 a[kGenRegs],
+                                               float4 b[kGenRegs])
+{
+    const int qs = n_s >> 2;
+#pragma unroll
+    for (int u = 0; u < kGenRegs; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        a[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        b[u] = a[u];
+        if (e < cn) {
+            const int i0 = wrap3(c0 + e, n_s);
+            const int i1 = wrap3(c0 + e + qs, n_s);
+            const int i2 = wrap3(c0 + e + 2 * qs, n_s);
+            const int i3 = wrap3(c0 + e + 3 * qs, n_s);
+            a[u] = make_float4(src[i0], src[i1], src[i2], src[i3]);
+            if (mirror) b[u] = make_float4(srcm[i0], srcm[i1], srcm[i2], srcm[i3]);
+        }
+    }
+}
+
+// Accumulate the candidates a0..a1 of one lane from the staged chunk.
+template <bool LONG, int AM>
+__device__ __forceinline__ void gen_candidates(const DevPair &pp, const float *tab, float inv_h,
+                                               float u_max, unsigned mbase, int two_o_s, int n_r,
+                                               const float4 *stage, int c0, int a0, int a1,
+                                               float row[8])
+{
+    for (int jq = a0; jq <= a1; ++jq) {
+        const float w = pair_weight_t<LONG, AM>(pp, tab, inv_h, u_max,
+                                                lon_numerator(mbase, jq, two_o_s, n_r));
+        const float4 v0 = stage[2 * (jq - c0)];
+        const float4 v1 = stage[2 * (jq - c0) + 1];
+        row[0] = fmaf(w, v0.x, row[0]);
+        row[1] = fmaf(w, v0.y, row[1]);
+        row[2] = fmaf(w, v0.z, row[2]);
+        row[3] = fmaf(w, v0.w, row[3]);
+        row[4] = fmaf(w, v1.x, row[4]);
+        row[5] = fmaf(w, v1.y, row[5]);
+        row[6] = fmaf(w, v1.z, row[6]);
+        row[7] = fmaf(w, v1.w, row[7]);
+    }
+}
+
 // Persistent general gather over tiles (plan, north ring, quadrant segment) x
-// maps.  LDS: the node table of the current plan, then the staged source row
-// as [pixel][8] = 4 quarter-turn images of ring s, then 4 of its mirror.
+// maps.  LDS: the node table of the current plan, then one staged chunk as
+// [pixel][8] = 4 quarter-turn images of ring s, then 4 of its mirror.  The
+// loads of the next chunk are in flight while the current one is multiplied.
 __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restrict__ views,
                                                       const int2 *__restrict__ tile_map,
                                                       int ntiles, MapIO io, int nmaps,
@@ -347,7 +428,6 @@ __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restr
         if (pi != cur) {
             load_table(tab, P.table, P.ntab);
             cur = pi;
-            __syncthreads();
         }
         const DevTile T = cst(P.gtiles)[lt];
         const int rn = T.r;
@@ -358,62 +438,92 @@ __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restr
         const bool active = (int)threadIdx.x < T.len;
         const int j = T.j0 + min((int)threadIdx.x, T.len - 1);
         const float *in = io.in[pi] + (size_t)map * P.npix;
-        double acc[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) acc[q] = 0.0;
-        for (int k = R.pair_begin; k < R.pair_end; ++k) {
-            const DevPair pp = cst(P.pairs)[k];
+
+        // first chunk of the first row
+        GenChunk ch;
+        ch.k = R.pair_begin;
+        {
+            const DevPair pp = cst(P.pairs)[ch.k];
+            int hi_max;
+            tile_window(pp, cst(P.rings)[pp.s].n, T, ch.c0, hi_max);
+            ch.cn = min(kGenChunk, hi_max - ch.c0 + 1);
+        }
+        float4 pa[kGenRegs], pb[kGenRegs];
+        {
+            const DevPair pp = cst(P.pairs)[ch.k];
             const DevRing S = cst(P.rings)[pp.s];
-            const float *src = in + S.first;
-            const float *srcm = in + cst(P.rings)[P.nrings - 1 - pp.s].first;
-            const int qs = S.n >> 2;
-            int lo_min, hi_max, lo, hi, dummy;
-            pair_window(pp, S.n, T.j0, lo_min, dummy);
-            pair_window(pp, S.n, T.j0 + T.len - 1, dummy, hi_max);
-            pair_window(pp, S.n, j, lo, hi);
-            const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
-            float row[8];
+            prefetch_chunk(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, mirror,
+                           S.n, ch.c0, ch.cn, pa, pb);
+        }
+        double acc[8];
+        float row[8];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) row[q] = 0.0f;
-            for (int c0 = lo_min; c0 <= hi_max; c0 += kGenChunk) {
-                const int cn = min(kGenChunk, hi_max - c0 + 1);
-                __syncthreads();
-                for (int e = threadIdx.x; e < cn; e += kThreads) {
-                    float4 a, b;
-                    a.x = src[wrap3(c0 + e, S.n)];
-                    a.y = src[wrap3(c0 + e + qs, S.n)];
-                    a.z = src[wrap3(c0 + e + 2 * qs, S.n)];
-                    a.w = src[wrap3(c0 + e + 3 * qs, S.n)];
-                    if (mirror) {
-                        b.x = srcm[wrap3(c0 + e, S.n)];
-                        b.y = srcm[wrap3(c0 + e + qs, S.n)];
-                        b.z = srcm[wrap3(c0 + e + 2 * qs, S.n)];
-                        b.w = srcm[wrap3(c0 + e + 3 * qs, S.n)];
-                    } else {
-                        b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-                    }
-                    stage[2 * e] = a;
-                    stage[2 * e + 1] = b;
-                }
-                __syncthreads();
-                const int a0 = max(lo, c0);
-                const int a1 = min(hi, c0 + cn - 1);
-                for (int jq = a0; jq <= a1; ++jq) {
-                    const float w = pair_weight(P, pp, tab, lon_numerator(mbase, jq, S.two_o, R.n));
-                    const float4 v0 = stage[2 * (jq - c0)];
-                    const float4 v1 = stage[2 * (jq - c0) + 1];
-                    row[0] = fmaf(w, v0.x, row[0]);
-                    row[1] = fmaf(w, v0.y, row[1]);
-                    row[2] = fmaf(w, v0.z, row[2]);
-                    row[3] = fmaf(w, v0.w, row[3]);
-                    row[4] = fmaf(w, v1.x, row[4]);
-                    row[5] = fmaf(w, v1.y, row[5]);
-                    row[6] = fmaf(w, v1.z, row[6]);
-                    row[7] = fmaf(w, v1.w, row[7]);
+        for (int q = 0; q < 8; ++q) {
+            acc[q] = 0.0;
+            row[q] = 0.0f;
+        }
+        while (ch.k < R.pair_end) {
+            __syncthreads();      // the previous chunk is no longer read
+#pragma unroll
+            for (int u = 0; u < kGenRegs; ++u) {
+                const int e = threadIdx.x + u * kThreads;
+                if (e < kGenChunk) {
+                    stage[2 * e] = pa[u];
+                    stage[2 * e + 1] = pb[u];
                 }
             }
+            __syncthreads();
+            const DevPair pp = cst(P.pairs)[ch.k];
+            const DevRing S = cst(P.rings)[pp.s];
+            // the next chunk: the rest of this row, else the next row
+            GenChunk nx;
+            int lo_min, hi_max;
+            tile_window(pp, S.n, T, lo_min, hi_max);
+            if (ch.c0 + kGenChunk <= hi_max) {
+                nx.k = ch.k;
+                nx.c0 = ch.c0 + kGenChunk;
+                nx.cn = min(kGenChunk, hi_max - nx.c0 + 1);
+            } else {
+                nx.k = ch.k + 1;
+                nx.c0 = 0;
+                nx.cn = 0;
+                if (nx.k < R.pair_end) {
+                    const DevPair pn = cst(P.pairs)[nx.k];
+                    int lo2, hi2;
+                    tile_window(pn, cst(P.rings)[pn.s].n, T, lo2, hi2);
+                    nx.c0 = lo2;
+                    nx.cn = min(kGenChunk, hi2 - lo2 + 1);
+                }
+            }
+            if (nx.k < R.pair_end) {
+                const DevPair pn = cst(P.pairs)[nx.k];
+                const DevRing Sn = cst(P.rings)[pn.s];
+                prefetch_chunk(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
+                               Sn.n, nx.c0, nx.cn, pa, pb);
+            }
+            // this lane's candidates inside the chunk
+            int lo, hi;
+            pair_window(pp, S.n, j, lo, hi);
+            const int a0 = max(lo, ch.c0);
+            const int a1 = min(hi, ch.c0 + ch.cn - 1);
+            const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+            const bool lg = (pp.mode & kPairLongSin) != 0;
+            switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+                case 0: gen_candidates<false, 0>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
+                case 1: gen_candidates<true, 0>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
+                case 2: gen_candidates<false, 1>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
+                case 3: gen_candidates<true, 1>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
+                case 4: gen_candidates<false, 2>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
+                default: gen_candidates<true, 2>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
+            }
+            if (nx.k != ch.k) {   // row complete: FP32 row sums into the FP64 totals
 #pragma unroll
-            for (int q = 0; q < 8; ++q) acc[q] += (double)row[q];
+                for (int q = 0; q < 8; ++q) {
+                    acc[q] += (double)row[q];
+                    row[q] = 0.0f;
+                }
+            }
+            ch = nx;
         }
         if (active) {
             float *out = io.out[pi] + (size_t)map * P.npix;
@@ -446,58 +556,185 @@ __global__ void k_set_table(float *table, const float *knots, int ntab, float om
 // table: rounded up to 16 bytes.
 __host__ __device__ constexpr int hist_offset_floats(int ntab) { return (ntab + 3) & ~3; }
 
-// Knot gradient sum_b g_b[p] x_b[q] hat_k(theta_pq) over all pairs, node and
-// fraction from FP64 geometry, accumulated per workgroup in an FP64 LDS
-// histogram and written to partials[block][ntab].  One pass serves NB maps.
-template <int NB>
-__global__ __launch_bounds__(kThreads) void k_knot_grad(DevPlanView P,
-                                                        const float *__restrict__ g,
-                                                        const float *__restrict__ x,
-                                                        int nbatch, unsigned int *counter,
-                                                        double *__restrict__ partials)
+// ------------------------------------------------------------ FP64 math --
+// Coefficients of the series below, evaluated at compile time:
+// asin(y) = sum_k c_k y^(2k+1), c_k = (2k)! / (4^k (k!)^2 (2k+1)), and
+// sin(x) = sum_k (-1)^k x^(2k+1) / (2k+1)!.
+__host__ __device__ constexpr double asin_coef(int k)
 {
-    // The dynamic LDS base is 16-byte aligned and the FP64 histogram starts at
-    // a 16-byte boundary: 64-bit LDS atomics need natural alignment.
-    extern __shared__ __align__(16) float lds_tab[];
-    double *hist = reinterpret_cast<double *>(lds_tab + hist_offset_floats(P.ntab));
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c *= (2.0 * i - 1.0) / (2.0 * i);
+    return c / (2.0 * k + 1.0);
+}
+__host__ __device__ constexpr double sin_coef(int k)
+{
+    double c = 1.0;
+    for (int i = 1; i <= k; ++i) c /= -(2.0 * i) * (2.0 * i + 1.0);
+    return c;
+}
+
+// sin(x) in FP64: through x^15 for |x| <= 0.35, through x^25 for |x| <= 2
+// (truncation below 1e-19 relative).
+template <bool LONG>
+__device__ __forceinline__ double sin_d(double x)
+{
+    constexpr int K = LONG ? 12 : 7;
+    const double x2 = x * x;
+    double p = sin_coef(K);
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) p = fma(p, x2, sin_coef(k));
+    return x * p;
+}
+
+// asin(y) in FP64 for 0 <= y <= 0.5 (truncation below 1e-16 relative).
+__device__ __forceinline__ double asin_d(double y)
+{
+    constexpr int K = 24;
+    const double z = y * y;
+    double p = asin_coef(K);
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) p = fma(p, z, asin_coef(k));
+    return y * p;
+}
+
+// theta = 2 asin(d/2) in FP64 from the squared chord, in the same three
+// regimes as theta_of: d (sum_k c_k (d^2/4)^k) with 8 terms for d <= 0.1 and
+// 16 terms for d^2 <= 0.245, and the full-range asin otherwise.
+template <int AM>
+__device__ __forceinline__ double theta_d(double d2)
+{
+    if (AM == 2) {
+        const double y = fmin(0.5 * sqrt(d2), 1.0);
+        if (y <= 0.5) return 2.0 * asin_d(y);
+        return 2.0 * (1.5707963267948966192 - 2.0 * asin_d(sqrt(0.5 * (1.0 - y))));
+    }
+    constexpr int K = AM == 0 ? 8 : 16;
+    const double z = 0.25 * d2;
+    double p = asin_coef(K);
+#pragma unroll
+    for (int k = K - 1; k >= 0; --k) p = fma(p, z, asin_coef(k));
+    return sqrt(d2) * p;
+}
+
+// Node index and fraction of one pair from the FP64 chord constants; false at
+// or beyond the cut.  (The knot gradient needs the fraction to ~1e-9: the hat
+// basis has slope 1/h in theta.)
+template <bool LONG, int AM>
+__device__ __forceinline__ bool pair_node_d(const DevPairD &pd, double inv_h, double u_max, int m,
+                                            int &node, double &frac)
+{
+    const double sx = sin_d<LONG>((double)m * pd.xscale);
+    const double u = theta_d<AM>(fma(pd.B, sx * sx, pd.A)) * inv_h;
+    node = (int)fmin(u, u_max - 1.0);
+    frac = u - (double)node;
+    return u < u_max;
+}
+
+// Scatter the candidates a0..a1 of one lane into the knot histogram: each
+// candidate's node and fraction serve the 8 images, whose products g x are
+// summed first.
+template <bool LONG, int AM>
+__device__ __forceinline__ void knot_candidates(const DevPairD &pd, double inv_h, double u_max,
+                                                unsigned mbase, int two_o_s, int n_r,
+                                                const float4 *stage, int c0, int a0, int a1,
+                                                const float gv[8], double *hist)
+{
+    for (int jq = a0; jq <= a1; ++jq) {
+        int node;
+        double frac;
+        const bool in = pair_node_d<LONG, AM>(pd, inv_h, u_max,
+                                               lon_numerator(mbase, jq, two_o_s, n_r), node, frac);
+        const float4 v0 = stage[2 * (jq - c0)];
+        const float4 v1 = stage[2 * (jq - c0) + 1];
+        float c = gv[0] * v0.x;
+        c = fmaf(gv[1], v0.y, c);
+        c = fmaf(gv[2], v0.z, c);
+        c = fmaf(gv[3], v0.w, c);
+        c = fmaf(gv[4], v1.x, c);
+        c = fmaf(gv[5], v1.y, c);
+        c = fmaf(gv[6], v1.z, c);
+        c = fmaf(gv[7], v1.w, c);
+        if (in && c != 0.0f) {
+            atomicAdd(&hist[node], (1.0 - frac) * (double)c);
+            atomicAdd(&hist[node + 1], frac * (double)c);
+        }
+    }
+}
+
+// Knot gradient sum_p g[p] sum_q hat_k(theta_pq) x[q] over all pairs of all
+// maps.  Tiles cover the first quadrant of every northern ring; a lane holds
+// g at the 8 images of its pixel, and the source row is staged as in
+// k_general.  Per-workgroup FP64 LDS histograms are written to
+// partials[block][ntab] and reduced in a fixed order by k_knot_reduce.
+__global__ __launch_bounds__(kThreads) void k_knot(const DevPlanView *__restrict__ views,
+                                                   const float *__restrict__ g,
+                                                   const float *__restrict__ x, int nmaps,
+                                                   unsigned int *counter,
+                                                   double *__restrict__ partials)
+{
+    // 16-byte aligned dynamic LDS: 64-bit LDS atomics need natural alignment.
+    extern __shared__ __align__(16) double hist[];
     __shared__ int s_item;
+    const DevPlanView P = cst(views)[0];
+    float4 *stage = reinterpret_cast<float4 *>(hist + ((P.ntab + 1) & ~1));
     for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) hist[i] = 0.0;
-    const int ngroups = (nbatch + NB - 1) / NB;
-    const int nitems = P.ntiles * ngroups;
+    const double u_max = (double)(P.ntab - 1);
+    const int nitems = P.nktiles * nmaps;
     for (;;) {
         const int item = next_item(counter, &s_item);
         if (item >= nitems) break;
-        const int ti = item / ngroups;
-        const int map0 = (item - ti * ngroups) * NB;
-        const int nm = min(NB, nbatch - map0);
-        const DevTile T = P.tiles[ti];
-        const DevRing R = P.rings[T.r];
-        for (int jj = threadIdx.x; jj < T.len; jj += blockDim.x) {
-            const int j = T.j0 + jj;
-            const size_t p = (size_t)(R.first + j);
-            float gp[NB];
+        const int ti = item / nmaps;
+        const int map = item - ti * nmaps;
+        const DevTile T = cst(P.ktiles)[ti];
+        const int rn = T.r;
+        const int rs = P.nrings - 1 - rn;
+        const bool mirror = rs != rn;
+        const DevRing R = cst(P.rings)[rn];
+        const int qr = R.n >> 2;
+        const bool active = (int)threadIdx.x < T.len;
+        const int j = T.j0 + min((int)threadIdx.x, T.len - 1);
+        const float *in = x + (size_t)map * P.npix;
+        const float *gm = g + (size_t)map * P.npix;
+        float gv[8];
 #pragma unroll
-            for (int b = 0; b < NB; ++b)
-                gp[b] = (b < nm) ? g[(size_t)(map0 + b) * P.npix + p] : 0.0f;
-            for (int k = R.pair_begin; k < R.pair_end; ++k) {
-                const DevPair pp = P.pairs[k];
-                const DevPairD pd = P.pairs_d[k];
-                const DevRing S = P.rings[pp.s];
-                int lo, hi;
-                pair_window(pp, S.n, j, lo, hi);
-                const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
-                for (int jq = lo; jq <= hi; ++jq) {
-                    int nd;
-                    double fd;
-                    if (!pair_node_fp64(P, pd, lon_numerator(mbase, jq, S.two_o, R.n), nd, fd))
-                        continue;
-                    const size_t q = (size_t)(S.first + wrap_index(jq, S.n));
-                    float c = 0.0f;
+        for (int q = 0; q < 4; ++q) {
+            gv[q] = active ? gm[R.first + j + q * qr] : 0.0f;
+            gv[4 + q] = (active && mirror) ? gm[cst(P.rings)[rs].first + j + q * qr] : 0.0f;
+        }
+        for (int k = R.pair_begin; k < R.pair_end; ++k) {
+            const DevPair pp = cst(P.pairs)[k];
+            const DevPairD pd = cst(P.pairs_d)[k];
+            const DevRing S = cst(P.rings)[pp.s];
+            const float *src = in + S.first;
+            const float *srcm = in + cst(P.rings)[P.nrings - 1 - pp.s].first;
+            int lo_min, hi_max, lo, hi;
+            tile_window(pp, S.n, T, lo_min, hi_max);
+            pair_window(pp, S.n, j, lo, hi);
+            const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+            const bool lg = (pp.mode & kPairLongSin) != 0;
+            for (int c0 = lo_min; c0 <= hi_max; c0 += kGenChunk) {
+                const int cn = min(kGenChunk, hi_max - c0 + 1);
+                float4 pa[kGenRegs], pb[kGenRegs];
+                prefetch_chunk(src, srcm, mirror, S.n, c0, cn, pa, pb);
+                __syncthreads();
 #pragma unroll
-                    for (int b = 0; b < NB; ++b)
-                        if (b < nm) c = fmaf(gp[b], x[(size_t)(map0 + b) * P.npix + q], c);
-                    atomicAdd(&hist[nd], (1.0 - fd) * (double)c);
-                    atomicAdd(&hist[nd + 1], fd * (double)c);
+                for (int u = 0; u < kGenRegs; ++u) {
+                    const int e = threadIdx.x + u * kThreads;
+                    if (e < kGenChunk) {
+                        stage[2 * e] = pa[u];
+                        stage[2 * e + 1] = pb[u];
+                    }
+                }
+                __syncthreads();
+                const int a0 = max(lo, c0);
+                const int a1 = min(hi, c0 + cn - 1);
+                switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+                    case 0: knot_candidates<false, 0>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
+                    case 1: knot_candidates<true, 0>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
+                    case 2: knot_candidates<false, 1>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
+                    case 3: knot_candidates<true, 1>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
+                    case 4: knot_candidates<false, 2>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
+                    default: knot_candidates<true, 2>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
                 }
             }
         }
@@ -557,16 +794,10 @@ static size_t gen_lds(int ntab)
 }
 static size_t knot_lds(int ntab)
 {
-    return (size_t)hist_offset_floats(ntab) * sizeof(float) + (size_t)ntab * sizeof(double);
+    return (size_t)((ntab + 1) & ~1) * sizeof(double) + (size_t)8 * kGenChunk * sizeof(float);
 }
 
-static int nb_index(int nbatch) { return nbatch >= 8 ? 3 : nbatch >= 4 ? 2 : nbatch >= 2 ? 1 : 0; }
 
-template <int NB>
-static int prepare_knot(Plan &p, int vi)
-{
-    return occupancy(k_knot_grad<NB>, knot_lds(p.desc.ntab), &p.occ_bwd_gk[vi]);
-}
 
 int prepare_launches(Plan &p)
 {
@@ -577,10 +808,8 @@ int prepare_launches(Plan &p)
     if ((rc = occupancy(k_general, gen_lds(p.desc.ntab), &p.occ_gen))) return rc;
     int most = 1;
     if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
-        if ((rc = prepare_knot<1>(p, 0)) || (rc = prepare_knot<2>(p, 1)) ||
-            (rc = prepare_knot<4>(p, 2)) || (rc = prepare_knot<8>(p, 3)))
-            return rc;
-        for (int v = 0; v < 4; ++v) most = std::max(most, p.occ_bwd_gk[v]);
+        if ((rc = occupancy(k_knot, knot_lds(p.desc.ntab), &p.occ_knot))) return rc;
+        most = p.occ_knot;
     }
     p.grid = most * p.cus;  // rows of the knot-gradient partials
     return ARKCOS_OK;
@@ -617,13 +846,15 @@ int launch_build_weights(const Plan &p, hipStream_t s)
 }
 
 // The two gathers of one plan over nbatch maps; they write disjoint rings.
-int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s)
+int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s,
+                   int parts)
 {
     MapIO io{};
     io.in[0] = in;
     io.out[0] = out;
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, p.d_counter);
-    const int nct = (int)p.ctiles.size(), ngt = (int)p.gtiles.size();
+    const int nct = (parts & ARKCOS_PART_CIRCULANT) ? (int)p.ctiles.size() : 0;
+    const int ngt = (parts & ARKCOS_PART_GENERAL) ? (int)p.gtiles.size() : 0;
     if (nct > 0) {
         const int grid = std::max(1, std::min(nct * nbatch, p.occ_circ * p.cus));
         hipLaunchKernelGGL(k_circ, dim3(grid), dim3(kThreads), circ_lds(), s,
@@ -640,16 +871,15 @@ int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipSt
     return ARKCOS_OK;
 }
 
-template <int NB>
-static int knot_nb(const Plan &p, const float *g, const float *x, float *gk, int nbatch,
-                   hipStream_t s)
+static int launch_knot(const Plan &p, const float *g, const float *x, float *gk, int nbatch,
+                       hipStream_t s)
 {
     const int ntab = p.desc.ntab;
-    const int items = (int)p.tiles.size() * ((nbatch + NB - 1) / NB);
-    const int grid = std::max(1, std::min({items, p.occ_bwd_gk[nb_index(NB)] * p.cus, p.grid}));
+    const int items = (int)p.ktiles.size() * nbatch;
+    const int grid = std::max(1, std::min({items, p.occ_knot * p.cus, p.grid}));
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, p.d_counter + 2);
-    hipLaunchKernelGGL(k_knot_grad<NB>, dim3(grid), dim3(kThreads), knot_lds(ntab), s, p.view(),
-                       g, x, nbatch, p.d_counter + 2, p.d_kpart);
+    hipLaunchKernelGGL(k_knot, dim3(grid), dim3(kThreads), knot_lds(ntab), s,
+                       (const DevPlanView *)p.d_view, g, x, nbatch, p.d_counter + 2, p.d_kpart);
     ARKCOS_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 255) / 256), dim3(256), 0, s, p.d_kpart, grid,
                        ntab, p.omega, gk);
@@ -665,16 +895,12 @@ int launch_backward(const Plan &p, const float *g, const float *x, float *gx, fl
         int rc = launch_forward(p, g, gx, nbatch, s);
         if (rc) return rc;
     }
-    if (gk) {
-        if (nbatch >= 8) return knot_nb<8>(p, g, x, gk, nbatch, s);
-        if (nbatch >= 4) return knot_nb<4>(p, g, x, gk, nbatch, s);
-        if (nbatch >= 2) return knot_nb<2>(p, g, x, gk, nbatch, s);
-        return knot_nb<1>(p, g, x, gk, nbatch, s);
-    }
+    if (gk) return launch_knot(p, g, x, gk, nbatch, s);
     return ARKCOS_OK;
 }
 
-int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s)
+int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s,
+                 int parts)
 {
     if ((int)b.plans.size() > kMaxMaps)
         return fail(ARKCOS_EUNSUPPORTED, "at most " + std::to_string(kMaxMaps) + " maps per batch");
@@ -684,11 +910,11 @@ int launch_batch(const Batch &b, const float *const *in, float *const *out, hipS
         io.out[k] = out[k];
     }
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.d_counter);
-    if (!b.cmap.empty())
+    if (!b.cmap.empty() && (parts & ARKCOS_PART_CIRCULANT))
         hipLaunchKernelGGL(k_circ, dim3(b.grid_circ), dim3(kThreads), circ_lds(), s,
                            (const DevPlanView *)b.d_views, (const int2 *)b.d_cmap,
                            (int)b.cmap.size(), io, 1, circ_buf_floats(), b.d_counter);
-    if (!b.gmap.empty())
+    if (!b.gmap.empty() && (parts & ARKCOS_PART_GENERAL))
         hipLaunchKernelGGL(k_general, dim3(b.grid_gen), dim3(kThreads), gen_lds(b.max_ntab), s,
                            (const DevPlanView *)b.d_views, (const int2 *)b.d_gmap,
                            (int)b.gmap.size(), io, 1, gen_tab_floats(b.max_ntab), b.d_counter + 1);

@@ -67,14 +67,16 @@ DevPlanView Plan::view() const
     v.wts = d_wts;
     v.ctiles = d_ctiles;
     v.gtiles = d_gtiles;
+    v.ktiles = d_ktiles;
     v.nctiles = (int)ctiles.size();
     v.ngtiles = (int)gtiles.size();
+    v.nktiles = (int)ktiles.size();
     v.nrows = (int)rows.size();
     v.nrings = nrings;
     v.ntiles = (int)tiles.size();
     v.ntab = desc.ntab;
     v.npix = (int)npix;
-    v.large_angle = large_angle ? 1 : 0;
+    v.angle_mode = angle_mode;
     v.inv_h = (float)((desc.ntab - 1) / desc.theta_cut);
     v.u_max = (float)(desc.ntab - 1);
     return v;
@@ -162,11 +164,13 @@ static int build_plan(Plan &P)
             double w = dphi * S.n / (2.0 * M_PI);
             w = w * (1.0 + 1e-5) + 0.02;
             if (whole || 2.0 * w + 1.0 >= (double)S.n) {
-                p.whole = 1;
+                p.mode = kPairWhole | kPairLongSin;
                 p.w = 0.0f;
                 per_pixel += S.n;
             } else {
-                p.whole = 0;
+                // largest |dphi/2| a candidate can have: (w + 1) pixels of ring s
+                const double xmax = (w + 1.0) * M_PI / (double)S.n;
+                p.mode = xmax > 0.35 ? kPairLongSin : 0;
                 p.w = (float)w;
                 per_pixel += std::floor(2.0 * w) + 1.0;
             }
@@ -208,9 +212,10 @@ static int build_plan(Plan &P)
         bool circ = true;
         for (int k = P.dev_rings[r].pair_begin; k < P.dev_rings[r].pair_end; ++k) {
             const DevPair &pp = P.pairs[k];
-            if (pp.whole || P.rings[pp.s].n != nbelt) circ = false;
+            const bool whole = (pp.mode & kPairWhole) != 0;
+            if (whole || P.rings[pp.s].n != nbelt) circ = false;
             // a group row spans the union of up to kGroupRings windows
-            if (!pp.whole && 2.0 * pp.w + 3.0 + kGroupRings > kCircMaxTaps) circ = false;
+            if (!whole && 2.0 * pp.w + 3.0 + kGroupRings > kCircMaxTaps) circ = false;
         }
         general[r] = circ ? 0 : 1;
     }
@@ -219,6 +224,7 @@ static int build_plan(Plan &P)
         const char g = general[r] | general[rm];
         general[r] = general[rm] = g;
     }
+    P.general_ring = general;
 
     // Circulant groups of up to kGroupRings consecutive circulant rings, each
     // with the union of its rings' source rows and tap ranges.
@@ -305,6 +311,22 @@ static int build_plan(Plan &P)
     }
     sort_by_cost(P.gtiles, cost);
     P.gtile_cost = cost;
+
+    // Knot-gradient tiles: the first quadrant of every northern ring.
+    P.ktiles.clear();
+    cost.clear();
+    for (int r = 0; r <= P.nrings - 1 - r; ++r) {
+        const int quarter = P.rings[r].n / 4;
+        for (int j0 = 0; j0 < quarter; j0 += kThreads) {
+            DevTile t{};
+            t.r = r;
+            t.j0 = j0;
+            t.len = std::min(kThreads, quarter - j0);
+            P.ktiles.push_back(t);
+            cost.push_back(ring_cost[r] * t.len + 1.0);
+        }
+    }
+    sort_by_cost(P.ktiles, cost);
     return ARKCOS_OK;
 }
 
@@ -313,10 +335,11 @@ static int build_plan(Plan &P)
 // interval (c - W, c + W), c = ((2j + 2o_r) n_s / n_r - 2o_s) / 2, with
 // W = dphi_max n_s / (2 pi).  A rotation by a quarter turn maps pixel j to
 // j + n_r/4 and shifts c by n_s/4, so a quarter of each ring is counted.
-static unsigned long long count_pairs(const Plan &P)
+static unsigned long long count_pairs(const Plan &P, unsigned long long *circ_total)
 {
     const double tc = P.desc.theta_cut;
     unsigned long long total = 0;
+    *circ_total = 0;
     for (int r = 0; r < P.nrings; ++r) {
         const HostRing &R = P.rings[r];
         const DevRing &dr = P.dev_rings[r];
@@ -344,6 +367,7 @@ static unsigned long long count_pairs(const Plan &P)
             ring_total += circulant ? part * (unsigned long long)R.n : 4ULL * part;
         }
         total += ring_total;
+        if (!P.general_ring[r]) *circ_total += ring_total;
     }
     return total;
 }
@@ -386,6 +410,7 @@ static void free_device(Plan &P)
         (void)hipFree(P.d_wts);
         (void)hipFree(P.d_ctiles);
         (void)hipFree(P.d_gtiles);
+        (void)hipFree(P.d_ktiles);
         (void)hipFree(P.d_view);
         (void)hipFree(P.d_table);
         (void)hipFree(P.d_counter);
@@ -401,6 +426,7 @@ static void free_device(Plan &P)
     P.d_wts = nullptr;
     P.d_ctiles = nullptr;
     P.d_gtiles = nullptr;
+    P.d_ktiles = nullptr;
     P.d_view = nullptr;
     P.d_table = nullptr;
     P.d_counter = nullptr;
@@ -464,6 +490,7 @@ static int to_device(Plan &P)
         std::vector<double> z((size_t)P.grid * P.desc.ntab, 0.0);
         if ((rc = upload(&P.d_kpart, z, &P.device_bytes))) return rc;
         if ((rc = upload(&P.d_pairs_d, P.pairs_d, &P.device_bytes))) return rc;
+        if ((rc = upload(&P.d_ktiles, P.ktiles, &P.device_bytes))) return rc;
     }
     {
         std::vector<DevPlanView> v(1, P.view());
@@ -561,7 +588,7 @@ int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
     P->tile = desc->tile ? desc->tile : 256;
     P->threads = forward_threads();
     P->host_only = (desc->flags & ARKCOS_PLAN_HOST_ONLY) != 0;
-    P->large_angle = desc->theta_cut > 0.5;
+    P->angle_mode = desc->theta_cut <= 0.1 ? 0 : (desc->theta_cut <= 0.5 ? 1 : 2);
     if (desc->ktab) P->ktab.assign(desc->ktab, desc->ktab + desc->ntab);
     int rc;
     try {
@@ -622,10 +649,24 @@ int arkcos_plan_pair_count(arkcos_plan_t plan, unsigned long long *pairs)
     if (!plan || !pairs) return fail(ARKCOS_EINVAL, "NULL pointer");
     Plan *P = reinterpret_cast<Plan *>(plan);
     if (!P->pairs_counted) {
-        P->pair_count = count_pairs(*P);
+        P->pair_count = count_pairs(*P, &P->pair_count_circ);
         P->pairs_counted = true;
     }
     *pairs = P->pair_count;
+    return ARKCOS_OK;
+}
+
+int arkcos_plan_pair_count_parts(arkcos_plan_t plan, unsigned long long *circulant,
+                                 unsigned long long *general)
+{
+    clear_error();
+    if (!plan) return fail(ARKCOS_EINVAL, "NULL plan");
+    unsigned long long total = 0;
+    int rc = arkcos_plan_pair_count(plan, &total);
+    if (rc) return rc;
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    if (circulant) *circulant = P->pair_count_circ;
+    if (general) *general = total - P->pair_count_circ;
     return ARKCOS_OK;
 }
 

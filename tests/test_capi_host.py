@@ -144,7 +144,16 @@ def test_exact_pair_count_matches_oracle(nside, tc_deg):
     theta < theta_cut is decided by the last bit of either computation."""
     tc = np.radians(tc_deg)
     p = A.Plan(nside, tc, np.ones(8), host_only=True)
-    assert p.pair_count() == int(O.pair_counts(nside, tc).sum())
+    counts = O.pair_counts(nside, tc)
+    assert p.pair_count() == int(counts.sum())
+    circ, gen = p.pair_count_parts()
+    assert circ + gen == p.pair_count()
+    # general rings comprise both polar caps, so at least their pairs
+    g = O.ring_geometry(nside)
+    caps = np.zeros(counts.size, bool)
+    for i in list(range(1, nside)) + list(range(3 * nside + 1, 4 * nside)):
+        caps[g["first"][i - 1]:g["first"][i - 1] + g["n"][i - 1]] = True
+    assert gen >= int(counts[caps].sum())
 
 
 def _in_disc_pairs(nside, tc):
