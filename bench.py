@@ -37,14 +37,18 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GPair-evals/s and maps/s at Nside 2048 (fwd, fwd+bwd, batched) vs plain kernel"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# Algorithmic FP32 work per in-disc pair term of each kernel:
-#   k_circ     one FMA with a precomputed weight;
-#   k_general  one FMA, plus a 24-FLOP weight evaluation (longitude, sine
-#              series, chord, angle series, table index, interpolation) shared
-#              by the 8 quarter-turn and mirror images;
-#   k_knot     8 FMAs of g x per candidate plus ~40 FLOP of FP64 geometry, per
-#              8 images.
-FLOP_PER_PAIR = {"k_circ": 2.0, "k_general": 2.0 + 24.0 / 8.0, "k_knot": (16.0 + 40.0) / 8.0}
+# Algorithmic FP32 work per in-disc pair term:
+#   k_circ       one FMA with a precomputed weight;
+#   k_general    one FMA, plus a 24-FLOP weight evaluation (longitude, sine
+#                series, chord, angle series, table index, interpolation)
+#                shared by the 16 quarter-turn, reflection and mirror images;
+#   k_knot_circ  one FMA of the ring-pair cross-correlation (circulant rings;
+#                the hat weights are applied once per distinct ring pair and
+#                tap);
+#   k_knot_gen   16 products g x per candidate plus ~44 FLOP of FP64 geometry
+#                and hat weights, per 16 images (general rings).
+FLOP_PER_PAIR = {"k_circ": 2.0, "k_general": 2.0 + 24.0 / 16.0,
+                 "k_knot_circ": 2.0, "k_knot_gen": (32.0 + 44.0) / 16.0}
 PROFILES = os.path.join(ROOT, "profiles")
 
 
@@ -81,6 +85,9 @@ def main() -> int:
                     help="skip the 16 plain launches the batch is compared with")
     ap.add_argument("--cpu-sample", type=int, default=6_000_000,
                     help="output pixels of the Nside-2048 oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device-to-device copy, the reference "
+                         "for scaling hardware byte counters")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -156,28 +163,38 @@ def main() -> int:
     ev = lambda: torch.cuda.Event(enable_timing=True)  # noqa: E731
     launches = []   # (part of the step, kernel, algorithmic FLOP, start event, end event)
 
-    def timed(record, part, kernel, pairs, fn):
+    def timed(record, part, kernel, flop, fn):
         e0, e1 = ev(), ev()
         e0.record(stream)
         fn()
         e1.record(stream)
         if record:
-            launches.append((part, kernel, FLOP_PER_PAIR[kernel] * pairs, e0, e1))
+            launches.append((part, kernel, flop, e0, e1))
+
+    def fl(kernel, pairs):
+        return FLOP_PER_PAIR[kernel] * pairs
 
     def step(record: bool):
         for i, (p, o, (pc, pg)) in enumerate(zip(fwd_plans, fwd_out, fwd_parts)):
-            timed(record, "fwd%d" % i, "k_circ", pc, lambda: p.convolve_part(x2048, o, CIRC))
-            timed(record, "fwd%d" % i, "k_general", pg, lambda: p.convolve_part(x2048, o, GEN))
+            timed(record, "fwd%d" % i, "k_circ", fl("k_circ", pc),
+                  lambda: p.convolve_part(x2048, o, CIRC))
+            timed(record, "fwd%d" % i, "k_general", fl("k_general", pg),
+                  lambda: p.convolve_part(x2048, o, GEN))
         pc, pg = g_parts
-        timed(record, "fwdbwd", "k_circ", pc, lambda: gplan.convolve_part(x2048, g_out, CIRC))
-        timed(record, "fwdbwd", "k_general", pg, lambda: gplan.convolve_part(x2048, g_out, GEN))
+        timed(record, "fwdbwd", "k_circ", fl("k_circ", pc),
+              lambda: gplan.convolve_part(x2048, g_out, CIRC))
+        timed(record, "fwdbwd", "k_general", fl("k_general", pg),
+              lambda: gplan.convolve_part(x2048, g_out, GEN))
         # adjoint: the operator is symmetric, so d/dmap is the same two gathers on g
-        timed(record, "fwdbwd", "k_circ", pc, lambda: gplan.convolve_part(gin, g_gx, CIRC))
-        timed(record, "fwdbwd", "k_general", pg, lambda: gplan.convolve_part(gin, g_gx, GEN))
-        timed(record, "fwdbwd", "k_knot", g_pairs,
+        timed(record, "fwdbwd", "k_circ", fl("k_circ", pc),
+              lambda: gplan.convolve_part(gin, g_gx, CIRC))
+        timed(record, "fwdbwd", "k_general", fl("k_general", pg),
+              lambda: gplan.convolve_part(gin, g_gx, GEN))
+        # knot gradient: correlation on circulant rings, per pair on general rings
+        timed(record, "fwdbwd", "k_knot", fl("k_knot_circ", pc) + fl("k_knot_gen", pg),
               lambda: gplan.backward(gin, x2048, want_map=False, want_knots=True))
-        timed(record, "batch", "k_circ", b_circ, graphs[CIRC].replay)
-        timed(record, "batch", "k_general", b_gen, graphs[GEN].replay)
+        timed(record, "batch", "k_circ", fl("k_circ", b_circ), graphs[CIRC].replay)
+        timed(record, "batch", "k_general", fl("k_general", b_gen), graphs[GEN].replay)
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
@@ -215,6 +232,14 @@ def main() -> int:
     kernels = {k: {"launches_per_step": v[2] // args.steps,
                    "avg_launch_ms": round(v[1] / v[2], 4),
                    "tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 2)} for k, v in kern.items()}
+
+    if args.copy_calibration:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).uniform_()
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read and written")
 
     plain16_ms = None
     if not args.no_plain_compare:
@@ -287,7 +312,7 @@ def main() -> int:
             "unit": "TFLOP/s",
             "frac": round(achieved / FP32_VECTOR_PEAK_TFLOPS, 4),
             "traffic": _traffic(dom),
-            "flop_per_pair": FLOP_PER_PAIR[dom],
+            "flop_per_pair": FLOP_PER_PAIR.get(dom),
             "avg_launch_ms": round(total_ms / nl, 4),
         },
         "cpu_baseline": cpu,

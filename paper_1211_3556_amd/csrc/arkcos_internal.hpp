@@ -78,15 +78,25 @@ struct DevTile {
     int pad;
 };
 
-// Rings per group and outputs per lane of the circulant kernel, and the
-// source pixels one pass of the general kernel stages per image.
+// Rings per group and outputs per lane of the circulant kernel; pixels per
+// general tile and source positions one pass of the general kernel stages;
+// source pixels one pass of the knot-gradient kernel stages per image.
 constexpr int kThreads = 256;
 constexpr int kGroupRings = 4;
 constexpr int kCircPix = 4;
 constexpr int kCircSeg = kThreads * kCircPix;
 constexpr int kCircMaxTaps = 256;   // wider rows make their rings general
+constexpr int kGenLanes = kThreads / 2;
+constexpr int kGenStage = 248;      // with a 16384-node table two workgroups fit a CU
 constexpr int kGenChunk = 320;
 constexpr int kMaxMaps = 32;
+// Circulant knot-gradient tiles: kKnotSeg pixels of a ring group, split into
+// sub-segments of kKnotSub; up to kKnotRows source rows and kKnotStage staged
+// floats per batch.
+constexpr int kKnotSeg = 256;
+constexpr int kKnotSub = 64;
+constexpr int kKnotRows = 64;
+constexpr int kKnotStage = 10240;
 
 // A group of up to kGroupRings consecutive belt rings r0 .. r0+nr-1 whose
 // source rings all have the ring's own pixel count: the weight of a pair then
@@ -122,11 +132,13 @@ struct DevPlanView {
     const DevRow *rows;      // their source rows
     float *wts;              // their weight rows (written by the weight-build kernel)
     const DevTile *ctiles;   // circulant tiles: (group, j0, len)
-    const DevTile *gtiles;   // general tiles: (north ring, j0, len) inside quadrant 0
-    const DevTile *ktiles;   // knot-gradient tiles: every northern ring, quadrant 0
+    const DevTile *gtiles;   // general tiles: (north ring, j0, len), pixels j <= jbar of quadrant 0
+    const DevTile *kctiles;  // circulant knot-gradient tiles: (group, j0, len)
+    const double *kw;        // FP64 node coordinate per circulant weight slot, or -1
     int nctiles;
     int ngtiles;
-    int nktiles;
+    int nkctiles;
+    int nkpart_circ;         // partial rows written by the circulant knot kernel
     int nrows;
     int nrings;
     int ntiles;
@@ -135,6 +147,7 @@ struct DevPlanView {
     int angle_mode;          // angle series: 0 (theta_cut <= 0.1), 1 (<= 0.5), 2 full range
     float inv_h;             // (ntab - 1) / theta_cut
     float u_max;             // ntab - 1 (strict upper bound of u = theta / h)
+    float u_coef[6];         // inv_h times the coefficients of the short angle series
 };
 
 // ------------------------------------------------------- shared FP32 math --
@@ -185,7 +198,7 @@ struct Plan {
     std::vector<DevRow> rows;
     std::vector<DevTile> ctiles;      // circulant tiles, longest first
     std::vector<DevTile> gtiles;      // general tiles, longest first
-    std::vector<DevTile> ktiles;      // knot-gradient tiles, longest first
+    std::vector<DevTile> kctiles;     // circulant knot-gradient tiles, longest first
     std::vector<double> ctile_cost, gtile_cost;
     long long nweights = 0;
     int max_taps = 0;
@@ -207,19 +220,20 @@ struct Plan {
     float *d_wts = nullptr;
     DevTile *d_ctiles = nullptr;
     DevTile *d_gtiles = nullptr;
-    DevTile *d_ktiles = nullptr;
+    DevTile *d_kctiles = nullptr;
+    double *d_kw = nullptr;             // knot node coordinates of the circulant slots
     DevPlanView *d_view = nullptr;      // device copy of view() (a batch of one plan)
     float *d_table = nullptr;
     unsigned int *d_counter = nullptr;  // persistent-queue counter (+ 1 spare)
     double *d_kpart = nullptr;          // knot-gradient partials [grid][ntab] (learnable)
-    int grid = 0;                       // rows of d_kpart: most resident backward workgroups
+    int grid = 0;                       // rows of d_kpart: grid_kc + grid_kg
+    int grid_kc = 0;                    // resident workgroups of the two knot kernels
+    int grid_kg = 0;
     int cus = 0;                        // compute units of the device
     int occ_circ = 0;                   // resident workgroups per CU of the two gathers
     int occ_gen = 0;
-    int occ_knot = 0;                   // and of the knot-gradient kernel
-    int occ_fwd[4] = {0, 0, 0, 0};      // unused slots kept zero
-    int occ_bwd_gxgk[4] = {0, 0, 0, 0};
-    int occ_bwd_gk[4] = {0, 0, 0, 0};
+    int occ_kc = 0;                     // and of the two knot-gradient kernels
+    int occ_kg = 0;
     long long device_bytes = 0;
 
     DevPlanView view() const;
@@ -251,6 +265,7 @@ int launch_backward(const Plan &p, const float *g, const float *x, float *gx, fl
 int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s,
                  int parts = ARKCOS_PART_ALL);
 int launch_build_weights(const Plan &p, hipStream_t s);
+int launch_build_knotw(const Plan &p, hipStream_t s);
 int device_lds_limit(int device, size_t *bytes);
 int prepare_launches(Plan &p);   // occupancy of every kernel variant, grid sizes
 int prepare_batch(Batch &b);

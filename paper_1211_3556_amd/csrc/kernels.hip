@@ -18,8 +18,10 @@
 //    are evaluated per pair from exact ring-pair constants: chord from
 //    d^2 = A + B sin^2(dphi/2), angle by series, node table in LDS with
 //    linear interpolation.  A quarter turn maps pixel j of a ring to
-//    j + n/4 and the N-S mirror maps ring i to ring 4N - i, so one weight
-//    serves eight pairs; source rows are staged in LDS as [pixel][8 images].
+//    j + n/4, the N-S mirror maps ring i to ring 4N - i and the reflection
+//    phi -> pi/2 - phi maps a pair to one with the opposite longitude
+//    difference, so one weight serves sixteen pairs; source rows are staged
+//    in LDS as four arrays of four images each.
 //
 // Sums are FP32 within a source-ring row and FP64 across rows.  No atomics
 // touch the outputs: results are bitwise reproducible.  This is a gather with
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict
     }
 }
 
-// --------------------------------------------------------- general gather --
+// ------------------------------------------- 8-image staging helpers --
 // Source pixels each lane prefetches per staged chunk.
 constexpr int kGenRegs = (kGenChunk + kThreads - 1) / kThreads;
 
@@ -379,18 +381,116 @@ __device__ __forceinline__ void prefetch_chunk(const float *src, const float *sr
     }
 }
 
-// Accumulate the candidates a0..a1 of one lane from the staged chunk.
-template <bool LONG, int AM>
-__device__ __forceinline__ void gen_candidates(const DevPair &pp, const float *tab, float inv_h,
-                                               float u_max, unsigned mbase, int two_o_s, int n_r,
-                                               const float4 *stage, int c0, int a0, int a1,
-                                               float row[8])
+
+// --------------------------------------------------------- general gather --
+// Reflection about phi = pi/4 (phi -> pi/2 - phi) maps pixel j of quadrant 0
+// of a ring with offset o to jbar = n/4 - 2o - j, and a pair (j, j') to
+// (jbar, j'bar) with the opposite longitude difference: the same weight.
+// Together with the four quarter turns and the N-S mirror one weight serves
+// sixteen pairs.  A general tile holds up to kGenLanes pixels j <= jbar of the
+// first quadrant of a northern ring; two lanes share each pixel and take
+// alternate candidates of its window, so one staged row of kGenStage source
+// positions covers the tile.  The stage holds, per source position j', the
+// four quarter turns of x at j' on ring s and on its mirror, then the same at
+// j'bar: four float4 arrays of kGenStage entries.
+
+// Largest value of `v` over the wave (wave-uniform result).
+__device__ __forceinline__ int wave_max(int v)
 {
-    for (int jq = a0; jq <= a1; ++jq) {
-        const float w = pair_weight_t<LONG, AM>(pp, tab, inv_h, u_max,
-                                                lon_numerator(mbase, jq, two_o_s, n_r));
-        const float4 v0 = stage[2 * (jq - c0)];
-        const float4 v1 = stage[2 * (jq - c0) + 1];
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    const int r0 = __builtin_amdgcn_readlane(v, 0);
+    const int r1 = __builtin_amdgcn_readlane(v, 16);
+    const int r2 = __builtin_amdgcn_readlane(v, 32);
+    const int r3 = __builtin_amdgcn_readlane(v, 48);
+    return max(max(r0, r1), max(r2, r3));
+}
+
+// u = theta / h from the squared chord.  For the short series the factor
+// 1/h is folded into the coefficients (u_coef = inv_h times those of
+// theta_of), which saves one multiply per pair.
+template <int AM>
+__device__ __forceinline__ float node_coord(float d2, const DevPlanView &P)
+{
+    if (AM == 2) return theta_of<2>(d2) * P.inv_h;
+    const float d = __builtin_amdgcn_sqrtf(d2);
+    float p;
+    if (AM == 1) {
+        p = P.u_coef[5];
+        p = fmaf(p, d2, P.u_coef[4]);
+        p = fmaf(p, d2, P.u_coef[3]);
+        p = fmaf(p, d2, P.u_coef[2]);
+    } else {
+        p = P.u_coef[2];
+    }
+    p = fmaf(p, d2, P.u_coef[1]);
+    p = fmaf(p, d2, P.u_coef[0]);
+    return d * p;
+}
+
+// One staged position per thread: source position c0 + e of ring s and its
+// reflection, four quarter turns each, on ring s (a, c) and its mirror (b, d).
+__device__ __forceinline__ void prefetch16(const float *src, const float *srcm, bool mirror,
+                                           int n_s, int two_o_s, int c0, int cn, float4 &a,
+                                           float4 &b, float4 &c, float4 &d)
+{
+    const int e = threadIdx.x;
+    a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    b = a;
+    c = a;
+    d = a;
+    if (e >= cn) return;
+    const int qs = n_s >> 2;
+    int jd = c0 + e;                       // -n_s < jd < 2 n_s
+    jd = jd < 0 ? jd + n_s : (jd >= n_s ? jd - n_s : jd);
+    int jr = qs - two_o_s - jd;           // -n_s < jr < n_s
+    jr = jr < 0 ? jr + n_s : jr;
+    int id[4], ir[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        id[k] = jd + k * qs;
+        id[k] = id[k] >= n_s ? id[k] - n_s : id[k];
+        ir[k] = jr + k * qs;
+        ir[k] = ir[k] >= n_s ? ir[k] - n_s : ir[k];
+    }
+    a = make_float4(src[id[0]], src[id[1]], src[id[2]], src[id[3]]);
+    c = make_float4(src[ir[0]], src[ir[1]], src[ir[2]], src[ir[3]]);
+    if (mirror) {
+        b = make_float4(srcm[id[0]], srcm[id[1]], srcm[id[2]], srcm[id[3]]);
+        d = make_float4(srcm[ir[0]], srcm[ir[1]], srcm[ir[2]], srcm[ir[3]]);
+    }
+}
+
+// T candidates jq0, jq0 + 2, ... of one lane in the staged chunk; those past
+// a1 get the table's zero slot.  The loop count is wave-uniform, so the
+// compiler can overlap consecutive candidates.
+template <bool LONG, int AM>
+__device__ __forceinline__ void gen_candidates16(const DevPair &pp, const DevPlanView &P,
+                                                 const float *tab, int m, int dm,
+                                                 const float4 *stage, int c0, int cn, int jq,
+                                                 int a1, int T, float row[16])
+{
+    const float zslot = (float)P.ntab;
+#pragma unroll 2
+    for (int t = 0; t < T; ++t) {
+        const bool valid = jq <= a1;
+        const int pos = min(max(jq - c0, 0), cn - 1);
+        const float x = (float)m * pp.xscale;              // half the longitude difference
+        const float sx = sin_series<LONG>(x);
+        const float d2 = fmaf(pp.B, sx * sx, pp.A);          // squared chord
+        const float u = node_coord<AM>(d2, P);
+        const float uc = (valid && u < P.u_max) ? u : zslot;
+        const int node = (int)uc;
+        const float frac = uc - (float)node;
+        const float k0 = tab[node];
+        const float k1 = tab[node + 1];
+        const float w = fmaf(frac, k1 - k0, k0);
+        const float4 v0 = stage[pos];
+        const float4 v1 = stage[kGenStage + pos];
+        const float4 v2 = stage[2 * kGenStage + pos];
+        const float4 v3 = stage[3 * kGenStage + pos];
         row[0] = fmaf(w, v0.x, row[0]);
         row[1] = fmaf(w, v0.y, row[1]);
         row[2] = fmaf(w, v0.z, row[2]);
@@ -399,13 +499,59 @@ __device__ __forceinline__ void gen_candidates(const DevPair &pp, const float *t
         row[5] = fmaf(w, v1.y, row[5]);
         row[6] = fmaf(w, v1.z, row[6]);
         row[7] = fmaf(w, v1.w, row[7]);
+        row[8] = fmaf(w, v2.x, row[8]);
+        row[9] = fmaf(w, v2.y, row[9]);
+        row[10] = fmaf(w, v2.z, row[10]);
+        row[11] = fmaf(w, v2.w, row[11]);
+        row[12] = fmaf(w, v3.x, row[12]);
+        row[13] = fmaf(w, v3.y, row[13]);
+        row[14] = fmaf(w, v3.z, row[14]);
+        row[15] = fmaf(w, v3.w, row[15]);
+        jq += 2;
+        m -= dm;
     }
 }
 
-// Persistent general gather over tiles (plan, north ring, quadrant segment) x
-// maps.  LDS: the node table of the current plan, then one staged chunk as
-// [pixel][8] = 4 quarter-turn images of ring s, then 4 of its mirror.  The
-// loads of the next chunk are in flight while the current one is multiplied.
+// Source rows of a tile are staged in chunks of kGenStage positions.
+struct GenStage {
+    int k;    // pair (row) index
+    int c0;   // first unwrapped source position
+    int cn;   // positions staged
+};
+
+// The chunk after `ch`: the rest of its row, else the first of the next row.
+__device__ __forceinline__ GenStage next_stage(const DevPlanView &P, const DevRing &R,
+                                               const DevTile &T, const GenStage &ch)
+{
+    GenStage nx;
+    const DevPair pp = cst(P.pairs)[ch.k];
+    int lo_min, hi_max;
+    tile_window(pp, cst(P.rings)[pp.s].n, T, lo_min, hi_max);
+    if (ch.c0 + kGenStage <= hi_max) {
+        nx.k = ch.k;
+        nx.c0 = ch.c0 + kGenStage;
+        nx.cn = min(kGenStage, hi_max - nx.c0 + 1);
+        return nx;
+    }
+    nx.k = ch.k + 1;
+    nx.c0 = 0;
+    nx.cn = 0;
+    if (nx.k < R.pair_end) {
+        const DevPair pn = cst(P.pairs)[nx.k];
+        tile_window(pn, cst(P.rings)[pn.s].n, T, nx.c0, hi_max);
+        nx.cn = min(kGenStage, hi_max - nx.c0 + 1);
+    }
+    return nx;
+}
+
+// FP32 partial sums are moved into the FP64 totals once a lane has
+// accumulated at least this many candidates since the last move.
+constexpr int kGenFlush = 48;
+
+// Persistent general gather over tiles (plan, north ring, half-quadrant
+// segment) x maps.  LDS: the node table of the current plan followed by two
+// zero entries (the slot of candidates outside the disc), then the stage.
+// The loads of the next chunk are in flight while the current one is used.
 __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restrict__ views,
                                                       const int2 *__restrict__ tile_map,
                                                       int ntiles, MapIO io, int nmaps,
@@ -416,6 +562,8 @@ __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restr
     float4 *stage = reinterpret_cast<float4 *>(lds + tab_floats);
     __shared__ int s_item;
     const int nitems = ntiles * nmaps;
+    const int ph = threadIdx.x & 1;
+    const int lane_pix = threadIdx.x >> 1;
     int cur = -1;
     for (;;) {
         const int item = next_item(counter, &s_item);
@@ -427,6 +575,7 @@ __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restr
         const DevPlanView P = cst(views)[pi];
         if (pi != cur) {
             load_table(tab, P.table, P.ntab);
+            if (threadIdx.x < 2) tab[P.ntab + threadIdx.x] = 0.0f;
             cur = pi;
         }
         const DevTile T = cst(P.gtiles)[lt];
@@ -435,109 +584,113 @@ __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restr
         const bool mirror = rs != rn;
         const DevRing R = cst(P.rings)[rn];
         const int qr = R.n >> 2;
-        const bool active = (int)threadIdx.x < T.len;
-        const int j = T.j0 + min((int)threadIdx.x, T.len - 1);
+        const bool active = lane_pix < T.len;
+        const int j = T.j0 + min(lane_pix, T.len - 1);
         const float *in = io.in[pi] + (size_t)map * P.npix;
 
-        // first chunk of the first row
-        GenChunk ch;
+        GenStage ch;
         ch.k = R.pair_begin;
         {
             const DevPair pp = cst(P.pairs)[ch.k];
             int hi_max;
             tile_window(pp, cst(P.rings)[pp.s].n, T, ch.c0, hi_max);
-            ch.cn = min(kGenChunk, hi_max - ch.c0 + 1);
+            ch.cn = min(kGenStage, hi_max - ch.c0 + 1);
         }
-        float4 pa[kGenRegs], pb[kGenRegs];
+        float4 pa, pb, pc, pd;
         {
             const DevPair pp = cst(P.pairs)[ch.k];
             const DevRing S = cst(P.rings)[pp.s];
-            prefetch_chunk(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, mirror,
-                           S.n, ch.c0, ch.cn, pa, pb);
+            prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, mirror, S.n,
+                       S.two_o, ch.c0, ch.cn, pa, pb, pc, pd);
         }
-        double acc[8];
-        float row[8];
+        double acc[16];
+        float row[16];
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 16; ++q) {
             acc[q] = 0.0;
             row[q] = 0.0f;
         }
+        int since = 0;
         while (ch.k < R.pair_end) {
             __syncthreads();      // the previous chunk is no longer read
-#pragma unroll
-            for (int u = 0; u < kGenRegs; ++u) {
-                const int e = threadIdx.x + u * kThreads;
-                if (e < kGenChunk) {
-                    stage[2 * e] = pa[u];
-                    stage[2 * e + 1] = pb[u];
-                }
+            if (threadIdx.x < kGenStage) {
+                stage[threadIdx.x] = pa;
+                stage[kGenStage + threadIdx.x] = pb;
+                stage[2 * kGenStage + threadIdx.x] = pc;
+                stage[3 * kGenStage + threadIdx.x] = pd;
             }
             __syncthreads();
             const DevPair pp = cst(P.pairs)[ch.k];
             const DevRing S = cst(P.rings)[pp.s];
-            // the next chunk: the rest of this row, else the next row
-            GenChunk nx;
-            int lo_min, hi_max;
-            tile_window(pp, S.n, T, lo_min, hi_max);
-            if (ch.c0 + kGenChunk <= hi_max) {
-                nx.k = ch.k;
-                nx.c0 = ch.c0 + kGenChunk;
-                nx.cn = min(kGenChunk, hi_max - nx.c0 + 1);
-            } else {
-                nx.k = ch.k + 1;
-                nx.c0 = 0;
-                nx.cn = 0;
-                if (nx.k < R.pair_end) {
-                    const DevPair pn = cst(P.pairs)[nx.k];
-                    int lo2, hi2;
-                    tile_window(pn, cst(P.rings)[pn.s].n, T, lo2, hi2);
-                    nx.c0 = lo2;
-                    nx.cn = min(kGenChunk, hi2 - lo2 + 1);
-                }
-            }
+            const GenStage nx = next_stage(P, R, T, ch);
             if (nx.k < R.pair_end) {
                 const DevPair pn = cst(P.pairs)[nx.k];
                 const DevRing Sn = cst(P.rings)[pn.s];
-                prefetch_chunk(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
-                               Sn.n, nx.c0, nx.cn, pa, pb);
+                prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
+                           Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
             }
-            // this lane's candidates inside the chunk
+            // this lane's candidates inside the chunk: a0 + ph, a0 + ph + 2, ...
             int lo, hi;
             pair_window(pp, S.n, j, lo, hi);
             const int a0 = max(lo, ch.c0);
             const int a1 = min(hi, ch.c0 + ch.cn - 1);
+            const int mine = max(0, (a1 - a0 + 2 - ph) >> 1);
+            const int nt = wave_max(mine);
+            const int jq0 = a0 + ph;
             const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+            const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
+            const int dm = 4 * R.n;
             const bool lg = (pp.mode & kPairLongSin) != 0;
             switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                case 0: gen_candidates<false, 0>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
-                case 1: gen_candidates<true, 0>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
-                case 2: gen_candidates<false, 1>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
-                case 3: gen_candidates<true, 1>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
-                case 4: gen_candidates<false, 2>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
-                default: gen_candidates<true, 2>(pp, tab, P.inv_h, P.u_max, mbase, S.two_o, R.n, stage, ch.c0, a0, a1, row); break;
+                case 0: gen_candidates16<false, 0>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 1: gen_candidates16<true, 0>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 2: gen_candidates16<false, 1>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 3: gen_candidates16<true, 1>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 4: gen_candidates16<false, 2>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                default: gen_candidates16<true, 2>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
             }
-            if (nx.k != ch.k) {   // row complete: FP32 row sums into the FP64 totals
+            since += nt;
+            if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < 16; ++q) {
                     acc[q] += (double)row[q];
                     row[q] = 0.0f;
                 }
+                since = 0;
             }
             ch = nx;
         }
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            acc[q] += (double)row[q];
+            acc[q] += __shfl_xor(acc[q], 1);   // the two lanes of a pixel
+        }
         if (active) {
             float *out = io.out[pi] + (size_t)map * P.npix;
-            float *o = out + R.first + j;
+            float *o = out + R.first;
+            float *om = out + cst(P.rings)[rs].first;
+            if (ph == 0) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) o[q * qr] = (float)acc[q];
-            if (mirror) {
-                float *om = out + cst(P.rings)[rs].first + j;
+                for (int q = 0; q < 4; ++q) o[j + q * qr] = (float)acc[q];
+                if (mirror) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) om[q * qr] = (float)acc[4 + q];
+                    for (int q = 0; q < 4; ++q) om[j + q * qr] = (float)acc[4 + q];
+                }
+            } else {
+                const int jb = qr - R.two_o - j;   // reflected pixel; j itself at a fixed point
+                if (jb != j && jb != qr) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) o[jb + q * qr] = (float)acc[8 + q];
+                    if (mirror) {
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) om[jb + q * qr] = (float)acc[12 + q];
+                    }
+                }
             }
         }
     }
 }
+
 
 __global__ void k_reset_counters(unsigned int *counter)
 {
@@ -630,22 +783,227 @@ __device__ __forceinline__ bool pair_node_d(const DevPairD &pd, double inv_h, do
     return u < u_max;
 }
 
-// Scatter the candidates a0..a1 of one lane into the knot histogram: each
-// candidate's node and fraction serve the 8 images, whose products g x are
-// summed first.
-template <bool LONG, int AM>
-__device__ __forceinline__ void knot_candidates(const DevPairD &pd, double inv_h, double u_max,
-                                                unsigned mbase, int two_o_s, int n_r,
-                                                const float4 *stage, int c0, int a0, int a1,
-                                                const float gv[8], double *hist)
+// The knot gradient is sum_p g[p] sum_q hat_k(theta_pq) x[q] over the in-disc
+// pairs of all maps.  Both kernels below scatter into a per-workgroup FP64
+// LDS histogram, written to partials[row][ntab] and reduced in a fixed order
+// by k_knot_reduce.
+
+// FP64 node coordinate u = theta / h of every circulant weight slot
+// (wts layout: row w_off + tap * kGroupRings + ring), or -1 outside the
+// ring's window or disc.  It depends on the geometry only.
+__global__ __launch_bounds__(kThreads) void k_build_knotw(DevPlanView P, double *kw)
 {
-    for (int jq = a0; jq <= a1; ++jq) {
-        int node;
-        double frac;
-        const bool in = pair_node_d<LONG, AM>(pd, inv_h, u_max,
-                                               lon_numerator(mbase, jq, two_o_s, n_r), node, frac);
-        const float4 v0 = stage[2 * (jq - c0)];
-        const float4 v1 = stage[2 * (jq - c0) + 1];
+    const int row = blockIdx.x;
+    if (row >= P.nrows) return;
+    const DevRow W = P.rows[row];
+    const DevGroup G = P.groups[W.g];
+    const int n = P.rings[G.r0].n;
+    const int two_o_s = P.rings[W.s].two_o;
+    const double u_max = (double)(P.ntab - 1);
+    for (int e = threadIdx.x; e < W.ntaps * kGroupRings; e += blockDim.x) {
+        const int t = e / kGroupRings;
+        const int i = e - t * kGroupRings;
+        const int k = W.k_lo + t;
+        double u = -1.0;
+        if (i < G.nr) {
+            const DevRing R = P.rings[G.r0 + i];
+            const int kk = R.pair_begin + (W.s - P.pairs[R.pair_begin].s);
+            if (kk >= R.pair_begin && kk < R.pair_end) {
+                const DevPair pp = P.pairs[kk];
+                int lo, hi;
+                pair_window(pp, n, 0, lo, hi);
+                if (k >= lo && k <= hi) {
+                    const DevPairD pd = P.pairs_d[kk];
+                    const bool lg = (pp.mode & kPairLongSin) != 0;
+                    const int m = n * (R.two_o - two_o_s - 2 * k);
+                    int node;
+                    double frac;
+                    bool in;
+                    switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+                        case 0: in = pair_node_d<false, 0>(pd, P.inv_h_d, u_max, m, node, frac); break;
+                        case 1: in = pair_node_d<true, 0>(pd, P.inv_h_d, u_max, m, node, frac); break;
+                        case 2: in = pair_node_d<false, 1>(pd, P.inv_h_d, u_max, m, node, frac); break;
+                        case 3: in = pair_node_d<true, 1>(pd, P.inv_h_d, u_max, m, node, frac); break;
+                        case 4: in = pair_node_d<false, 2>(pd, P.inv_h_d, u_max, m, node, frac); break;
+                        default: in = pair_node_d<true, 2>(pd, P.inv_h_d, u_max, m, node, frac); break;
+                    }
+                    if (in) u = (double)node + frac;
+                }
+            }
+        }
+        kw[W.w_off + e] = u;
+    }
+}
+
+// Add c * hat(u) to the histogram (u >= 0: node floor(u), fraction u - node).
+__device__ __forceinline__ void hat_scatter(double *hist, double u, float c)
+{
+    const int node = (int)u;
+    const double frac = u - (double)node;
+    atomicAdd(&hist[node], (1.0 - frac) * (double)c);
+    atomicAdd(&hist[node + 1], frac * (double)c);
+}
+
+// ------------------------------------------- circulant rings: correlation --
+// On circulant rings theta depends on (r, s, tap) only, so
+//   sum_j g_r[j] sum_k hat(u(r, s, k)) x_s[j + k]
+//     = sum_k hat(u(r, s, k)) C(r, s, k),   C(r, s, k) = sum_j g_r[j] x_s[j + k]:
+// the pair loop becomes a cross-correlation of ring r of g with ring s of x,
+// and each distinct (r, s, k) is binned once.  A tile is kKnotSeg pixels of
+// the kGroupRings rings of a group; its g is staged once as float4 (one
+// value per ring) in strips of kKnotSub pixels, and its source rows are
+// staged in batches, each row as one strip of x per sub-segment.  A unit of
+// work is (row, 4 consecutive taps, sub-segment): 16 FP32 sums of kKnotSub
+// products, scattered with the node coordinates of k_build_knotw.
+constexpr int kKnotSubs = kKnotSeg / kKnotSub;
+
+__device__ __forceinline__ int knot_strip(int ntaps4) { return (kKnotSub + ntaps4 - 1) | 1; }
+
+__global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__restrict__ views,
+                                                        const float *__restrict__ g,
+                                                        const float *__restrict__ x, int nmaps,
+                                                        unsigned int *counter,
+                                                        double *__restrict__ partials)
+{
+    extern __shared__ __align__(16) double hist[];
+    __shared__ int s_item;
+    __shared__ int s_rows;                   // rows in the current batch
+    __shared__ int s_uprefix[kKnotRows + 1]; // units before each row of the batch
+    __shared__ int s_xoff[kKnotRows];        // its staged x strips
+    const DevPlanView P = cst(views)[0];
+    float4 *gs = reinterpret_cast<float4 *>(hist + ((P.ntab + 1) & ~1));
+    float *xs = reinterpret_cast<float *>(gs + kKnotSubs * (kKnotSub + 1));
+    for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) hist[i] = 0.0;
+    const int nitems = P.nkctiles * nmaps;
+    for (;;) {
+        const int item = next_item(counter, &s_item);
+        if (item >= nitems) break;
+        const int ti = item / nmaps;
+        const int map = item - ti * nmaps;
+        const DevTile T = cst(P.kctiles)[ti];
+        const DevGroup G = cst(P.groups)[T.r];
+        const int n = cst(P.rings)[G.r0].n;
+        const float *in = x + (size_t)map * P.npix;
+        const float *gm = g + (size_t)map * P.npix;
+        const int nsub = (T.len + kKnotSub - 1) / kKnotSub;
+        // g of the group's rings over the tile (zero past the last ring)
+        for (int e = threadIdx.x; e < T.len; e += blockDim.x) {
+            float v[kGroupRings];
+#pragma unroll
+            for (int i = 0; i < kGroupRings; ++i)
+                v[i] = i < G.nr ? gm[cst(P.rings)[G.r0 + i].first + T.j0 + e] : 0.0f;
+            gs[(e / kKnotSub) * (kKnotSub + 1) + e % kKnotSub] = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        for (int rb = G.row_begin; rb < G.row_end;) {
+            __syncthreads();   // the previous batch is no longer read
+            if (threadIdx.x == 0) {
+                int r = rb, units = 0, xo = 0;
+                s_uprefix[0] = 0;
+                while (r < G.row_end && r - rb < kKnotRows) {
+                    const int nt4 = (cst(P.rows)[r].ntaps + 3) & ~3;
+                    const int need = nsub * knot_strip(nt4);
+                    if (r > rb && xo + need > kKnotStage) break;
+                    s_xoff[r - rb] = xo;
+                    xo += need;
+                    units += (nt4 >> 2) * nsub;
+                    s_uprefix[r - rb + 1] = units;
+                    ++r;
+                }
+                s_rows = r - rb;
+            }
+            __syncthreads();
+            const int nrows = s_rows;
+            // stage x: row r, sub-segment q, strip position p holds
+            // x_s[j0 + q kKnotSub + k_lo + p] for the positions its units read
+            // (-n < k_lo and k_lo + ntaps + 2 < n/2 + 4, so wrap3 applies)
+            for (int rr = 0; rr < nrows; ++rr) {
+                const DevRow W = cst(P.rows)[rb + rr];
+                const int nt4 = (W.ntaps + 3) & ~3;
+                const int strip = knot_strip(nt4);
+                const float *src = in + cst(P.rings)[W.s].first;
+                float *dst = xs + s_xoff[rr];
+                for (int e = threadIdx.x; e < nsub * strip; e += blockDim.x) {
+                    const int q = e / strip;
+                    const int p = e - q * strip;
+                    const int used = min(kKnotSub, T.len - q * kKnotSub) + nt4 - 1;
+                    dst[e] = p < used ? src[wrap3(T.j0 + q * kKnotSub + W.k_lo + p, n)] : 0.0f;
+                }
+            }
+            __syncthreads();
+            const int nunits = s_uprefix[nrows];
+            for (int u = threadIdx.x; u < nunits; u += blockDim.x) {
+                int rr = 0, rh = nrows - 1;   // last row whose units start at or before u
+                while (rr < rh) {
+                    const int mid = (rr + rh + 1) >> 1;
+                    if (s_uprefix[mid] <= u) rr = mid;
+                    else rh = mid - 1;
+                }
+                const DevRow W = cst(P.rows)[rb + rr];
+                const int v = u - s_uprefix[rr];
+                const int tb = v / nsub;
+                const int q = v - tb * nsub;
+                const int strip = knot_strip((W.ntaps + 3) & ~3);
+                const float *xp = xs + s_xoff[rr] + q * strip + 4 * tb;
+                const float4 *gp = gs + q * (kKnotSub + 1);
+                const int len = min(kKnotSub, T.len - q * kKnotSub);
+                float c[kGroupRings][4];
+#pragma unroll
+                for (int i = 0; i < kGroupRings; ++i)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) c[i][t] = 0.0f;
+                float x0 = xp[0], x1 = xp[1], x2 = xp[2];
+#pragma unroll 4
+                for (int e = 0; e < len; ++e) {
+                    const float x3 = xp[e + 3];
+                    const float4 gv = gp[e];
+                    const float gg[kGroupRings] = {gv.x, gv.y, gv.z, gv.w};
+#pragma unroll
+                    for (int i = 0; i < kGroupRings; ++i) {
+                        c[i][0] = fmaf(gg[i], x0, c[i][0]);
+                        c[i][1] = fmaf(gg[i], x1, c[i][1]);
+                        c[i][2] = fmaf(gg[i], x2, c[i][2]);
+                        c[i][3] = fmaf(gg[i], x3, c[i][3]);
+                    }
+                    x0 = x1;
+                    x1 = x2;
+                    x2 = x3;
+                }
+                cptr<double> kw = cst(P.kw + W.w_off);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int tap = 4 * tb + t;
+                    if (tap >= W.ntaps) break;
+#pragma unroll
+                    for (int i = 0; i < kGroupRings; ++i) {
+                        const double uu = kw[tap * kGroupRings + i];
+                        if (uu >= 0.0 && c[i][t] != 0.0f) hat_scatter(hist, uu, c[i][t]);
+                    }
+                }
+            }
+            rb += nrows;
+        }
+        __syncthreads();   // gs is restaged by the next item
+    }
+    __syncthreads();
+    double *dst = partials + (size_t)blockIdx.x * P.ntab;
+    for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) dst[i] = hist[i];
+}
+
+// ------------------------------------------------- general rings: per pair --
+// Candidates T of one lane, as in the general gather: the sixteen products
+// g x of a candidate share its FP64 node coordinate.
+template <bool LONG, int AM>
+__device__ __forceinline__ void knot_candidates16(const DevPairD &pd, double inv_h, double u_max,
+                                                  int m, int dm, const float4 *stage, int c0,
+                                                  int cn, int jq, int a1, int T,
+                                                  const float gv[16], double *hist)
+{
+    for (int t = 0; t < T; ++t) {
+        const int pos = min(max(jq - c0, 0), cn - 1);
+        const float4 v0 = stage[pos];
+        const float4 v1 = stage[kGenStage + pos];
+        const float4 v2 = stage[2 * kGenStage + pos];
+        const float4 v3 = stage[3 * kGenStage + pos];
         float c = gv[0] * v0.x;
         c = fmaf(gv[1], v0.y, c);
         c = fmaf(gv[2], v0.z, c);
@@ -654,96 +1012,134 @@ __device__ __forceinline__ void knot_candidates(const DevPairD &pd, double inv_h
         c = fmaf(gv[5], v1.y, c);
         c = fmaf(gv[6], v1.z, c);
         c = fmaf(gv[7], v1.w, c);
-        if (in && c != 0.0f) {
-            atomicAdd(&hist[node], (1.0 - frac) * (double)c);
-            atomicAdd(&hist[node + 1], frac * (double)c);
+        c = fmaf(gv[8], v2.x, c);
+        c = fmaf(gv[9], v2.y, c);
+        c = fmaf(gv[10], v2.z, c);
+        c = fmaf(gv[11], v2.w, c);
+        c = fmaf(gv[12], v3.x, c);
+        c = fmaf(gv[13], v3.y, c);
+        c = fmaf(gv[14], v3.z, c);
+        c = fmaf(gv[15], v3.w, c);
+        if (jq <= a1 && c != 0.0f) {
+            int node;
+            double frac;
+            if (pair_node_d<LONG, AM>(pd, inv_h, u_max, m, node, frac)) {
+                atomicAdd(&hist[node], (1.0 - frac) * (double)c);
+                atomicAdd(&hist[node + 1], frac * (double)c);
+            }
         }
+        jq += 2;
+        m -= dm;
     }
 }
 
-// Knot gradient sum_p g[p] sum_q hat_k(theta_pq) x[q] over all pairs of all
-// maps.  Tiles cover the first quadrant of every northern ring; a lane holds
-// g at the 8 images of its pixel, and the source row is staged as in
-// k_general.  Per-workgroup FP64 LDS histograms are written to
-// partials[block][ntab] and reduced in a fixed order by k_knot_reduce.
-__global__ __launch_bounds__(kThreads) void k_knot(const DevPlanView *__restrict__ views,
-                                                   const float *__restrict__ g,
-                                                   const float *__restrict__ x, int nmaps,
-                                                   unsigned int *counter,
-                                                   double *__restrict__ partials)
+// Pairs whose output ring is general, over the general tiles (sixteen images
+// per pixel, two lanes per pixel, source rows staged as in k_general).  A
+// lane holds g at the sixteen output images of its pixel; at a fixed point
+// of the reflection the reflected images are the pixel's own and get zero.
+__global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__restrict__ views,
+                                                       const float *__restrict__ g,
+                                                       const float *__restrict__ x, int nmaps,
+                                                       unsigned int *counter,
+                                                       double *__restrict__ partials)
 {
-    // 16-byte aligned dynamic LDS: 64-bit LDS atomics need natural alignment.
     extern __shared__ __align__(16) double hist[];
     __shared__ int s_item;
     const DevPlanView P = cst(views)[0];
     float4 *stage = reinterpret_cast<float4 *>(hist + ((P.ntab + 1) & ~1));
     for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) hist[i] = 0.0;
     const double u_max = (double)(P.ntab - 1);
-    const int nitems = P.nktiles * nmaps;
+    const int ph = threadIdx.x & 1;
+    const int lane_pix = threadIdx.x >> 1;
+    const int nitems = P.ngtiles * nmaps;
     for (;;) {
         const int item = next_item(counter, &s_item);
         if (item >= nitems) break;
         const int ti = item / nmaps;
         const int map = item - ti * nmaps;
-        const DevTile T = cst(P.ktiles)[ti];
+        const DevTile T = cst(P.gtiles)[ti];
         const int rn = T.r;
         const int rs = P.nrings - 1 - rn;
         const bool mirror = rs != rn;
         const DevRing R = cst(P.rings)[rn];
         const int qr = R.n >> 2;
-        const bool active = (int)threadIdx.x < T.len;
-        const int j = T.j0 + min((int)threadIdx.x, T.len - 1);
+        const bool active = lane_pix < T.len;
+        const int j = T.j0 + min(lane_pix, T.len - 1);
+        const int jb = qr - R.two_o - j;
+        const bool refl = active && jb != j && jb != qr;
         const float *in = x + (size_t)map * P.npix;
         const float *gm = g + (size_t)map * P.npix;
-        float gv[8];
+        float gv[16];
+        {
+            const float *gn = gm + R.first;
+            const float *gsm = gm + cst(P.rings)[rs].first;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            gv[q] = active ? gm[R.first + j + q * qr] : 0.0f;
-            gv[4 + q] = (active && mirror) ? gm[cst(P.rings)[rs].first + j + q * qr] : 0.0f;
-        }
-        for (int k = R.pair_begin; k < R.pair_end; ++k) {
-            const DevPair pp = cst(P.pairs)[k];
-            const DevPairD pd = cst(P.pairs_d)[k];
-            const DevRing S = cst(P.rings)[pp.s];
-            const float *src = in + S.first;
-            const float *srcm = in + cst(P.rings)[P.nrings - 1 - pp.s].first;
-            int lo_min, hi_max, lo, hi;
-            tile_window(pp, S.n, T, lo_min, hi_max);
-            pair_window(pp, S.n, j, lo, hi);
-            const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
-            const bool lg = (pp.mode & kPairLongSin) != 0;
-            for (int c0 = lo_min; c0 <= hi_max; c0 += kGenChunk) {
-                const int cn = min(kGenChunk, hi_max - c0 + 1);
-                float4 pa[kGenRegs], pb[kGenRegs];
-                prefetch_chunk(src, srcm, mirror, S.n, c0, cn, pa, pb);
-                __syncthreads();
-#pragma unroll
-                for (int u = 0; u < kGenRegs; ++u) {
-                    const int e = threadIdx.x + u * kThreads;
-                    if (e < kGenChunk) {
-                        stage[2 * e] = pa[u];
-                        stage[2 * e + 1] = pb[u];
-                    }
-                }
-                __syncthreads();
-                const int a0 = max(lo, c0);
-                const int a1 = min(hi, c0 + cn - 1);
-                switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                    case 0: knot_candidates<false, 0>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
-                    case 1: knot_candidates<true, 0>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
-                    case 2: knot_candidates<false, 1>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
-                    case 3: knot_candidates<true, 1>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
-                    case 4: knot_candidates<false, 2>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
-                    default: knot_candidates<true, 2>(pd, P.inv_h_d, u_max, mbase, S.two_o, R.n, stage, c0, a0, a1, gv, hist); break;
-                }
+            for (int q = 0; q < 4; ++q) {
+                gv[q] = active ? gn[j + q * qr] : 0.0f;
+                gv[4 + q] = (active && mirror) ? gsm[j + q * qr] : 0.0f;
+                gv[8 + q] = refl ? gn[jb + q * qr] : 0.0f;
+                gv[12 + q] = (refl && mirror) ? gsm[jb + q * qr] : 0.0f;
             }
+        }
+        GenStage ch;
+        ch.k = R.pair_begin;
+        {
+            const DevPair pp = cst(P.pairs)[ch.k];
+            int hi_max;
+            tile_window(pp, cst(P.rings)[pp.s].n, T, ch.c0, hi_max);
+            ch.cn = min(kGenStage, hi_max - ch.c0 + 1);
+        }
+        float4 pa, pb, pc, pd4;
+        {
+            const DevPair pp = cst(P.pairs)[ch.k];
+            const DevRing S = cst(P.rings)[pp.s];
+            prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, mirror, S.n,
+                       S.two_o, ch.c0, ch.cn, pa, pb, pc, pd4);
+        }
+        while (ch.k < R.pair_end) {
+            __syncthreads();
+            if (threadIdx.x < kGenStage) {
+                stage[threadIdx.x] = pa;
+                stage[kGenStage + threadIdx.x] = pb;
+                stage[2 * kGenStage + threadIdx.x] = pc;
+                stage[3 * kGenStage + threadIdx.x] = pd4;
+            }
+            __syncthreads();
+            const DevPair pp = cst(P.pairs)[ch.k];
+            const DevPairD pd = cst(P.pairs_d)[ch.k];
+            const DevRing S = cst(P.rings)[pp.s];
+            const GenStage nx = next_stage(P, R, T, ch);
+            if (nx.k < R.pair_end) {
+                const DevPair pn = cst(P.pairs)[nx.k];
+                const DevRing Sn = cst(P.rings)[pn.s];
+                prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
+                           Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd4);
+            }
+            int lo, hi;
+            pair_window(pp, S.n, j, lo, hi);
+            const int a0 = max(lo, ch.c0);
+            const int a1 = min(hi, ch.c0 + ch.cn - 1);
+            const int nt = wave_max(max(0, (a1 - a0 + 2 - ph) >> 1));
+            const int jq0 = a0 + ph;
+            const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+            const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
+            const int dm = 4 * R.n;
+            const bool lg = (pp.mode & kPairLongSin) != 0;
+            switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+                case 0: knot_candidates16<false, 0>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 1: knot_candidates16<true, 0>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 2: knot_candidates16<false, 1>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 3: knot_candidates16<true, 1>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 4: knot_candidates16<false, 2>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                default: knot_candidates16<true, 2>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+            }
+            ch = nx;
         }
     }
     __syncthreads();
-    double *dst = partials + (size_t)blockIdx.x * P.ntab;
+    double *dst = partials + ((size_t)P.nkpart_circ + blockIdx.x) * P.ntab;
     for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) dst[i] = hist[i];
 }
-
 // Fixed-order reduction of the per-workgroup partials, scaled by Omega.
 __global__ void k_knot_reduce(const double *__restrict__ partials, int nblocks, int ntab,
                               double omega, float *__restrict__ gk)
@@ -787,14 +1183,24 @@ static int occupancy(K kernel, size_t lds, int *per_cu)
 // Two row buffers of kStageRegs * kThreads floats each.
 static int circ_buf_floats() { return kStageRegs * kThreads; }
 static size_t circ_lds() { return (size_t)2 * circ_buf_floats() * sizeof(float); }
-static int gen_tab_floats(int ntab) { return hist_offset_floats(ntab); }
+// Node table plus its two zero entries, rounded up to 16 bytes, then four
+// float4 arrays of kGenStage staged positions.
+static int gen_tab_floats(int ntab) { return (ntab + 2 + 3) & ~3; }
 static size_t gen_lds(int ntab)
 {
-    return (size_t)(gen_tab_floats(ntab) + 8 * kGenChunk) * sizeof(float);
+    return (size_t)(gen_tab_floats(ntab) + 16 * kGenStage) * sizeof(float);
 }
-static size_t knot_lds(int ntab)
+// FP64 histogram (16-byte aligned), then the staged g and x of a circulant
+// knot tile, or the general stage.
+static size_t knot_hist_bytes(int ntab) { return (size_t)((ntab + 1) & ~1) * sizeof(double); }
+static size_t knot_circ_lds(int ntab)
 {
-    return (size_t)((ntab + 1) & ~1) * sizeof(double) + (size_t)8 * kGenChunk * sizeof(float);
+    return knot_hist_bytes(ntab) + (size_t)kKnotSubs * (kKnotSub + 1) * sizeof(float4) +
+           (size_t)kKnotStage * sizeof(float);
+}
+static size_t knot_gen_lds(int ntab)
+{
+    return knot_hist_bytes(ntab) + (size_t)4 * kGenStage * sizeof(float4);
 }
 
 
@@ -806,12 +1212,15 @@ int prepare_launches(Plan &p)
     int rc;
     if ((rc = occupancy(k_circ, circ_lds(), &p.occ_circ))) return rc;
     if ((rc = occupancy(k_general, gen_lds(p.desc.ntab), &p.occ_gen))) return rc;
-    int most = 1;
+    p.grid_kc = p.grid_kg = 0;
     if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
-        if ((rc = occupancy(k_knot, knot_lds(p.desc.ntab), &p.occ_knot))) return rc;
-        most = p.occ_knot;
+        if ((rc = occupancy(k_knot_circ, knot_circ_lds(p.desc.ntab), &p.occ_kc))) return rc;
+        if ((rc = occupancy(k_knot_gen, knot_gen_lds(p.desc.ntab), &p.occ_kg))) return rc;
+        // one partial row per resident workgroup of each knot kernel
+        p.grid_kc = p.kctiles.empty() ? 0 : p.occ_kc * p.cus;
+        p.grid_kg = p.gtiles.empty() ? 0 : p.occ_kg * p.cus;
     }
-    p.grid = most * p.cus;  // rows of the knot-gradient partials
+    p.grid = std::max(1, p.grid_kc + p.grid_kg);
     return ARKCOS_OK;
 }
 
@@ -871,18 +1280,33 @@ int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipSt
     return ARKCOS_OK;
 }
 
+int launch_build_knotw(const Plan &p, hipStream_t s)
+{
+    if (p.rows.empty()) return ARKCOS_OK;
+    hipLaunchKernelGGL(k_build_knotw, dim3((unsigned)p.rows.size()), dim3(kThreads), 0, s,
+                       p.view(), p.d_kw);
+    ARKCOS_HIP_CHECK(hipGetLastError());
+    return ARKCOS_OK;
+}
+
+// Circulant rings by correlation, general rings per pair; every partial row
+// is written (the grids are the rows reserved at plan creation), then reduced.
 static int launch_knot(const Plan &p, const float *g, const float *x, float *gk, int nbatch,
                        hipStream_t s)
 {
     const int ntab = p.desc.ntab;
-    const int items = (int)p.ktiles.size() * nbatch;
-    const int grid = std::max(1, std::min({items, p.occ_knot * p.cus, p.grid}));
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, p.d_counter + 2);
-    hipLaunchKernelGGL(k_knot, dim3(grid), dim3(kThreads), knot_lds(ntab), s,
-                       (const DevPlanView *)p.d_view, g, x, nbatch, p.d_counter + 2, p.d_kpart);
+    if (p.grid_kc > 0)
+        hipLaunchKernelGGL(k_knot_circ, dim3(p.grid_kc), dim3(kThreads), knot_circ_lds(ntab), s,
+                           (const DevPlanView *)p.d_view, g, x, nbatch, p.d_counter + 2,
+                           p.d_kpart);
+    if (p.grid_kg > 0)
+        hipLaunchKernelGGL(k_knot_gen, dim3(p.grid_kg), dim3(kThreads), knot_gen_lds(ntab), s,
+                           (const DevPlanView *)p.d_view, g, x, nbatch, p.d_counter + 3,
+                           p.d_kpart);
     ARKCOS_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 255) / 256), dim3(256), 0, s, p.d_kpart, grid,
-                       ntab, p.omega, gk);
+    hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 255) / 256), dim3(256), 0, s, p.d_kpart,
+                       p.grid_kc + p.grid_kg, ntab, p.omega, gk);
     ARKCOS_HIP_CHECK(hipGetLastError());
     return ARKCOS_OK;
 }

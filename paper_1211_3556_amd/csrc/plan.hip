@@ -67,18 +67,25 @@ DevPlanView Plan::view() const
     v.wts = d_wts;
     v.ctiles = d_ctiles;
     v.gtiles = d_gtiles;
-    v.ktiles = d_ktiles;
+    v.kctiles = d_kctiles;
+    v.kw = d_kw;
     v.nctiles = (int)ctiles.size();
     v.ngtiles = (int)gtiles.size();
-    v.nktiles = (int)ktiles.size();
+    v.nkctiles = (int)kctiles.size();
+    v.nkpart_circ = grid_kc;
     v.nrows = (int)rows.size();
     v.nrings = nrings;
     v.ntiles = (int)tiles.size();
     v.ntab = desc.ntab;
     v.npix = (int)npix;
     v.angle_mode = angle_mode;
-    v.inv_h = (float)((desc.ntab - 1) / desc.theta_cut);
+    const double ih = (desc.ntab - 1) / desc.theta_cut;
+    v.inv_h = (float)ih;
     v.u_max = (float)(desc.ntab - 1);
+    // theta = d (1 + d^2/24 + 3 d^4/640 + 5 d^6/7168 + 35 d^8/294912 + 63 d^10/2883584)
+    const double c[6] = {1.0, 1.0 / 24.0, 3.0 / 640.0, 5.0 / 7168.0, 35.0 / 294912.0,
+                         63.0 / 2883584.0};
+    for (int k = 0; k < 6; ++k) v.u_coef[k] = (float)(ih * c[k]);
     return v;
 }
 
@@ -292,19 +299,21 @@ static int build_plan(Plan &P)
     sort_by_cost(P.ctiles, cost);
     P.ctile_cost = cost;
 
-    // General tiles: up to kThreads pixels of the first quadrant of a general
-    // ring of the northern half (equator included); each lane produces the
-    // four quarter-turn images on the ring and on its mirror ring.
+    // General tiles: up to kGenLanes pixels j <= jbar = n/4 - 2o - j of the
+    // first quadrant of a general ring of the northern half (equator
+    // included); each pixel yields its four quarter turns, their reflections
+    // about phi = pi/4 and the mirror images of all eight.
     P.gtiles.clear();
     cost.clear();
     for (int r = 0; r <= P.nrings - 1 - r; ++r) {
         if (!general[r]) continue;
         const int quarter = P.rings[r].n / 4;
-        for (int j0 = 0; j0 < quarter; j0 += kThreads) {
+        const int lanes = (P.rings[r].two_o ? (quarter - 1) / 2 : quarter / 2) + 1;
+        for (int j0 = 0; j0 < lanes; j0 += kGenLanes) {
             DevTile t{};
             t.r = r;
             t.j0 = j0;
-            t.len = std::min(kThreads, quarter - j0);
+            t.len = std::min(kGenLanes, lanes - j0);
             P.gtiles.push_back(t);
             cost.push_back(ring_cost[r] * t.len + 1.0);
         }
@@ -312,21 +321,23 @@ static int build_plan(Plan &P)
     sort_by_cost(P.gtiles, cost);
     P.gtile_cost = cost;
 
-    // Knot-gradient tiles: the first quadrant of every northern ring.
-    P.ktiles.clear();
+    // Circulant knot-gradient tiles: kKnotSeg consecutive pixels of every
+    // ring of a group.
+    P.kctiles.clear();
     cost.clear();
-    for (int r = 0; r <= P.nrings - 1 - r; ++r) {
-        const int quarter = P.rings[r].n / 4;
-        for (int j0 = 0; j0 < quarter; j0 += kThreads) {
+    for (int g = 0; g < (int)P.groups.size(); ++g) {
+        double taps = 0.0;
+        for (int q = P.groups[g].row_begin; q < P.groups[g].row_end; ++q) taps += P.rows[q].ntaps;
+        for (int j0 = 0; j0 < nbelt; j0 += kKnotSeg) {
             DevTile t{};
-            t.r = r;
+            t.r = g;
             t.j0 = j0;
-            t.len = std::min(kThreads, quarter - j0);
-            P.ktiles.push_back(t);
-            cost.push_back(ring_cost[r] * t.len + 1.0);
+            t.len = std::min(kKnotSeg, nbelt - j0);
+            P.kctiles.push_back(t);
+            cost.push_back(taps * t.len + 1.0);
         }
     }
-    sort_by_cost(P.ktiles, cost);
+    sort_by_cost(P.kctiles, cost);
     return ARKCOS_OK;
 }
 
@@ -410,7 +421,8 @@ static void free_device(Plan &P)
         (void)hipFree(P.d_wts);
         (void)hipFree(P.d_ctiles);
         (void)hipFree(P.d_gtiles);
-        (void)hipFree(P.d_ktiles);
+        (void)hipFree(P.d_kctiles);
+        (void)hipFree(P.d_kw);
         (void)hipFree(P.d_view);
         (void)hipFree(P.d_table);
         (void)hipFree(P.d_counter);
@@ -426,7 +438,8 @@ static void free_device(Plan &P)
     P.d_wts = nullptr;
     P.d_ctiles = nullptr;
     P.d_gtiles = nullptr;
-    P.d_ktiles = nullptr;
+    P.d_kctiles = nullptr;
+    P.d_kw = nullptr;
     P.d_view = nullptr;
     P.d_table = nullptr;
     P.d_counter = nullptr;
@@ -490,7 +503,12 @@ static int to_device(Plan &P)
         std::vector<double> z((size_t)P.grid * P.desc.ntab, 0.0);
         if ((rc = upload(&P.d_kpart, z, &P.device_bytes))) return rc;
         if ((rc = upload(&P.d_pairs_d, P.pairs_d, &P.device_bytes))) return rc;
-        if ((rc = upload(&P.d_ktiles, P.ktiles, &P.device_bytes))) return rc;
+        if ((rc = upload(&P.d_kctiles, P.kctiles, &P.device_bytes))) return rc;
+        if ((rc = upload(&P.d_kw, std::vector<double>((size_t)std::max<long long>(P.nweights, 1), -1.0),
+                         &P.device_bytes)))
+            return rc;
+        if ((rc = launch_build_knotw(P, nullptr))) return rc;
+        ARKCOS_HIP_CHECK(hipStreamSynchronize(nullptr));
     }
     {
         std::vector<DevPlanView> v(1, P.view());
