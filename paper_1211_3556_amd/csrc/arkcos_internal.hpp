@@ -86,8 +86,10 @@ constexpr int kGroupRings = 4;
 constexpr int kCircPix = 4;
 constexpr int kCircSeg = kThreads * kCircPix;
 constexpr int kCircMaxTaps = 256;   // wider rows make their rings general
-constexpr int kGenLanes = kThreads / 2;
-constexpr int kGenStage = 248;      // with a 16384-node table two workgroups fit a CU
+constexpr int kGenLanes = 128;       // pixels per general tile
+constexpr int kGenThreads = 512;     // general-gather workgroup: kGenPhases lanes per pixel
+constexpr int kGenPhases = kGenThreads / kGenLanes;
+constexpr int kGenStage = 248;       // with a 16384-node table two workgroups fit a CU
 constexpr int kGenChunk = 320;
 constexpr int kMaxMaps = 32;
 // Circulant knot-gradient tiles: kKnotSeg pixels of a ring group, split into

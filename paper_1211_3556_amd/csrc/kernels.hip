@@ -240,6 +240,8 @@ __global__ __launch_bounds__(kThreads) void k_build_weights(DevPlanView P)
 // Source pixels each lane prefetches per row: a row spans at most
 // kCircSeg + kCircMaxTaps - 1 pixels.
 constexpr int kStageRegs = (kCircSeg + kCircMaxTaps + kThreads - 1) / kThreads;
+// Weights each lane prefetches per row: kGroupRings per tap.
+constexpr int kWeightRegs = kCircMaxTaps * kGroupRings / kThreads;
 
 // Issue the global loads of one staged row (pixels base .. base+nstage-1 of a
 // ring of n pixels, wrapped) into registers.
@@ -253,15 +255,34 @@ __device__ __forceinline__ void prefetch_row(const float *src, int base, int nst
     }
 }
 
+// The same for the row's nw = ntaps * kGroupRings weights.
+__device__ __forceinline__ void prefetch_weights(const float *w, int nw, float v[kWeightRegs])
+{
+#pragma unroll
+    for (int u = 0; u < kWeightRegs; ++u) {
+        const int e = threadIdx.x + u * kThreads;
+        v[u] = (e < nw) ? w[e] : 0.0f;
+    }
+}
+
+// FP32 partial sums move into the FP64 totals once this many taps (FP32
+// terms per output) have accumulated, and at the end of a tile.
+constexpr int kCircFlush = 64;
+
 // Persistent circulant gather over tiles (plan, group, segment) x maps.  Rows
-// are double-buffered: the loads of row t+1 are in flight while row t is
-// multiplied, and one barrier per row separates the buffers.
+// are double-buffered: the loads of row t+1 (source pixels and weights) are
+// in flight while row t is multiplied, and one barrier per row separates the
+// buffers.  The weights of a tap are read from LDS by every lane at one
+// address (a broadcast), so the FMAs take all operands from vector registers:
+// an FMA with a scalar-register operand issues at about 0.6x the rate on
+// gfx950.
 __global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict__ views,
                                                    const int2 *__restrict__ tile_map,
                                                    int ntiles, MapIO io, int nmaps,
                                                    int buf_floats, unsigned int *counter)
 {
     extern __shared__ __align__(16) float xs[];
+    float *wls = xs + 2 * buf_floats;      // two weight buffers of kCircMaxTaps float4
     __shared__ int s_item;
     const int nitems = ntiles * nmaps;
     for (;;) {
@@ -281,35 +302,40 @@ __global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict
         for (int r = 0; r < kGroupRings; ++r)
 #pragma unroll
             for (int i = 0; i < kCircPix; ++i) acc[r][i] = 0.0;
-        float v[kStageRegs];
+        float v[kStageRegs], wv[kWeightRegs];
         {
             const DevRow W = cst(P.rows)[G.row_begin];
             prefetch_row(in + cst(P.rings)[W.s].first, T.j0 + W.k_lo, T.len + W.ntaps - 1, n, v);
+            prefetch_weights(P.wts + W.w_off, W.ntaps * kGroupRings, wv);
         }
+        float racc[kGroupRings][kCircPix];
+#pragma unroll
+        for (int r = 0; r < kGroupRings; ++r)
+#pragma unroll
+            for (int i = 0; i < kCircPix; ++i) racc[r][i] = 0.0f;
+        int since = 0;   // taps summed in FP32 since the last move into FP64
         int buf = 0;
         for (int row = G.row_begin; row < G.row_end; ++row) {
             const DevRow W = cst(P.rows)[row];
             float *xb = xs + buf * buf_floats;
+            float *wb = wls + buf * kCircMaxTaps * kGroupRings;
 #pragma unroll
             for (int u = 0; u < kStageRegs; ++u) xb[threadIdx.x + u * kThreads] = v[u];
+#pragma unroll
+            for (int u = 0; u < kWeightRegs; ++u) wb[threadIdx.x + u * kThreads] = wv[u];
             __syncthreads();
             if (row + 1 < G.row_end) {
                 const DevRow W1 = cst(P.rows)[row + 1];
                 prefetch_row(in + cst(P.rings)[W1.s].first, T.j0 + W1.k_lo,
                              T.len + W1.ntaps - 1, n, v);
+                prefetch_weights(P.wts + W1.w_off, W1.ntaps * kGroupRings, wv);
             }
-            float racc[kGroupRings][kCircPix];
-#pragma unroll
-            for (int r = 0; r < kGroupRings; ++r)
-#pragma unroll
-                for (int i = 0; i < kCircPix; ++i) racc[r][i] = 0.0f;
-            cptr<float> w = cst(P.wts + W.w_off);
+            const float4 *w4 = reinterpret_cast<const float4 *>(wb);
             const float *x0 = xb + threadIdx.x;
-#pragma unroll 2
+#pragma unroll 4
             for (int t = 0; t < W.ntaps; ++t) {
-                float wr[kGroupRings];
-#pragma unroll
-                for (int r = 0; r < kGroupRings; ++r) wr[r] = w[t * kGroupRings + r];
+                const float4 wt = w4[t];
+                const float wr[kGroupRings] = {wt.x, wt.y, wt.z, wt.w};
 #pragma unroll
                 for (int i = 0; i < kCircPix; ++i) {
                     const float x = x0[i * kThreads + t];
@@ -317,10 +343,17 @@ __global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict
                     for (int r = 0; r < kGroupRings; ++r) racc[r][i] = fmaf(wr[r], x, racc[r][i]);
                 }
             }
+            since += W.ntaps;
+            if (since >= kCircFlush || row + 1 == G.row_end) {
 #pragma unroll
-            for (int r = 0; r < kGroupRings; ++r)
+                for (int r = 0; r < kGroupRings; ++r)
 #pragma unroll
-                for (int i = 0; i < kCircPix; ++i) acc[r][i] += (double)racc[r][i];
+                    for (int i = 0; i < kCircPix; ++i) {
+                        acc[r][i] += (double)racc[r][i];
+                        racc[r][i] = 0.0f;
+                    }
+                since = 0;
+            }
             buf ^= 1;
         }
         float *out = io.out[pi] + (size_t)map * P.npix;
@@ -388,9 +421,10 @@ __device__ __forceinline__ void prefetch_chunk(const float *src, const float *sr
 // (jbar, j'bar) with the opposite longitude difference: the same weight.
 // Together with the four quarter turns and the N-S mirror one weight serves
 // sixteen pairs.  A general tile holds up to kGenLanes pixels j <= jbar of the
-// first quadrant of a northern ring; two lanes share each pixel and take
-// alternate candidates of its window, so one staged row of kGenStage source
-// positions covers the tile.  The stage holds, per source position j', the
+// first quadrant of a northern ring; kGenPhases lanes share each pixel and
+// take every kGenPhases-th candidate of its window, so one staged row of
+// kGenStage source positions covers the tile, and one node table in LDS
+// serves kGenThreads lanes.  The stage holds, per source position j', the
 // four quarter turns of x at j' on ring s and on its mirror, then the same at
 // j'bar: four float4 arrays of kGenStage entries.
 
@@ -408,25 +442,57 @@ __device__ __forceinline__ int wave_max(int v)
     return max(max(r0, r1), max(r2, r3));
 }
 
+// A wave-uniform value held in a vector register.  On gfx950 a VALU
+// instruction with a scalar-register operand issues at about 0.6x the rate of
+// one with vector operands only, and an FMA can read one scalar register at
+// most; copies made once, outside a loop, avoid both.
+__device__ __forceinline__ float vreg(float s)
+{
+    float v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+__device__ __forceinline__ int vreg(int s)
+{
+    int v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(s));
+    return v;
+}
+
 // u = theta / h from the squared chord.  For the short series the factor
 // 1/h is folded into the coefficients (u_coef = inv_h times those of
-// theta_of), which saves one multiply per pair.
+// theta_of), which saves one multiply per pair; `lead` is the highest
+// coefficient, in a vector register.
+struct UCoef {
+    float c[6];     // u_coef in vector registers
+    float inv_h;
+};
+
 template <int AM>
-__device__ __forceinline__ float node_coord(float d2, const DevPlanView &P)
+__device__ __forceinline__ UCoef ucoef(const DevPlanView &P)
 {
-    if (AM == 2) return theta_of<2>(d2) * P.inv_h;
+    UCoef u;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) u.c[k] = (AM == 1 || k < 3) ? vreg(P.u_coef[k]) : 0.0f;
+    u.inv_h = vreg(P.inv_h);
+    return u;
+}
+
+template <int AM>
+__device__ __forceinline__ float node_coord(float d2, const UCoef &uc)
+{
+    if (AM == 2) return theta_of<2>(d2) * uc.inv_h;
     const float d = __builtin_amdgcn_sqrtf(d2);
     float p;
     if (AM == 1) {
-        p = P.u_coef[5];
-        p = fmaf(p, d2, P.u_coef[4]);
-        p = fmaf(p, d2, P.u_coef[3]);
-        p = fmaf(p, d2, P.u_coef[2]);
+        p = fmaf(uc.c[5], d2, uc.c[4]);
+        p = fmaf(p, d2, uc.c[3]);
+        p = fmaf(p, d2, uc.c[2]);
     } else {
-        p = P.u_coef[2];
+        p = uc.c[2];
     }
-    p = fmaf(p, d2, P.u_coef[1]);
-    p = fmaf(p, d2, P.u_coef[0]);
+    p = fmaf(p, d2, uc.c[1]);
+    p = fmaf(p, d2, uc.c[0]);
     return d * p;
 }
 
@@ -466,31 +532,40 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
 // T candidates jq0, jq0 + 2, ... of one lane in the staged chunk; those past
 // a1 get the table's zero slot.  The loop count is wave-uniform, so the
 // compiler can overlap consecutive candidates.
-template <bool LONG, int AM>
+template <bool LONG, int AM, int STEP>
 __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const DevPlanView &P,
                                                  const float *tab, int m, int dm,
                                                  const float4 *stage, int c0, int cn, int jq,
                                                  int a1, int T, float row[16])
 {
-    const float zslot = (float)P.ntab;
+    // every uniform operand of the loop in a vector register
+    const float zslot = vreg((float)P.ntab);
+    const float A = vreg(pp.A);
+    const float B = vreg(pp.B);
+    const float xscale = vreg(pp.xscale);
+    const float u_max = vreg(P.u_max);
+    const UCoef ucf = ucoef<AM>(P);
+    const int last = vreg(cn - 1 + c0);
+    const int dmv = vreg(dm);
+    const float4 *st = stage - c0;                           // indexed by jq >= c0
 #pragma unroll 2
     for (int t = 0; t < T; ++t) {
         const bool valid = jq <= a1;
-        const int pos = min(max(jq - c0, 0), cn - 1);
-        const float x = (float)m * pp.xscale;              // half the longitude difference
+        const int pos = min(jq, last);
+        const float x = (float)m * xscale;                 // half the longitude difference
         const float sx = sin_series<LONG>(x);
-        const float d2 = fmaf(pp.B, sx * sx, pp.A);          // squared chord
-        const float u = node_coord<AM>(d2, P);
-        const float uc = (valid && u < P.u_max) ? u : zslot;
+        const float d2 = fmaf(B, sx * sx, A);                // squared chord
+        const float u = node_coord<AM>(d2, ucf);
+        const float uc = (valid && u < u_max) ? u : zslot;
         const int node = (int)uc;
-        const float frac = uc - (float)node;
+        const float frac = __builtin_amdgcn_fractf(uc);
         const float k0 = tab[node];
         const float k1 = tab[node + 1];
         const float w = fmaf(frac, k1 - k0, k0);
-        const float4 v0 = stage[pos];
-        const float4 v1 = stage[kGenStage + pos];
-        const float4 v2 = stage[2 * kGenStage + pos];
-        const float4 v3 = stage[3 * kGenStage + pos];
+        const float4 v0 = st[pos];
+        const float4 v1 = st[kGenStage + pos];
+        const float4 v2 = st[2 * kGenStage + pos];
+        const float4 v3 = st[3 * kGenStage + pos];
         row[0] = fmaf(w, v0.x, row[0]);
         row[1] = fmaf(w, v0.y, row[1]);
         row[2] = fmaf(w, v0.z, row[2]);
@@ -507,8 +582,8 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const DevPla
         row[13] = fmaf(w, v3.y, row[13]);
         row[14] = fmaf(w, v3.z, row[14]);
         row[15] = fmaf(w, v3.w, row[15]);
-        jq += 2;
-        m -= dm;
+        jq += STEP;
+        m -= dmv;
     }
 }
 
@@ -552,18 +627,17 @@ constexpr int kGenFlush = 48;
 // segment) x maps.  LDS: the node table of the current plan followed by two
 // zero entries (the slot of candidates outside the disc), then the stage.
 // The loads of the next chunk are in flight while the current one is used.
-__global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restrict__ views,
-                                                      const int2 *__restrict__ tile_map,
-                                                      int ntiles, MapIO io, int nmaps,
-                                                      int tab_floats, unsigned int *counter)
+__global__ __launch_bounds__(kGenThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ tile_map,
+               int ntiles, MapIO io, int nmaps, int tab_floats, unsigned int *counter)
 {
     extern __shared__ __align__(16) float lds[];
     float *tab = lds;
     float4 *stage = reinterpret_cast<float4 *>(lds + tab_floats);
     __shared__ int s_item;
     const int nitems = ntiles * nmaps;
-    const int ph = threadIdx.x & 1;
-    const int lane_pix = threadIdx.x >> 1;
+    const int ph = threadIdx.x % kGenPhases;
+    const int lane_pix = threadIdx.x / kGenPhases;
     int cur = -1;
     for (;;) {
         const int item = next_item(counter, &s_item);
@@ -629,25 +703,26 @@ __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restr
                 prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
                            Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
             }
-            // this lane's candidates inside the chunk: a0 + ph, a0 + ph + 2, ...
+            // this lane's candidates inside the chunk: a0 + ph, a0 + ph + kGenPhases, ...
             int lo, hi;
             pair_window(pp, S.n, j, lo, hi);
             const int a0 = max(lo, ch.c0);
             const int a1 = min(hi, ch.c0 + ch.cn - 1);
-            const int mine = max(0, (a1 - a0 + 2 - ph) >> 1);
+            const int mine = a1 - a0 - ph >= 0 ? (a1 - a0 - ph) / kGenPhases + 1 : 0;
             const int nt = wave_max(mine);
             const int jq0 = a0 + ph;
             const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
             const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
-            const int dm = 4 * R.n;
+            const int dm = 2 * kGenPhases * R.n;
             const bool lg = (pp.mode & kPairLongSin) != 0;
+            constexpr int K = kGenPhases;
             switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                case 0: gen_candidates16<false, 0>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 1: gen_candidates16<true, 0>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 2: gen_candidates16<false, 1>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 3: gen_candidates16<true, 1>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 4: gen_candidates16<false, 2>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                default: gen_candidates16<true, 2>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 0: gen_candidates16<false, 0, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 1: gen_candidates16<true, 0, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 2: gen_candidates16<false, 1, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 3: gen_candidates16<true, 1, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 4: gen_candidates16<false, 2, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                default: gen_candidates16<true, 2, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
             }
             since += nt;
             if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
@@ -663,7 +738,9 @@ __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restr
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
             acc[q] += (double)row[q];
-            acc[q] += __shfl_xor(acc[q], 1);   // the two lanes of a pixel
+#pragma unroll
+            for (int x = 1; x < kGenPhases; x <<= 1)
+                acc[q] += __shfl_xor(acc[q], x);   // the lanes of a pixel, same order in each
         }
         if (active) {
             float *out = io.out[pi] + (size_t)map * P.npix;
@@ -676,7 +753,7 @@ __global__ __launch_bounds__(kThreads) void k_general(const DevPlanView *__restr
 #pragma unroll
                     for (int q = 0; q < 4; ++q) om[j + q * qr] = (float)acc[4 + q];
                 }
-            } else {
+            } else if (ph == 1) {
                 const int jb = qr - R.two_o - j;   // reflected pixel; j itself at a fixed point
                 if (jb != j && jb != qr) {
 #pragma unroll
@@ -916,17 +993,24 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
             // stage x: row r, sub-segment q, strip position p holds
             // x_s[j0 + q kKnotSub + k_lo + p] for the positions its units read
             // (-n < k_lo and k_lo + ntaps + 2 < n/2 + 4, so wrap3 applies)
-            for (int rr = 0; rr < nrows; ++rr) {
+            // Each wave stages whole rows; q = e / strip by a float reciprocal,
+            // exact here: e < 2^11, and (e + 1/2) / strip stays at least
+            // 1 / (2 strip) > 2^-10 away from an integer.
+            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+            for (int rr = wave; rr < nrows; rr += kThreads / 64) {
                 const DevRow W = cst(P.rows)[rb + rr];
                 const int nt4 = (W.ntaps + 3) & ~3;
                 const int strip = knot_strip(nt4);
+                const float inv_strip = 1.0f / (float)strip;
                 const float *src = in + cst(P.rings)[W.s].first;
                 float *dst = xs + s_xoff[rr];
-                for (int e = threadIdx.x; e < nsub * strip; e += blockDim.x) {
-                    const int q = e / strip;
+                const int base = T.j0 + W.k_lo;
+#pragma unroll 4
+                for (int e = lane; e < nsub * strip; e += 64) {
+                    const int q = (int)(((float)e + 0.5f) * inv_strip);
                     const int p = e - q * strip;
                     const int used = min(kKnotSub, T.len - q * kKnotSub) + nt4 - 1;
-                    dst[e] = p < used ? src[wrap3(T.j0 + q * kKnotSub + W.k_lo + p, n)] : 0.0f;
+                    dst[e] = p < used ? src[wrap3(base + q * kKnotSub + p, n)] : 0.0f;
                 }
             }
             __syncthreads();
@@ -1140,15 +1224,28 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
     double *dst = partials + ((size_t)P.nkpart_circ + blockIdx.x) * P.ntab;
     for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) dst[i] = hist[i];
 }
-// Fixed-order reduction of the per-workgroup partials, scaled by Omega.
-__global__ void k_knot_reduce(const double *__restrict__ partials, int nblocks, int ntab,
-                              double omega, float *__restrict__ gk)
+// Fixed-order reduction of the per-workgroup partials, scaled by Omega: a
+// block of kReduceWaves waves covers 64 knots, wave w sums rows w, w + kReduceWaves, ...,
+// and the wave sums are added in wave order.
+constexpr int kReduceWaves = 16;
+__global__ __launch_bounds__(64 * kReduceWaves) void k_knot_reduce(
+    const double *__restrict__ partials, int nblocks, int ntab, double omega,
+    float *__restrict__ gk)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= ntab) return;
+    __shared__ double red[kReduceWaves][64];
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int k = blockIdx.x * 64 + lane;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partials[(size_t)b * ntab + k];
-    gk[k] = (float)(omega * s);
+    if (k < ntab)
+        for (int b = w; b < nblocks; b += kReduceWaves) s += partials[(size_t)b * ntab + k];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && k < ntab) {
+        double t = 0.0;
+        for (int i = 0; i < kReduceWaves; ++i) t += red[i][lane];
+        gk[k] = (float)(omega * t);
+    }
 }
 
 // ---------------------------------------------------------------- launch --
@@ -1169,20 +1266,24 @@ int device_lds_limit(int device, size_t *bytes)
 
 // Resident workgroups per CU for a kernel with `lds` bytes of dynamic LDS.
 template <class K>
-static int occupancy(K kernel, size_t lds, int *per_cu)
+static int occupancy(K kernel, size_t lds, int *per_cu, int threads = kThreads)
 {
     ARKCOS_HIP_CHECK(hipFuncSetAttribute((const void *)kernel,
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    ARKCOS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, kThreads, lds));
+    ARKCOS_HIP_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, kernel, threads, lds));
     if (*per_cu < 1)
         return fail(ARKCOS_EUNSUPPORTED, "kernel cannot be resident with " +
                                              std::to_string(lds) + " bytes of LDS");
     return ARKCOS_OK;
 }
 
-// Two row buffers of kStageRegs * kThreads floats each.
+// Two row buffers of kStageRegs * kThreads floats each, then two weight
+// buffers of kCircMaxTaps * kGroupRings floats.
 static int circ_buf_floats() { return kStageRegs * kThreads; }
-static size_t circ_lds() { return (size_t)2 * circ_buf_floats() * sizeof(float); }
+static size_t circ_lds()
+{
+    return (size_t)2 * (circ_buf_floats() + kCircMaxTaps * kGroupRings) * sizeof(float);
+}
 // Node table plus its two zero entries, rounded up to 16 bytes, then four
 // float4 arrays of kGenStage staged positions.
 static int gen_tab_floats(int ntab) { return (ntab + 2 + 3) & ~3; }
@@ -1211,7 +1312,7 @@ int prepare_launches(Plan &p)
                                            p.device));
     int rc;
     if ((rc = occupancy(k_circ, circ_lds(), &p.occ_circ))) return rc;
-    if ((rc = occupancy(k_general, gen_lds(p.desc.ntab), &p.occ_gen))) return rc;
+    if ((rc = occupancy(k_general, gen_lds(p.desc.ntab), &p.occ_gen, kGenThreads))) return rc;
     p.grid_kc = p.grid_kg = 0;
     if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
         if ((rc = occupancy(k_knot_circ, knot_circ_lds(p.desc.ntab), &p.occ_kc))) return rc;
@@ -1230,7 +1331,7 @@ int prepare_batch(Batch &b)
                                            b.device));
     int occ_c = 0, occ_g = 0, rc;
     if ((rc = occupancy(k_circ, circ_lds(), &occ_c))) return rc;
-    if ((rc = occupancy(k_general, gen_lds(b.max_ntab), &occ_g))) return rc;
+    if ((rc = occupancy(k_general, gen_lds(b.max_ntab), &occ_g, kGenThreads))) return rc;
     b.grid_circ = std::max(1, std::min((int)b.cmap.size(), occ_c * b.cus));
     b.grid_gen = std::max(1, std::min((int)b.gmap.size(), occ_g * b.cus));
     return ARKCOS_OK;
@@ -1272,7 +1373,7 @@ int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipSt
     }
     if (ngt > 0) {
         const int grid = std::max(1, std::min(ngt * nbatch, p.occ_gen * p.cus));
-        hipLaunchKernelGGL(k_general, dim3(grid), dim3(kThreads), gen_lds(p.desc.ntab), s,
+        hipLaunchKernelGGL(k_general, dim3(grid), dim3(kGenThreads), gen_lds(p.desc.ntab), s,
                            (const DevPlanView *)p.d_view, (const int2 *)nullptr, ngt, io, nbatch,
                            gen_tab_floats(p.desc.ntab), p.d_counter + 1);
     }
@@ -1305,8 +1406,8 @@ static int launch_knot(const Plan &p, const float *g, const float *x, float *gk,
                            (const DevPlanView *)p.d_view, g, x, nbatch, p.d_counter + 3,
                            p.d_kpart);
     ARKCOS_HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 255) / 256), dim3(256), 0, s, p.d_kpart,
-                       p.grid_kc + p.grid_kg, ntab, p.omega, gk);
+    hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 63) / 64), dim3(64 * kReduceWaves), 0, s,
+                       p.d_kpart, p.grid_kc + p.grid_kg, ntab, p.omega, gk);
     ARKCOS_HIP_CHECK(hipGetLastError());
     return ARKCOS_OK;
 }
@@ -1339,7 +1440,7 @@ int launch_batch(const Batch &b, const float *const *in, float *const *out, hipS
                            (const DevPlanView *)b.d_views, (const int2 *)b.d_cmap,
                            (int)b.cmap.size(), io, 1, circ_buf_floats(), b.d_counter);
     if (!b.gmap.empty() && (parts & ARKCOS_PART_GENERAL))
-        hipLaunchKernelGGL(k_general, dim3(b.grid_gen), dim3(kThreads), gen_lds(b.max_ntab), s,
+        hipLaunchKernelGGL(k_general, dim3(b.grid_gen), dim3(kGenThreads), gen_lds(b.max_ntab), s,
                            (const DevPlanView *)b.d_views, (const int2 *)b.d_gmap,
                            (int)b.gmap.size(), io, 1, gen_tab_floats(b.max_ntab), b.d_counter + 1);
     ARKCOS_HIP_CHECK(hipGetLastError());
