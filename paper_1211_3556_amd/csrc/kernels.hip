@@ -421,10 +421,10 @@ __device__ __forceinline__ void prefetch_chunk(const float *src, const float *sr
 // (jbar, j'bar) with the opposite longitude difference: the same weight.
 // Together with the four quarter turns and the N-S mirror one weight serves
 // sixteen pairs.  A general tile holds up to kGenLanes pixels j <= jbar of the
-// first quadrant of a northern ring; kGenPhases lanes share each pixel and
-// take every kGenPhases-th candidate of its window, so one staged row of
-// kGenStage source positions covers the tile, and one node table in LDS
-// serves kGenThreads lanes.  The stage holds, per source position j', the
+// first quadrant of a northern ring; kGenPhases lanes (more in a shorter
+// tile, up to one wave) share each pixel and take every kGenPhases-th
+// candidate of its window, so one staged row of kGenStage source positions
+// covers the tile, and one node table in LDS serves kGenThreads lanes.  The stage holds, per source position j', the
 // four quarter turns of x at j' on ring s and on its mirror, then the same at
 // j'bar: four float4 arrays of kGenStage entries.
 
@@ -532,9 +532,9 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
 // T candidates jq0, jq0 + 2, ... of one lane in the staged chunk; those past
 // a1 get the table's zero slot.  The loop count is wave-uniform, so the
 // compiler can overlap consecutive candidates.
-template <bool LONG, int AM, int STEP>
+template <bool LONG, int AM>
 __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const DevPlanView &P,
-                                                 const float *tab, int m, int dm,
+                                                 const float *tab, int m, int dm, int step,
                                                  const float4 *stage, int c0, int cn, int jq,
                                                  int a1, int T, float row[16])
 {
@@ -547,6 +547,7 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const DevPla
     const UCoef ucf = ucoef<AM>(P);
     const int last = vreg(cn - 1 + c0);
     const int dmv = vreg(dm);
+    const int stepv = vreg(step);
     const float4 *st = stage - c0;                           // indexed by jq >= c0
 #pragma unroll 2
     for (int t = 0; t < T; ++t) {
@@ -582,7 +583,7 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const DevPla
         row[13] = fmaf(w, v3.y, row[13]);
         row[14] = fmaf(w, v3.z, row[14]);
         row[15] = fmaf(w, v3.w, row[15]);
-        jq += STEP;
+        jq += stepv;
         m -= dmv;
     }
 }
@@ -636,8 +637,6 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
     float4 *stage = reinterpret_cast<float4 *>(lds + tab_floats);
     __shared__ int s_item;
     const int nitems = ntiles * nmaps;
-    const int ph = threadIdx.x % kGenPhases;
-    const int lane_pix = threadIdx.x / kGenPhases;
     int cur = -1;
     for (;;) {
         const int item = next_item(counter, &s_item);
@@ -658,6 +657,13 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
         const bool mirror = rs != rn;
         const DevRing R = cst(P.rings)[rn];
         const int qr = R.n >> 2;
+        // 2^lp lanes per pixel: kGenPhases for a full tile, more (up to a
+        // wave) for a shorter one, so that every lane works
+        int lp = 2;
+        while (lp < 6 && (kGenThreads >> (lp + 1)) >= T.len) ++lp;
+        const int nph = 1 << lp;
+        const int ph = threadIdx.x & (nph - 1);
+        const int lane_pix = threadIdx.x >> lp;
         const bool active = lane_pix < T.len;
         const int j = T.j0 + min(lane_pix, T.len - 1);
         const float *in = io.in[pi] + (size_t)map * P.npix;
@@ -703,26 +709,25 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
                 prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
                            Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
             }
-            // this lane's candidates inside the chunk: a0 + ph, a0 + ph + kGenPhases, ...
+            // this lane's candidates inside the chunk: a0 + ph, a0 + ph + nph, ...
             int lo, hi;
             pair_window(pp, S.n, j, lo, hi);
             const int a0 = max(lo, ch.c0);
             const int a1 = min(hi, ch.c0 + ch.cn - 1);
-            const int mine = a1 - a0 - ph >= 0 ? (a1 - a0 - ph) / kGenPhases + 1 : 0;
+            const int mine = a1 - a0 - ph >= 0 ? ((a1 - a0 - ph) >> lp) + 1 : 0;
             const int nt = wave_max(mine);
             const int jq0 = a0 + ph;
             const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
             const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
-            const int dm = 2 * kGenPhases * R.n;
+            const int dm = 2 * nph * R.n;
             const bool lg = (pp.mode & kPairLongSin) != 0;
-            constexpr int K = kGenPhases;
             switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                case 0: gen_candidates16<false, 0, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 1: gen_candidates16<true, 0, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 2: gen_candidates16<false, 1, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 3: gen_candidates16<true, 1, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 4: gen_candidates16<false, 2, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                default: gen_candidates16<true, 2, K>(pp, P, tab, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 0: gen_candidates16<false, 0>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 1: gen_candidates16<true, 0>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 2: gen_candidates16<false, 1>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 3: gen_candidates16<true, 1>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                case 4: gen_candidates16<false, 2>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
+                default: gen_candidates16<true, 2>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
             }
             since += nt;
             if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
@@ -736,11 +741,10 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
             ch = nx;
         }
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            acc[q] += (double)row[q];
+        for (int q = 0; q < 16; ++q) acc[q] += (double)row[q];
+        for (int x = 1; x < nph; x <<= 1) {       // the lanes of a pixel, same order in each
 #pragma unroll
-            for (int x = 1; x < kGenPhases; x <<= 1)
-                acc[q] += __shfl_xor(acc[q], x);   // the lanes of a pixel, same order in each
+            for (int q = 0; q < 16; ++q) acc[q] += __shfl_xor(acc[q], x);
         }
         if (active) {
             float *out = io.out[pi] + (size_t)map * P.npix;
