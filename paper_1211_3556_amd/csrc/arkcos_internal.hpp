@@ -75,8 +75,9 @@ struct DevTile {
     int r;
     int j0;
     int len;
-    int pad;
+    int flags;     // general tiles: kTileLongSin if any source row needs the long sine
 };
+constexpr int kTileLongSin = 1;
 
 // Rings per group and outputs per lane of the circulant kernel; pixels per
 // general tile and source positions one pass of the general kernel stages;

@@ -431,10 +431,12 @@ __device__ __forceinline__ void prefetch_chunk(const float *src, const float *sr
 // Largest value of `v` over the wave (wave-uniform result).
 __device__ __forceinline__ int wave_max(int v)
 {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false));  // row_half_mirror
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false));  // row_mirror
+    // every lane is active and every source lane exists, so each DPP move
+    // folds into the max that uses it
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true));  // row_half_mirror
+    v = max(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, true));  // row_mirror
     const int r0 = __builtin_amdgcn_readlane(v, 0);
     const int r1 = __builtin_amdgcn_readlane(v, 16);
     const int r2 = __builtin_amdgcn_readlane(v, 32);
@@ -498,53 +500,73 @@ __device__ __forceinline__ float node_coord(float d2, const UCoef &uc)
 
 // One staged position per thread: source position c0 + e of ring s and its
 // reflection, four quarter turns each, on ring s (a, c) and its mirror (b, d).
+// Threads at or past cn load nothing: positions past the chunk are never
+// read.  Loads address their ring by 32-bit byte offsets shared between a
+// ring and its mirror (the ring's base stays in scalar registers).
+__device__ __forceinline__ float ld_off(const float *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, bool mirror,
                                            int n_s, int two_o_s, int c0, int cn, float4 &a,
                                            float4 &b, float4 &c, float4 &d)
 {
     const int e = threadIdx.x;
-    a = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    b = a;
-    c = a;
-    d = a;
     if (e >= cn) return;
     const int qs = n_s >> 2;
     int jd = c0 + e;                       // -n_s < jd < 2 n_s
     jd = jd < 0 ? jd + n_s : (jd >= n_s ? jd - n_s : jd);
     int jr = qs - two_o_s - jd;           // -n_s < jr < n_s
     jr = jr < 0 ? jr + n_s : jr;
-    int id[4], ir[4];
+    unsigned od[4], orf[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        id[k] = jd + k * qs;
-        id[k] = id[k] >= n_s ? id[k] - n_s : id[k];
-        ir[k] = jr + k * qs;
-        ir[k] = ir[k] >= n_s ? ir[k] - n_s : ir[k];
+        int i = jd + k * qs;
+        od[k] = 4u * (unsigned)(i >= n_s ? i - n_s : i);
+        i = jr + k * qs;
+        orf[k] = 4u * (unsigned)(i >= n_s ? i - n_s : i);
     }
-    a = make_float4(src[id[0]], src[id[1]], src[id[2]], src[id[3]]);
-    c = make_float4(src[ir[0]], src[ir[1]], src[ir[2]], src[ir[3]]);
+    a = make_float4(ld_off(src, od[0]), ld_off(src, od[1]), ld_off(src, od[2]), ld_off(src, od[3]));
+    c = make_float4(ld_off(src, orf[0]), ld_off(src, orf[1]), ld_off(src, orf[2]),
+                    ld_off(src, orf[3]));
     if (mirror) {
-        b = make_float4(srcm[id[0]], srcm[id[1]], srcm[id[2]], srcm[id[3]]);
-        d = make_float4(srcm[ir[0]], srcm[ir[1]], srcm[ir[2]], srcm[ir[3]]);
+        b = make_float4(ld_off(srcm, od[0]), ld_off(srcm, od[1]), ld_off(srcm, od[2]),
+                        ld_off(srcm, od[3]));
+        d = make_float4(ld_off(srcm, orf[0]), ld_off(srcm, orf[1]), ld_off(srcm, orf[2]),
+                        ld_off(srcm, orf[3]));
+    } else {   // the equator ring is its own mirror: its south images are unused
+        b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        d = b;
     }
 }
 
 // T candidates jq0, jq0 + 2, ... of one lane in the staged chunk; those past
 // a1 get the table's zero slot.  The loop count is wave-uniform, so the
 // compiler can overlap consecutive candidates.
+// Plan constants of the candidate loop, in vector registers.
+template <int AM>
+struct GenConst {
+    float zslot;     // index of the table's zero entries
+    float u_max;
+    UCoef ucf;
+    __device__ __forceinline__ GenConst(const DevPlanView &P)
+        : zslot(vreg((float)P.ntab)), u_max(vreg(P.u_max)), ucf(ucoef<AM>(P)) {}
+};
+
 template <bool LONG, int AM>
-__device__ __forceinline__ void gen_candidates16(const DevPair &pp, const DevPlanView &P,
+__device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenConst<AM> &gc,
                                                  const float *tab, int m, int dm, int step,
                                                  const float4 *stage, int c0, int cn, int jq,
                                                  int a1, int T, float row[16])
 {
     // every uniform operand of the loop in a vector register
-    const float zslot = vreg((float)P.ntab);
+    const float zslot = gc.zslot;
     const float A = vreg(pp.A);
     const float B = vreg(pp.B);
     const float xscale = vreg(pp.xscale);
-    const float u_max = vreg(P.u_max);
-    const UCoef ucf = ucoef<AM>(P);
+    const float u_max = gc.u_max;
+    const UCoef &ucf = gc.ucf;
     const int last = vreg(cn - 1 + c0);
     const int dmv = vreg(dm);
     const int stepv = vreg(step);
@@ -624,6 +646,125 @@ __device__ __forceinline__ GenStage next_stage(const DevPlanView &P, const DevRi
 // accumulated at least this many candidates since the last move.
 constexpr int kGenFlush = 48;
 
+// One general tile: its source rows in staged chunks, the candidates of each
+// lane, the sum over the lanes of a pixel and the sixteen output images.
+// LONG and AM are fixed per tile, so the candidate loop has one form and the
+// row sums stay in place across rows.
+template <bool LONG, int AM>
+__device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab, float4 *stage,
+                                         const DevTile &T, const float *in, float *out)
+{
+    const int rn = T.r;
+    const int rs = P.nrings - 1 - rn;           // mirror ring
+    const bool mirror = rs != rn;
+    const DevRing R = cst(P.rings)[rn];
+    const int qr = R.n >> 2;
+    // 2^lp lanes per pixel: kGenPhases for a full tile, more (up to a
+    // wave) for a shorter one, so that every lane works
+    int lp = 2;
+    while (lp < 6 && (kGenThreads >> (lp + 1)) >= T.len) ++lp;
+    const int nph = 1 << lp;
+    const int ph = threadIdx.x & (nph - 1);
+    const int lane_pix = threadIdx.x >> lp;
+    const bool active = lane_pix < T.len;
+    const int j = T.j0 + min(lane_pix, T.len - 1);
+    const GenConst<AM> gc(P);
+
+    GenStage ch;
+    ch.k = R.pair_begin;
+    {
+        const DevPair pp = cst(P.pairs)[ch.k];
+        int hi_max;
+        tile_window(pp, cst(P.rings)[pp.s].n, T, ch.c0, hi_max);
+        ch.cn = min(kGenStage, hi_max - ch.c0 + 1);
+    }
+    float4 pa, pb, pc, pd;
+    {
+        const DevPair pp = cst(P.pairs)[ch.k];
+        const DevRing S = cst(P.rings)[pp.s];
+        prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, mirror, S.n,
+                   S.two_o, ch.c0, ch.cn, pa, pb, pc, pd);
+    }
+    double acc[16];
+    float row[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        acc[q] = 0.0;
+        row[q] = 0.0f;
+    }
+    int since = 0;
+    while (ch.k < R.pair_end) {
+        __syncthreads();      // the previous chunk is no longer read
+        if ((int)threadIdx.x < ch.cn) {
+            stage[threadIdx.x] = pa;
+            stage[kGenStage + threadIdx.x] = pb;
+            stage[2 * kGenStage + threadIdx.x] = pc;
+            stage[3 * kGenStage + threadIdx.x] = pd;
+        }
+        __syncthreads();
+        const DevPair pp = cst(P.pairs)[ch.k];
+        const DevRing S = cst(P.rings)[pp.s];
+        const GenStage nx = next_stage(P, R, T, ch);
+        if (nx.k < R.pair_end) {
+            const DevPair pn = cst(P.pairs)[nx.k];
+            const DevRing Sn = cst(P.rings)[pn.s];
+            prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
+                       Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
+        }
+        // this lane's candidates inside the chunk: a0 + ph, a0 + ph + nph, ...
+        int lo, hi;
+        pair_window(pp, S.n, j, lo, hi);
+        const int a0 = max(lo, ch.c0);
+        const int a1 = min(hi, ch.c0 + ch.cn - 1);
+        const int mine = a1 - a0 - ph >= 0 ? ((a1 - a0 - ph) >> lp) + 1 : 0;
+        const int nt = wave_max(mine);
+        const int jq0 = a0 + ph;
+        const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+        const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
+        const int dm = 2 * nph * R.n;
+        gen_candidates16<LONG, AM>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt,
+                                   row);
+        since += nt;
+        if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                acc[q] += (double)row[q];
+                row[q] = 0.0f;
+            }
+            since = 0;
+        }
+        ch = nx;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] += (double)row[q];
+    for (int x = 1; x < nph; x <<= 1) {       // the lanes of a pixel, same order in each
+#pragma unroll
+        for (int q = 0; q < 16; ++q) acc[q] += __shfl_xor(acc[q], x);
+    }
+    if (active) {
+        float *o = out + R.first;
+        float *om = out + cst(P.rings)[rs].first;
+        if (ph == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[j + q * qr] = (float)acc[q];
+            if (mirror) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) om[j + q * qr] = (float)acc[4 + q];
+            }
+        } else if (ph == 1) {
+            const int jb = qr - R.two_o - j;   // reflected pixel; j itself at a fixed point
+            if (jb != j && jb != qr) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o[jb + q * qr] = (float)acc[8 + q];
+                if (mirror) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) om[jb + q * qr] = (float)acc[12 + q];
+                }
+            }
+        }
+    }
+}
+
 // Persistent general gather over tiles (plan, north ring, half-quadrant
 // segment) x maps.  LDS: the node table of the current plan followed by two
 // zero entries (the slot of candidates outside the disc), then the stage.
@@ -652,126 +793,19 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
             cur = pi;
         }
         const DevTile T = cst(P.gtiles)[lt];
-        const int rn = T.r;
-        const int rs = P.nrings - 1 - rn;           // mirror ring
-        const bool mirror = rs != rn;
-        const DevRing R = cst(P.rings)[rn];
-        const int qr = R.n >> 2;
-        // 2^lp lanes per pixel: kGenPhases for a full tile, more (up to a
-        // wave) for a shorter one, so that every lane works
-        int lp = 2;
-        while (lp < 6 && (kGenThreads >> (lp + 1)) >= T.len) ++lp;
-        const int nph = 1 << lp;
-        const int ph = threadIdx.x & (nph - 1);
-        const int lane_pix = threadIdx.x >> lp;
-        const bool active = lane_pix < T.len;
-        const int j = T.j0 + min(lane_pix, T.len - 1);
         const float *in = io.in[pi] + (size_t)map * P.npix;
-
-        GenStage ch;
-        ch.k = R.pair_begin;
-        {
-            const DevPair pp = cst(P.pairs)[ch.k];
-            int hi_max;
-            tile_window(pp, cst(P.rings)[pp.s].n, T, ch.c0, hi_max);
-            ch.cn = min(kGenStage, hi_max - ch.c0 + 1);
-        }
-        float4 pa, pb, pc, pd;
-        {
-            const DevPair pp = cst(P.pairs)[ch.k];
-            const DevRing S = cst(P.rings)[pp.s];
-            prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, mirror, S.n,
-                       S.two_o, ch.c0, ch.cn, pa, pb, pc, pd);
-        }
-        double acc[16];
-        float row[16];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            acc[q] = 0.0;
-            row[q] = 0.0f;
-        }
-        int since = 0;
-        while (ch.k < R.pair_end) {
-            __syncthreads();      // the previous chunk is no longer read
-            if (threadIdx.x < kGenStage) {
-                stage[threadIdx.x] = pa;
-                stage[kGenStage + threadIdx.x] = pb;
-                stage[2 * kGenStage + threadIdx.x] = pc;
-                stage[3 * kGenStage + threadIdx.x] = pd;
-            }
-            __syncthreads();
-            const DevPair pp = cst(P.pairs)[ch.k];
-            const DevRing S = cst(P.rings)[pp.s];
-            const GenStage nx = next_stage(P, R, T, ch);
-            if (nx.k < R.pair_end) {
-                const DevPair pn = cst(P.pairs)[nx.k];
-                const DevRing Sn = cst(P.rings)[pn.s];
-                prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
-                           Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
-            }
-            // this lane's candidates inside the chunk: a0 + ph, a0 + ph + nph, ...
-            int lo, hi;
-            pair_window(pp, S.n, j, lo, hi);
-            const int a0 = max(lo, ch.c0);
-            const int a1 = min(hi, ch.c0 + ch.cn - 1);
-            const int mine = a1 - a0 - ph >= 0 ? ((a1 - a0 - ph) >> lp) + 1 : 0;
-            const int nt = wave_max(mine);
-            const int jq0 = a0 + ph;
-            const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
-            const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
-            const int dm = 2 * nph * R.n;
-            const bool lg = (pp.mode & kPairLongSin) != 0;
-            switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                case 0: gen_candidates16<false, 0>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 1: gen_candidates16<true, 0>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 2: gen_candidates16<false, 1>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 3: gen_candidates16<true, 1>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                case 4: gen_candidates16<false, 2>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-                default: gen_candidates16<true, 2>(pp, P, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt, row); break;
-            }
-            since += nt;
-            if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
-#pragma unroll
-                for (int q = 0; q < 16; ++q) {
-                    acc[q] += (double)row[q];
-                    row[q] = 0.0f;
-                }
-                since = 0;
-            }
-            ch = nx;
-        }
-#pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += (double)row[q];
-        for (int x = 1; x < nph; x <<= 1) {       // the lanes of a pixel, same order in each
-#pragma unroll
-            for (int q = 0; q < 16; ++q) acc[q] += __shfl_xor(acc[q], x);
-        }
-        if (active) {
-            float *out = io.out[pi] + (size_t)map * P.npix;
-            float *o = out + R.first;
-            float *om = out + cst(P.rings)[rs].first;
-            if (ph == 0) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) o[j + q * qr] = (float)acc[q];
-                if (mirror) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) om[j + q * qr] = (float)acc[4 + q];
-                }
-            } else if (ph == 1) {
-                const int jb = qr - R.two_o - j;   // reflected pixel; j itself at a fixed point
-                if (jb != j && jb != qr) {
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) o[jb + q * qr] = (float)acc[8 + q];
-                    if (mirror) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q) om[jb + q * qr] = (float)acc[12 + q];
-                    }
-                }
-            }
+        float *out = io.out[pi] + (size_t)map * P.npix;
+        const bool lg = (T.flags & kTileLongSin) != 0;
+        switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+            case 0: gen_tile<false, 0>(P, tab, stage, T, in, out); break;
+            case 1: gen_tile<true, 0>(P, tab, stage, T, in, out); break;
+            case 2: gen_tile<false, 1>(P, tab, stage, T, in, out); break;
+            case 3: gen_tile<true, 1>(P, tab, stage, T, in, out); break;
+            case 4: gen_tile<false, 2>(P, tab, stage, T, in, out); break;
+            default: gen_tile<true, 2>(P, tab, stage, T, in, out); break;
         }
     }
 }
-
 
 __global__ void k_reset_counters(unsigned int *counter)
 {
@@ -1186,7 +1220,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
         }
         while (ch.k < R.pair_end) {
             __syncthreads();
-            if (threadIdx.x < kGenStage) {
+            if ((int)threadIdx.x < ch.cn) {
                 stage[threadIdx.x] = pa;
                 stage[kGenStage + threadIdx.x] = pb;
                 stage[2 * kGenStage + threadIdx.x] = pc;

@@ -309,11 +309,15 @@ static int build_plan(Plan &P)
         if (!general[r]) continue;
         const int quarter = P.rings[r].n / 4;
         const int lanes = (P.rings[r].two_o ? (quarter - 1) / 2 : quarter / 2) + 1;
+        int flags = 0;
+        for (int k = P.dev_rings[r].pair_begin; k < P.dev_rings[r].pair_end; ++k)
+            if (P.pairs[k].mode & kPairLongSin) flags |= kTileLongSin;
         for (int j0 = 0; j0 < lanes; j0 += kGenLanes) {
             DevTile t{};
             t.r = r;
             t.j0 = j0;
             t.len = std::min(kGenLanes, lanes - j0);
+            t.flags = flags;
             P.gtiles.push_back(t);
             cost.push_back(ring_cost[r] * t.len + 1.0);
         }
