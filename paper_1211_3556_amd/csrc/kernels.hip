@@ -10,9 +10,10 @@
 //    depends on j' - j only.  Each (r, s) has one weight row, evaluated once
 //    per node table by k_build_weights with exactly the per-pair arithmetic.
 //    The gather is then a correlation: a workgroup owns kGroupRings
-//    consecutive output rings and kCircSeg pixels of each, stages one source
-//    row at a time in LDS, and every LDS read feeds kGroupRings FMAs whose
-//    weights are wave-uniform scalar operands.
+//    consecutive output rings and kCircSeg pixels of each (4 consecutive
+//    pixels per lane), stages one source row and its weights at a time in
+//    LDS, and per quad of taps two float4 reads of the row and four broadcast
+//    reads of the weights feed 64 FMAs.
 //
 //  * k_general (polar caps and belt rings whose disc reaches a cap).  Weights
 //    are evaluated per pair from exact ring-pair constants: chord from
@@ -238,7 +239,8 @@ __global__ __launch_bounds__(kThreads) void k_build_weights(DevPlanView P)
 }
 
 // Source pixels each lane prefetches per row: a row spans at most
-// kCircSeg + kCircMaxTaps - 1 pixels.
+// kCircSeg + kCircMaxTaps - 1 pixels, and the reads of the last tap quad reach
+// kCircSeg + kCircMaxTaps - 1 as well (lane 255, taps padded to 256).
 constexpr int kStageRegs = (kCircSeg + kCircMaxTaps + kThreads - 1) / kThreads;
 // Weights each lane prefetches per row: kGroupRings per tap.
 constexpr int kWeightRegs = kCircMaxTaps * kGroupRings / kThreads;
@@ -275,7 +277,8 @@ constexpr int kCircFlush = 64;
 // buffers.  The weights of a tap are read from LDS by every lane at one
 // address (a broadcast), so the FMAs take all operands from vector registers:
 // an FMA with a scalar-register operand issues at about 0.6x the rate on
-// gfx950.
+// gfx950.  Lane l owns pixels 4l .. 4l+3 of the segment, so a quad of taps
+// needs 7 consecutive staged pixels, read as two aligned float4.
 __global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict__ views,
                                                    const int2 *__restrict__ tile_map,
                                                    int ntiles, MapIO io, int nmaps,
@@ -330,17 +333,23 @@ __global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict
                              T.len + W1.ntaps - 1, n, v);
                 prefetch_weights(P.wts + W1.w_off, W1.ntaps * kGroupRings, wv);
             }
+            // lane l owns pixels 4l .. 4l+3: taps t0 .. t0+3 need x[4l + t0 .. 4l + t0 + 6],
+            // two aligned float4 reads (rows are zero-padded to whole tap quads)
             const float4 *w4 = reinterpret_cast<const float4 *>(wb);
-            const float *x0 = xb + threadIdx.x;
-#pragma unroll 4
-            for (int t = 0; t < W.ntaps; ++t) {
-                const float4 wt = w4[t];
-                const float wr[kGroupRings] = {wt.x, wt.y, wt.z, wt.w};
+            const float4 *x4 = reinterpret_cast<const float4 *>(xb) + threadIdx.x;
+            for (int q = 0; q < W.ntaps; q += 4) {
+                const float4 xa = x4[q >> 2];
+                const float4 xc = x4[(q >> 2) + 1];
+                const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xc.x, xc.y, xc.z, xc.w};
 #pragma unroll
-                for (int i = 0; i < kCircPix; ++i) {
-                    const float x = x0[i * kThreads + t];
+                for (int tt = 0; tt < 4; ++tt) {
+                    const float4 wt = w4[q + tt];
+                    const float wr[kGroupRings] = {wt.x, wt.y, wt.z, wt.w};
 #pragma unroll
-                    for (int r = 0; r < kGroupRings; ++r) racc[r][i] = fmaf(wr[r], x, racc[r][i]);
+                    for (int i = 0; i < kCircPix; ++i)
+#pragma unroll
+                        for (int r = 0; r < kGroupRings; ++r)
+                            racc[r][i] = fmaf(wr[r], xv[i + tt], racc[r][i]);
                 }
             }
             since += W.ntaps;
@@ -357,14 +366,13 @@ __global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict
             buf ^= 1;
         }
         float *out = io.out[pi] + (size_t)map * P.npix;
+        if (4 * (int)threadIdx.x < T.len) {   // T.len is a multiple of 4
 #pragma unroll
-        for (int r = 0; r < kGroupRings; ++r) {
-            if (r >= G.nr) break;
-            float *o = out + cst(P.rings)[G.r0 + r].first + T.j0;
+            for (int r = 0; r < kGroupRings; ++r) {
+                if (r >= G.nr) break;
+                float *o = out + cst(P.rings)[G.r0 + r].first + T.j0 + 4 * threadIdx.x;
 #pragma unroll
-            for (int i = 0; i < kCircPix; ++i) {
-                const int jj = threadIdx.x + i * kThreads;
-                if (jj < T.len) o[jj] = (float)acc[r][i];
+                for (int i = 0; i < kCircPix; ++i) o[i] = (float)acc[r][i];
             }
         }
     }
