@@ -982,6 +982,19 @@ constexpr int kKnotSubs = kKnotSeg / kKnotSub;
 
 __device__ __forceinline__ int knot_strip(int ntaps4) { return (kKnotSub + ntaps4 - 1) | 1; }
 
+// Direct global -> LDS load of one float per active lane: lane l's value
+// lands at dst[l] (dst wave-uniform).  Nothing passes through registers, so
+// a wave can issue all its staging loads back to back and wait once.
+#if defined(__HIP_DEVICE_COMPILE__)
+__device__ __forceinline__ void load_to_lds(const float *src, float *dst)
+{
+    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
+                                     (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+}
+#else
+__device__ __forceinline__ void load_to_lds(const float *, float *) {}
+#endif
+
 __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__restrict__ views,
                                                         const float *__restrict__ g,
                                                         const float *__restrict__ x, int nmaps,
@@ -1009,41 +1022,66 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
         const float *in = x + (size_t)map * P.npix;
         const float *gm = g + (size_t)map * P.npix;
         const int nsub = (T.len + kKnotSub - 1) / kKnotSub;
-        // g of the group's rings over the tile (zero past the last ring)
-        for (int e = threadIdx.x; e < T.len; e += blockDim.x) {
-            float v[kGroupRings];
+        // g of the group's rings over the tile: sub-segment q holds float4
+        // (one value per ring) for its pixels, 64 per q plus a pad entry.
+        // Rings past the group's last and pixels past the tile are left
+        // unset: their sums are never scattered.
+        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        int firsts[kGroupRings];      // (uniform) first pixel of each ring of the group
 #pragma unroll
-            for (int i = 0; i < kGroupRings; ++i)
-                v[i] = i < G.nr ? gm[cst(P.rings)[G.r0 + i].first + T.j0 + e] : 0.0f;
-            gs[(e / kKnotSub) * (kKnotSub + 1) + e % kKnotSub] = make_float4(v[0], v[1], v[2], v[3]);
+        for (int i = 0; i < kGroupRings; ++i)
+            firsts[i] = cst(P.rings)[G.r0 + min(i, G.nr - 1)].first + T.j0;
+        for (int c = wave; c < nsub * kGroupRings; c += kThreads / 64) {
+            const int q = c / kGroupRings;            // 64 floats: 16 pixels x 4 rings
+            const int f = (c - q * kGroupRings) * 64 + lane;
+            const int e = q * kKnotSub + (f >> 2);
+            const int i = f & 3;
+            const int fi = i == 0 ? firsts[0] : i == 1 ? firsts[1] : i == 2 ? firsts[2] : firsts[3];
+            if (i < G.nr && e < T.len)
+                load_to_lds(gm + fi + e, reinterpret_cast<float *>(gs + q * (kKnotSub + 1)) + (f - lane));
         }
         for (int rb = G.row_begin; rb < G.row_end;) {
             __syncthreads();   // the previous batch is no longer read
-            if (threadIdx.x == 0) {
-                int r = rb, units = 0, xo = 0;
-                s_uprefix[0] = 0;
-                while (r < G.row_end && r - rb < kKnotRows) {
+            if (wave == 0) {
+                // the batch: the longest run of rows from rb whose strips fit
+                // kKnotStage (the first always does), by prefix sums over a wave
+                const int r = rb + lane;
+                int need = 0, units = 0;
+                if (r < G.row_end) {
                     const int nt4 = (cst(P.rows)[r].ntaps + 3) & ~3;
-                    const int need = nsub * knot_strip(nt4);
-                    if (r > rb && xo + need > kKnotStage) break;
-                    s_xoff[r - rb] = xo;
-                    xo += need;
-                    units += (nt4 >> 2) * nsub;
-                    s_uprefix[r - rb + 1] = units;
-                    ++r;
+                    need = nsub * knot_strip(nt4);
+                    units = (nt4 >> 2) * nsub;
                 }
-                s_rows = r - rb;
+                int cneed = need, cunits = units;
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    const int a = __shfl_up(cneed, d);
+                    const int b = __shfl_up(cunits, d);
+                    if (lane >= d) {
+                        cneed += a;
+                        cunits += b;
+                    }
+                }
+                const bool fits = r < G.row_end && (lane == 0 || cneed <= kKnotStage);
+                const int nfit = __popcll(__ballot(fits));   // the whole wave votes
+                if (fits) {   // need > 0, so the fitting rows are a prefix
+                    s_xoff[lane] = cneed - need;
+                    s_uprefix[lane + 1] = cunits;
+                }
+                if (lane == 0) {
+                    s_uprefix[0] = 0;
+                    s_rows = nfit;
+                }
             }
             __syncthreads();
             const int nrows = s_rows;
             // stage x: row r, sub-segment q, strip position p holds
             // x_s[j0 + q kKnotSub + k_lo + p] for the positions its units read
-            // (-n < k_lo and k_lo + ntaps + 2 < n/2 + 4, so wrap3 applies)
-            // Each wave stages whole rows; q = e / strip by a float reciprocal,
-            // exact here: e < 2^11, and (e + 1/2) / strip stays at least
-            // 1 / (2 strip) > 2^-10 away from an integer.
-            const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-            for (int rr = wave; rr < nrows; rr += kThreads / 64) {
+            // (-n < k_lo and k_lo + ntaps + 2 < n/2 + 4, so wrap3 applies).
+            // Waves take 64-float pieces of each row; q = e / strip by a float
+            // reciprocal, exact here: e < 2^11, and (e + 1/2) / strip stays at
+            // least 1 / (2 strip) > 2^-10 away from an integer.
+            for (int rr = 0; rr < nrows; ++rr) {
                 const DevRow W = cst(P.rows)[rb + rr];
                 const int nt4 = (W.ntaps + 3) & ~3;
                 const int strip = knot_strip(nt4);
@@ -1051,14 +1089,16 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 const float *src = in + cst(P.rings)[W.s].first;
                 float *dst = xs + s_xoff[rr];
                 const int base = T.j0 + W.k_lo;
-#pragma unroll 4
-                for (int e = lane; e < nsub * strip; e += 64) {
+                for (int e0 = wave * 64; e0 < nsub * strip; e0 += kThreads) {
+                    const int e = e0 + lane;
                     const int q = (int)(((float)e + 0.5f) * inv_strip);
                     const int p = e - q * strip;
                     const int used = min(kKnotSub, T.len - q * kKnotSub) + nt4 - 1;
-                    dst[e] = p < used ? src[wrap3(base + q * kKnotSub + p, n)] : 0.0f;
+                    if (e < nsub * strip && p < used)
+                        load_to_lds(src + wrap3(base + q * kKnotSub + p, n), dst + e0);
                 }
             }
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's direct loads have landed
             __syncthreads();
             const int nunits = s_uprefix[nrows];
             for (int u = threadIdx.x; u < nunits; u += blockDim.x) {
