@@ -1006,6 +1006,8 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
     __shared__ int s_rows;                   // rows in the current batch
     __shared__ int s_uprefix[kKnotRows + 1]; // units before each row of the batch
     __shared__ int s_xoff[kKnotRows];        // its staged x strips
+    __shared__ int s_woff[kKnotRows];        // its weight-slot offset
+    __shared__ int s_ntaps[kKnotRows];       // and tap count
     const DevPlanView P = cst(views)[0];
     float4 *gs = reinterpret_cast<float4 *>(hist + ((P.ntab + 1) & ~1));
     float *xs = reinterpret_cast<float *>(gs + kKnotSubs * (kKnotSub + 1));
@@ -1046,11 +1048,14 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 // the batch: the longest run of rows from rb whose strips fit
                 // kKnotStage (the first always does), by prefix sums over a wave
                 const int r = rb + lane;
-                int need = 0, units = 0;
+                int need = 0, units = 0, woff = 0, ntaps = 0;
                 if (r < G.row_end) {
-                    const int nt4 = (cst(P.rows)[r].ntaps + 3) & ~3;
+                    const DevRow W = cst(P.rows)[r];
+                    ntaps = W.ntaps;
+                    woff = W.w_off;
+                    const int nt4 = (ntaps + 3) & ~3;
                     need = nsub * knot_strip(nt4);
-                    units = (nt4 >> 2) * nsub;
+                    units = (nt4 >> 2) * kKnotSubs;   // (tap quad, sub-segment) pairs
                 }
                 int cneed = need, cunits = units;
 #pragma unroll
@@ -1067,6 +1072,8 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 if (fits) {   // need > 0, so the fitting rows are a prefix
                     s_xoff[lane] = cneed - need;
                     s_uprefix[lane + 1] = cunits;
+                    s_woff[lane] = woff;
+                    s_ntaps[lane] = ntaps;
                 }
                 if (lane == 0) {
                     s_uprefix[0] = 0;
@@ -1108,14 +1115,24 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                     if (s_uprefix[mid] <= u) rr = mid;
                     else rh = mid - 1;
                 }
-                const DevRow W = cst(P.rows)[rb + rr];
                 const int v = u - s_uprefix[rr];
-                const int tb = v / nsub;
-                const int q = v - tb * nsub;
-                const int strip = knot_strip((W.ntaps + 3) & ~3);
+                const int tb = v / kKnotSubs;            // tap quad
+                const int q = v - tb * kKnotSubs;        // sub-segment
+                if (q >= nsub) continue;                 // short tile
+                const int ntaps = s_ntaps[rr];
+                const int strip = knot_strip((ntaps + 3) & ~3);
                 const float *xp = xs + s_xoff[rr] + q * strip + 4 * tb;
                 const float4 *gp = gs + q * (kKnotSub + 1);
                 const int len = min(kKnotSub, T.len - q * kKnotSub);
+                // node coordinates of the unit's taps, loaded ahead of the sums
+                // (clamped into the row; taps past it are dropped below)
+                const double *kw = P.kw + s_woff[rr];
+                double uu[4][kGroupRings];
+#pragma unroll
+                for (int t = 0; t < 4; ++t)
+#pragma unroll
+                    for (int i = 0; i < kGroupRings; ++i)
+                        uu[t][i] = kw[min(4 * tb + t, ntaps - 1) * kGroupRings + i];
                 float c[kGroupRings][4];
 #pragma unroll
                 for (int i = 0; i < kGroupRings; ++i)
@@ -1138,16 +1155,12 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                     x1 = x2;
                     x2 = x3;
                 }
-                cptr<double> kw = cst(P.kw + W.w_off);
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
-                    const int tap = 4 * tb + t;
-                    if (tap >= W.ntaps) break;
+                    if (4 * tb + t >= ntaps) break;
 #pragma unroll
-                    for (int i = 0; i < kGroupRings; ++i) {
-                        const double uu = kw[tap * kGroupRings + i];
-                        if (uu >= 0.0 && c[i][t] != 0.0f) hat_scatter(hist, uu, c[i][t]);
-                    }
+                    for (int i = 0; i < kGroupRings; ++i)
+                        if (uu[t][i] >= 0.0 && c[i][t] != 0.0f) hat_scatter(hist, uu[t][i], c[i][t]);
                 }
             }
             rb += nrows;
