@@ -576,14 +576,18 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
     const float u_max = gc.u_max;
     const UCoef &ucf = gc.ucf;
     const int last = vreg(cn - 1 + c0);
-    const int dmv = vreg(dm);
     const int stepv = vreg(step);
+    // The longitude numerator m falls by dm per candidate.  It is kept as an
+    // FP32 integer: exact while |m| < 2^24 (windows up to ~45 degrees at
+    // n = 8192), so x = m xscale rounds once, and no conversion is needed.
+    float mf = (float)m;
+    const float dmf = vreg((float)dm);
     const float4 *st = stage - c0;                           // indexed by jq >= c0
 #pragma unroll 2
     for (int t = 0; t < T; ++t) {
         const bool valid = jq <= a1;
         const int pos = min(jq, last);
-        const float x = (float)m * xscale;                 // half the longitude difference
+        const float x = mf * xscale;                         // half the longitude difference
         const float sx = sin_series<LONG>(x);
         const float d2 = fmaf(B, sx * sx, A);                // squared chord
         const float u = node_coord<AM>(d2, ucf);
@@ -614,7 +618,7 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         row[14] = fmaf(w, v3.z, row[14]);
         row[15] = fmaf(w, v3.w, row[15]);
         jq += stepv;
-        m -= dmv;
+        mf -= dmf;
     }
 }
 
