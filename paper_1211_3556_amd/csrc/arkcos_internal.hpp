@@ -75,9 +75,10 @@ struct DevTile {
     int r;
     int j0;
     int len;
-    int flags;     // general tiles: kTileLongSin if any source row needs the long sine
+    int flags;     // general tiles: kTileLongSin, kTileIntM
 };
-constexpr int kTileLongSin = 1;
+constexpr int kTileLongSin = 1;   // some source row needs the long sine series
+constexpr int kTileIntM = 2;      // a longitude numerator may reach 2^24: keep it in int32
 
 // Rings per group and outputs per lane of the circulant kernel; pixels per
 // general tile and source positions one pass of the general kernel stages;

@@ -562,7 +562,7 @@ struct GenConst {
         : zslot(vreg((float)P.ntab)), u_max(vreg(P.u_max)), ucf(ucoef<AM>(P)) {}
 };
 
-template <bool LONG, int AM>
+template <bool LONG, int AM, bool INTM>
 __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenConst<AM> &gc,
                                                  const float *tab, int m, int dm, int step,
                                                  const float4 *stage, int c0, int cn, int jq,
@@ -578,16 +578,18 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
     const int last = vreg(cn - 1 + c0);
     const int stepv = vreg(step);
     // The longitude numerator m falls by dm per candidate.  It is kept as an
-    // FP32 integer: exact while |m| < 2^24 (windows up to ~45 degrees at
-    // n = 8192), so x = m xscale rounds once, and no conversion is needed.
+    // FP32 integer, exact while |m| < 2^24 (the plan checks this per ring and
+    // otherwise selects INTM), so x = m xscale rounds once with no conversion.
     float mf = (float)m;
     const float dmf = vreg((float)dm);
+    int mi = m;
+    const int dmi = vreg(dm);
     const float4 *st = stage - c0;                           // indexed by jq >= c0
 #pragma unroll 2
     for (int t = 0; t < T; ++t) {
         const bool valid = jq <= a1;
         const int pos = min(jq, last);
-        const float x = mf * xscale;                         // half the longitude difference
+        const float x = (INTM ? (float)mi : mf) * xscale;   // half the longitude difference
         const float sx = sin_series<LONG>(x);
         const float d2 = fmaf(B, sx * sx, A);                // squared chord
         const float u = node_coord<AM>(d2, ucf);
@@ -618,7 +620,10 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         row[14] = fmaf(w, v3.z, row[14]);
         row[15] = fmaf(w, v3.w, row[15]);
         jq += stepv;
-        mf -= dmf;
+        if (INTM)
+            mi -= dmi;
+        else
+            mf -= dmf;
     }
 }
 
@@ -662,7 +667,7 @@ constexpr int kGenFlush = 48;
 // lane, the sum over the lanes of a pixel and the sixteen output images.
 // LONG and AM are fixed per tile, so the candidate loop has one form and the
 // row sums stay in place across rows.
-template <bool LONG, int AM>
+template <bool LONG, int AM, bool INTM>
 __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab, float4 *stage,
                                          const DevTile &T, const float *in, float *out)
 {
@@ -734,7 +739,7 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
         const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
         const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
         const int dm = 2 * nph * R.n;
-        gen_candidates16<LONG, AM>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt,
+        gen_candidates16<LONG, AM, INTM>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt,
                                    row);
         since += nt;
         if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
@@ -808,13 +813,21 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
         const float *in = io.in[pi] + (size_t)map * P.npix;
         float *out = io.out[pi] + (size_t)map * P.npix;
         const bool lg = (T.flags & kTileLongSin) != 0;
-        switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-            case 0: gen_tile<false, 0>(P, tab, stage, T, in, out); break;
-            case 1: gen_tile<true, 0>(P, tab, stage, T, in, out); break;
-            case 2: gen_tile<false, 1>(P, tab, stage, T, in, out); break;
-            case 3: gen_tile<true, 1>(P, tab, stage, T, in, out); break;
-            case 4: gen_tile<false, 2>(P, tab, stage, T, in, out); break;
-            default: gen_tile<true, 2>(P, tab, stage, T, in, out); break;
+        if (T.flags & kTileIntM) {   // wide windows on large rings (long sine implied)
+            switch (P.angle_mode) {
+                case 0: gen_tile<true, 0, true>(P, tab, stage, T, in, out); break;
+                case 1: gen_tile<true, 1, true>(P, tab, stage, T, in, out); break;
+                default: gen_tile<true, 2, true>(P, tab, stage, T, in, out); break;
+            }
+        } else {
+            switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+                case 0: gen_tile<false, 0, false>(P, tab, stage, T, in, out); break;
+                case 1: gen_tile<true, 0, false>(P, tab, stage, T, in, out); break;
+                case 2: gen_tile<false, 1, false>(P, tab, stage, T, in, out); break;
+                case 3: gen_tile<true, 1, false>(P, tab, stage, T, in, out); break;
+                case 4: gen_tile<false, 2, false>(P, tab, stage, T, in, out); break;
+                default: gen_tile<true, 2, false>(P, tab, stage, T, in, out); break;
+            }
         }
     }
 }

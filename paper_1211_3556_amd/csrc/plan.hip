@@ -305,13 +305,23 @@ static int build_plan(Plan &P)
     // about phi = pi/4 and the mirror images of all eight.
     P.gtiles.clear();
     cost.clear();
+    // test hook: every general tile takes the int32 numerator path
+    const char *fim = getenv("ARKCOS_FORCE_INT_NUMERATOR");
+    const bool force_int_m = fim && std::string(fim) == "1";
     for (int r = 0; r <= P.nrings - 1 - r; ++r) {
         if (!general[r]) continue;
         const int quarter = P.rings[r].n / 4;
         const int lanes = (P.rings[r].two_o ? (quarter - 1) / 2 : quarter / 2) + 1;
-        int flags = 0;
-        for (int k = P.dev_rings[r].pair_begin; k < P.dev_rings[r].pair_end; ++k)
-            if (P.pairs[k].mode & kPairLongSin) flags |= kTileLongSin;
+        // |m| = 2 n_r |c - j'| over the candidates, including those a wave
+        // runs past a lane's window (at most 64 lanes per pixel, +4 for the
+        // spread of windows across a wave)
+        int flags = force_int_m ? (kTileIntM | kTileLongSin) : 0;
+        for (int k = P.dev_rings[r].pair_begin; k < P.dev_rings[r].pair_end; ++k) {
+            const DevPair &pp = P.pairs[k];
+            if (pp.mode & kPairLongSin) flags |= kTileLongSin;
+            const double W = (pp.mode & kPairWhole) ? 0.5 * P.rings[pp.s].n + 1.0 : pp.w + 1.0;
+            if (2.0 * P.rings[r].n * (W + 70.0) >= 16777216.0) flags |= kTileIntM | kTileLongSin;
+        }
         for (int j0 = 0; j0 < lanes; j0 += kGenLanes) {
             DevTile t{};
             t.r = r;

@@ -159,6 +159,26 @@ def test_small_and_ragged_full_maps(nside, tc_deg):
     assert rel_rms(y, ref) <= REL_RMS_TOL
 
 
+@pytest.mark.parametrize("nside,tc_deg", [(64, 6.0), (16, 74.7)])
+def test_int32_numerator_path(monkeypatch, nside, tc_deg):
+    """The general gather carries the longitude numerator m as an exact FP32
+    integer and switches to int32 on rings where |m| could reach 2^24 (wide
+    windows at Nside >= 1024).  A test hook forces the int32 path everywhere
+    at a size the oracle checks in full."""
+    tc = np.radians(tc_deg)
+    assert_tie_free(nside, tc)
+    k = W.gaussian_profile_knots(tc / 3, tc, 2048)
+    x = W.white_noise(nside, 91)
+    log("int32 numerator path Nside %d cut %.1f deg" % (nside, tc_deg))
+    y_f = _conv_gpu(_A().Plan(nside, tc, k), x)
+    monkeypatch.setenv("ARKCOS_FORCE_INT_NUMERATOR", "1")
+    y_i = _conv_gpu(_A().Plan(nside, tc, k), x)
+    ref = O.convolve(nside, tc, k, x)
+    assert rel_rms(y_i, ref) <= REL_RMS_TOL
+    # same weights up to the sine series, which the int32 path always takes long
+    assert rel_rms(y_i, y_f) <= 5e-7
+
+
 @pytest.mark.parametrize("nside,tc_deg", [(5, 118.3), (100, 3.31)])
 def test_rough_table_error_bound(nside, tc_deg):
     """A table of iid random nodes is the worst case for FP32 angles: an error
