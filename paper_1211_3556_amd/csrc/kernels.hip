@@ -866,12 +866,15 @@ __host__ __device__ constexpr double sin_coef(int k)
     return c;
 }
 
-// sin(x) in FP64: through x^15 for |x| <= 0.35, through x^25 for |x| <= 2
-// (truncation below 1e-19 relative).
+// The knot gradient needs node fractions to ~1e-9 (the hat basis has slope
+// 1/h in theta), so these FP64 series keep truncation near 1e-15 relative.
+
+// sin(x) in FP64: through x^11 for |x| <= 0.35 (truncation below 6e-15
+// relative), through x^21 for |x| <= 2 (below 2e-16).
 template <bool LONG>
 __device__ __forceinline__ double sin_d(double x)
 {
-    constexpr int K = LONG ? 12 : 7;
+    constexpr int K = LONG ? 10 : 5;
     const double x2 = x * x;
     double p = sin_coef(K);
 #pragma unroll
@@ -879,10 +882,10 @@ __device__ __forceinline__ double sin_d(double x)
     return x * p;
 }
 
-// asin(y) in FP64 for 0 <= y <= 0.5 (truncation below 1e-16 relative).
+// asin(y) in FP64 for 0 <= y <= 0.5 (truncation below 2e-15 relative).
 __device__ __forceinline__ double asin_d(double y)
 {
-    constexpr int K = 24;
+    constexpr int K = 20;
     const double z = y * y;
     double p = asin_coef(K);
 #pragma unroll
@@ -890,23 +893,34 @@ __device__ __forceinline__ double asin_d(double y)
     return y * p;
 }
 
+// sqrt in FP64 from the hardware reciprocal square root and two Newton
+// steps (each at least squares the relative error), with sqrt(0) = 0.
+__device__ __forceinline__ double sqrt_d(double a)
+{
+    double r = __builtin_amdgcn_rsq(a);
+#pragma unroll
+    for (int i = 0; i < 2; ++i) r = r * fma(-0.5 * a, r * r, 1.5);
+    return a > 0.0 ? a * r : 0.0;
+}
+
 // theta = 2 asin(d/2) in FP64 from the squared chord, in the same three
-// regimes as theta_of: d (sum_k c_k (d^2/4)^k) with 8 terms for d <= 0.1 and
-// 16 terms for d^2 <= 0.245, and the full-range asin otherwise.
+// regimes as theta_of: d (sum_k c_k (d^2/4)^k) with 5 terms for d <= 0.1 and
+// 11 terms for d^2 <= 0.245 (truncation below 2e-15), and the full-range
+// asin otherwise.
 template <int AM>
 __device__ __forceinline__ double theta_d(double d2)
 {
     if (AM == 2) {
-        const double y = fmin(0.5 * sqrt(d2), 1.0);
+        const double y = fmin(0.5 * sqrt_d(d2), 1.0);
         if (y <= 0.5) return 2.0 * asin_d(y);
-        return 2.0 * (1.5707963267948966192 - 2.0 * asin_d(sqrt(0.5 * (1.0 - y))));
+        return 2.0 * (1.5707963267948966192 - 2.0 * asin_d(sqrt_d(0.5 * (1.0 - y))));
     }
-    constexpr int K = AM == 0 ? 8 : 16;
+    constexpr int K = AM == 0 ? 4 : 10;
     const double z = 0.25 * d2;
     double p = asin_coef(K);
 #pragma unroll
     for (int k = K - 1; k >= 0; --k) p = fma(p, z, asin_coef(k));
-    return sqrt(d2) * p;
+    return sqrt_d(d2) * p;
 }
 
 // Node index and fraction of one pair from the FP64 chord constants; false at
