@@ -65,8 +65,11 @@ typedef struct {
                              caller keeps ownership).  NULL only with ARKCOS_PLAN_LEARNABLE,
                              in which case knots must be set before the first convolve */
     int max_batch;        /* largest nbatch a call may pass (>= 1); sizes the workspace  */
-    int tile;             /* output pixels per tile, 0 = default; else 64 .. 4096,
-                             a multiple of 64                                           */
+    int tile;             /* tile-size hint: 0, or 64 .. 4096 and a multiple of 64
+                             (else EINVAL).  Reported back in info; the gathers'
+                             tile shapes are fixed by their register layouts
+                             (1024-pixel circulant segments, 128-pixel general
+                             tiles), so the hint does not change them            */
     unsigned flags;       /* ARKCOS_PLAN_* bits                                         */
 } arkcos_plan_desc;
 
@@ -75,7 +78,7 @@ typedef struct {
     int nrings;                    /* 4 Nside - 1                                       */
     long long npix;                /* 12 Nside^2                                        */
     long long ring_pairs;          /* (output ring, source ring) pairs in the plan      */
-    long long tiles;               /* work items per map                                */
+    long long tiles;               /* work items per map: circulant + general tiles     */
     long long candidates;          /* window pixels the kernels visit per map           */
     double omega;                  /* 4 pi / Npix                                       */
     int ntab;

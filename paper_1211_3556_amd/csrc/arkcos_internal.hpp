@@ -128,7 +128,6 @@ struct DevRow {
 struct DevPlanView {
     const DevRing *rings;
     const DevPair *pairs;
-    const DevTile *tiles;
     const float *table;      // ntab FP32 values Omega * K_k
     const DevPairD *pairs_d; // FP64 chord constants (learnable plans), else NULL
     double inv_h_d;          // (ntab - 1) / theta_cut in FP64
@@ -145,7 +144,6 @@ struct DevPlanView {
     int nkpart_circ;         // partial rows written by the circulant knot kernel
     int nrows;
     int nrings;
-    int ntiles;
     int ntab;
     int npix;
     int angle_mode;          // angle series: 0 (theta_cut <= 0.1), 1 (<= 0.5), 2 full range
@@ -197,7 +195,6 @@ struct Plan {
     std::vector<DevRing> dev_rings;
     std::vector<DevPair> pairs;
     std::vector<DevPairD> pairs_d;    // same order as pairs
-    std::vector<DevTile> tiles;       // per-ring tiles (knot gradient), longest first
     std::vector<DevGroup> groups;
     std::vector<DevRow> rows;
     std::vector<DevTile> ctiles;      // circulant tiles, longest first
@@ -218,7 +215,6 @@ struct Plan {
     DevRing *d_rings = nullptr;
     DevPair *d_pairs = nullptr;
     DevPairD *d_pairs_d = nullptr;
-    DevTile *d_tiles = nullptr;
     DevGroup *d_groups = nullptr;
     DevRow *d_rows = nullptr;
     float *d_wts = nullptr;

@@ -58,7 +58,6 @@ DevPlanView Plan::view() const
     DevPlanView v{};
     v.rings = d_rings;
     v.pairs = d_pairs;
-    v.tiles = d_tiles;
     v.table = d_table;
     v.pairs_d = d_pairs_d;
     v.inv_h_d = (desc.ntab - 1) / desc.theta_cut;
@@ -75,7 +74,6 @@ DevPlanView Plan::view() const
     v.nkpart_circ = grid_kc;
     v.nrows = (int)rows.size();
     v.nrings = nrings;
-    v.ntiles = (int)tiles.size();
     v.ntab = desc.ntab;
     v.npix = (int)npix;
     v.angle_mode = angle_mode;
@@ -190,21 +188,7 @@ static int build_plan(Plan &P)
         P.candidates += (long long)std::llround(per_pixel * R.n);
     }
 
-    // Per-ring tiles of `tile` pixels, longest first (knot-gradient kernel).
-    P.tiles.clear();
     std::vector<double> cost;
-    for (int r = 0; r < P.nrings; ++r) {
-        const int n = P.rings[r].n;
-        for (int j0 = 0; j0 < n; j0 += P.tile) {
-            DevTile t{};
-            t.r = r;
-            t.j0 = j0;
-            t.len = std::min(P.tile, n - j0);
-            P.tiles.push_back(t);
-            cost.push_back(ring_cost[r] * t.len);
-        }
-    }
-    sort_by_cost(P.tiles, cost);
 
     // Ring classes.  A belt ring whose source rings are all belt rings (4N
     // pixels each, windows narrower than a ring) is circulant: the weight of
@@ -429,7 +413,6 @@ static void free_device(Plan &P)
         (void)hipFree(P.d_rings);
         (void)hipFree(P.d_pairs);
         (void)hipFree(P.d_pairs_d);
-        (void)hipFree(P.d_tiles);
         (void)hipFree(P.d_groups);
         (void)hipFree(P.d_rows);
         (void)hipFree(P.d_wts);
@@ -446,7 +429,6 @@ static void free_device(Plan &P)
     P.d_rings = nullptr;
     P.d_pairs = nullptr;
     P.d_pairs_d = nullptr;
-    P.d_tiles = nullptr;
     P.d_groups = nullptr;
     P.d_rows = nullptr;
     P.d_wts = nullptr;
@@ -501,7 +483,6 @@ static int to_device(Plan &P)
     P.device_bytes = 0;
     if ((rc = upload(&P.d_rings, P.dev_rings, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_pairs, P.pairs, &P.device_bytes))) return rc;
-    if ((rc = upload(&P.d_tiles, P.tiles, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_groups, P.groups, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_rows, P.rows, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_ctiles, P.ctiles, &P.device_bytes))) return rc;
@@ -657,7 +638,7 @@ int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info)
     info->nrings = P->nrings;
     info->npix = P->npix;
     info->ring_pairs = (long long)P->pairs.size();
-    info->tiles = (long long)P->tiles.size();
+    info->tiles = (long long)(P->ctiles.size() + P->gtiles.size());
     info->candidates = P->candidates;
     info->omega = P->omega;
     info->ntab = P->desc.ntab;

@@ -203,17 +203,18 @@ def test_plan_info_is_consistent():
     assert inf["nside"] == 32 and inf["nrings"] == 127 and inf["npix"] == 12288
     assert inf["tile"] == 128 and inf["ntab"] == 100 and inf["device_bytes"] == 0
     assert abs(inf["omega"] - 4 * np.pi / 12288) < 1e-18
-    assert inf["tiles"] == sum(-(-n // 128) for n in O.ring_geometry(32)["n"])
+    assert inf["tiles"] == inf["circulant_tiles"] + inf["general_tiles"]
     assert inf["candidates"] >= p.pair_count()
 
 
 @pytest.mark.parametrize("nside,tc_deg", [(1, 5.0), (8, 3.0), (64, 6.0), (100, 3.31), (512, 1.5),
-                                          (2048, 20.0 / 60), (16, 75.0)])
+                                          (2048, 20.0 / 60), (16, 75.0), (300, 100.0)])
 def test_ring_classes_cover_every_ring(nside, tc_deg):
     """Every ring is gathered by exactly one kernel: circulant belt rings
     (whose whole disc stays in the belt) or general rings (caps, belt edges),
-    mirror-symmetric, with general tiles covering the first quadrant of each
-    northern general ring."""
+    mirror-symmetric.  General tiles cover the pixels j <= jbar = n/4 - 2o - j
+    of the first quadrant of each northern general ring (the reflection
+    phi -> pi/2 - phi supplies the rest), up to 128 pixels per tile."""
     p = A.Plan(nside, np.radians(tc_deg), np.ones(8), host_only=True)
     inf = p.info()
     assert inf["circulant_rings"] + inf["general_rings"] == 4 * nside - 1
@@ -221,7 +222,11 @@ def test_ring_classes_cover_every_ring(nside, tc_deg):
     assert inf["general_rings"] % 2 == 1 or inf["circulant_rings"] % 2 == 1
     g = O.ring_geometry(nside)
     if inf["general_rings"] == 4 * nside - 1:
-        quarters = sum(-(-(int(n) // 4) // 256) for n in g["n"][:2 * nside])
-        assert inf["general_tiles"] == quarters
+        tiles = 0
+        for n, phi0 in zip(g["n"][:2 * nside], g["phi0"][:2 * nside]):
+            q = int(n) // 4
+            lanes = ((q - 1) // 2 if phi0 > 0 else q // 2) + 1
+            tiles += -(-lanes // 128)
+        assert inf["general_tiles"] == tiles
     if inf["circulant_rings"]:
         assert inf["weights"] > 0 and inf["circulant_tiles"] > 0
