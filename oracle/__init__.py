@@ -13,7 +13,10 @@ through ctypes.  This module adds:
   lambda_l = 2 pi int_0^theta_cut K(theta) P_l(cos theta) sin theta dtheta,
   applied to the interpolated, truncated real-space kernel (Gauss-Legendre on
   every linear segment of the table);
-* ``real_ylm`` -- real spherical harmonics for the Funk-Hecke checks.
+* ``real_ylm`` -- real spherical harmonics for the Funk-Hecke checks;
+* ``two_piece_nodes`` / ``paper_bias`` -- the biased node placement of Sec. 3
+  (half of the nodes inside the first 1/16 of the support) as an explicit
+  node list, which every kernel-table function here accepts as ``nodes``.
 
 Parity pins for every function here are in ``tests/test_oracle_pins.py``.
 """
@@ -52,12 +55,15 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.orc_ring.argtypes = [ctypes.c_long, ctypes.c_long, _dp, _dp, _dp, _lp, _lp, _dp]
         lib.orc_pix2vec.argtypes = [ctypes.c_long, ctypes.c_long, _lp, _dp]
-        lib.orc_tabulate.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp]
+        lib.orc_tabulate.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp,
+                                     _dp]
         for name in ("orc_convolve", "orc_convolve_exhaustive"):
             getattr(lib, name).argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp,
-                                           _dp, ctypes.c_long, _lp, _dp, _lp]
+                                           _dp, _dp, ctypes.c_long, _lp, _dp, _lp]
         lib.orc_knot_grad.argtypes = [ctypes.c_long, ctypes.c_double, ctypes.c_long,
-                                      _dp, _dp, _dp]
+                                      _dp, _dp, _dp, _dp]
+        lib.orc_kernel_eval.argtypes = [ctypes.c_double, ctypes.c_long, _dp, _dp, ctypes.c_long,
+                                        _dp, _dp]
         lib.orc_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -65,6 +71,16 @@ def _load():
 
 def _d(a):
     return a.ctypes.data_as(_dp)
+
+
+def _nodes(nodes, ntab):
+    """(pointer, keep-alive array) of an optional explicit node list."""
+    if nodes is None:
+        return None, None
+    nodes = np.ascontiguousarray(nodes, dtype=np.float64)
+    if nodes.size != ntab:
+        raise ValueError("%d node angles for a table of %d values" % (nodes.size, ntab))
+    return _d(nodes), nodes
 
 
 def _l(a):
@@ -119,18 +135,60 @@ def gaussian_bl(fwhm_rad: float, lmax: int) -> np.ndarray:
     return np.exp(-0.5 * ell * (ell + 1.0) * sigma * sigma)
 
 
-def tabulate(bl, theta_cut: float, ntab: int) -> np.ndarray:
-    """Node table K(theta_k) = sum_l (2l+1)/(4 pi) b_l P_l(cos theta_k)."""
+def two_piece_nodes(theta_cut: float, ntab: int, theta_break: float, k_break: int
+                    ) -> np.ndarray:
+    """Node angles of a table that is uniform on each of two pieces: nodes
+    0..k_break evenly spaced on [0, theta_break], nodes k_break..ntab-1 evenly
+    spaced on [theta_break, theta_cut] (node k_break sits on the break)."""
+    if not (0.0 < theta_break < theta_cut) or not (1 <= k_break <= ntab - 2):
+        raise ValueError("need 0 < theta_break < theta_cut and 1 <= k_break <= ntab - 2")
+    fine = theta_break * (np.arange(k_break + 1) / k_break)
+    coarse = theta_break + (theta_cut - theta_break) * (
+        np.arange(1, ntab - k_break) / (ntab - 1 - k_break))
+    nodes = np.concatenate([fine, coarse])
+    nodes[k_break] = theta_break
+    nodes[-1] = theta_cut
+    return nodes
+
+
+def paper_bias(theta_cut: float, ntab: int) -> tuple[float, int]:
+    """The bias of Sec. 3: half of the nodes (ceil(ntab/2) of them, nodes
+    0..k_break) inside the first 1/16 of the support [0, theta_cut]."""
+    return theta_cut / 16.0, (ntab - 1) // 2
+
+
+def biased_nodes(theta_cut: float, ntab: int) -> np.ndarray:
+    """Node angles of the Sec. 3 biased table."""
+    tb, kb = paper_bias(theta_cut, ntab)
+    return two_piece_nodes(theta_cut, ntab, tb, kb)
+
+
+def tabulate(bl, theta_cut: float, ntab: int, nodes=None) -> np.ndarray:
+    """Node table K(theta_k) = sum_l (2l+1)/(4 pi) b_l P_l(cos theta_k) at the
+    uniform nodes, or at `nodes` when given."""
     bl = np.ascontiguousarray(bl, dtype=np.float64)
     out = np.empty(ntab)
-    _check(_load().orc_tabulate(_d(bl), bl.size - 1, float(theta_cut), ntab, _d(out)),
+    nptr, _keep = _nodes(nodes, ntab)
+    _check(_load().orc_tabulate(_d(bl), bl.size - 1, float(theta_cut), ntab, nptr, _d(out)),
            "tabulate")
     return out
 
 
+def kernel_eval(theta_cut: float, ktab, theta, nodes=None) -> np.ndarray:
+    """The interpolated, truncated kernel K(theta) of a node table."""
+    ktab = np.ascontiguousarray(ktab, dtype=np.float64)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.empty(theta.size)
+    nptr, _keep = _nodes(nodes, ktab.size)
+    _check(_load().orc_kernel_eval(float(theta_cut), ktab.size, nptr, _d(ktab), theta.size,
+                                   _d(theta), _d(out)), "kernel_eval")
+    return out
+
+
 def convolve(nside: int, theta_cut: float, ktab, x, pixels=None, exhaustive=False,
-             return_pairs=False):
-    """y[p] = Omega sum_{theta_pq < theta_cut} K(theta_pq) x[q] at `pixels`."""
+             return_pairs=False, nodes=None):
+    """y[p] = Omega sum_{theta_pq < theta_cut} K(theta_pq) x[q] at `pixels`
+    (K on the uniform nodes, or on `nodes` when given)."""
     lib = _load()
     ktab = np.ascontiguousarray(ktab, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
@@ -144,7 +202,8 @@ def convolve(nside: int, theta_cut: float, ktab, x, pixels=None, exhaustive=Fals
     y = np.empty(neval)
     pairs = np.empty(neval, dtype=np.int64)
     fn = lib.orc_convolve_exhaustive if exhaustive else lib.orc_convolve
-    _check(fn(nside, float(theta_cut), ktab.size, _d(ktab), _d(x), neval, pix_ptr, _d(y),
+    nptr, _keep = _nodes(nodes, ktab.size)
+    _check(fn(nside, float(theta_cut), ktab.size, nptr, _d(ktab), _d(x), neval, pix_ptr, _d(y),
               _l(pairs)), "convolve")
     return (y, pairs) if return_pairs else y
 
@@ -156,23 +215,25 @@ def pair_counts(nside: int, theta_cut: float, pixels=None, exhaustive=False) -> 
     return pairs
 
 
-def map_grad(nside: int, theta_cut: float, ktab, g) -> np.ndarray:
+def map_grad(nside: int, theta_cut: float, ktab, g, nodes=None) -> np.ndarray:
     """dL/dx = A^T g.  The operator is symmetric (theta_pq = theta_qp and Omega
     is the same for every pixel), so A^T g is the same direct sum applied to g."""
-    return convolve(nside, theta_cut, ktab, g)
+    return convolve(nside, theta_cut, ktab, g, nodes=nodes)
 
 
-def knot_grad(nside: int, theta_cut: float, ntab: int, x, g) -> np.ndarray:
+def knot_grad(nside: int, theta_cut: float, ntab: int, x, g, nodes=None) -> np.ndarray:
     """dL/dK_k = Omega sum_p g[p] sum_q Lambda_k(theta_pq) x[q] (hat basis)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     g = np.ascontiguousarray(g, dtype=np.float64)
     out = np.empty(ntab)
-    _check(_load().orc_knot_grad(nside, float(theta_cut), ntab, _d(x), _d(g), _d(out)),
+    nptr, _keep = _nodes(nodes, ntab)
+    _check(_load().orc_knot_grad(nside, float(theta_cut), ntab, nptr, _d(x), _d(g), _d(out)),
            "knot_grad")
     return out
 
 
-def legendre_coefficients(ktab, theta_cut: float, ells, order: int = 12) -> np.ndarray:
+def legendre_coefficients(ktab, theta_cut: float, ells, order: int = 12, nodes=None
+                          ) -> np.ndarray:
     """lambda_l = 2 pi int_0^theta_cut K_lin(theta) P_l(cos theta) sin(theta) dtheta.
 
     This is the Legendre transform operator of eq. 1 applied to the truncated,
@@ -184,14 +245,16 @@ def legendre_coefficients(ktab, theta_cut: float, ells, order: int = 12) -> np.n
 
     ktab = np.asarray(ktab, dtype=np.float64)
     ntab = ktab.size
-    h = theta_cut / (ntab - 1)
+    if nodes is None:
+        nodes = theta_cut * (np.arange(ntab) / (ntab - 1))
+    nodes = np.asarray(nodes, dtype=np.float64)
+    width = np.diff(nodes)[:, None]                 # segment widths
     xg, wg = np.polynomial.legendre.leggauss(order)
-    tt = 0.5 * (xg + 1.0)                           # nodes on [0, 1]
+    tt = 0.5 * (xg + 1.0)                           # quadrature points on [0, 1]
     ww = 0.5 * wg
-    k = np.arange(ntab - 1)[:, None]
-    theta = (k + tt[None, :]) * h                   # (ntab-1, order)
+    theta = nodes[:-1, None] + tt[None, :] * width  # (ntab-1, order)
     kval = (1.0 - tt[None, :]) * ktab[:-1, None] + tt[None, :] * ktab[1:, None]
-    base = 2.0 * np.pi * h * ww[None, :] * kval * np.sin(theta)
+    base = 2.0 * np.pi * width * ww[None, :] * kval * np.sin(theta)
     ct = np.cos(theta)
     return np.array([np.sum(base * eval_legendre(int(l), ct)) for l in np.atleast_1d(ells)])
 

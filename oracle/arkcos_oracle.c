@@ -30,6 +30,11 @@
  * Readings where the paper is silent (each listed in the design doc):
  *   - the table has ntab nodes at theta_k = k h, h = theta_cut/(ntab-1),
  *     and K is linear in theta between nodes;
+ *   - the biased table of Sec. 3 (half the nodes inside the first 1/16 of the
+ *     support) is given as an explicit increasing node list theta_0 = 0 <
+ *     ... < theta_{ntab-1} = theta_cut; K is again linear in theta between
+ *     consecutive nodes, and the node interval of an angle is found by
+ *     bisection over that list;
  *   - the cut is strict: pairs with theta >= theta_cut get K = 0;
  *   - HEALPix RING pixel centres follow Gorski et al. (2005), the pixelisation
  *     the paper names for its data.
@@ -135,26 +140,53 @@ static double separation(const double a[3], const double b[3])
     return 2.0 * asin(half);
 }
 
-/* linear interpolation of the node table on [0, theta_cut]; zero outside */
+/*
+ * Linear interpolation of the node table (Sec. 3).  nodes == NULL: uniform
+ * nodes theta_k = k theta_cut/(ntab-1).  Otherwise nodes[0..ntab-1] lists the
+ * node angles (0 = nodes[0] < ... < nodes[ntab-1] = theta_cut) and the
+ * interval [nodes[i], nodes[i+1]) holding theta is found by bisection.
+ * Returns the left node i and the fraction t of the way to node i+1.
+ */
 static void interp_weights(double theta, double theta_cut, long ntab,
-                           long *i, double *t)
+                           const double *nodes, long *i, double *t)
 {
-    double h = theta_cut / (double)(ntab - 1);
-    double u = theta / h;
-    long k = (long)floor(u);
-    if (k > ntab - 2) k = ntab - 2;
-    if (k < 0) k = 0;
-    *i = k;
-    *t = u - (double)k;
+    if (!nodes) {
+        double h = theta_cut / (double)(ntab - 1);
+        double u = theta / h;
+        long k = (long)floor(u);
+        if (k > ntab - 2) k = ntab - 2;
+        if (k < 0) k = 0;
+        *i = k;
+        *t = u - (double)k;
+        return;
+    }
+    long lo = 0, hi = ntab - 1;          /* invariant: nodes[lo] <= theta */
+    while (hi - lo > 1) {
+        long mid = lo + (hi - lo) / 2;
+        if (nodes[mid] <= theta) lo = mid; else hi = mid;
+    }
+    *i = lo;
+    *t = (theta - nodes[lo]) / (nodes[lo + 1] - nodes[lo]);
 }
 
+/* zero at and beyond theta_cut (the truncation of eq. 1) */
 static double kernel_value(double theta, double theta_cut, long ntab,
-                           const double *ktab)
+                           const double *nodes, const double *ktab)
 {
     if (!(theta < theta_cut)) return 0.0;
     long i; double t;
-    interp_weights(theta, theta_cut, ntab, &i, &t);
+    interp_weights(theta, theta_cut, ntab, nodes, &i, &t);
     return (1.0 - t) * ktab[i] + t * ktab[i + 1];
+}
+
+/* An explicit node list must start at 0, increase strictly and end at the cut. */
+static int bad_nodes(double theta_cut, long ntab, const double *nodes)
+{
+    if (!nodes) return 0;
+    if (nodes[0] != 0.0 || nodes[ntab - 1] != theta_cut) return 1;
+    for (long k = 1; k < ntab; ++k)
+        if (!(nodes[k] > nodes[k - 1])) return 1;
+    return 0;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -259,20 +291,22 @@ int orc_pix2vec(long nside, long npix, const long *pix, double *xyz)
 
 /*
  * Kernel table from a beam: K(theta_k) = sum_{l<=lmax} (2l+1)/(4 pi) b_l
- * P_l(cos theta_k) at theta_k = k theta_cut/(ntab-1).  This is the inverse of
+ * P_l(cos theta_k) at theta_k = k theta_cut/(ntab-1), or at theta_k = nodes[k]
+ * for an explicit node list.  This is the inverse of
  * the Legendre transform operator of eq. 1 applied to the eq. 5 kernel with
  * C_l = 1.  Legendre polynomials by the three-term recurrence
  *   (l+1) P_{l+1} = (2l+1) x P_l - l P_{l-1}.
  */
 int orc_tabulate(const double *bl, long lmax, double theta_cut, long ntab,
-                 double *ktab)
+                 const double *nodes, double *ktab)
 {
     if (lmax < 0 || ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI)
         return -1;
+    if (bad_nodes(theta_cut, ntab, nodes)) return -1;
     double h = theta_cut / (double)(ntab - 1);
     #pragma omp parallel for schedule(static)
     for (long k = 0; k < ntab; ++k) {
-        double x = cos((double)k * h);
+        double x = cos(nodes ? nodes[k] : (double)k * h);
         double pm1 = 1.0, p = x;          /* P_0, P_1 */
         double sum = bl[0];               /* l = 0 term times 4 pi */
         if (lmax >= 1) sum += 3.0 * bl[1] * x;
@@ -289,14 +323,16 @@ int orc_tabulate(const double *bl, long lmax, double theta_cut, long ntab,
 /*
  * Windowed direct sum at a list of output pixels (pix == NULL: all pixels,
  * in RING order).  y has npix_eval entries; pairs_out (nullable) receives
- * the number of in-disc pairs per evaluated pixel.
+ * the number of in-disc pairs per evaluated pixel.  nodes: NULL for the
+ * uniform table, else the ntab node angles.
  */
-int orc_convolve(long nside, double theta_cut, long ntab, const double *ktab,
-                 const double *x, long npix_eval, const long *pix, double *y,
-                 long *pairs_out)
+int orc_convolve(long nside, double theta_cut, long ntab, const double *nodes,
+                 const double *ktab, const double *x, long npix_eval,
+                 const long *pix, double *y, long *pairs_out)
 {
     if (nside < 1 || ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI)
         return -1;
+    if (bad_nodes(theta_cut, ntab, nodes)) return -1;
     long total = 12L * nside * nside;
     if (!pix) npix_eval = total;
     ring_rec *t = ring_table(nside);
@@ -314,7 +350,7 @@ int orc_convolve(long nside, double theta_cut, long ntab, const double *ktab,
             if (cnt < 0) { bad = 2; continue; }
             double acc = 0.0;
             for (long m = 0; m < cnt; ++m)
-                acc += kernel_value(nb.v[m].theta, theta_cut, ntab, ktab) * x[nb.v[m].q];
+                acc += kernel_value(nb.v[m].theta, theta_cut, ntab, nodes, ktab) * x[nb.v[m].q];
             y[k] = omega * acc;
             if (pairs_out) pairs_out[k] = cnt;
         }
@@ -328,12 +364,13 @@ int orc_convolve(long nside, double theta_cut, long ntab, const double *ktab,
  * Exhaustive all-pairs sum (every q tested, no windows); for small Nside.
  */
 int orc_convolve_exhaustive(long nside, double theta_cut, long ntab,
-                            const double *ktab, const double *x,
-                            long npix_eval, const long *pix, double *y,
-                            long *pairs_out)
+                            const double *nodes, const double *ktab,
+                            const double *x, long npix_eval, const long *pix,
+                            double *y, long *pairs_out)
 {
     if (nside < 1 || ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI)
         return -1;
+    if (bad_nodes(theta_cut, ntab, nodes)) return -1;
     long total = 12L * nside * nside;
     if (!pix) npix_eval = total;
     ring_rec *t = ring_table(nside);
@@ -354,7 +391,7 @@ int orc_convolve_exhaustive(long nside, double theta_cut, long ntab,
         for (long q = 0; q < total; ++q) {
             double th = separation(v + 3 * p, v + 3 * q);
             if (th < theta_cut) {
-                acc += kernel_value(th, theta_cut, ntab, ktab) * x[q];
+                acc += kernel_value(th, theta_cut, ntab, nodes, ktab) * x[q];
                 ++cnt;
             }
         }
@@ -373,11 +410,12 @@ int orc_convolve_exhaustive(long nside, double theta_cut, long ntab,
  * t to node i+1), the derivative of the interpolated kernel with respect to
  * its nodes.  gk has ntab entries.
  */
-int orc_knot_grad(long nside, double theta_cut, long ntab, const double *x,
-                  const double *g, double *gk)
+int orc_knot_grad(long nside, double theta_cut, long ntab, const double *nodes,
+                  const double *x, const double *g, double *gk)
 {
     if (nside < 1 || ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI)
         return -1;
+    if (bad_nodes(theta_cut, ntab, nodes)) return -1;
     long total = 12L * nside * nside;
     ring_rec *t = ring_table(nside);
     if (!t) return -2;
@@ -397,7 +435,7 @@ int orc_knot_grad(long nside, double theta_cut, long ntab, const double *x,
             if (cnt < 0) { bad = 1; continue; }
             for (long m = 0; m < cnt; ++m) {
                 long i; double tt;
-                interp_weights(nb.v[m].theta, theta_cut, ntab, &i, &tt);
+                interp_weights(nb.v[m].theta, theta_cut, ntab, nodes, &i, &tt);
                 double c = omega * g[p] * x[nb.v[m].q];
                 mine[i] += (1.0 - tt) * c;
                 mine[i + 1] += tt * c;
@@ -413,6 +451,22 @@ int orc_knot_grad(long nside, double theta_cut, long ntab, const double *x,
     free(part);
     free(t);
     return bad ? -2 : 0;
+}
+
+/*
+ * The interpolated, truncated kernel itself at n angles (0 at and beyond the
+ * cut); nodes as for orc_convolve.
+ */
+int orc_kernel_eval(double theta_cut, long ntab, const double *nodes,
+                    const double *ktab, long n, const double *theta, double *out)
+{
+    if (ntab < 2 || !(theta_cut > 0.0) || theta_cut > M_PI || n < 0) return -1;
+    if (bad_nodes(theta_cut, ntab, nodes)) return -1;
+    for (long k = 0; k < n; ++k) {
+        if (!(theta[k] >= 0.0)) return -1;
+        out[k] = kernel_value(theta[k], theta_cut, ntab, nodes, ktab);
+    }
+    return 0;
 }
 
 /* Number of threads the oracle runs with (for reporting). */

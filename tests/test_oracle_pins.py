@@ -5,8 +5,9 @@ phi offset (golden HEALPix fixtures, symmetries, area identities), a dropped or
 wrong pixel area Omega (constant map vs the Legendre transform lambda_0), a
 wrong node spacing or interpolation (impulse maps against numpy.interp, the
 Funk-Hecke checks), a missing neighbour (exhaustive all-pairs), a Legendre
-recurrence slip (closed forms, scipy), or a wrong gradient (central finite
-differences, which are exact for a quadratic loss).
+recurrence slip (closed forms, scipy), a wrong gradient (central finite
+differences, which are exact for a quadratic loss), or a misplaced node of the
+biased table of Sec. 3 (the paper's printed break angle and node share).
 """
 import os
 
@@ -320,3 +321,165 @@ def test_gradient_euler_identities():
     gy = g @ y
     assert abs(k @ gk - gy) < 1e-12 * np.abs(g).sum() * np.abs(y).max()
     assert abs(x @ gx - gy) < 1e-12 * np.abs(g).sum() * np.abs(y).max()
+
+
+# ------------------------------------------------------ biased node table --
+# Sec. 3 places half of the nodes inside the first 1/16 of the support.  The
+# oracle takes such a table as an explicit node list (two_piece_nodes) and
+# finds node intervals by bisection; these pins fix the placement from the
+# paper's printed figures and the sums on it from numpy.interp, brute force,
+# the uniform special case, Funk-Hecke and finite differences.
+
+def test_biased_nodes_match_paper_figures():
+    frac_support, frac_nodes, break_arcmin = _load_golden("biased_grid_sec3.txt")
+    tc = break_arcmin / frac_support * W.ARCMIN            # 120 arcmin
+    for ntab in (4, 5, 257, 4096, 16384):
+        nodes = O.biased_nodes(tc, ntab)
+        tb, kb = O.paper_bias(tc, ntab)
+        assert nodes.size == ntab and nodes[0] == 0.0 and nodes[-1] == tc
+        assert np.all(np.diff(nodes) > 0)
+        assert nodes[kb] == tb
+        assert abs(tb / W.ARCMIN - break_arcmin) < 1e-12
+        inside = int(np.count_nonzero(nodes <= tb))
+        assert inside == -(-ntab // 2)                    # half of the nodes, rounded up
+        assert abs(inside / ntab - frac_nodes) <= 0.5 / ntab + 1e-15
+        # uniform on each piece, finer on the first
+        d = np.diff(nodes)
+        np.testing.assert_allclose(d[:kb], tb / kb, rtol=1e-9)
+        np.testing.assert_allclose(d[kb:], (tc - tb) / (ntab - 1 - kb), rtol=1e-9)
+        assert d[0] < d[-1]
+
+
+def test_two_piece_nodes_rejects_bad_breaks():
+    for tb, kb in ((0.0, 3), (1.0, 3), (0.5, 0), (0.5, 9)):
+        with pytest.raises(ValueError):
+            O.two_piece_nodes(1.0, 10, tb, kb)
+
+
+@pytest.mark.parametrize("nside,q", [(8, 0), (8, 300), (16, 1500), (16, 767)])
+def test_biased_impulse_map_samples_interpolated_kernel(nside, q):
+    """x = delta_q on a biased table: y_p = Omega numpy.interp(theta_pq, nodes, K)."""
+    npix = 12 * nside * nside
+    tc = np.radians(40.0)
+    k = np.random.default_rng(q + 1).uniform(0.5, 2.0, 29)
+    nodes = O.biased_nodes(tc, k.size)
+    x = np.zeros(npix)
+    x[q] = 1.0
+    y = O.convolve(nside, tc, k, x, nodes=nodes)
+    v = O.pix2vec(nside)
+    cross = np.linalg.norm(np.cross(v, v[q]), axis=1)
+    theta = np.arctan2(cross, v @ v[q])
+    ref = np.where(theta < tc, np.interp(theta, nodes, k), 0.0) * 4 * np.pi / npix
+    np.testing.assert_allclose(y, ref, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(O.kernel_eval(tc, k, theta, nodes=nodes) * 4 * np.pi / npix, ref,
+                               rtol=1e-12, atol=1e-15)
+
+
+def test_kernel_eval_is_piecewise_linear_interpolation():
+    tc = 0.3
+    rng = np.random.default_rng(31)
+    k = rng.standard_normal(40)
+    nodes = O.two_piece_nodes(tc, k.size, 0.07, 25)
+    th = np.concatenate([rng.uniform(0, tc, 5000), nodes, [tc, 0.4, np.pi]])
+    ref = np.where(th < tc, np.interp(th, nodes, k), 0.0)
+    np.testing.assert_allclose(O.kernel_eval(tc, k, th, nodes=nodes), ref, rtol=1e-13,
+                               atol=1e-14)
+    uni = tc * np.arange(k.size) / (k.size - 1)
+    np.testing.assert_allclose(O.kernel_eval(tc, k, th),
+                               np.where(th < tc, np.interp(th, uni, k), 0.0),
+                               rtol=0, atol=1e-13)
+
+
+def test_uniform_node_list_reduces_to_uniform_table():
+    nside, tc = 16, np.radians(12.0)
+    rng = np.random.default_rng(32)
+    x, g = rng.standard_normal((2, 12 * nside * nside))
+    k = rng.uniform(0.2, 1.0, 41)
+    uni = tc * (np.arange(k.size) / (k.size - 1))
+    uni[-1] = tc
+    y0, y1 = O.convolve(nside, tc, k, x), O.convolve(nside, tc, k, x, nodes=uni)
+    np.testing.assert_allclose(y1, y0, rtol=0, atol=1e-13 * np.abs(y0).max())
+    g0, g1 = O.knot_grad(nside, tc, k.size, x, g), O.knot_grad(nside, tc, k.size, x, g, nodes=uni)
+    np.testing.assert_allclose(g1, g0, rtol=0, atol=1e-13 * np.abs(g0).max())
+
+
+@pytest.mark.parametrize("nside,tc_deg", [(4, 60.0), (8, 20.0), (16, 9.0)])
+def test_biased_windowed_equals_exhaustive(nside, tc_deg):
+    rng = np.random.default_rng(nside + 77)
+    x = rng.standard_normal(12 * nside * nside)
+    k = rng.standard_normal(64)
+    tc = np.radians(tc_deg)
+    nodes = O.biased_nodes(tc, k.size)
+    y1, p1 = O.convolve(nside, tc, k, x, return_pairs=True, nodes=nodes)
+    y2, p2 = O.convolve(nside, tc, k, x, exhaustive=True, return_pairs=True, nodes=nodes)
+    np.testing.assert_array_equal(p1, p2)
+    np.testing.assert_allclose(y1, y2, rtol=0, atol=1e-14 * max(1.0, np.abs(y2).max()))
+
+
+def test_biased_tabulation_matches_scipy_legendre_sum():
+    rng = np.random.default_rng(33)
+    bl = rng.uniform(-1, 1, 61)
+    tc, ntab = 0.8, 50
+    nodes = O.biased_nodes(tc, ntab)
+    ref = sum((2 * l + 1) * bl[l] * eval_legendre(l, np.cos(nodes)) for l in range(61)) / (4 * np.pi)
+    np.testing.assert_allclose(O.tabulate(bl, tc, ntab, nodes=nodes), ref,
+                               atol=1e-13 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("ell,m", [(2, 1), (8, 0)])
+def test_biased_band_limited_ylm_funk_hecke(ell, m):
+    """Funk-Hecke on a biased table: Y_lm comes back scaled by the Legendre
+    transform of that table's interpolated kernel."""
+    fw, tc = np.radians(6.0), np.radians(15.0)
+    nodes = O.biased_nodes(tc, 2048)
+    k = O.tabulate(O.gaussian_bl(fw, 300), tc, 2048, nodes=nodes)
+    lam = O.legendre_coefficients(k, tc, [ell], nodes=nodes)[0]
+    errs = []
+    for nside in (16, 32, 64):
+        v = O.pix2vec(nside)
+        f = O.real_ylm(ell, m, v)
+        y = O.convolve(nside, tc, k, f, nodes=nodes)
+        errs.append(np.sqrt(np.mean((y - lam * f) ** 2) / np.mean((lam * f) ** 2)))
+    assert errs[2] < 2e-3
+    assert errs[1] < errs[0] / 2.0 and errs[2] < errs[1] / 2.0
+
+
+def test_biased_knot_gradient_central_differences_and_euler():
+    nside, tc = 8, np.radians(25.0)
+    rng = np.random.default_rng(34)
+    x, t = rng.standard_normal((2, 12 * nside * nside))
+    k = rng.uniform(0.2, 1.0, 32)
+    nodes = O.biased_nodes(tc, k.size)
+    y = O.convolve(nside, tc, k, x, nodes=nodes)
+    g = 2.0 * (y - t)
+    gk = O.knot_grad(nside, tc, k.size, x, g, nodes=nodes)
+    h = 1e-3 * np.abs(k).max()
+    for kk in range(0, 32, 3):
+        e = np.zeros_like(k)
+        e[kk] = h
+        fd = (_loss(O.convolve(nside, tc, k + e, x, nodes=nodes), t)
+              - _loss(O.convolve(nside, tc, k - e, x, nodes=nodes), t)) / (2 * h)
+        assert abs(fd - gk[kk]) < 1e-8 * max(1.0, np.abs(gk).max())
+    assert abs(k @ gk - g @ y) < 1e-12 * np.abs(g).sum() * np.abs(y).max()
+
+
+def test_bias_trades_outer_for_inner_interpolation_error():
+    """What the bias of Sec. 3 buys: with the same node count the fine piece
+    is 8x finer than a uniform table, so the linear-interpolation error of a
+    smooth profile (h^2 |K''| / 8) inside theta_cut/16 falls ~64-fold, while
+    the coarse piece is 15/8 as wide, raising the error there ~(15/8)^2."""
+    tc, ntab = np.radians(2.0), 1025
+    sig = tc / 5.0
+    f = lambda th: np.exp(-0.5 * (th / sig) ** 2)   # noqa: E731
+    uni = tc * np.arange(ntab) / (ntab - 1)
+    bia = O.biased_nodes(tc, ntab)
+    th_in = np.linspace(0.0, tc / 16, 20001)[:-1]
+    th_out = np.linspace(tc / 8, tc, 20001)[:-1]
+    err = {}
+    for name, nodes in (("uni", uni), ("bia", bia)):
+        k = f(nodes)
+        err[name] = [np.abs(O.kernel_eval(tc, k, th, nodes=nodes) - f(th)).max()
+                     for th in (th_in, th_out)]
+    assert err["bia"][0] < err["uni"][0] / 50.0
+    assert err["bia"][1] < err["uni"][1] * (15 / 8) ** 2 * 1.05
+    assert err["bia"][1] > err["uni"][1] * 3.0
