@@ -85,6 +85,8 @@ def main() -> int:
                     help="skip the 16 plain launches the batch is compared with")
     ap.add_argument("--cpu-sample", type=int, default=6_000_000,
                     help="output pixels of the Nside-2048 oracle sample")
+    ap.add_argument("--no-biased", action="store_true",
+                    help="skip the biased-node-table forwards reported beside the step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy, the reference "
                          "for scaling hardware byte counters")
@@ -252,6 +254,58 @@ def main() -> int:
         torch.cuda.synchronize()
         plain16_ms = e0.elapsed_time(e1)
 
+    # Biased node tables (Sec. 3), outside the step: the same split kernel on a
+    # biased and on a uniform table, for the 15 arcmin workload and for the
+    # paper's split example (240 arcmin).  Each gather timed over `reps` calls.
+    biased = None
+    if not args.no_biased:
+        biased = {}
+        reps = 3
+        for name, s in (("split_15arcmin", W.C3B), ("split_example_240arcmin", W.SPLIT_EXAMPLE)):
+            log("biased-table forwards: %s" % name)
+            bl = A.gaussian_bl(s.fwhm, s.ell_max) * W.high_ell_mask(s.ell_max)
+            tb, kb = A.paper_bias(s.theta_cut, s.ntab)
+            plans = {
+                "biased": A.Plan(s.nside, s.theta_cut,
+                                 A.tabulate_legendre_at(bl, A.grid_nodes(s.theta_cut, s.ntab,
+                                                                         tb, kb)),
+                                 theta_break=tb, k_break=kb),
+                "uniform": A.Plan(s.nside, s.theta_cut,
+                                  A.tabulate_legendre(bl, s.theta_cut, s.ntab)),
+            }
+            x = dev_map(s.nside, s.seed)
+            y = torch.empty_like(x)
+            pc, pg = plans["biased"].pair_count_parts()
+            rec = {"nside": s.nside, "fwhm_arcmin": round(s.fwhm / W.ARCMIN, 3),
+                   "ell_range": [W.SPLIT_ELL + 1, s.ell_max],
+                   "theta_cut_arcmin": round(s.theta_cut / W.ARCMIN, 3), "ntab": s.ntab,
+                   "theta_break_arcmin": round(tb / W.ARCMIN, 4), "k_break": kb,
+                   "pairs": pc + pg}
+            for label, p in plans.items():
+                for part in (CIRC, GEN):
+                    p.convolve_part(x, y, part)
+                torch.cuda.synchronize()
+                t = {}
+                for part, kname in ((CIRC, "k_circ"), (GEN, "k_general")):
+                    e0, e1 = ev(), ev()
+                    e0.record(stream)
+                    for _ in range(reps):
+                        p.convolve_part(x, y, part)
+                    e1.record(stream)
+                    torch.cuda.synchronize()
+                    t[kname] = e0.elapsed_time(e1) / reps
+                tot = t["k_circ"] + t["k_general"]
+                rec[label] = {"ms": round(tot, 4),
+                              "k_circ_ms": round(t["k_circ"], 4),
+                              "k_general_ms": round(t["k_general"], 4),
+                              "gpair_per_s": round((pc + pg) / (tot * 1e-3) / 1e9, 2),
+                              "k_general_tflops": round(FLOP_PER_PAIR["k_general"] * pg
+                                                        / (t["k_general"] * 1e-3) / 1e12, 2)}
+            rec["biased_over_uniform"] = round(rec["biased"]["ms"] / rec["uniform"]["ms"], 4)
+            biased[name] = rec
+            del plans
+            torch.cuda.synchronize()
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -303,6 +357,7 @@ def main() -> int:
                       "plain16_ms": None if plain16_ms is None else round(plain16_ms, 4),
                       "speedup_vs_plain16": None if plain16_ms is None else round(plain16_ms / b_ms, 3)},
             "kernels": kernels,
+            "biased_table": biased,
         },
         "roofline": {
             "kernel": dom,

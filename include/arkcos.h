@@ -14,9 +14,11 @@
  *     out[p] = Omega * sum_{q : theta(p,q) < theta_cut} K(theta(p,q)) in[q],
  *     Omega  = 4 pi / Npix,  Npix = 12 Nside^2,
  *
- * where K is linear in theta between ntab nodes spaced h = theta_cut/(ntab-1)
- * on [0, theta_cut] (Sec. 3, interpolation of the real-space kernel), and
- * K = 0 for theta >= theta_cut.  Sums run in FP32 on the device.
+ * where K is linear in theta between ntab nodes on [0, theta_cut] (Sec. 3,
+ * interpolation of the real-space kernel), and K = 0 for theta >= theta_cut.
+ * The nodes are uniform, theta_k = k theta_cut/(ntab-1), or -- the biased
+ * table of Sec. 3 -- uniform on each of two pieces with a finer first piece
+ * (see arkcos_plan_desc).  Sums run in FP32 on the device.
  *
  * Conventions for every function:
  *   - returns ARKCOS_OK (0) or a negative status; never aborts or throws;
@@ -60,7 +62,7 @@ enum {
 typedef struct {
     int nside;            /* HEALPix resolution, 1 .. ARKCOS_MAX_NSIDE (any integer)       */
     double theta_cut;     /* radians, 0 < theta_cut <= pi                                 */
-    int ntab;             /* >= 2 nodes, uniform on [0, theta_cut] inclusive              */
+    int ntab;             /* >= 2 nodes on [0, theta_cut] inclusive (node grid below)     */
     const double *ktab;   /* host FP64 node values K(theta_k), length ntab; copied (the
                              caller keeps ownership).  NULL only with ARKCOS_PLAN_LEARNABLE,
                              in which case knots must be set before the first convolve */
@@ -71,6 +73,19 @@ typedef struct {
                              (1024-pixel circulant segments, 128-pixel general
                              tiles), so the hint does not change them            */
     unsigned flags;       /* ARKCOS_PLAN_* bits                                         */
+    /* Node grid.  theta_break = 0 and k_break = 0: uniform nodes
+     * theta_k = k theta_cut/(ntab-1).  Otherwise the two-piece table of the
+     * biased interpolation of Sec. 3: nodes 0..k_break evenly spaced on
+     * [0, theta_break] and nodes k_break..ntab-1 evenly spaced on
+     * [theta_break, theta_cut].  Needs 0 < theta_break < theta_cut,
+     * 1 <= k_break <= ntab-2 and a first piece at least as fine as the second,
+     * theta_break/k_break <= (theta_cut-theta_break)/(ntab-1-k_break)
+     * (else EINVAL).  The paper's bias puts half of the nodes in the first
+     * 1/16 of the support: theta_break = theta_cut/16, k_break = (ntab-1)/2
+     * (integer division).  Kernel tables are values at these nodes
+     * (arkcos_grid_nodes, arkcos_tabulate_legendre_at).                      */
+    double theta_break;
+    int k_break;
 } arkcos_plan_desc;
 
 typedef struct {
@@ -91,6 +106,8 @@ typedef struct {
     long long circulant_tiles;     /* work items of the two gathers per map             */
     long long general_tiles;
     long long weights;             /* FP32 entries of the circulant weight rows         */
+    double theta_break;            /* node grid of the descriptor (0, 0: uniform)       */
+    int k_break;
 } arkcos_plan_info;
 
 /* The two gathers of a forward convolution (they write disjoint rings). */
@@ -111,6 +128,29 @@ typedef struct {
  */
 int arkcos_tabulate_legendre(const double *b_l, int lmax, double theta_cut, int ntab,
                              double *ktab_out);
+
+/*
+ * Node angles of a table (the grid of arkcos_plan_desc: theta_break = 0 and
+ * k_break = 0 for uniform nodes, else the two-piece biased grid of Sec. 3).
+ *   theta_out  host, ntab doubles, caller-allocated; theta_out[0] = 0 and
+ *              theta_out[ntab-1] = theta_cut exactly                   [out]
+ * EINVAL on the descriptor errors of arkcos_plan_create for these fields,
+ * ntab < 2 or a NULL pointer.
+ */
+int arkcos_grid_nodes(double theta_cut, int ntab, double theta_break, int k_break,
+                      double *theta_out);
+
+/*
+ * The eq. 5 kernel profile of arkcos_tabulate_legendre at n arbitrary angles
+ * theta[k] in [0, pi] (e.g. the nodes of a biased grid):
+ * out[k] = sum_{l=0}^{lmax} (2l+1)/(4 pi) b_l P_l(cos theta[k]).  Host FP64.
+ *   b_l   host, lmax+1 doubles                  [in]
+ *   theta host, n doubles                       [in]
+ *   out   host, n doubles, caller-allocated     [out]
+ * EINVAL on lmax < 0, n < 1, an angle outside [0, pi] or NULL pointers.
+ */
+int arkcos_tabulate_legendre_at(const double *b_l, int lmax, const double *theta, int n,
+                                double *out);
 
 /*
  * HEALPix RING geometry of ring `ring` (1 .. 4 Nside - 1), as the library's

@@ -12,7 +12,8 @@ Wandelt & Elsner (2012), Sec. 2 (eq. 1, the ARKCoS term of eq. 3):
     out[p] = Omega * sum_{q : theta(p,q) < theta_cut} K(theta(p,q)) in[q]
 
 on HEALPix RING maps, with K linear in theta between ntab nodes on
-[0, theta_cut] (Sec. 3).
+[0, theta_cut] (Sec. 3): uniform nodes, or the biased two-piece table of Sec. 3
+(``paper_bias``, ``grid_nodes``).
 """
 from __future__ import annotations
 
@@ -22,7 +23,7 @@ import os
 import numpy as np
 
 __all__ = ["ArkcosError", "Plan", "Batch", "ArkcosConvFn", "conv", "tabulate_legendre",
-           "ring_info", "gaussian_bl", "library_path", "load_library", "PLAN_HOST_ONLY",
+           "tabulate_legendre_at", "grid_nodes", "paper_bias", "ring_info", "gaussian_bl", "library_path", "load_library", "PLAN_HOST_ONLY",
            "PLAN_LEARNABLE", "PART_CIRCULANT", "PART_GENERAL", "PART_ALL", "MAX_GRAD_NTAB",
            "MAX_NSIDE"]
 
@@ -52,7 +53,8 @@ class ArkcosError(RuntimeError):
 class _PlanDesc(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int), ("theta_cut", ctypes.c_double), ("ntab", ctypes.c_int),
                 ("ktab", ctypes.POINTER(ctypes.c_double)), ("max_batch", ctypes.c_int),
-                ("tile", ctypes.c_int), ("flags", ctypes.c_uint)]
+                ("tile", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("theta_break", ctypes.c_double), ("k_break", ctypes.c_int)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -63,7 +65,8 @@ class _PlanInfo(ctypes.Structure):
                 ("threads_per_block", ctypes.c_int), ("device_bytes", ctypes.c_longlong),
                 ("circulant_rings", ctypes.c_int), ("general_rings", ctypes.c_int),
                 ("circulant_tiles", ctypes.c_longlong), ("general_tiles", ctypes.c_longlong),
-                ("weights", ctypes.c_longlong)]
+                ("weights", ctypes.c_longlong), ("theta_break", ctypes.c_double),
+                ("k_break", ctypes.c_int)]
 
 
 _lib = None
@@ -87,6 +90,8 @@ def load_library():
     lib = ctypes.CDLL(_LIB_PATH)
     sig = {
         "arkcos_tabulate_legendre": [_dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp],
+        "arkcos_tabulate_legendre_at": [_dp, ctypes.c_int, _dp, ctypes.c_int, _dp],
+        "arkcos_grid_nodes": [ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int, _dp],
         "arkcos_ring_info": [ctypes.c_int, ctypes.c_int, _dp, _dp, _ip,
                              ctypes.POINTER(ctypes.c_longlong), _dp],
         "arkcos_plan_create": [ctypes.POINTER(_PlanDesc), ctypes.POINTER(_vp)],
@@ -161,6 +166,32 @@ def tabulate_legendre(b_l, theta_cut: float, ntab: int) -> np.ndarray:
     return out
 
 
+def paper_bias(theta_cut: float, ntab: int) -> tuple[float, int]:
+    """(theta_break, k_break) of the biased table of Sec. 3: half of the nodes
+    (nodes 0..(ntab-1)//2) inside the first 1/16 of the support."""
+    return theta_cut / 16.0, (ntab - 1) // 2
+
+
+def grid_nodes(theta_cut: float, ntab: int, theta_break: float = 0.0, k_break: int = 0
+               ) -> np.ndarray:
+    """Node angles of a table (arkcos_grid_nodes): uniform for (0, 0), else two
+    pieces, each uniform, meeting at node k_break = theta_break."""
+    out = np.empty(ntab, dtype=np.float64)
+    _call("arkcos_grid_nodes", float(theta_cut), int(ntab), float(theta_break), int(k_break),
+          out.ctypes.data_as(_dp))
+    return out
+
+
+def tabulate_legendre_at(b_l, theta) -> np.ndarray:
+    """sum_l (2l+1)/(4 pi) b_l P_l(cos theta) at the given angles (arkcos_tabulate_legendre_at)."""
+    b = np.ascontiguousarray(b_l, dtype=np.float64)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    out = np.empty(th.size, dtype=np.float64)
+    _call("arkcos_tabulate_legendre_at", b.ctypes.data_as(_dp), b.size - 1,
+          th.ctypes.data_as(_dp), th.size, out.ctypes.data_as(_dp))
+    return out
+
+
 def ring_info(nside: int, ring: int) -> dict:
     """Geometry of ring `ring` (1-based) as the library's plan computes it."""
     z, s, p0 = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
@@ -175,11 +206,14 @@ class Plan:
 
     ``ktab`` is a host FP64 node table of ``ntab`` values (copied); with
     ``learnable=True`` it may be omitted and knots set later with ``set_knots``.
+    ``theta_break``/``k_break`` choose the node grid (0, 0: uniform; see
+    ``grid_nodes`` and ``paper_bias``); ``biased=True`` is the Sec. 3 bias.
     """
 
     def __init__(self, nside: int, theta_cut: float, ktab=None, ntab: int | None = None,
                  max_batch: int = 1, tile: int = 0, learnable: bool = False,
-                 host_only: bool = False):
+                 host_only: bool = False, theta_break: float = 0.0, k_break: int = 0,
+                 biased: bool = False):
         if ktab is not None:
             ktab = np.ascontiguousarray(ktab, dtype=np.float64)
             ntab = ktab.size if ntab is None else ntab
@@ -187,16 +221,22 @@ class Plan:
                 raise ValueError("ktab has %d values, ntab is %d" % (ktab.size, ntab))
         if ntab is None:
             raise ValueError("give ktab or ntab")
+        if biased:
+            if theta_break or k_break:
+                raise ValueError("give biased=True or theta_break/k_break, not both")
+            theta_break, k_break = paper_bias(theta_cut, ntab)
         flags = (PLAN_LEARNABLE if learnable else 0) | (PLAN_HOST_ONLY if host_only else 0)
         desc = _PlanDesc(int(nside), float(theta_cut), int(ntab),
                          ktab.ctypes.data_as(_dp) if ktab is not None else None,
-                         int(max_batch), int(tile), flags)
+                         int(max_batch), int(tile), flags, float(theta_break), int(k_break))
         h = _vp()
         _call("arkcos_plan_create", ctypes.byref(desc), ctypes.byref(h))
         self._h = h
         self.nside = int(nside)
         self.theta_cut = float(theta_cut)
         self.ntab = int(ntab)
+        self.theta_break = float(theta_break)
+        self.k_break = int(k_break)
         self.max_batch = int(max_batch)
         self.learnable = learnable
         self.host_only = host_only
@@ -223,6 +263,10 @@ class Plan:
         inf = _PlanInfo()
         _call("arkcos_plan_get_info", self._h, ctypes.byref(inf))
         return {k: getattr(inf, k) for k, _ in _PlanInfo._fields_}
+
+    def nodes(self) -> np.ndarray:
+        """Node angles of the plan's table."""
+        return grid_nodes(self.theta_cut, self.ntab, self.theta_break, self.k_break)
 
     def pair_count(self) -> int:
         c = ctypes.c_ulonglong()

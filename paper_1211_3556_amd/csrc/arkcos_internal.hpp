@@ -60,8 +60,9 @@ constexpr int kPairLongSin = 2;
 static_assert(sizeof(DevPair) == 32, "DevPair layout");
 
 // FP64 copy of the chord constants of a ring pair, used where the node index
-// and fraction must be exact to ~1e-9 (the knot gradient: the hat basis has
-// slope 1/h, so an FP32 angle moves node fractions by ~1e-7 u).
+// and fraction must be exact to ~1e-9: the circulant weight rows (built once
+// per table) and the knot gradient (the hat basis has slope 1/h, so an FP32
+// angle moves node fractions by ~1e-7 u).
 struct DevPairD {
     double A;
     double B;
@@ -129,8 +130,10 @@ struct DevPlanView {
     const DevRing *rings;
     const DevPair *pairs;
     const float *table;      // ntab FP32 values Omega * K_k
-    const DevPairD *pairs_d; // FP64 chord constants (learnable plans), else NULL
-    double inv_h_d;          // (ntab - 1) / theta_cut in FP64
+    const DevPairD *pairs_d; // FP64 chord constants of the pairs
+    double inv_h_d;          // a0 in FP64 (node coordinate map below)
+    double bias_r_d;         // r and c in FP64
+    double bias_c_d;
     const DevGroup *groups;  // circulant ring groups
     const DevRow *rows;      // their source rows
     float *wts;              // their weight rows (written by the weight-build kernel)
@@ -147,9 +150,18 @@ struct DevPlanView {
     int ntab;
     int npix;
     int angle_mode;          // angle series: 0 (theta_cut <= 0.1), 1 (<= 0.5), 2 full range
-    float inv_h;             // (ntab - 1) / theta_cut
-    float u_max;             // ntab - 1 (strict upper bound of u = theta / h)
-    float u_coef[6];         // inv_h times the coefficients of the short angle series
+    // Node coordinate u of an angle (node k at u = k):  u0 = a0 theta, and
+    // u = u0 on a uniform grid (a0 = (ntab-1)/theta_cut), u = min(u0, r u0 + c)
+    // on the two-piece biased grid (a0 = k_break/theta_break the fine piece's
+    // 1/h; r u0 + c the coarse piece's coordinate, which is the smaller one
+    // beyond the break).  r = 1 and c = 0 on a uniform grid.
+    int biased;
+    float inv_h;             // a0
+    float u_max;             // ntab - 1 (strict upper bound of u)
+    float u0_max;            // a0 theta_cut: the cut, tested on u0
+    float bias_r;
+    float bias_c;
+    float u_coef[6];         // a0 times the coefficients of the short angle series
 };
 
 // ------------------------------------------------------- shared FP32 math --

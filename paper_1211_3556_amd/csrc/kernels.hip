@@ -8,7 +8,8 @@
 //  * k_circ (circulant rings: belt rings whose whole disc lies in the belt).
 //    All their source rings have 4N pixels, so the weight of (r, j; s, j')
 //    depends on j' - j only.  Each (r, s) has one weight row, evaluated once
-//    per node table by k_build_weights with exactly the per-pair arithmetic.
+//    per node table by k_build_weights (angles in FP64, weights rounded once
+//    to FP32).
 //    The gather is then a correlation: a workgroup owns kGroupRings
 //    consecutive output rings and kCircSeg pixels of each (4 consecutive
 //    pixels per lane), stages one source row and its weights at a time in
@@ -16,7 +17,7 @@
 //    reads of the weights feed 64 FMAs.
 //
 //  * k_general (polar caps and belt rings whose disc reaches a cap).  Weights
-//    are evaluated per pair from exact ring-pair constants: chord from
+//    are evaluated per pair in FP32 from exact ring-pair constants: chord from
 //    d^2 = A + B sin^2(dphi/2), angle by series, node table in LDS with
 //    linear interpolation.  A quarter turn maps pixel j of a ring to
 //    j + n/4, the N-S mirror maps ring i to ring 4N - i and the reflection
@@ -129,40 +130,6 @@ __device__ __forceinline__ float theta_of(float d2)
     return d * p;
 }
 
-// Interpolated, Omega-scaled weight of one pair (0 at or beyond theta_cut).
-// Branch-free: the node index is clamped into the table and the weight masked.
-template <bool LONG, int AM>
-__device__ __forceinline__ float pair_weight_t(const DevPair &pp, const float *tab, float inv_h,
-                                               float u_max, int m)
-{
-    const float x = (float)m * pp.xscale;          // half the longitude difference
-    const float sx = sin_series<LONG>(x);
-    const float d2 = fmaf(pp.B, sx * sx, pp.A);      // squared chord
-    const float u = theta_of<AM>(d2) * inv_h;
-    const float uc = fminf(u, u_max);
-    const int node = min((int)uc, (int)u_max - 1);
-    const float frac = uc - (float)node;
-    const float k0 = tab[node];
-    const float k1 = tab[node + 1];
-    const float w = fmaf(frac, k1 - k0, k0);
-    return (u < u_max) ? w : 0.0f;
-}
-
-// The same weight with the series chosen at run time from the pair and plan.
-__device__ __forceinline__ float pair_weight(const DevPlanView &P, const DevPair &pp,
-                                             const float *tab, int m)
-{
-    const bool lg = (pp.mode & kPairLongSin) != 0;
-    switch (P.angle_mode) {
-        case 0: return lg ? pair_weight_t<true, 0>(pp, tab, P.inv_h, P.u_max, m)
-                          : pair_weight_t<false, 0>(pp, tab, P.inv_h, P.u_max, m);
-        case 1: return lg ? pair_weight_t<true, 1>(pp, tab, P.inv_h, P.u_max, m)
-                          : pair_weight_t<false, 1>(pp, tab, P.inv_h, P.u_max, m);
-        default: return lg ? pair_weight_t<true, 2>(pp, tab, P.inv_h, P.u_max, m)
-                           : pair_weight_t<false, 2>(pp, tab, P.inv_h, P.u_max, m);
-    }
-}
-
 __device__ __forceinline__ int wrap_index(int jq, int n)
 {
     jq = (jq < 0) ? jq + n : jq;
@@ -207,37 +174,6 @@ struct MapIO {
 };
 
 // ------------------------------------------------------- circulant gather --
-// Weight rows of the circulant groups, one workgroup per row: tap k of ring r
-// is the per-pair weight at the exact longitude numerator
-// m = n (2o_r - 2o_s - 2k), zero where k is outside the (r, s) window.
-__global__ __launch_bounds__(kThreads) void k_build_weights(DevPlanView P)
-{
-    const int row = blockIdx.x;
-    if (row >= P.nrows) return;
-    const DevRow W = P.rows[row];
-    const DevGroup G = P.groups[W.g];
-    const int n = P.rings[G.r0].n;
-    const int two_o_s = P.rings[W.s].two_o;
-    for (int e = threadIdx.x; e < W.ntaps * kGroupRings; e += blockDim.x) {
-        const int t = e / kGroupRings;
-        const int i = e - t * kGroupRings;
-        const int k = W.k_lo + t;
-        float w = 0.0f;
-        if (i < G.nr) {
-            const DevRing R = P.rings[G.r0 + i];
-            const int kk = R.pair_begin + (W.s - P.pairs[R.pair_begin].s);
-            if (kk >= R.pair_begin && kk < R.pair_end) {
-                const DevPair pp = P.pairs[kk];
-                int lo, hi;
-                pair_window(pp, n, 0, lo, hi);
-                if (k >= lo && k <= hi)
-                    w = pair_weight(P, pp, P.table, n * (R.two_o - two_o_s - 2 * k));
-            }
-        }
-        P.wts[W.w_off + e] = w;
-    }
-}
-
 // Source pixels each lane prefetches per row: a row spans at most
 // kCircSeg + kCircMaxTaps - 1 pixels, and the reads of the last tap quad reach
 // kCircSeg + kCircMaxTaps - 1 as well (lane 255, taps padded to 256).
@@ -556,13 +492,17 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
 template <int AM>
 struct GenConst {
     float zslot;     // index of the table's zero entries
-    float u_max;
+    float u_max;     // the cut on u0 (u0_max; ntab - 1 on a uniform grid)
+    float br, bc;    // coarse-piece map of a biased grid
     UCoef ucf;
     __device__ __forceinline__ GenConst(const DevPlanView &P)
-        : zslot(vreg((float)P.ntab)), u_max(vreg(P.u_max)), ucf(ucoef<AM>(P)) {}
+        : zslot(vreg((float)P.ntab)), u_max(vreg(P.u0_max)), br(vreg(P.bias_r)),
+          bc(vreg(P.bias_c)), ucf(ucoef<AM>(P)) {}
 };
 
-template <bool LONG, int AM, bool INTM>
+// BIAS: the plan's node grid is the two-piece biased one, u = min(u0, r u0 + c);
+// otherwise u = u0 and the map costs nothing.
+template <bool LONG, int AM, bool INTM, bool BIAS>
 __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenConst<AM> &gc,
                                                  const float *tab, int m, int dm, int step,
                                                  const float4 *stage, int c0, int cn, int jq,
@@ -592,8 +532,9 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         const float x = (INTM ? (float)mi : mf) * xscale;   // half the longitude difference
         const float sx = sin_series<LONG>(x);
         const float d2 = fmaf(B, sx * sx, A);                // squared chord
-        const float u = node_coord<AM>(d2, ucf);
-        const float uc = (valid && u < u_max) ? u : zslot;
+        const float u0 = node_coord<AM>(d2, ucf);
+        const float u = BIAS ? fminf(u0, fmaf(u0, gc.br, gc.bc)) : u0;
+        const float uc = (valid && u0 < u_max) ? u : zslot;
         const int node = (int)uc;
         const float frac = __builtin_amdgcn_fractf(uc);
         const float k0 = tab[node];
@@ -665,9 +606,9 @@ constexpr int kGenFlush = 48;
 
 // One general tile: its source rows in staged chunks, the candidates of each
 // lane, the sum over the lanes of a pixel and the sixteen output images.
-// LONG and AM are fixed per tile, so the candidate loop has one form and the
-// row sums stay in place across rows.
-template <bool LONG, int AM, bool INTM>
+// LONG, AM, INTM and BIAS are fixed per tile, so the candidate loop has one
+// form and the row sums stay in place across rows.
+template <bool LONG, int AM, bool INTM, bool BIAS>
 __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab, float4 *stage,
                                          const DevTile &T, const float *in, float *out)
 {
@@ -739,7 +680,7 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
         const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
         const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
         const int dm = 2 * nph * R.n;
-        gen_candidates16<LONG, AM, INTM>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt,
+        gen_candidates16<LONG, AM, INTM, BIAS>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt,
                                    row);
         since += nt;
         if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
@@ -782,6 +723,32 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
     }
 }
 
+// The candidate-loop form of a tile: sine series, angle series and numerator
+// type from the tile and plan, the node-grid map from BIAS.
+template <bool BIAS>
+__device__ __forceinline__ void gen_tile_variant(const DevPlanView &P, const float *tab,
+                                                 float4 *stage, const DevTile &T,
+                                                 const float *in, float *out)
+{
+    const bool lg = (T.flags & kTileLongSin) != 0;
+    if (T.flags & kTileIntM) {   // wide windows on large rings (long sine implied)
+        switch (P.angle_mode) {
+            case 0: gen_tile<true, 0, true, BIAS>(P, tab, stage, T, in, out); break;
+            case 1: gen_tile<true, 1, true, BIAS>(P, tab, stage, T, in, out); break;
+            default: gen_tile<true, 2, true, BIAS>(P, tab, stage, T, in, out); break;
+        }
+    } else {
+        switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+            case 0: gen_tile<false, 0, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 1: gen_tile<true, 0, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 2: gen_tile<false, 1, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 3: gen_tile<true, 1, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 4: gen_tile<false, 2, false, BIAS>(P, tab, stage, T, in, out); break;
+            default: gen_tile<true, 2, false, BIAS>(P, tab, stage, T, in, out); break;
+        }
+    }
+}
+
 // Persistent general gather over tiles (plan, north ring, half-quadrant
 // segment) x maps.  LDS: the node table of the current plan followed by two
 // zero entries (the slot of candidates outside the disc), then the stage.
@@ -812,23 +779,10 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
         const DevTile T = cst(P.gtiles)[lt];
         const float *in = io.in[pi] + (size_t)map * P.npix;
         float *out = io.out[pi] + (size_t)map * P.npix;
-        const bool lg = (T.flags & kTileLongSin) != 0;
-        if (T.flags & kTileIntM) {   // wide windows on large rings (long sine implied)
-            switch (P.angle_mode) {
-                case 0: gen_tile<true, 0, true>(P, tab, stage, T, in, out); break;
-                case 1: gen_tile<true, 1, true>(P, tab, stage, T, in, out); break;
-                default: gen_tile<true, 2, true>(P, tab, stage, T, in, out); break;
-            }
-        } else {
-            switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                case 0: gen_tile<false, 0, false>(P, tab, stage, T, in, out); break;
-                case 1: gen_tile<true, 0, false>(P, tab, stage, T, in, out); break;
-                case 2: gen_tile<false, 1, false>(P, tab, stage, T, in, out); break;
-                case 3: gen_tile<true, 1, false>(P, tab, stage, T, in, out); break;
-                case 4: gen_tile<false, 2, false>(P, tab, stage, T, in, out); break;
-                default: gen_tile<true, 2, false>(P, tab, stage, T, in, out); break;
-            }
-        }
+        if (P.biased)
+            gen_tile_variant<true>(P, tab, stage, T, in, out);
+        else
+            gen_tile_variant<false>(P, tab, stage, T, in, out);
     }
 }
 
@@ -923,18 +877,27 @@ __device__ __forceinline__ double theta_d(double d2)
     return sqrt_d(d2) * p;
 }
 
+// FP64 node coordinate map of a plan: u = min(a0 theta, r a0 theta + c)
+// (r = 1, c = 0 on a uniform grid, where the min returns a0 theta exactly).
+struct NodeMapD {
+    double a0, r, c, u_max;
+    __device__ __forceinline__ explicit NodeMapD(const DevPlanView &P)
+        : a0(P.inv_h_d), r(P.bias_r_d), c(P.bias_c_d), u_max((double)(P.ntab - 1)) {}
+};
+
 // Node index and fraction of one pair from the FP64 chord constants; false at
 // or beyond the cut.  (The knot gradient needs the fraction to ~1e-9: the hat
 // basis has slope 1/h in theta.)
 template <bool LONG, int AM>
-__device__ __forceinline__ bool pair_node_d(const DevPairD &pd, double inv_h, double u_max, int m,
+__device__ __forceinline__ bool pair_node_d(const DevPairD &pd, const NodeMapD &nm, int m,
                                             int &node, double &frac)
 {
     const double sx = sin_d<LONG>((double)m * pd.xscale);
-    const double u = theta_d<AM>(fma(pd.B, sx * sx, pd.A)) * inv_h;
-    node = (int)fmin(u, u_max - 1.0);
+    const double u0 = theta_d<AM>(fma(pd.B, sx * sx, pd.A)) * nm.a0;
+    const double u = fmin(u0, fma(u0, nm.r, nm.c));
+    node = (int)fmin(u, nm.u_max - 1.0);
     frac = u - (double)node;
-    return u < u_max;
+    return u < nm.u_max;
 }
 
 // The knot gradient is sum_p g[p] sum_q hat_k(theta_pq) x[q] over the in-disc
@@ -942,9 +905,72 @@ __device__ __forceinline__ bool pair_node_d(const DevPairD &pd, double inv_h, do
 // LDS histogram, written to partials[row][ntab] and reduced in a fixed order
 // by k_knot_reduce.
 
-// FP64 node coordinate u = theta / h of every circulant weight slot
-// (wts layout: row w_off + tap * kGroupRings + ring), or -1 outside the
-// ring's window or disc.  It depends on the geometry only.
+// Circulant weight slots (row w_off + tap * kGroupRings + ring): tap k of
+// ring r of a group on source ring s is the pair at the exact longitude
+// numerator m = n (2o_r - 2o_s - 2k).  FP64 node coordinate u of slot e of
+// row W, or -1 outside the ring's window or disc.  It depends on the
+// geometry only.
+__device__ __forceinline__ double slot_node(const DevPlanView &P, const NodeMapD &nm,
+                                            const DevRow &W, const DevGroup &G, int n,
+                                            int two_o_s, int e)
+{
+    const int t = e / kGroupRings;
+    const int i = e - t * kGroupRings;
+    const int k = W.k_lo + t;
+    if (i >= G.nr) return -1.0;
+    const DevRing R = P.rings[G.r0 + i];
+    const int kk = R.pair_begin + (W.s - P.pairs[R.pair_begin].s);
+    if (kk < R.pair_begin || kk >= R.pair_end) return -1.0;
+    const DevPair pp = P.pairs[kk];
+    int lo, hi;
+    pair_window(pp, n, 0, lo, hi);
+    if (k < lo || k > hi) return -1.0;
+    const DevPairD pd = P.pairs_d[kk];
+    const bool lg = (pp.mode & kPairLongSin) != 0;
+    const int m = n * (R.two_o - two_o_s - 2 * k);
+    int node;
+    double frac;
+    bool in;
+    switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+        case 0: in = pair_node_d<false, 0>(pd, nm, m, node, frac); break;
+        case 1: in = pair_node_d<true, 0>(pd, nm, m, node, frac); break;
+        case 2: in = pair_node_d<false, 1>(pd, nm, m, node, frac); break;
+        case 3: in = pair_node_d<true, 1>(pd, nm, m, node, frac); break;
+        case 4: in = pair_node_d<false, 2>(pd, nm, m, node, frac); break;
+        default: in = pair_node_d<true, 2>(pd, nm, m, node, frac); break;
+    }
+    return in ? (double)node + frac : -1.0;
+}
+
+// Weight rows of the circulant groups, one workgroup per row: the
+// interpolated, Omega-scaled FP32 table at the slot's FP64 node coordinate,
+// rounded once (0 outside the window or disc).  The weights are built once
+// per table, so the FP64 angle costs nothing in the gather and the
+// circulant weights carry no FP32 angle error.
+__global__ __launch_bounds__(kThreads) void k_build_weights(DevPlanView P)
+{
+    const int row = blockIdx.x;
+    if (row >= P.nrows) return;
+    const DevRow W = P.rows[row];
+    const DevGroup G = P.groups[W.g];
+    const int n = P.rings[G.r0].n;
+    const int two_o_s = P.rings[W.s].two_o;
+    const NodeMapD nm(P);
+    for (int e = threadIdx.x; e < W.ntaps * kGroupRings; e += blockDim.x) {
+        const double u = slot_node(P, nm, W, G, n, two_o_s, e);
+        float w = 0.0f;
+        if (u >= 0.0) {
+            const int node = (int)u;               // u < ntab - 1
+            const double frac = u - (double)node;
+            const double k0 = P.table[node];
+            const double k1 = P.table[node + 1];
+            w = (float)fma(frac, k1 - k0, k0);
+        }
+        P.wts[W.w_off + e] = w;
+    }
+}
+
+// FP64 node coordinate of every circulant weight slot (knot gradients).
 __global__ __launch_bounds__(kThreads) void k_build_knotw(DevPlanView P, double *kw)
 {
     const int row = blockIdx.x;
@@ -953,40 +979,9 @@ __global__ __launch_bounds__(kThreads) void k_build_knotw(DevPlanView P, double 
     const DevGroup G = P.groups[W.g];
     const int n = P.rings[G.r0].n;
     const int two_o_s = P.rings[W.s].two_o;
-    const double u_max = (double)(P.ntab - 1);
-    for (int e = threadIdx.x; e < W.ntaps * kGroupRings; e += blockDim.x) {
-        const int t = e / kGroupRings;
-        const int i = e - t * kGroupRings;
-        const int k = W.k_lo + t;
-        double u = -1.0;
-        if (i < G.nr) {
-            const DevRing R = P.rings[G.r0 + i];
-            const int kk = R.pair_begin + (W.s - P.pairs[R.pair_begin].s);
-            if (kk >= R.pair_begin && kk < R.pair_end) {
-                const DevPair pp = P.pairs[kk];
-                int lo, hi;
-                pair_window(pp, n, 0, lo, hi);
-                if (k >= lo && k <= hi) {
-                    const DevPairD pd = P.pairs_d[kk];
-                    const bool lg = (pp.mode & kPairLongSin) != 0;
-                    const int m = n * (R.two_o - two_o_s - 2 * k);
-                    int node;
-                    double frac;
-                    bool in;
-                    switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                        case 0: in = pair_node_d<false, 0>(pd, P.inv_h_d, u_max, m, node, frac); break;
-                        case 1: in = pair_node_d<true, 0>(pd, P.inv_h_d, u_max, m, node, frac); break;
-                        case 2: in = pair_node_d<false, 1>(pd, P.inv_h_d, u_max, m, node, frac); break;
-                        case 3: in = pair_node_d<true, 1>(pd, P.inv_h_d, u_max, m, node, frac); break;
-                        case 4: in = pair_node_d<false, 2>(pd, P.inv_h_d, u_max, m, node, frac); break;
-                        default: in = pair_node_d<true, 2>(pd, P.inv_h_d, u_max, m, node, frac); break;
-                    }
-                    if (in) u = (double)node + frac;
-                }
-            }
-        }
-        kw[W.w_off + e] = u;
-    }
+    const NodeMapD nm(P);
+    for (int e = threadIdx.x; e < W.ntaps * kGroupRings; e += blockDim.x)
+        kw[W.w_off + e] = slot_node(P, nm, W, G, n, two_o_s, e);
 }
 
 // Add c * hat(u) to the histogram (u >= 0: node floor(u), fraction u - node).
@@ -1207,7 +1202,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
 // Candidates T of one lane, as in the general gather: the sixteen products
 // g x of a candidate share its FP64 node coordinate.
 template <bool LONG, int AM>
-__device__ __forceinline__ void knot_candidates16(const DevPairD &pd, double inv_h, double u_max,
+__device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const NodeMapD &nm,
                                                   int m, int dm, const float4 *stage, int c0,
                                                   int cn, int jq, int a1, int T,
                                                   const float gv[16], double *hist)
@@ -1237,7 +1232,7 @@ __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, double inv
         if (jq <= a1 && c != 0.0f) {
             int node;
             double frac;
-            if (pair_node_d<LONG, AM>(pd, inv_h, u_max, m, node, frac)) {
+            if (pair_node_d<LONG, AM>(pd, nm, m, node, frac)) {
                 atomicAdd(&hist[node], (1.0 - frac) * (double)c);
                 atomicAdd(&hist[node + 1], frac * (double)c);
             }
@@ -1262,7 +1257,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
     const DevPlanView P = cst(views)[0];
     float4 *stage = reinterpret_cast<float4 *>(hist + ((P.ntab + 1) & ~1));
     for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) hist[i] = 0.0;
-    const double u_max = (double)(P.ntab - 1);
+    const NodeMapD nm(P);
     const int ph = threadIdx.x & 1;
     const int lane_pix = threadIdx.x >> 1;
     const int nitems = P.ngtiles * nmaps;
@@ -1340,12 +1335,12 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
             const int dm = 4 * R.n;
             const bool lg = (pp.mode & kPairLongSin) != 0;
             switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                case 0: knot_candidates16<false, 0>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                case 1: knot_candidates16<true, 0>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                case 2: knot_candidates16<false, 1>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                case 3: knot_candidates16<true, 1>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                case 4: knot_candidates16<false, 2>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                default: knot_candidates16<true, 2>(pd, P.inv_h_d, u_max, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 0: knot_candidates16<false, 0>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 1: knot_candidates16<true, 0>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 2: knot_candidates16<false, 1>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 3: knot_candidates16<true, 1>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 4: knot_candidates16<false, 2>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                default: knot_candidates16<true, 2>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
             }
             ch = nx;
         }

@@ -60,7 +60,6 @@ DevPlanView Plan::view() const
     v.pairs = d_pairs;
     v.table = d_table;
     v.pairs_d = d_pairs_d;
-    v.inv_h_d = (desc.ntab - 1) / desc.theta_cut;
     v.groups = d_groups;
     v.rows = d_rows;
     v.wts = d_wts;
@@ -77,9 +76,27 @@ DevPlanView Plan::view() const
     v.ntab = desc.ntab;
     v.npix = (int)npix;
     v.angle_mode = angle_mode;
-    const double ih = (desc.ntab - 1) / desc.theta_cut;
+    // node coordinate map: u0 = a0 theta, u = min(u0, r u0 + c)
+    const bool biased = desc.k_break > 0;
+    double ih = (desc.ntab - 1) / desc.theta_cut, r = 1.0, c0 = 0.0;
+    if (biased) {
+        const double a1 = (desc.ntab - 1 - desc.k_break) / (desc.theta_cut - desc.theta_break);
+        ih = desc.k_break / desc.theta_break;
+        r = a1 / ih;
+        // c >= 0 since the first piece is at least as fine as the second;
+        // clamping its rounding keeps u >= 0 (the node index and fraction of
+        // a self-pair at theta = 0 must be 0)
+        c0 = std::max(0.0, desc.k_break - desc.theta_break * a1);
+    }
+    v.biased = biased ? 1 : 0;
+    v.inv_h_d = ih;
+    v.bias_r_d = r;
+    v.bias_c_d = c0;
     v.inv_h = (float)ih;
     v.u_max = (float)(desc.ntab - 1);
+    v.u0_max = biased ? (float)(ih * desc.theta_cut) : v.u_max;
+    v.bias_r = (float)r;
+    v.bias_c = (float)c0;
     // theta = d (1 + d^2/24 + 3 d^4/640 + 5 d^6/7168 + 35 d^8/294912 + 63 d^10/2883584)
     const double c[6] = {1.0, 1.0 / 24.0, 3.0 / 640.0, 5.0 / 7168.0, 35.0 / 294912.0,
                          63.0 / 2883584.0};
@@ -385,12 +402,11 @@ static unsigned long long count_pairs(const Plan &P, unsigned long long *circ_to
 // c_l = (2l+1) b_l / (4 pi): with alpha_k = (2k+1) x / (k+1) and
 // beta_k = -k / (k+1), y_k = c_k + alpha_k y_{k+1} + beta_{k+1} y_{k+2},
 // y_{L+1} = y_{L+2} = 0, and the sum is y_0.
-static void tabulate(const double *bl, int lmax, double theta_cut, int ntab, double *out)
+static void tabulate_at(const double *bl, int lmax, const double *theta, int n, double *out)
 {
-    const double h = theta_cut / (double)(ntab - 1);
     const double inv4pi = 1.0 / (4.0 * M_PI);
-    for (int k = 0; k < ntab; ++k) {
-        const double x = std::cos(k * h);
+    for (int k = 0; k < n; ++k) {
+        const double x = std::cos(theta[k]);
         double y1 = 0.0, y2 = 0.0;  // y_{l+1}, y_{l+2}
         for (int l = lmax; l >= 0; --l) {
             const double alpha = (2.0 * l + 1.0) * x / (l + 1.0);
@@ -401,6 +417,36 @@ static void tabulate(const double *bl, int lmax, double theta_cut, int ntab, dou
         }
         out[k] = y1;
     }
+}
+
+// Node angles of the grid of a plan descriptor (uniform, or two pieces that
+// are each uniform: the biased table of Sec. 3).
+static void grid_nodes(double tc, int ntab, double tb, int kb, double *out)
+{
+    if (kb == 0) {
+        const double h = tc / (double)(ntab - 1);
+        for (int k = 0; k < ntab; ++k) out[k] = k * h;
+    } else {
+        for (int k = 0; k <= kb; ++k) out[k] = tb * ((double)k / kb);
+        for (int k = kb + 1; k < ntab; ++k)
+            out[k] = tb + (tc - tb) * ((double)(k - kb) / (ntab - 1 - kb));
+        out[kb] = tb;
+    }
+    out[ntab - 1] = tc;
+}
+
+// Validity of a node grid; EINVAL with a message, else ARKCOS_OK.
+static int check_grid(double tc, int ntab, double tb, int kb)
+{
+    if (tb == 0.0 && kb == 0) return ARKCOS_OK;
+    if (!(tb > 0.0 && tb < tc))
+        return fail(ARKCOS_EINVAL, "theta_break must lie in (0, theta_cut), or be 0 with k_break 0");
+    if (kb < 1 || kb > ntab - 2)
+        return fail(ARKCOS_EINVAL, "k_break must lie in 1..ntab-2, or be 0 with theta_break 0");
+    if (tb / kb > (tc - tb) / (ntab - 1 - kb) * (1.0 + 1e-12))
+        return fail(ARKCOS_EINVAL, "the first piece of a biased grid must be at least as fine "
+                                   "as the second");
+    return ARKCOS_OK;
 }
 
 static void free_device(Plan &P)
@@ -483,6 +529,7 @@ static int to_device(Plan &P)
     P.device_bytes = 0;
     if ((rc = upload(&P.d_rings, P.dev_rings, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_pairs, P.pairs, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_pairs_d, P.pairs_d, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_groups, P.groups, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_rows, P.rows, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_ctiles, P.ctiles, &P.device_bytes))) return rc;
@@ -497,7 +544,6 @@ static int to_device(Plan &P)
     if ((P.desc.flags & ARKCOS_PLAN_LEARNABLE) && P.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
         std::vector<double> z((size_t)P.grid * P.desc.ntab, 0.0);
         if ((rc = upload(&P.d_kpart, z, &P.device_bytes))) return rc;
-        if ((rc = upload(&P.d_pairs_d, P.pairs_d, &P.device_bytes))) return rc;
         if ((rc = upload(&P.d_kctiles, P.kctiles, &P.device_bytes))) return rc;
         if ((rc = upload(&P.d_kw, std::vector<double>((size_t)std::max<long long>(P.nweights, 1), -1.0),
                          &P.device_bytes)))
@@ -548,7 +594,38 @@ int arkcos_tabulate_legendre(const double *b_l, int lmax, double theta_cut, int 
     if (ntab < 2) return fail(ARKCOS_EINVAL, "ntab must be >= 2");
     if (!(theta_cut > 0.0) || theta_cut > M_PI)
         return fail(ARKCOS_EINVAL, "theta_cut must lie in (0, pi]");
-    tabulate(b_l, lmax, theta_cut, ntab, ktab_out);
+    std::vector<double> th(ntab);
+    const double h = theta_cut / (double)(ntab - 1);
+    for (int k = 0; k < ntab; ++k) th[k] = k * h;
+    tabulate_at(b_l, lmax, th.data(), ntab, ktab_out);
+    return ARKCOS_OK;
+}
+
+int arkcos_tabulate_legendre_at(const double *b_l, int lmax, const double *theta, int n,
+                                double *out)
+{
+    clear_error();
+    if (!b_l || !theta || !out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    if (lmax < 0) return fail(ARKCOS_EINVAL, "lmax must be >= 0");
+    if (n < 1) return fail(ARKCOS_EINVAL, "n must be >= 1");
+    for (int k = 0; k < n; ++k)
+        if (!(theta[k] >= 0.0 && theta[k] <= M_PI))
+            return fail(ARKCOS_EINVAL, "angles must lie in [0, pi]");
+    tabulate_at(b_l, lmax, theta, n, out);
+    return ARKCOS_OK;
+}
+
+int arkcos_grid_nodes(double theta_cut, int ntab, double theta_break, int k_break,
+                      double *theta_out)
+{
+    clear_error();
+    if (!theta_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    if (ntab < 2) return fail(ARKCOS_EINVAL, "ntab must be >= 2");
+    if (!(theta_cut > 0.0) || theta_cut > M_PI)
+        return fail(ARKCOS_EINVAL, "theta_cut must lie in (0, pi]");
+    int rc = check_grid(theta_cut, ntab, theta_break, k_break);
+    if (rc) return rc;
+    grid_nodes(theta_cut, ntab, theta_break, k_break, theta_out);
     return ARKCOS_OK;
 }
 
@@ -586,6 +663,8 @@ int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
         return fail(ARKCOS_EINVAL, "ktab may be NULL only for a learnable plan");
     if (desc->flags & ~(ARKCOS_PLAN_HOST_ONLY | ARKCOS_PLAN_LEARNABLE))
         return fail(ARKCOS_EINVAL, "unknown flag bits");
+    if (int rc = check_grid(desc->theta_cut, desc->ntab, desc->theta_break, desc->k_break))
+        return rc;
     const long long npix = 12LL * desc->nside * desc->nside;
     if ((long long)desc->max_batch * npix > 0x7fffffffLL * 4)
         return fail(ARKCOS_EUNSUPPORTED, "max_batch * Npix too large");
@@ -653,6 +732,8 @@ int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info)
     info->circulant_tiles = (long long)P->ctiles.size();
     info->general_tiles = (long long)P->gtiles.size();
     info->weights = P->nweights;
+    info->theta_break = P->desc.theta_break;
+    info->k_break = P->desc.k_break;
     return ARKCOS_OK;
 }
 

@@ -45,6 +45,27 @@ def to_host(t) -> np.ndarray:
 REL_RMS_TOL = 1e-6
 
 
+def angle_condition(theta_cut: float, ktab, nodes=None, samples: int = 200001) -> float:
+    """kappa = rms(theta K'(theta)) / rms(K(theta)) over the disc (area weight
+    sin theta), from the oracle's interpolated kernel.  An FP32 angle with
+    relative error e moves a weight by e theta K', so a direct sum over white
+    noise carries a relative rms error of about e kappa."""
+    th = np.linspace(0.0, theta_cut, samples)[:-1]
+    k = O.kernel_eval(theta_cut, ktab, th, nodes=nodes)
+    dk = np.gradient(k, th)
+    w = np.sin(th)
+    return float(np.sqrt(np.sum((th * dk) ** 2 * w) / np.sum(k * k * w)))
+
+
+def angle_tolerance(theta_cut: float, ktab, nodes=None) -> float:
+    """Relative rms error bar of a GPU output for a kernel of angle condition
+    kappa: REL_RMS_TOL, or 2 eps_32 kappa where that is larger.  The FP32 chord
+    and angle series of the general gather round about six times, each within
+    eps_32/2, so the angle's relative rms error stays below 2 eps_32."""
+    eps = float(np.finfo(np.float32).eps)
+    return max(REL_RMS_TOL, 2.0 * eps * angle_condition(theta_cut, ktab, nodes))
+
+
 def assert_tie_free(nside: int, theta_cut: float, rel: float = 1e-7) -> None:
     """No pixel pair sits on the cut: at such lattice ties the strict test
     theta < theta_cut is decided by the last bit of either computation."""

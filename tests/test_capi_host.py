@@ -230,3 +230,72 @@ def test_ring_classes_cover_every_ring(nside, tc_deg):
         assert inf["general_tiles"] == tiles
     if inf["circulant_rings"]:
         assert inf["weights"] > 0 and inf["circulant_tiles"] > 0
+
+
+# ---------------------------------------------------------- biased grid --
+
+@pytest.mark.parametrize("tc,ntab,tb_frac,kb", [
+    (np.radians(2.0), 16384, 1 / 16, 8191), (0.3, 257, 1 / 16, 128), (0.3, 4, 0.1, 1),
+    (np.pi, 1000, 0.25, 700), (0.01, 3, 0.4, 1),
+])
+def test_grid_nodes_match_oracle(tc, ntab, tb_frac, kb):
+    tb = tb_frac * tc
+    a = A.grid_nodes(tc, ntab, tb, kb)
+    o = O.two_piece_nodes(tc, ntab, tb, kb)
+    assert a[0] == 0.0 and a[-1] == tc and a[kb] == tb
+    np.testing.assert_allclose(a, o, rtol=4e-16, atol=0)
+    u = A.grid_nodes(tc, ntab)
+    np.testing.assert_allclose(u, tc * np.arange(ntab) / (ntab - 1), rtol=4e-16, atol=0)
+    assert u[-1] == tc
+
+
+def test_paper_bias_matches_oracle():
+    for ntab in (2 + 1, 4, 4096, 16384, 16385):
+        assert A.paper_bias(0.2, ntab) == O.paper_bias(0.2, ntab)
+
+
+@pytest.mark.parametrize("tb,kb,msg", [
+    (0.01, 0, "k_break"), (0.0, 3, "theta_break"), (0.2, 3, "theta_break"),
+    (-0.01, 3, "theta_break"), (0.01, 15, "k_break"), (0.01, -1, "k_break"),
+    (0.15, 1, "fine"),
+])
+def test_grid_argument_errors(tb, kb, msg):
+    with pytest.raises(A.ArkcosError) as e:
+        A.Plan(8, 0.2, np.ones(16), host_only=True, theta_break=tb, k_break=kb)
+    assert e.value.status == -1 and msg in str(e.value)
+    with pytest.raises(A.ArkcosError) as e:
+        A.grid_nodes(0.2, 16, tb, kb)
+    assert e.value.status == -1
+
+
+def test_biased_plan_info_and_nodes():
+    tc = np.radians(3.0)
+    p = A.Plan(16, tc, np.ones(101), host_only=True, biased=True)
+    inf = p.info()
+    assert inf["k_break"] == 50 and inf["theta_break"] == tc / 16
+    nodes = p.nodes()
+    assert nodes[50] == tc / 16 and nodes[-1] == tc
+    with pytest.raises(ValueError):
+        A.Plan(16, tc, np.ones(101), host_only=True, biased=True, k_break=3)
+    # the grid changes neither the geometry nor the pair count
+    q = A.Plan(16, tc, np.ones(101), host_only=True)
+    assert q.pair_count() == p.pair_count() and q.info()["tiles"] == inf["tiles"]
+
+
+def test_tabulate_at_nodes_matches_oracle():
+    am = np.pi / 180 / 60
+    bl = O.gaussian_bl(5.0 * am, 6143)
+    tc = 15.0 * am
+    nodes = O.biased_nodes(tc, 2049)
+    ko = O.tabulate(bl, tc, nodes.size, nodes=nodes)
+    ka = A.tabulate_legendre_at(bl, A.grid_nodes(tc, 2049, *A.paper_bias(tc, 2049)))
+    assert np.max(np.abs(ka - ko)) < 2e-14 * 6143 * np.abs(ko).max()
+    lib = A.load_library()
+    th = np.array([0.1, 3.5])
+    out = np.empty(2)
+    f = lib.arkcos_tabulate_legendre_at
+    assert f(bl.ctypes.data_as(A._dp), 10, th.ctypes.data_as(A._dp), 2,
+             out.ctypes.data_as(A._dp)) == -1                       # angle above pi
+    assert f(bl.ctypes.data_as(A._dp), 10, th.ctypes.data_as(A._dp), 0,
+             out.ctypes.data_as(A._dp)) == -1
+    assert f(None, 10, th.ctypes.data_as(A._dp), 1, out.ctypes.data_as(A._dp)) == -1

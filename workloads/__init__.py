@@ -131,10 +131,41 @@ def eval_pixels(nside: int, size: int, seed: int, max_strata_ring_pixels: int | 
     return np.array(sorted(pick), dtype=np.int64)
 
 
-def gaussian_profile_knots(fwhm: float, theta_cut: float, ntab: int) -> np.ndarray:
-    """Synthetic node values: a small-angle Gaussian profile
-    exp(-theta^2 / (2 sigma^2)) / (2 pi sigma^2) sampled at k theta_cut/(ntab-1).
-    Used where both sides must start from byte-identical knots."""
+def gaussian_profile_at(fwhm: float, theta) -> np.ndarray:
+    """Synthetic node values: the small-angle Gaussian profile
+    exp(-theta^2 / (2 sigma^2)) / (2 pi sigma^2) at the given angles."""
     sigma = fwhm / np.sqrt(8.0 * np.log(2.0))
-    theta = np.arange(ntab) * (theta_cut / (ntab - 1))
+    theta = np.asarray(theta, dtype=np.float64)
     return np.exp(-0.5 * (theta / sigma) ** 2) / (2.0 * np.pi * sigma * sigma)
+
+
+def gaussian_profile_knots(fwhm: float, theta_cut: float, ntab: int) -> np.ndarray:
+    """gaussian_profile_at sampled at k theta_cut/(ntab-1).  Used where both
+    sides must start from byte-identical knots."""
+    return gaussian_profile_at(fwhm, np.arange(ntab) * (theta_cut / (ntab - 1)))
+
+
+# The ell at which the split example of Sec. 3 truncates its harmonic-space
+# kernel.  The real-space part of such a split carries the beam's content
+# above it and oscillates at small angles, which is what the biased table of
+# Sec. 3 is for.
+SPLIT_ELL = 1500
+
+# Biased-table workload: Nside 2048, 5 arcmin beam restricted to
+# SPLIT_ELL < l <= 6143, theta_cut 15 arcmin, 16384 nodes with half of them
+# inside theta_cut / 16.
+C3B = MapSpec(nside=2048, fwhm=5.0 * ARCMIN, theta_cut=15.0 * ARCMIN, ntab=16384, seed=3,
+              lmax=6143)
+
+
+# The split example of Sec. 3 at the paper's map size: a 7 arcmin beam with
+# l <= 4096, the harmonic part truncated at l = 1500, the real-space part cut
+# at 240 arcmin, on a 16384-node biased table.
+SPLIT_EXAMPLE = MapSpec(nside=2048, fwhm=7.0 * ARCMIN, theta_cut=240.0 * ARCMIN, ntab=16384,
+                        seed=7, lmax=4096)
+
+
+def high_ell_mask(lmax: int, ell_split: int = SPLIT_ELL) -> np.ndarray:
+    """0/1 weights over l = 0..lmax keeping l > ell_split: applied to a beam's
+    b_l it gives the real-space part of a sharp harmonic split."""
+    return (np.arange(lmax + 1) > ell_split).astype(np.float64)
