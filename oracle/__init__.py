@@ -14,6 +14,9 @@ through ctypes.  This module adds:
   applied to the interpolated, truncated real-space kernel (Gauss-Legendre on
   every linear segment of the table);
 * ``real_ylm`` -- real spherical harmonics for the Funk-Hecke checks;
+* ``harmonic`` -- the harmonic-space half of the split: the truncated
+  l-space kernel applied by spherical-harmonic analysis (pixel quadrature)
+  and synthesis, written out as plain sums;
 * ``two_piece_nodes`` / ``paper_bias`` -- the biased node placement of Sec. 3
   (half of the nodes inside the first 1/16 of the support) as an explicit
   node list, which every kernel-table function here accepts as ``nodes``.
@@ -64,6 +67,8 @@ def _load():
                                       _dp, _dp, _dp, _dp]
         lib.orc_kernel_eval.argtypes = [ctypes.c_double, ctypes.c_long, _dp, _dp, ctypes.c_long,
                                         _dp, _dp]
+        lib.orc_harmonic.argtypes = [ctypes.c_long, ctypes.c_long, _dp, _dp, _dp]
+        lib.orc_legendre_lm.argtypes = [ctypes.c_long, ctypes.c_double, _dp]
         lib.orc_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -257,6 +262,28 @@ def legendre_coefficients(ktab, theta_cut: float, ells, order: int = 12, nodes=N
     base = 2.0 * np.pi * width * ww[None, :] * kval * np.sin(theta)
     ct = np.cos(theta)
     return np.array([np.sum(base * eval_legendre(int(l), ct)) for l in np.atleast_1d(ells)])
+
+
+def harmonic(nside: int, khat, x) -> np.ndarray:
+    """The harmonic-space half of the split (Sec. 2, eq. 1): Khat_l, l <= lcut =
+    len(khat) - 1, applied by spherical-harmonic analysis with the pixel
+    quadrature a_lm = Omega sum_p x_p conj(Y_lm(p)) and synthesis
+    y_p = sum_l Khat_l sum_m a_lm Y_lm(p)."""
+    khat = np.ascontiguousarray(khat, dtype=np.float64)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.size != npix(nside):
+        raise ValueError("map has %d pixels, Nside %d needs %d" % (x.size, nside, npix(nside)))
+    y = np.empty_like(x)
+    _check(_load().orc_harmonic(nside, khat.size - 1, _d(khat), _d(x), _d(y)), "harmonic")
+    return y
+
+
+def legendre_lm(lmax: int, theta: float) -> np.ndarray:
+    """Orthonormal lambda_lm(cos theta), 0 <= m <= l <= lmax, as an
+    (lmax+1, lmax+1) array indexed [l, m] (zero above the diagonal)."""
+    out = np.zeros((lmax + 1, lmax + 1))
+    _check(_load().orc_legendre_lm(lmax, float(theta), _d(out)), "legendre_lm")
+    return out
 
 
 def real_ylm(ell: int, m: int, vec) -> np.ndarray:

@@ -483,3 +483,66 @@ def test_bias_trades_outer_for_inner_interpolation_error():
     assert err["bia"][0] < err["uni"][0] / 50.0
     assert err["bia"][1] < err["uni"][1] * (15 / 8) ** 2 * 1.05
     assert err["bia"][1] > err["uni"][1] * 3.0
+
+
+# ------------------------------------------------ harmonic-space half (SHT) --
+# The l-space half of the split applies Khat_l, l <= lcut, by analysis with the
+# pixel quadrature and synthesis.  By the addition theorem
+#     sum_m Y_lm(p) conj(Y_lm(q)) = (2l+1)/(4 pi) P_l(cos theta_pq),
+# that operator is exactly the all-pairs sum with the untruncated Legendre
+# kernel Omega sum_l (2l+1)/(4 pi) Khat_l P_l(cos theta_pq): a closed form
+# the pins below evaluate with scipy, independently of the transforms.
+
+@pytest.mark.parametrize("theta", [0.0, 0.3, 1.1, np.pi / 2, 2.9])
+def test_legendre_lm_matches_scipy(theta):
+    from scipy.special import sph_harm_y
+    L = 40
+    lam = O.legendre_lm(L, theta)
+    for l in range(L + 1):
+        for m in range(l + 1):
+            ref = sph_harm_y(l, m, theta, 0.0).real
+            assert abs(lam[l, m] - ref) < 1e-13 * max(1.0, abs(ref)), (l, m)
+
+
+def _addition_theorem(nside, khat, x):
+    v = O.pix2vec(nside)
+    c = np.clip(v @ v.T, -1.0, 1.0)
+    kern = sum((2 * l + 1) / (4 * np.pi) * khat[l] * eval_legendre(l, c)
+               for l in range(khat.size))
+    return (4 * np.pi / x.size) * kern @ x
+
+
+@pytest.mark.parametrize("nside,lcut", [(1, 0), (1, 9), (2, 5), (2, 30), (4, 11), (4, 23),
+                                        (8, 23), (8, 40)])
+def test_harmonic_equals_addition_theorem_sum(nside, lcut):
+    """lcut below, at and above 3 Nside - 1 (longitude frequencies above the
+    ring lengths included): the transform pair equals the all-pairs sum."""
+    rng = np.random.default_rng(100 * nside + lcut)
+    x = rng.standard_normal(12 * nside * nside)
+    khat = rng.uniform(-1.0, 1.0, lcut + 1)
+    y = O.harmonic(nside, khat, x)
+    ref = _addition_theorem(nside, khat, x)
+    np.testing.assert_allclose(y, ref, rtol=0, atol=1e-12 * np.abs(ref).max())
+
+
+def test_harmonic_monopole_closed_form():
+    """lcut = 0: y = Khat_0 (Omega sum x) / (4 pi) on every pixel."""
+    nside = 16
+    x = np.random.default_rng(5).standard_normal(12 * nside * nside)
+    y = O.harmonic(nside, [2.5], x)
+    np.testing.assert_allclose(y, 2.5 * (4 * np.pi / x.size) * x.sum() / (4 * np.pi),
+                               rtol=1e-12)
+
+
+def test_harmonic_band_limited_quadrature_convergence():
+    """A band-limited Y_lm input with l <= lcut comes back scaled by Khat_l up
+    to the HEALPix quadrature error, which falls as Nside grows."""
+    ell, m = 5, 3
+    khat = np.linspace(1.0, 2.0, 12)
+    errs = []
+    for nside in (8, 16, 32):
+        f = O.real_ylm(ell, m, O.pix2vec(nside))
+        y = O.harmonic(nside, khat, f)
+        errs.append(np.sqrt(np.mean((y - khat[ell] * f) ** 2) / np.mean((khat[ell] * f) ** 2)))
+    assert errs[2] < 1e-2
+    assert errs[1] < errs[0] / 2.0 and errs[2] < errs[1] / 2.0
