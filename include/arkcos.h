@@ -39,6 +39,7 @@ extern "C" {
 
 typedef struct arkcos_plan *arkcos_plan_t;    /* opaque; owns host + device plan data */
 typedef struct arkcos_batch *arkcos_batch_t;  /* opaque; owns a tile queue over plans  */
+typedef struct arkcos_harm *arkcos_harm_t;    /* opaque; harmonic-space half of a split */
 
 enum {
     ARKCOS_OK = 0,
@@ -58,6 +59,8 @@ enum {
 #define ARKCOS_MAX_NSIDE 8192
 /* Largest node count for which knot gradients are supported. */
 #define ARKCOS_MAX_GRAD_NTAB 8192
+/* Largest l_cut of the harmonic-space half (one order's coefficients fit LDS). */
+#define ARKCOS_MAX_LCUT 4095
 
 typedef struct {
     int nside;            /* HEALPix resolution, 1 .. ARKCOS_MAX_NSIDE (any integer)       */
@@ -304,6 +307,62 @@ int arkcos_batch_destroy(arkcos_batch_t batch);
 /* ----------------------------------------------------------- diagnostics -- */
 
 /* Static text for a status code. */
+/* ------------------------------------------- harmonic-space half (SHT) -- */
+
+/*
+ * The l-space half of the split convolution (Sec. 2, eq. 1, and the
+ * l-space cost eq. 4): the truncated harmonic kernel Khat_l, l <= lcut,
+ * applied by spherical-harmonic analysis with the pixel quadrature and
+ * synthesis on a HEALPix RING map,
+ *     a_lm = Omega sum_p in[p] conj(Y_lm(p)),
+ *     out[p] = sum_{l <= lcut} Khat_l sum_{m=-l..l} a_lm Y_lm(p),
+ * with orthonormal Y_lm.  By the addition theorem this equals the all-pairs
+ * sum Omega sum_q K_l(theta_pq) in[q] with the untruncated kernel
+ * K_l(theta) = sum_l (2l+1)/(4 pi) Khat_l P_l(cos theta).  The paper applies
+ * this half on host cores; here it runs on the GPU in FP64.
+ *
+ * arkcos_harm_create: Nside 1..ARKCOS_MAX_NSIDE, lcut 0..ARKCOS_MAX_LCUT
+ * (EUNSUPPORTED above), khat host FP64 of lcut+1 values (copied), max_batch
+ * >= 1.  Allocates device memory on the current device (synchronously):
+ * per-ring longitude sums (lcut+1) x (4 Nside - 1) complex FP64, per-chunk
+ * partial coefficients, recurrence tables.  EINVAL, ENOMEM, EDEVICE.
+ */
+int arkcos_harm_create(int nside, int lcut, const double *khat, int max_batch,
+                       arkcos_harm_t *out);
+
+/* Release a transform plan (synchronises the device).  NULL is accepted. */
+int arkcos_harm_destroy(arkcos_harm_t harm);
+
+/* Replace Khat_l (host FP64, lcut+1 values; synchronous upload). */
+int arkcos_harm_set_kernel(arkcos_harm_t harm, const double *khat);
+
+/* Nside, lcut, number of (l, m >= 0) coefficients and device bytes; any
+ * out-pointer may be NULL. */
+int arkcos_harm_get_info(arkcos_harm_t harm, int *nside, int *lcut, long long *nalm,
+                         long long *device_bytes);
+
+/*
+ * The l-space half on nbatch maps (same layout as arkcos_convolve).
+ *   d_in        device FP32, nbatch x Npix                                [in]
+ *   d_out       device FP32, nbatch x Npix: overwritten (accumulate = 0) or
+ *               added to (accumulate = 1)                                  [out]
+ * d_in and d_out must not overlap.  Stream-ordered, no allocation or
+ * synchronisation; a transform plan serves one stream at a time (its
+ * workspace is shared by its calls).  EINVAL on bad arguments.
+ */
+int arkcos_harm_convolve(arkcos_harm_t harm, const float *d_in, float *d_out, int nbatch,
+                         int accumulate, void *stream);
+
+/*
+ * The full split convolution of Sec. 2 (eq. 1): out = (real-space half of
+ * `plan`) + (l-space half of `harm`), i.e. the approximate kernel
+ * Ktilde_l = Khat_l + P_{l theta} Khat_theta applied to each map.  The two
+ * halves run back to back on `stream`.  The plans must share Nside (EINVAL);
+ * other arguments and errors as arkcos_convolve and arkcos_harm_convolve.
+ */
+int arkcos_split_convolve(arkcos_plan_t plan, arkcos_harm_t harm, const float *d_in,
+                          float *d_out, int nbatch, void *stream);
+
 const char *arkcos_status_string(int status);
 
 /* Per-thread detail of the last failing call ("" if none). */

@@ -22,7 +22,8 @@ import os
 
 import numpy as np
 
-__all__ = ["ArkcosError", "Plan", "Batch", "ArkcosConvFn", "conv", "tabulate_legendre",
+__all__ = ["ArkcosError", "Plan", "Batch", "Harm", "split_convolve", "ArkcosConvFn", "conv",
+           "tabulate_legendre",
            "tabulate_legendre_at", "grid_nodes", "paper_bias", "ring_info", "gaussian_bl", "library_path", "load_library", "PLAN_HOST_ONLY",
            "PLAN_LEARNABLE", "PART_CIRCULANT", "PART_GENERAL", "PART_ALL", "MAX_GRAD_NTAB",
            "MAX_NSIDE"]
@@ -37,6 +38,7 @@ PART_GENERAL = 2
 PART_ALL = 3
 MAX_NSIDE = 8192
 MAX_GRAD_NTAB = 8192
+MAX_LCUT = 4095
 
 _STATUS = {0: "ARKCOS_OK", -1: "ARKCOS_EINVAL", -2: "ARKCOS_ENOMEM", -3: "ARKCOS_EDEVICE",
            -4: "ARKCOS_EUNSUPPORTED", -5: "ARKCOS_ESTATE"}
@@ -111,6 +113,13 @@ def load_library():
         "arkcos_batch_convolve_part": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int,
                                        _vp],
         "arkcos_batch_destroy": [_vp],
+        "arkcos_harm_create": [ctypes.c_int, ctypes.c_int, _dp, ctypes.c_int, ctypes.POINTER(_vp)],
+        "arkcos_harm_destroy": [_vp],
+        "arkcos_harm_set_kernel": [_vp, _dp],
+        "arkcos_harm_get_info": [_vp, _ip, _ip, ctypes.POINTER(ctypes.c_longlong),
+                                 ctypes.POINTER(ctypes.c_longlong)],
+        "arkcos_harm_convolve": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
+        "arkcos_split_convolve": [_vp, _vp, _vp, _vp, ctypes.c_int, _vp],
         "arkcos_status_string": [ctypes.c_int],
         "arkcos_last_error": [],
         "arkcos_version": [],
@@ -442,3 +451,92 @@ class Batch:
         ous = (_vp * n)(*[o.data_ptr() for o in outs])
         _call("arkcos_batch_convolve_part", self._h, ins, ous, int(part), _stream_ptr(stream))
         return outs
+
+
+class Harm:
+    """The harmonic-space half of a split convolution (arkcos_harm_*): Khat_l,
+    l <= lcut = len(khat) - 1, applied by spherical-harmonic analysis (pixel
+    quadrature) and synthesis on the GPU."""
+
+    def __init__(self, nside: int, khat, max_batch: int = 1):
+        k = np.ascontiguousarray(khat, dtype=np.float64)
+        if k.ndim != 1 or k.size < 1:
+            raise ValueError("khat must be a 1-D array of lcut + 1 values")
+        h = _vp()
+        _call("arkcos_harm_create", int(nside), k.size - 1, k.ctypes.data_as(_dp), int(max_batch),
+              ctypes.byref(h))
+        self._h = h
+        self.nside = int(nside)
+        self.lcut = k.size - 1
+        self.npix = 12 * self.nside * self.nside
+        self.max_batch = int(max_batch)
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().arkcos_harm_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n, lc = ctypes.c_int(), ctypes.c_int()
+        na, db = ctypes.c_longlong(), ctypes.c_longlong()
+        _call("arkcos_harm_get_info", self._h, ctypes.byref(n), ctypes.byref(lc),
+              ctypes.byref(na), ctypes.byref(db))
+        return {"nside": n.value, "lcut": lc.value, "nalm": na.value, "device_bytes": db.value}
+
+    def set_kernel(self, khat) -> None:
+        k = np.ascontiguousarray(khat, dtype=np.float64)
+        if k.size != self.lcut + 1:
+            raise ValueError("khat must have lcut + 1 = %d values" % (self.lcut + 1))
+        _call("arkcos_harm_set_kernel", self._h, k.ctypes.data_as(_dp))
+
+    def _shape(self, x):
+        if x.dim() == 1 and x.numel() == self.npix:
+            return 1
+        if x.dim() == 2 and x.shape[1] == self.npix:
+            return x.shape[0]
+        raise ValueError("map must have shape (Npix,) or (B, Npix) with Npix = %d" % self.npix)
+
+    def convolve(self, x, out=None, accumulate: bool = False, stream=None):
+        """The l-space half of a (Npix,) or (B, Npix) FP32 device tensor, written
+        to `out` or (accumulate=True) added to it."""
+        import torch
+        x = _dev_f32(x, "x")
+        nb = self._shape(x)
+        if out is None:
+            if accumulate:
+                raise ValueError("accumulate needs an out tensor")
+            out = torch.empty_like(x)
+        else:
+            _dev_f32(out, "out")
+            if out.shape != x.shape:
+                raise ValueError("out must have the shape of x")
+        _call("arkcos_harm_convolve", self._h, _vp(x.data_ptr()), _vp(out.data_ptr()), nb,
+              1 if accumulate else 0, _stream_ptr(stream))
+        return out
+
+
+def split_convolve(plan: Plan, harm: Harm, x, out=None, stream=None):
+    """The full split convolution (arkcos_split_convolve): the real-space half
+    of `plan` plus the l-space half of `harm`."""
+    import torch
+    x = _dev_f32(x, "x")
+    nb = plan._shape(x)
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _dev_f32(out, "out")
+        if out.shape != x.shape:
+            raise ValueError("out must have the shape of x")
+    _call("arkcos_split_convolve", plan.handle, harm.handle, _vp(x.data_ptr()),
+          _vp(out.data_ptr()), nb, _stream_ptr(stream))
+    return out

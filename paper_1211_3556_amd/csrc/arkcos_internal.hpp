@@ -191,6 +191,9 @@ struct HostRing {
     int two_o;
 };
 
+// HEALPix RING geometry of ring i (1-based) at resolution N (plan.hip).
+HostRing ring_geometry(int N, int i);
+
 struct Plan {
     arkcos_plan_desc desc{};
     int nside = 0;

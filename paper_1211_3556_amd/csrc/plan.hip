@@ -28,7 +28,7 @@ void clear_error() { g_last_error.clear(); }
 // HEALPix RING geometry of ring i (1-based) at resolution N (Gorski et al.
 // 2005, the map format of Sec. 2).  Polar rings use the cancellation-free
 // sin(theta) = sqrt(a (2 - a)) with a = 1 - |z| = i^2 / (3 N^2).
-static HostRing ring_geometry(int N, int i)
+HostRing ring_geometry(int N, int i)
 {
     HostRing g{};
     const double dN = N;

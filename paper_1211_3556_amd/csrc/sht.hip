@@ -1,0 +1,657 @@
+// Harmonic-space half of the split convolution (Sutter, Wandelt & Elsner 2012,
+// Sec. 2, eq. 1): the truncated l-space kernel Khat_l, l <= lcut, applied to a
+// HEALPix RING map by spherical-harmonic analysis with the pixel quadrature
+// and synthesis,
+//
+//     a_lm = Omega sum_p x_p conj(Y_lm(p)),
+//     y_p  = sum_{l <= lcut} Khat_l sum_m a_lm Y_lm(p),
+//
+// with Y_lm = lambda_lm(cos theta) e^{i m phi} and the orthonormal associated
+// Legendre functions lambda_lm.  The paper runs this half on host cores with an
+// SHT library while the GPU sums the real-space half; here both halves run on
+// the GPU, in five stream-ordered kernels per map, all in FP64:
+//
+//  1. k_sht_dft_fwd   per ring: F_r(m) = sum_j x_j e^{-i m phi_j}, m <= lcut,
+//                     by Goertzel's second-order recurrence (one FMA and one
+//                     add per sample and frequency, no phase table);
+//  2. k_sht_leg_fwd   per (m, chunk of northern rings): lambda_lm by its
+//                     recurrence in l, times the even / odd N-S combinations
+//                     of F, reduced over the chunk's rings through LDS into
+//                     per-chunk partial a_lm;
+//  3. k_sht_mul       a_lm = Omega Khat_l sum over chunks (fixed order);
+//  4. k_sht_leg_bwd   per (m, northern ring): G_r(m) = sum_l a_lm lambda_lm,
+//                     split into even and odd parts for the ring and its
+//                     mirror;
+//  5. k_sht_dft_bwd   per ring: y_j = Re sum_m c_m G_r(m) e^{i m phi_j}
+//                     (c_0 = 1, c_m = 2) by Clenshaw's recurrence, one pass
+//                     for the pixel pair j, n - j.
+//
+// lambda_mm underflows FP64 for large m near the poles, so the recurrence
+// carries a power-of-two scale: a value is lam * 2^(512 sc) with sc <= 0, and
+// terms are used only once sc reaches 0 (below that they are < 2^-330 times
+// the ring's other terms).  Results are deterministic: no atomics.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "arkcos_internal.hpp"
+
+namespace arkcos {
+
+// One ring as the transform kernels see it (0-based).
+struct ShtRing {
+    double z;       // cos theta
+    double s;       // sin theta
+    double log2s;   // log2 sin theta
+    int n;          // pixels
+    int first;      // RING index of pixel 0
+    int two_o;      // 1: pixel j at phi = (j + 1/2) 2 pi / n, 0: at j 2 pi / n
+    int pad;
+};
+static_assert(sizeof(ShtRing) == 40, "ShtRing layout");
+
+constexpr int kShtThreads = 256;
+constexpr int kShtChunk = 4096;     // samples of a ring staged per pass (FP64)
+constexpr int kShtMaxFreq = 8;      // frequencies per thread and pass in k_sht_dft_fwd
+constexpr int kLegBlock = 8;        // degrees l per LDS reduction in k_sht_leg_fwd
+constexpr int kLegCols = 2 * kLegBlock;            // re, im per degree
+constexpr int kLegSegs = kShtThreads / kLegCols;   // row segments of a column
+constexpr int kShtPairs = 2;        // pixel pairs per thread in k_sht_dft_bwd
+constexpr double kScaleUp = 0x1p128;     // rescale threshold of a scaled value
+constexpr double kScaleStep = 0x1p-512;  // one scale step
+
+// First entry of order m in the (l, m) layout: for each m, l = m .. L.
+__host__ __device__ inline long long alm_base(int m, int L)
+{
+    return (long long)m * (L + 1) - (long long)m * (m - 1) / 2;
+}
+
+// lambda_mm of a ring in scaled form: returns the mantissa and sets sc.
+__device__ __forceinline__ double lambda_mm_scaled(double mnorm, int m, double log2s, int &sc)
+{
+    const double e = mnorm + (double)m * log2s;   // log2 |lambda_mm|
+    if (e >= -384.0) {
+        sc = 0;
+        return exp2(e);
+    }
+    sc = (int)floor((e + 384.0) / 512.0);          // mantissa in [2^-384, 2^128)
+    return exp2(e - 512.0 * sc);
+}
+
+// One step of the l recurrence, lambda_l = A z lambda_{l-1} - B lambda_{l-2},
+// with a rescale while the value is scaled.  Returns the usable value (0 while
+// scaled).
+__device__ __forceinline__ double lambda_step(double A, double B, double z, double &l1, double &l2,
+                                              int &sc)
+{
+    const double v = fma(A * z, l1, -B * l2);
+    l2 = l1;
+    l1 = v;
+    if (sc < 0) {
+        if (fabs(l1) > kScaleUp) {
+            l1 *= kScaleStep;
+            l2 *= kScaleStep;
+            ++sc;
+        }
+        return sc == 0 ? l1 : 0.0;
+    }
+    return v;
+}
+
+// ------------------------------------------------------------ analysis --
+// Goertzel: s_j = x_j + 2 cos(w) s_{j-1} - s_{j-2}; after n samples
+// sum_j x_j e^{-i w j} = e^{i w} s_{n-1} - s_{n-2}.  Two samples per step
+// update (s1, s2) in place: s2 <- c s1 + x_j - s2, s1 <- c s2 + x_{j+1} - s1.
+// Ring lengths are multiples of 4, so every staged count is even.  One launch
+// covers frequencies m = m0 + thread + k kShtThreads, k < K.
+template <int K>
+__global__ __launch_bounds__(kShtThreads) void k_sht_dft_fwd(const ShtRing *__restrict__ rings,
+                                                             const float *__restrict__ x,
+                                                             double2 *__restrict__ F, int m0,
+                                                             int L, int nrings)
+{
+    __shared__ double2 sx[kShtChunk / 2];
+    const int r = blockIdx.x;
+    const ShtRing R = rings[r];
+    const float *xr = x + R.first;
+    double c[K], s1[K], s2[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int m = m0 + threadIdx.x + k * kShtThreads;
+        c[k] = 2.0 * cospi(2.0 * (double)(m % R.n) / (double)R.n);
+        s1[k] = 0.0;
+        s2[k] = 0.0;
+    }
+    for (int j0 = 0; j0 < R.n; j0 += kShtChunk) {
+        const int half = min(kShtChunk, R.n - j0) / 2;
+        __syncthreads();
+        for (int j = threadIdx.x; j < half; j += kShtThreads) {
+            const float2 v = *reinterpret_cast<const float2 *>(xr + j0 + 2 * j);
+            sx[j] = make_double2((double)v.x, (double)v.y);
+        }
+        __syncthreads();
+        for (int j = 0; j < half; ++j) {
+            const double2 v = sx[j];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                s2[k] = fma(c[k], s1[k], v.x - s2[k]);
+                s1[k] = fma(c[k], s2[k], v.y - s1[k]);
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int m = m0 + threadIdx.x + k * kShtThreads;
+        if (m > L) continue;
+        double sw, cw;
+        sincospi(2.0 * (double)(m % R.n) / (double)R.n, &sw, &cw);
+        const double xre = cw * s1[k] - s2[k];
+        const double xim = sw * s1[k];
+        // times e^{-i m phi_0}, phi_0 = two_o pi / n
+        const long long q = ((long long)m * R.two_o) % (2LL * R.n);
+        double sp, cp;
+        sincospi((double)q / (double)R.n, &sp, &cp);
+        F[(size_t)m * nrings + r] = make_double2(cp * xre + sp * xim, cp * xim - sp * xre);
+    }
+}
+
+// Partial a_lm of one chunk of northern rings (the equator last): ring r and
+// its mirror 4N-2-r (0-based) have lambda_lm(pi - theta) = (-1)^(l+m)
+// lambda_lm(theta), so they enter through E = F_r + F_mirror (l + m even) and
+// O = F_r - F_mirror (l + m odd); the equator enters once, through E.
+__global__ __launch_bounds__(kShtThreads) void k_sht_leg_fwd(
+    const ShtRing *__restrict__ rings, const double2 *__restrict__ F,
+    const double2 *__restrict__ rec, const double *__restrict__ mnorm, double *__restrict__ part,
+    int L, int nrings, int nnorth, long long nalm)
+{
+    __shared__ double red[kLegCols][kShtThreads + 1];
+    __shared__ double red2[kLegSegs][kLegCols];
+    const int m = blockIdx.y;
+    const int chunk = blockIdx.x;
+    const int i = chunk * kShtThreads + threadIdx.x;
+    const bool act = i < nnorth;
+    const int ii = act ? i : 0;
+    const ShtRing R = rings[ii];
+    const int mir = nrings - 1 - ii;
+    double2 E = make_double2(0.0, 0.0), O = E;
+    if (act) {
+        const double2 a = F[(size_t)m * nrings + ii];
+        if (mir == ii) {
+            E = a;
+        } else {
+            const double2 b = F[(size_t)m * nrings + mir];
+            E = make_double2(a.x + b.x, a.y + b.y);
+            O = make_double2(a.x - b.x, a.y - b.y);
+        }
+    }
+    int sc;
+    double l1 = lambda_mm_scaled(mnorm[m], m, R.log2s, sc);
+    double l2 = 0.0;
+    const long long base = alm_base(m, L);
+    const double z = R.z;
+    for (int l0 = m; l0 <= L; l0 += kLegBlock) {
+        double pr[kLegBlock], pim[kLegBlock];
+#pragma unroll
+        for (int k = 0; k < kLegBlock; ++k) {
+            const int l = l0 + k;
+            double v = 0.0;
+            if (l <= L) {
+                if (l == m) {
+                    v = sc == 0 ? l1 : 0.0;
+                } else {
+                    const double2 ab = rec[base + (l - m)];
+                    v = lambda_step(ab.x, ab.y, z, l1, l2, sc);
+                }
+            }
+            const double2 src = ((l + m) & 1) ? O : E;
+            pr[k] = v * src.x;
+            pim[k] = v * src.y;
+        }
+#pragma unroll
+        for (int k = 0; k < kLegBlock; ++k) {
+            red[2 * k][threadIdx.x] = pr[k];
+            red[2 * k + 1][threadIdx.x] = pim[k];
+        }
+        __syncthreads();
+        {
+            // column col (degree l0 + col/2, re or im) summed over one segment
+            // of kShtThreads / kLegSegs rings
+            constexpr int rows = kShtThreads / kLegSegs;
+            const int col = threadIdx.x % kLegCols;
+            const int seg = threadIdx.x / kLegCols;
+            double s = 0.0;
+            for (int q = 0; q < rows; ++q) s += red[col][seg * rows + q];
+            red2[seg][col] = s;
+        }
+        __syncthreads();
+        if (threadIdx.x < kLegCols) {
+            double t = 0.0;
+            for (int sgm = 0; sgm < kLegSegs; ++sgm) t += red2[sgm][threadIdx.x];
+            const int l = l0 + (threadIdx.x >> 1);
+            if (l <= L)
+                part[2 * ((size_t)chunk * nalm + base + (l - m)) + (threadIdx.x & 1)] = t;
+        }
+    }
+}
+
+// a_lm = Omega Khat_l sum over the ring chunks, in chunk order.
+__global__ __launch_bounds__(kShtThreads) void k_sht_mul(const double2 *__restrict__ part,
+                                                         const double *__restrict__ kscale,
+                                                         double2 *__restrict__ alm, int L,
+                                                         int nchunk, long long nalm)
+{
+    const int m = blockIdx.y;
+    const int l = m + blockIdx.x * kShtThreads + threadIdx.x;
+    if (l > L) return;
+    const long long idx = alm_base(m, L) + (l - m);
+    double2 s = make_double2(0.0, 0.0);
+    for (int c = 0; c < nchunk; ++c) {
+        const double2 p = part[(size_t)c * nalm + idx];
+        s.x += p.x;
+        s.y += p.y;
+    }
+    alm[idx] = make_double2(kscale[l] * s.x, kscale[l] * s.y);
+}
+
+// ----------------------------------------------------------- synthesis --
+// G_r(m) = sum_l a_lm lambda_lm(theta_r) for a northern ring and its mirror.
+__global__ __launch_bounds__(kShtThreads) void k_sht_leg_bwd(
+    const ShtRing *__restrict__ rings, const double2 *__restrict__ alm,
+    const double2 *__restrict__ rec, const double *__restrict__ mnorm, double2 *__restrict__ G,
+    int L, int nrings, int nnorth)
+{
+    const int m = blockIdx.y;
+    const int i = blockIdx.x * kShtThreads + threadIdx.x;
+    if (i >= nnorth) return;
+    const ShtRing R = rings[i];
+    const int mir = nrings - 1 - i;
+    int sc;
+    double l1 = lambda_mm_scaled(mnorm[m], m, R.log2s, sc);
+    double l2 = 0.0;
+    const long long base = alm_base(m, L);
+    const double z = R.z;
+    double2 ae = make_double2(0.0, 0.0), ao = ae;   // l + m even, odd
+    {
+        const double v = sc == 0 ? l1 : 0.0;
+        const double2 a = alm[base];
+        ae.x = fma(v, a.x, ae.x);
+        ae.y = fma(v, a.y, ae.y);
+    }
+    int l = m + 1;
+    for (; l + 1 <= L; l += 2) {
+        const double2 r1 = rec[base + (l - m)];
+        const double v1 = lambda_step(r1.x, r1.y, z, l1, l2, sc);
+        const double2 a1 = alm[base + (l - m)];
+        ao.x = fma(v1, a1.x, ao.x);
+        ao.y = fma(v1, a1.y, ao.y);
+        const double2 r2 = rec[base + (l + 1 - m)];
+        const double v2 = lambda_step(r2.x, r2.y, z, l1, l2, sc);
+        const double2 a2 = alm[base + (l + 1 - m)];
+        ae.x = fma(v2, a2.x, ae.x);
+        ae.y = fma(v2, a2.y, ae.y);
+    }
+    if (l <= L) {
+        const double2 r1 = rec[base + (l - m)];
+        const double v1 = lambda_step(r1.x, r1.y, z, l1, l2, sc);
+        const double2 a1 = alm[base + (l - m)];
+        ao.x = fma(v1, a1.x, ao.x);
+        ao.y = fma(v1, a1.y, ao.y);
+    }
+    G[(size_t)m * nrings + i] = make_double2(ae.x + ao.x, ae.y + ao.y);
+    if (mir != i) G[(size_t)m * nrings + mir] = make_double2(ae.x - ao.x, ae.y - ao.y);
+}
+
+// y_j = Re sum_m H_m e^{i m a_j}, a_j = 2 pi j / n, H_m = c_m G_r(m) e^{i m phi_0}:
+// with C = sum Re H_m cos(m a) and S = sum Im H_m sin(m a) (Clenshaw, shared
+// coefficient 2 cos a), y_j = C - S and y_{n-j} = C + S.
+__global__ __launch_bounds__(kShtThreads) void k_sht_dft_bwd(const ShtRing *__restrict__ rings,
+                                                             const double2 *__restrict__ G,
+                                                             float *__restrict__ out, int L,
+                                                             int nrings, int accumulate)
+{
+    extern __shared__ double2 H[];
+    const int r = blockIdx.x;
+    const ShtRing R = rings[r];
+    for (int m = threadIdx.x; m <= L; m += kShtThreads) {
+        const double2 g = G[(size_t)m * nrings + r];
+        const long long q = ((long long)m * R.two_o) % (2LL * R.n);
+        double sp, cp;
+        sincospi((double)q / (double)R.n, &sp, &cp);
+        const double c = m == 0 ? 1.0 : 2.0;
+        H[m] = make_double2(c * (g.x * cp - g.y * sp), c * (g.x * sp + g.y * cp));
+    }
+    __syncthreads();
+    float *o = out + R.first;
+    const int npairs = R.n / 2 + 1;     // j = 0 .. n/2
+    for (int j0 = threadIdx.x * kShtPairs; j0 < npairs; j0 += kShtThreads * kShtPairs) {
+        double cc[kShtPairs], b1[kShtPairs], b2[kShtPairs], d1[kShtPairs], d2[kShtPairs];
+#pragma unroll
+        for (int k = 0; k < kShtPairs; ++k) {
+            cc[k] = 2.0 * cospi(2.0 * (double)(j0 + k) / (double)R.n);
+            b1[k] = b2[k] = d1[k] = d2[k] = 0.0;
+        }
+        // b_m = h_m + 2 cos(a) b_{m+1} - b_{m+2} from m = L down, two steps
+        // at a time in place (b1 holds the newest term); an odd count starts
+        // from b_L = h_L
+        int m = L;
+        if (((L + 1) & 1) != 0) {
+            const double2 h = H[L];
+#pragma unroll
+            for (int k = 0; k < kShtPairs; ++k) {
+                b1[k] = h.x;
+                d1[k] = h.y;
+            }
+            m = L - 1;
+        }
+        for (; m > 0; m -= 2) {
+            const double2 ha = H[m];
+            const double2 hb = H[m - 1];
+#pragma unroll
+            for (int k = 0; k < kShtPairs; ++k) {
+                b2[k] = fma(cc[k], b1[k], ha.x - b2[k]);
+                b1[k] = fma(cc[k], b2[k], hb.x - b1[k]);
+                d2[k] = fma(cc[k], d1[k], ha.y - d2[k]);
+                d1[k] = fma(cc[k], d2[k], hb.y - d1[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < kShtPairs; ++k) {
+            const int j = j0 + k;
+            if (j >= npairs) continue;
+            double sa, ca;
+            sincospi(2.0 * (double)j / (double)R.n, &sa, &ca);
+            const double C = b1[k] - b2[k] * ca;     // b_0 - b_1 cos a
+            const double S = d2[k] * sa;             // d_1 sin a
+            const float y0 = (float)(C - S);
+            o[j] = accumulate ? o[j] + y0 : y0;
+            const int jm = j == 0 ? 0 : R.n - j;
+            if (jm != j) {
+                const float y1 = (float)(C + S);
+                o[jm] = accumulate ? o[jm] + y1 : y1;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- host --
+struct Harm {
+    int nside = 0;
+    int nrings = 0;
+    int nnorth = 0;     // northern rings and the equator: 2 Nside
+    int lcut = 0;
+    int max_batch = 1;
+    int nchunk = 0;
+    int device = -1;
+    long long npix = 0;
+    long long nalm = 0;
+    double omega = 0.0;
+    std::vector<double> khat;
+    ShtRing *d_rings = nullptr;
+    double2 *d_rec = nullptr;
+    double *d_mnorm = nullptr;
+    double *d_kscale = nullptr;
+    double2 *d_F = nullptr;       // F, then G: (lcut+1) x nrings
+    double2 *d_part = nullptr;    // nchunk x nalm
+    double2 *d_alm = nullptr;
+    long long device_bytes = 0;
+};
+
+static void harm_free(Harm &h)
+{
+    if (h.device >= 0) {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(h.device);
+        (void)hipDeviceSynchronize();
+        for (void *p : {(void *)h.d_rings, (void *)h.d_rec, (void *)h.d_mnorm, (void *)h.d_kscale,
+                        (void *)h.d_F, (void *)h.d_part, (void *)h.d_alm})
+            if (p) (void)hipFree(p);
+        (void)hipSetDevice(cur);
+    }
+    h.d_rings = nullptr;
+    h.d_rec = nullptr;
+    h.d_mnorm = nullptr;
+    h.d_kscale = nullptr;
+    h.d_F = nullptr;
+    h.d_part = nullptr;
+    h.d_alm = nullptr;
+}
+
+static int harm_alloc(void **p, size_t bytes, long long *total)
+{
+    if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ARKCOS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    *total += (long long)bytes;
+    return ARKCOS_OK;
+}
+
+static int harm_upload_kernel(Harm &h)
+{
+    std::vector<double> ks(h.lcut + 1);
+    for (int l = 0; l <= h.lcut; ++l) ks[l] = h.omega * h.khat[l];
+    ARKCOS_HIP_CHECK(hipMemcpy(h.d_kscale, ks.data(), ks.size() * sizeof(double),
+                               hipMemcpyHostToDevice));
+    return ARKCOS_OK;
+}
+
+static int harm_build(Harm &h)
+{
+    const int L = h.lcut;
+    std::vector<ShtRing> rings(h.nrings);
+    for (int i = 0; i < h.nrings; ++i) {
+        const HostRing g = ring_geometry(h.nside, i + 1);
+        rings[i].z = g.z;
+        rings[i].s = g.s;
+        rings[i].log2s = std::log2(g.s);
+        rings[i].n = g.n;
+        rings[i].first = (int)g.first;
+        rings[i].two_o = g.two_o;
+        rings[i].pad = 0;
+    }
+    // recurrence coefficients A = a_lm, B = a_lm b_lm, and log2 of the
+    // lambda_mm normalisation sqrt((2m+1)!!/(4 pi (2m)!!))
+    std::vector<double2> rec((size_t)h.nalm);
+    std::vector<double> mnorm(L + 1);
+    double acc = -std::log2(4.0 * M_PI);
+    for (int m = 0; m <= L; ++m) {
+        if (m > 0) acc += std::log2((2.0 * m + 1.0) / (2.0 * m));
+        mnorm[m] = 0.5 * acc;
+        const long long base = alm_base(m, L);
+        rec[base] = make_double2(0.0, 0.0);
+        for (int l = m + 1; l <= L; ++l) {
+            const double dl = l, dm = m;
+            const double a = std::sqrt((4.0 * dl * dl - 1.0) / (dl * dl - dm * dm));
+            const double b = std::sqrt(((dl - 1.0) * (dl - 1.0) - dm * dm) /
+                                       (4.0 * (dl - 1.0) * (dl - 1.0) - 1.0));
+            rec[base + (l - m)] = make_double2(a, a * b);
+        }
+    }
+    ARKCOS_HIP_CHECK(hipGetDevice(&h.device));
+    int rc;
+    if ((rc = harm_alloc((void **)&h.d_rings, rings.size() * sizeof(ShtRing), &h.device_bytes)))
+        return rc;
+    if ((rc = harm_alloc((void **)&h.d_rec, rec.size() * sizeof(double2), &h.device_bytes)))
+        return rc;
+    if ((rc = harm_alloc((void **)&h.d_mnorm, mnorm.size() * sizeof(double), &h.device_bytes)))
+        return rc;
+    if ((rc = harm_alloc((void **)&h.d_kscale, (L + 1) * sizeof(double), &h.device_bytes)))
+        return rc;
+    if ((rc = harm_alloc((void **)&h.d_F, (size_t)(L + 1) * h.nrings * sizeof(double2),
+                         &h.device_bytes)))
+        return rc;
+    if ((rc = harm_alloc((void **)&h.d_part, (size_t)h.nchunk * h.nalm * sizeof(double2),
+                         &h.device_bytes)))
+        return rc;
+    if ((rc = harm_alloc((void **)&h.d_alm, (size_t)h.nalm * sizeof(double2), &h.device_bytes)))
+        return rc;
+    ARKCOS_HIP_CHECK(hipMemcpy(h.d_rings, rings.data(), rings.size() * sizeof(ShtRing),
+                               hipMemcpyHostToDevice));
+    ARKCOS_HIP_CHECK(hipMemcpy(h.d_rec, rec.data(), rec.size() * sizeof(double2),
+                               hipMemcpyHostToDevice));
+    ARKCOS_HIP_CHECK(hipMemcpy(h.d_mnorm, mnorm.data(), mnorm.size() * sizeof(double),
+                               hipMemcpyHostToDevice));
+    return harm_upload_kernel(h);
+}
+
+// The five kernels for one map.
+static int harm_launch(const Harm &h, const float *in, float *out, int accumulate, hipStream_t s)
+{
+    const int L = h.lcut;
+    // frequencies per thread, kShtMaxFreq per launch
+    for (int m0 = 0, left = (L + kShtThreads) / kShtThreads; left > 0;
+         m0 += kShtMaxFreq * kShtThreads, left -= kShtMaxFreq) {
+        switch (std::min(left, kShtMaxFreq)) {
+#define ARKCOS_DFT_CASE(K)                                                                   \
+    case K:                                                                                  \
+        hipLaunchKernelGGL(k_sht_dft_fwd<K>, dim3(h.nrings), dim3(kShtThreads), 0, s,       \
+                           h.d_rings, in, h.d_F, m0, L, h.nrings);                           \
+        break;
+            ARKCOS_DFT_CASE(1) ARKCOS_DFT_CASE(2) ARKCOS_DFT_CASE(3) ARKCOS_DFT_CASE(4)
+            ARKCOS_DFT_CASE(5) ARKCOS_DFT_CASE(6) ARKCOS_DFT_CASE(7)
+            default: ARKCOS_DFT_CASE(8)
+#undef ARKCOS_DFT_CASE
+        }
+    }
+    hipLaunchKernelGGL(k_sht_leg_fwd, dim3(h.nchunk, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
+                       h.d_F, h.d_rec, h.d_mnorm, (double *)h.d_part, L, h.nrings, h.nnorth,
+                       h.nalm);
+    hipLaunchKernelGGL(k_sht_mul, dim3((L + kShtThreads) / kShtThreads, L + 1), dim3(kShtThreads),
+                       0, s, h.d_part, h.d_kscale, h.d_alm, L, h.nchunk, h.nalm);
+    hipLaunchKernelGGL(k_sht_leg_bwd, dim3(h.nchunk, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
+                       h.d_alm, h.d_rec, h.d_mnorm, h.d_F, L, h.nrings, h.nnorth);
+    hipLaunchKernelGGL(k_sht_dft_bwd, dim3(h.nrings), dim3(kShtThreads),
+                       (size_t)(L + 1) * sizeof(double2), s, h.d_rings, h.d_F, out, L, h.nrings,
+                       accumulate);
+    ARKCOS_HIP_CHECK(hipGetLastError());
+    return ARKCOS_OK;
+}
+
+static bool overlap(const float *a, const float *b, long long n)
+{
+    return a < b + n && b < a + n;
+}
+
+}  // namespace arkcos
+
+using namespace arkcos;
+
+extern "C" {
+
+int arkcos_harm_create(int nside, int lcut, const double *khat, int max_batch,
+                       arkcos_harm_t *out)
+{
+    clear_error();
+    if (!out) return fail(ARKCOS_EINVAL, "NULL output pointer");
+    *out = nullptr;
+    if (nside < 1 || nside > ARKCOS_MAX_NSIDE)
+        return fail(ARKCOS_EINVAL, "nside must lie in 1.." + std::to_string(ARKCOS_MAX_NSIDE));
+    if (lcut < 0) return fail(ARKCOS_EINVAL, "lcut must be >= 0");
+    if (lcut > ARKCOS_MAX_LCUT)
+        return fail(ARKCOS_EUNSUPPORTED, "lcut above " + std::to_string(ARKCOS_MAX_LCUT));
+    if (!khat) return fail(ARKCOS_EINVAL, "NULL khat");
+    if (max_batch < 1) return fail(ARKCOS_EINVAL, "max_batch must be >= 1");
+    Harm *h = new (std::nothrow) Harm();
+    if (!h) return fail(ARKCOS_ENOMEM, "host allocation failed");
+    h->nside = nside;
+    h->nrings = 4 * nside - 1;
+    h->nnorth = 2 * nside;
+    h->lcut = lcut;
+    h->max_batch = max_batch;
+    h->npix = 12LL * nside * nside;
+    h->omega = 4.0 * M_PI / (double)h->npix;
+    h->nalm = alm_base(lcut + 1, lcut);
+    h->nchunk = (h->nnorth + kShtThreads - 1) / kShtThreads;
+    int rc;
+    try {
+        h->khat.assign(khat, khat + lcut + 1);
+        rc = harm_build(*h);
+    } catch (const std::bad_alloc &) {
+        rc = fail(ARKCOS_ENOMEM, "host allocation failed while building the transform plan");
+    }
+    if (rc != ARKCOS_OK) {
+        harm_free(*h);
+        delete h;
+        return rc;
+    }
+    *out = reinterpret_cast<arkcos_harm_t>(h);
+    return ARKCOS_OK;
+}
+
+int arkcos_harm_destroy(arkcos_harm_t harm)
+{
+    clear_error();
+    if (!harm) return ARKCOS_OK;
+    Harm *h = reinterpret_cast<Harm *>(harm);
+    harm_free(*h);
+    delete h;
+    return ARKCOS_OK;
+}
+
+int arkcos_harm_set_kernel(arkcos_harm_t harm, const double *khat)
+{
+    clear_error();
+    if (!harm || !khat) return fail(ARKCOS_EINVAL, "NULL pointer");
+    Harm *h = reinterpret_cast<Harm *>(harm);
+    h->khat.assign(khat, khat + h->lcut + 1);
+    int cur = 0;
+    ARKCOS_HIP_CHECK(hipGetDevice(&cur));
+    ARKCOS_HIP_CHECK(hipSetDevice(h->device));
+    int rc = harm_upload_kernel(*h);
+    (void)hipSetDevice(cur);
+    return rc;
+}
+
+int arkcos_harm_get_info(arkcos_harm_t harm, int *nside, int *lcut, long long *nalm,
+                         long long *device_bytes)
+{
+    clear_error();
+    if (!harm) return fail(ARKCOS_EINVAL, "NULL transform plan");
+    const Harm *h = reinterpret_cast<const Harm *>(harm);
+    if (nside) *nside = h->nside;
+    if (lcut) *lcut = h->lcut;
+    if (nalm) *nalm = h->nalm;
+    if (device_bytes) *device_bytes = h->device_bytes;
+    return ARKCOS_OK;
+}
+
+int arkcos_harm_convolve(arkcos_harm_t harm, const float *d_in, float *d_out, int nbatch,
+                         int accumulate, void *stream)
+{
+    clear_error();
+    if (!harm || !d_in || !d_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Harm *h = reinterpret_cast<const Harm *>(harm);
+    if (nbatch < 1 || nbatch > h->max_batch)
+        return fail(ARKCOS_EINVAL, "nbatch must lie in 1.." + std::to_string(h->max_batch));
+    if (accumulate != 0 && accumulate != 1) return fail(ARKCOS_EINVAL, "accumulate must be 0 or 1");
+    if (overlap(d_in, d_out, h->npix * nbatch))
+        return fail(ARKCOS_EINVAL, "d_in and d_out overlap");
+    for (int b = 0; b < nbatch; ++b) {
+        int rc = harm_launch(*h, d_in + (size_t)b * h->npix, d_out + (size_t)b * h->npix,
+                             accumulate, (hipStream_t)stream);
+        if (rc) return rc;
+    }
+    return ARKCOS_OK;
+}
+
+int arkcos_split_convolve(arkcos_plan_t plan, arkcos_harm_t harm, const float *d_in,
+                          float *d_out, int nbatch, void *stream)
+{
+    clear_error();
+    if (!plan || !harm) return fail(ARKCOS_EINVAL, "NULL plan");
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    const Harm *h = reinterpret_cast<const Harm *>(harm);
+    if (P->nside != h->nside)
+        return fail(ARKCOS_EINVAL, "the two halves are planned for different Nside");
+    int rc = arkcos_convolve(plan, d_in, d_out, nbatch, stream);
+    if (rc) return rc;
+    return arkcos_harm_convolve(harm, d_in, d_out, nbatch, 1, stream);
+}
+
+}  // extern "C"

@@ -299,3 +299,18 @@ def test_tabulate_at_nodes_matches_oracle():
     assert f(bl.ctypes.data_as(A._dp), 10, th.ctypes.data_as(A._dp), 0,
              out.ctypes.data_as(A._dp)) == -1
     assert f(None, 10, th.ctypes.data_as(A._dp), 1, out.ctypes.data_as(A._dp)) == -1
+
+
+@pytest.mark.parametrize("nside,lcut,kind,status", [
+    (0, 10, "ok", -1), (8193, 10, "ok", -1), (8, -1, "ok", -1), (8, 4096, "ok", -4),
+    (8, 10, "null", -1), (8, 10, "batch", -1),
+])
+def test_harm_argument_errors(nside, lcut, kind, status):
+    lib = A.load_library()
+    k = np.ones(max(lcut, 0) + 1)
+    h = ctypes.c_void_p()
+    rc = lib.arkcos_harm_create(nside, lcut, None if kind == "null" else k.ctypes.data_as(A._dp),
+                                0 if kind == "batch" else 1, ctypes.byref(h))
+    assert rc == status and not h.value
+    assert lib.arkcos_harm_destroy(None) == 0
+    assert lib.arkcos_harm_convolve(None, None, None, 1, 0, None) == -1
