@@ -20,6 +20,11 @@ each kernel's launch time is measured inside the timed region.  The unit of
 work is one in-disc pair term (theta_pq < theta_cut), counted exactly by the
 plan; `value` is total pairs / total step time, in GPair-evals/s.  One JSON
 line is printed.
+
+Beside the step (not part of `value`), the breakdown reports the biased node
+table of Sec. 3 against a uniform one, and the split convolution of the
+paper's example: the l-space half (GPU spherical-harmonic transforms at
+l_cut 1500) and the real-space half (240 arcmin cut) at Nside 2048.
 """
 from __future__ import annotations
 
@@ -37,6 +42,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GPair-evals/s and maps/s at Nside 2048 (fwd, fwd+bwd, batched) vs plain kernel"
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+FP64_VECTOR_PEAK_TFLOPS = 78.6
 # Algorithmic FP32 work per in-disc pair term:
 #   k_circ       one FMA with a precomputed weight;
 #   k_general    one FMA, plus a 24-FLOP weight evaluation (longitude, sine
@@ -86,7 +92,8 @@ def main() -> int:
     ap.add_argument("--cpu-sample", type=int, default=6_000_000,
                     help="output pixels of the Nside-2048 oracle sample")
     ap.add_argument("--no-biased", action="store_true",
-                    help="skip the biased-node-table forwards reported beside the step")
+                    help="skip the biased-node-table forwards and the split convolution "
+                         "reported beside the step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy, the reference "
                          "for scaling hardware byte counters")
@@ -303,8 +310,49 @@ def main() -> int:
                                                         / (t["k_general"] * 1e-3) / 1e12, 2)}
             rec["biased_over_uniform"] = round(rec["biased"]["ms"] / rec["uniform"]["ms"], 4)
             biased[name] = rec
+            if s is W.SPLIT_EXAMPLE:
+                split_real, split_x, split_pairs = plans["biased"], x, pc + pg
             del plans
             torch.cuda.synchronize()
+
+        # The split convolution of the example (Sec. 2, eq. 1): the l-space half
+        # Khat_l = b_l, l <= 1500, by GPU spherical-harmonic transforms, plus the
+        # real-space half above (the beam's content above l = 1500, cut at 240').
+        s = W.SPLIT_EXAMPLE
+        L = W.SPLIT_ELL
+        log("split convolution: l-space half at l_cut %d" % L)
+        harm = A.Harm(s.nside, A.gaussian_bl(s.fwhm, L))
+        y = torch.empty_like(split_x)
+        harm.convolve(split_x, y)
+        A.split_convolve(split_real, harm, split_x, y)
+        torch.cuda.synchronize()
+        res = {}
+        for label, fn in (("l_space_half", lambda: harm.convolve(split_x, y)),
+                          ("split_total", lambda: A.split_convolve(split_real, harm, split_x, y))):
+            e0, e1 = ev(), ev()
+            e0.record(stream)
+            for _ in range(reps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            res[label] = e0.elapsed_time(e1) / reps
+        npix, nnorth = 12 * s.nside ** 2, 2 * s.nside
+        nalm = (L + 1) * (L + 2) // 2
+        # algorithmic FP64 FLOP: Goertzel 3 per (pixel, m); Clenshaw 3 per
+        # (pixel, m); Legendre recurrence 4 plus 2 (analysis) or 4 (synthesis)
+        # per (l, m, northern ring)
+        flop64 = 6.0 * npix * (L + 1) + (6.0 + 8.0) * nnorth * nalm
+        tf = flop64 / (res["l_space_half"] * 1e-3) / 1e12
+        biased["split_example"] = {
+            "nside": s.nside, "l_cut": L, "theta_cut_arcmin": round(s.theta_cut / W.ARCMIN, 3),
+            "l_space_half_ms": round(res["l_space_half"], 4),
+            "l_space_fp64_tflops": round(tf, 2),
+            "l_space_fp64_frac": round(tf / FP64_VECTOR_PEAK_TFLOPS, 4),
+            "real_space_pairs": split_pairs,
+            "split_total_ms": round(res["split_total"], 4),
+            "maps_per_s": round(1e3 / res["split_total"], 2)}
+        del harm, split_real
+        torch.cuda.synchronize()
 
     cpu = None
     if not args.no_cpu_baseline:
