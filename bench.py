@@ -94,6 +94,8 @@ def main() -> int:
     ap.add_argument("--no-biased", action="store_true",
                     help="skip the biased-node-table forwards and the split convolution "
                          "reported beside the step")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the Nside 4096 / 8192 forwards reported beside the step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain 256 MiB device-to-device copy, the reference "
                          "for scaling hardware byte counters")
@@ -354,6 +356,41 @@ def main() -> int:
         del harm, split_real
         torch.cuda.synchronize()
 
+    # All-sky maps at Nside 4096 and 8192 (beyond the paper's single-GPU limit),
+    # outside the step; the input is seeded N(0,1) noise drawn on the device.
+    large = None
+    if not args.no_large:
+        large = []
+        for s in W.LARGE:
+            log("large map: Nside %d" % s.nside)
+            p = A.Plan(s.nside, s.theta_cut, table(s))
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(s.seed)
+            x = torch.randn(12 * s.nside ** 2, generator=gen, device=dev)
+            y = torch.empty_like(x)
+            pc, pg = p.pair_count_parts()
+            p.convolve(x, y)
+            torch.cuda.synchronize()
+            t = {}
+            for part, kname in ((CIRC, "k_circ"), (GEN, "k_general")):
+                e0, e1 = ev(), ev()
+                e0.record(stream)
+                for _ in range(3):
+                    p.convolve_part(x, y, part)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                t[kname] = e0.elapsed_time(e1) / 3
+            tot = t["k_circ"] + t["k_general"]
+            large.append({"nside": s.nside, "npix": 12 * s.nside ** 2,
+                          "fwhm_arcmin": round(s.fwhm / W.ARCMIN, 3),
+                          "theta_cut_arcmin": round(s.theta_cut / W.ARCMIN, 3), "ntab": s.ntab,
+                          "pairs": pc + pg, "ms": round(tot, 4),
+                          "k_circ_ms": round(t["k_circ"], 4), "k_general_ms": round(t["k_general"], 4),
+                          "gpair_per_s": round((pc + pg) / (tot * 1e-3) / 1e9, 2),
+                          "maps_per_s": round(1e3 / tot, 2)})
+            del p, x, y
+            torch.cuda.synchronize()
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle as O
@@ -406,6 +443,7 @@ def main() -> int:
                       "speedup_vs_plain16": None if plain16_ms is None else round(plain16_ms / b_ms, 3)},
             "kernels": kernels,
             "biased_table": biased,
+            "large_nside": large,
         },
         "roofline": {
             "kernel": dom,

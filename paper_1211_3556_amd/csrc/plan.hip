@@ -10,6 +10,7 @@
 #include <cstring>
 #include <numeric>
 #include <string>
+#include <thread>
 
 #include "arkcos_internal.hpp"
 
@@ -361,12 +362,13 @@ static int build_plan(Plan &P)
 // interval (c - W, c + W), c = ((2j + 2o_r) n_s / n_r - 2o_s) / 2, with
 // W = dphi_max n_s / (2 pi).  A rotation by a quarter turn maps pixel j to
 // j + n_r/4 and shifts c by n_s/4, so a quarter of each ring is counted.
-static unsigned long long count_pairs(const Plan &P, unsigned long long *circ_total)
+// Exact in-disc pairs of output rings r0, r0 + step, ... (all, and circulant).
+static void count_pairs_rings(const Plan &P, int r0, int step, unsigned long long *all,
+                              unsigned long long *circ)
 {
     const double tc = P.desc.theta_cut;
-    unsigned long long total = 0;
-    *circ_total = 0;
-    for (int r = 0; r < P.nrings; ++r) {
+    unsigned long long total = 0, circ_total = 0;
+    for (int r = r0; r < P.nrings; r += step) {
         const HostRing &R = P.rings[r];
         const DevRing &dr = P.dev_rings[r];
         unsigned long long ring_total = 0;
@@ -393,7 +395,29 @@ static unsigned long long count_pairs(const Plan &P, unsigned long long *circ_to
             ring_total += circulant ? part * (unsigned long long)R.n : 4ULL * part;
         }
         total += ring_total;
-        if (!P.general_ring[r]) *circ_total += ring_total;
+        if (!P.general_ring[r]) circ_total += ring_total;
+    }
+    *all = total;
+    *circ = circ_total;
+}
+
+// The rings are counted on host threads (interleaved, so each thread gets a
+// share of the large belt and small polar rings); integer sums, so the
+// result does not depend on the thread count.
+static unsigned long long count_pairs(const Plan &P, unsigned long long *circ_total)
+{
+    const int nt = (int)std::max(1u, std::min(32u, std::thread::hardware_concurrency()));
+    std::vector<unsigned long long> all(nt, 0), circ(nt, 0);
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t)
+        pool.emplace_back(count_pairs_rings, std::cref(P), t, nt, &all[t], &circ[t]);
+    count_pairs_rings(P, 0, nt, &all[0], &circ[0]);
+    for (std::thread &th : pool) th.join();
+    unsigned long long total = 0;
+    *circ_total = 0;
+    for (int t = 0; t < nt; ++t) {
+        total += all[t];
+        *circ_total += circ[t];
     }
     return total;
 }

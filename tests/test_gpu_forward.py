@@ -261,3 +261,20 @@ def test_rejects_bad_calls():
         plan.backward(x, x, want_map=False, want_knots=True)   # not learnable
     with pytest.raises(TypeError):
         plan.convolve(torch.zeros(768, device="cuda", dtype=torch.float64))
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_large_nside_sampled(k):
+    """Nside 4096 and 8192 all-sky maps (805 M pixels at 8192) on one GPU,
+    on sampled pixels of every ring class, in the launch configuration the
+    benchmark times."""
+    s = W.LARGE[k]
+    log("large Nside %d theta_cut %.2f arcmin" % (s.nside, s.theta_cut / W.ARCMIN))
+    x = W.white_noise(s.nside, s.seed)
+    plan = _A().Plan(s.nside, s.theta_cut, gpu_table(s))
+    y = _conv_gpu(plan, x)
+    pix = W.eval_pixels(s.nside, 4096, s.seed, max_strata_ring_pixels=256)
+    ref = O.convolve(s.nside, s.theta_cut, oracle_table(s), x, pixels=pix)
+    err = rel_rms(y[pix], ref)
+    log("large Nside %d rel rms %.3e over %d pixels" % (s.nside, err, pix.size))
+    assert err <= REL_RMS_TOL
