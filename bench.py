@@ -388,6 +388,24 @@ def main() -> int:
                           "k_circ_ms": round(t["k_circ"], 4), "k_general_ms": round(t["k_general"], 4),
                           "gpair_per_s": round((pc + pg) / (tot * 1e-3) / 1e9, 2),
                           "maps_per_s": round(1e3 / tot, 2)})
+            if s.nside == 8192:
+                # a ~500 deg^2 polar-cap patch (rings 1..2208, theta <= 12.6 deg):
+                # a ring-range plan writes only those rings
+                pcap = A.Plan(s.nside, s.theta_cut, table(s), rings=(1, 2208))
+                cap_pairs = pcap.pair_count()
+                pcap.convolve(x, y)
+                torch.cuda.synchronize()
+                e0, e1 = ev(), ev()
+                e0.record(stream)
+                for _ in range(3):
+                    pcap.convolve(x, y)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                cms = e0.elapsed_time(e1) / 3
+                large[-1]["polar_cap_patch"] = {
+                    "rings": [1, 2208], "area_deg2": 499, "pairs": cap_pairs,
+                    "ms": round(cms, 4), "gpair_per_s": round(cap_pairs / (cms * 1e-3) / 1e9, 2)}
+                del pcap
             del p, x, y
             torch.cuda.synchronize()
 

@@ -89,6 +89,16 @@ typedef struct {
      * (arkcos_grid_nodes, arkcos_tabulate_legendre_at).                      */
     double theta_break;
     int k_break;
+    /* Output ring range (partial sky, e.g. a survey patch placed on a polar
+     * cap, the use the paper's Sec. 5 suggests for small-area maps):
+     * ring_first = ring_last = 0 computes every ring; otherwise only output
+     * rings ring_first..ring_last (1-based, inclusive, within 1..4 Nside-1,
+     * else EINVAL) are written, the other output pixels are left untouched,
+     * and the cost scales with the range.  Input pixels are read wherever
+     * they lie within theta_cut of the range.  Such plans support the forward
+     * and batched calls; arkcos_convolve_backward returns EUNSUPPORTED.       */
+    int ring_first;
+    int ring_last;
 } arkcos_plan_desc;
 
 typedef struct {
@@ -104,13 +114,15 @@ typedef struct {
     unsigned flags;
     int threads_per_block;
     long long device_bytes;        /* device memory the plan holds                      */
-    int circulant_rings;           /* rings gathered with precomputed weight rows       */
-    int general_rings;             /* rings gathered with per-pair weights              */
+    int circulant_rings;           /* output rings gathered with precomputed weight rows */
+    int general_rings;             /* output rings gathered with per-pair weights       */
     long long circulant_tiles;     /* work items of the two gathers per map             */
     long long general_tiles;
     long long weights;             /* FP32 entries of the circulant weight rows         */
     double theta_break;            /* node grid of the descriptor (0, 0: uniform)       */
     int k_break;
+    int ring_first;                /* output ring range of the descriptor (0, 0: all)   */
+    int ring_last;
 } arkcos_plan_info;
 
 /* The two gathers of a forward convolution (they write disjoint rings). */

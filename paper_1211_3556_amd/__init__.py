@@ -56,7 +56,8 @@ class _PlanDesc(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int), ("theta_cut", ctypes.c_double), ("ntab", ctypes.c_int),
                 ("ktab", ctypes.POINTER(ctypes.c_double)), ("max_batch", ctypes.c_int),
                 ("tile", ctypes.c_int), ("flags", ctypes.c_uint),
-                ("theta_break", ctypes.c_double), ("k_break", ctypes.c_int)]
+                ("theta_break", ctypes.c_double), ("k_break", ctypes.c_int),
+                ("ring_first", ctypes.c_int), ("ring_last", ctypes.c_int)]
 
 
 class _PlanInfo(ctypes.Structure):
@@ -68,7 +69,8 @@ class _PlanInfo(ctypes.Structure):
                 ("circulant_rings", ctypes.c_int), ("general_rings", ctypes.c_int),
                 ("circulant_tiles", ctypes.c_longlong), ("general_tiles", ctypes.c_longlong),
                 ("weights", ctypes.c_longlong), ("theta_break", ctypes.c_double),
-                ("k_break", ctypes.c_int)]
+                ("k_break", ctypes.c_int), ("ring_first", ctypes.c_int),
+                ("ring_last", ctypes.c_int)]
 
 
 _lib = None
@@ -217,12 +219,14 @@ class Plan:
     ``learnable=True`` it may be omitted and knots set later with ``set_knots``.
     ``theta_break``/``k_break`` choose the node grid (0, 0: uniform; see
     ``grid_nodes`` and ``paper_bias``); ``biased=True`` is the Sec. 3 bias.
+    ``rings=(first, last)`` (1-based, inclusive) restricts the output to a
+    ring range (partial sky); other output pixels are left untouched.
     """
 
     def __init__(self, nside: int, theta_cut: float, ktab=None, ntab: int | None = None,
                  max_batch: int = 1, tile: int = 0, learnable: bool = False,
                  host_only: bool = False, theta_break: float = 0.0, k_break: int = 0,
-                 biased: bool = False):
+                 biased: bool = False, rings=None):
         if ktab is not None:
             ktab = np.ascontiguousarray(ktab, dtype=np.float64)
             ntab = ktab.size if ntab is None else ntab
@@ -237,7 +241,8 @@ class Plan:
         flags = (PLAN_LEARNABLE if learnable else 0) | (PLAN_HOST_ONLY if host_only else 0)
         desc = _PlanDesc(int(nside), float(theta_cut), int(ntab),
                          ktab.ctypes.data_as(_dp) if ktab is not None else None,
-                         int(max_batch), int(tile), flags, float(theta_break), int(k_break))
+                         int(max_batch), int(tile), flags, float(theta_break), int(k_break),
+                         *((0, 0) if rings is None else (int(rings[0]), int(rings[1]))))
         h = _vp()
         _call("arkcos_plan_create", ctypes.byref(desc), ctypes.byref(h))
         self._h = h

@@ -76,10 +76,12 @@ struct DevTile {
     int r;
     int j0;
     int len;
-    int flags;     // general tiles: kTileLongSin, kTileIntM
+    int flags;     // general tiles: kTileLongSin, kTileIntM, kTileSkipNorth, kTileSkipSouth
 };
 constexpr int kTileLongSin = 1;   // some source row needs the long sine series
 constexpr int kTileIntM = 2;      // a longitude numerator may reach 2^24: keep it in int32
+constexpr int kTileSkipNorth = 4; // the northern ring is outside the plan's ring range
+constexpr int kTileSkipSouth = 8; // its mirror ring is outside the plan's ring range
 
 // Rings per group and outputs per lane of the circulant kernel; pixels per
 // general tile and source positions one pass of the general kernel stages;

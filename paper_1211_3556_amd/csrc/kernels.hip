@@ -699,22 +699,29 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
 #pragma unroll
         for (int q = 0; q < 16; ++q) acc[q] += __shfl_xor(acc[q], x);
     }
+    // a ring-range plan leaves rings outside its range untouched
+    const bool wn = (T.flags & kTileSkipNorth) == 0;
+    const bool ws = mirror && (T.flags & kTileSkipSouth) == 0;
     if (active) {
         float *o = out + R.first;
         float *om = out + cst(P.rings)[rs].first;
         if (ph == 0) {
+            if (wn) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) o[j + q * qr] = (float)acc[q];
-            if (mirror) {
+                for (int q = 0; q < 4; ++q) o[j + q * qr] = (float)acc[q];
+            }
+            if (ws) {
 #pragma unroll
                 for (int q = 0; q < 4; ++q) om[j + q * qr] = (float)acc[4 + q];
             }
         } else if (ph == 1) {
             const int jb = qr - R.two_o - j;   // reflected pixel; j itself at a fixed point
             if (jb != j && jb != qr) {
+                if (wn) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q) o[jb + q * qr] = (float)acc[8 + q];
-                if (mirror) {
+                    for (int q = 0; q < 4; ++q) o[jb + q * qr] = (float)acc[8 + q];
+                }
+                if (ws) {
 #pragma unroll
                     for (int q = 0; q < 4; ++q) om[jb + q * qr] = (float)acc[12 + q];
                 }

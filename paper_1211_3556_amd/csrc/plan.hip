@@ -234,19 +234,23 @@ static int build_plan(Plan &P)
         general[r] = general[rm] = g;
     }
     P.general_ring = general;
+    // output rings of a ring-range plan (0-based, inclusive); all rings otherwise
+    const int out_lo = P.desc.ring_first > 0 ? P.desc.ring_first - 1 : 0;
+    const int out_hi = P.desc.ring_first > 0 ? P.desc.ring_last - 1 : P.nrings - 1;
+    auto in_range = [&](int r) { return r >= out_lo && r <= out_hi; };
 
-    // Circulant groups of up to kGroupRings consecutive circulant rings, each
-    // with the union of its rings' source rows and tap ranges.
+    // Circulant groups of up to kGroupRings consecutive circulant output rings,
+    // each with the union of its rings' source rows and tap ranges.
     P.groups.clear();
     P.rows.clear();
     P.nweights = 0;
     P.max_taps = 0;
     for (int r = 0; r < P.nrings;) {
-        if (general[r]) { ++r; continue; }
+        if (general[r] || !in_range(r)) { ++r; continue; }
         DevGroup G{};
         G.r0 = r;
         G.nr = 0;
-        while (r < P.nrings && !general[r] && G.nr < kGroupRings) { ++G.nr; ++r; }
+        while (r < P.nrings && !general[r] && in_range(r) && G.nr < kGroupRings) { ++G.nr; ++r; }
         G.row_begin = (int)P.rows.size();
         int s_lo = 1 << 30, s_hi = -1;
         for (int i = 0; i < G.nr; ++i) {
@@ -312,12 +316,16 @@ static int build_plan(Plan &P)
     const bool force_int_m = fim && std::string(fim) == "1";
     for (int r = 0; r <= P.nrings - 1 - r; ++r) {
         if (!general[r]) continue;
+        const int rm = P.nrings - 1 - r;
+        if (!in_range(r) && !in_range(rm)) continue;
         const int quarter = P.rings[r].n / 4;
         const int lanes = (P.rings[r].two_o ? (quarter - 1) / 2 : quarter / 2) + 1;
         // |m| = 2 n_r |c - j'| over the candidates, including those a wave
         // runs past a lane's window (at most 64 lanes per pixel, +4 for the
         // spread of windows across a wave)
         int flags = force_int_m ? (kTileIntM | kTileLongSin) : 0;
+        if (!in_range(r)) flags |= kTileSkipNorth;
+        if (!in_range(rm)) flags |= kTileSkipSouth;
         for (int k = P.dev_rings[r].pair_begin; k < P.dev_rings[r].pair_end; ++k) {
             const DevPair &pp = P.pairs[k];
             if (pp.mode & kPairLongSin) flags |= kTileLongSin;
@@ -368,7 +376,10 @@ static void count_pairs_rings(const Plan &P, int r0, int step, unsigned long lon
 {
     const double tc = P.desc.theta_cut;
     unsigned long long total = 0, circ_total = 0;
+    const int out_lo = P.desc.ring_first > 0 ? P.desc.ring_first - 1 : 0;
+    const int out_hi = P.desc.ring_first > 0 ? P.desc.ring_last - 1 : P.nrings - 1;
     for (int r = r0; r < P.nrings; r += step) {
+        if (r < out_lo || r > out_hi) continue;
         const HostRing &R = P.rings[r];
         const DevRing &dr = P.dev_rings[r];
         unsigned long long ring_total = 0;
@@ -689,6 +700,11 @@ int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
         return fail(ARKCOS_EINVAL, "unknown flag bits");
     if (int rc = check_grid(desc->theta_cut, desc->ntab, desc->theta_break, desc->k_break))
         return rc;
+    if (!(desc->ring_first == 0 && desc->ring_last == 0) &&
+        !(desc->ring_first >= 1 && desc->ring_first <= desc->ring_last &&
+          desc->ring_last <= 4 * desc->nside - 1))
+        return fail(ARKCOS_EINVAL, "ring range must be 0, 0 or 1 <= ring_first <= ring_last <= "
+                                   "4 nside - 1");
     const long long npix = 12LL * desc->nside * desc->nside;
     if ((long long)desc->max_batch * npix > 0x7fffffffLL * 4)
         return fail(ARKCOS_EUNSUPPORTED, "max_batch * Npix too large");
@@ -751,8 +767,12 @@ int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info)
     info->device_bytes = P->device_bytes;
     int circ = 0;
     for (const DevGroup &g : P->groups) circ += g.nr;
+    const int nout = P->desc.ring_first > 0 ? P->desc.ring_last - P->desc.ring_first + 1
+                                            : P->nrings;
     info->circulant_rings = circ;
-    info->general_rings = P->nrings - circ;
+    info->general_rings = nout - circ;
+    info->ring_first = P->desc.ring_first;
+    info->ring_last = P->desc.ring_last;
     info->circulant_tiles = (long long)P->ctiles.size();
     info->general_tiles = (long long)P->gtiles.size();
     info->weights = P->nweights;

@@ -314,3 +314,31 @@ def test_harm_argument_errors(nside, lcut, kind, status):
     assert rc == status and not h.value
     assert lib.arkcos_harm_destroy(None) == 0
     assert lib.arkcos_harm_convolve(None, None, None, 1, 0, None) == -1
+
+
+# ------------------------------------------------------ ring-range plans --
+
+@pytest.mark.parametrize("nside,tc_deg,rings", [(16, 7.0, (1, 10)), (16, 7.0, (12, 40)),
+                                                (16, 30.0, (31, 31)), (16, 7.0, (50, 63)),
+                                                (8, 100.0, (2, 29))])
+def test_ring_range_pair_count_and_info(nside, tc_deg, rings):
+    """A ring-range plan counts the in-disc pairs of its output rings only:
+    the oracle's per-pixel counts summed over those rings."""
+    tc = np.radians(tc_deg)
+    p = A.Plan(nside, tc, np.ones(8), host_only=True, rings=rings)
+    pc = O.pair_counts(nside, tc)
+    g = O.ring_geometry(nside)
+    lo, hi = g["first"][rings[0] - 1], g["first"][rings[1] - 1] + g["n"][rings[1] - 1]
+    assert p.pair_count() == int(pc[lo:hi].sum())
+    inf = p.info()
+    assert (inf["ring_first"], inf["ring_last"]) == rings
+    assert inf["circulant_rings"] + inf["general_rings"] == rings[1] - rings[0] + 1
+    full = A.Plan(nside, tc, np.ones(8), host_only=True)
+    assert inf["tiles"] <= full.info()["tiles"]
+
+
+@pytest.mark.parametrize("rings", [(0, 5), (5, 0), (6, 5), (1, 64), (-1, 3)])
+def test_ring_range_errors(rings):
+    with pytest.raises(A.ArkcosError) as e:
+        A.Plan(16, 0.1, np.ones(8), host_only=True, rings=rings)
+    assert e.value.status == -1 and "ring range" in str(e.value)
