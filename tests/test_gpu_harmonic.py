@@ -166,3 +166,26 @@ def test_split_convolution_matches_oracle_halves():
     out = torch.empty_like(xd)
     assert lib.arkcos_split_convolve(other.handle, harm.handle, xd.data_ptr(), out.data_ptr(), 1,
                                      None) == -1
+
+
+@pytest.mark.parametrize("lcut,tc_deg", [(94, 16.0), (150, 8.0)])
+def test_scytale_split_error_matches_eq2(lcut, tc_deg):
+    """A split made by the splitting tool, applied by the two GPU halves to
+    band-limited noise, differs from the full kernel (oracle, l <= lmax) by
+    the eq. 2 estimate over alpha (the paper's estimated vs actual error)."""
+    from paper_1211_3556_amd import scytale as S
+    A = _A()
+    nside, lmax = 128, 256
+    K = np.sqrt(S.cmb_like_cl(lmax, l_damp=lmax / 3.0)) * O.gaussian_bl(112 * W.ARCMIN, lmax)
+    sp = S.split_kernel(K, lcut, np.radians(tc_deg), ntab=2049)
+    x = O.harmonic(nside, np.ones(lmax + 1), W.white_noise(nside, 8))
+    plan = A.Plan(nside, sp.theta_cut, sp.khat_theta, theta_break=sp.theta_break,
+                  k_break=sp.k_break)
+    harm = A.Harm(nside, sp.khat_l)
+    log("scytale split lcut %d theta_cut %.0f deg" % (lcut, tc_deg))
+    y = to_host(A.split_convolve(plan, harm, to_dev(x)))
+    yf = O.harmonic(nside, K, x)
+    actual = rel_rms(y, yf)
+    est = sp.sigma / 5.0
+    log("scytale split actual %.3e, eq. 2 / alpha %.3e" % (actual, est))
+    assert 0.7 * est < actual < 1.4 * est
