@@ -166,13 +166,17 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_dft_fwd(const ShtRing *__re
 // O = F_r - F_mirror (l + m odd); the equator enters once, through E.
 __global__ __launch_bounds__(kShtThreads) void k_sht_leg_fwd(
     const ShtRing *__restrict__ rings, const double2 *__restrict__ F,
-    const double2 *__restrict__ rec, const double *__restrict__ mnorm, double *__restrict__ part,
-    int L, int nrings, int nnorth, long long nalm)
+    const double2 *__restrict__ rec, const double *__restrict__ mnorm,
+    const int *__restrict__ ring_lo, double *__restrict__ part, int L, int nrings, int nnorth,
+    long long nalm)
 {
     __shared__ double red[kLegCols][kShtThreads + 1];
     __shared__ double red2[kLegSegs][kLegCols];
     const int m = blockIdx.y;
     const int chunk = blockIdx.x;
+    // chunks whose rings all lie below ring_lo[m] contribute nothing (and
+    // k_sht_mul skips their partials)
+    if ((chunk + 1) * kShtThreads <= ring_lo[m]) return;
     const int i = chunk * kShtThreads + threadIdx.x;
     const bool act = i < nnorth;
     const int ii = act ? i : 0;
@@ -196,21 +200,38 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_leg_fwd(
     const double z = R.z;
     for (int l0 = m; l0 <= L; l0 += kLegBlock) {
         double pr[kLegBlock], pim[kLegBlock];
+        if (l0 > m && l0 + kLegBlock - 1 <= L && !__any(sc < 0)) {
+            // a full block with every lane of the wave unscaled: plain steps,
+            // the block's coefficients loaded together
+            double2 ab[kLegBlock];
 #pragma unroll
-        for (int k = 0; k < kLegBlock; ++k) {
-            const int l = l0 + k;
-            double v = 0.0;
-            if (l <= L) {
-                if (l == m) {
-                    v = sc == 0 ? l1 : 0.0;
-                } else {
-                    const double2 ab = rec[base + (l - m)];
-                    v = lambda_step(ab.x, ab.y, z, l1, l2, sc);
-                }
+            for (int k = 0; k < kLegBlock; ++k) ab[k] = rec[base + (l0 + k - m)];
+#pragma unroll
+            for (int k = 0; k < kLegBlock; ++k) {
+                const double v = fma(ab[k].x * z, l1, -ab[k].y * l2);
+                l2 = l1;
+                l1 = v;
+                const double2 src = ((l0 + k + m) & 1) ? O : E;
+                pr[k] = v * src.x;
+                pim[k] = v * src.y;
             }
-            const double2 src = ((l + m) & 1) ? O : E;
-            pr[k] = v * src.x;
-            pim[k] = v * src.y;
+        } else {
+#pragma unroll
+            for (int k = 0; k < kLegBlock; ++k) {
+                const int l = l0 + k;
+                double v = 0.0;
+                if (l <= L) {
+                    if (l == m) {
+                        v = sc == 0 ? l1 : 0.0;
+                    } else {
+                        const double2 ab = rec[base + (l - m)];
+                        v = lambda_step(ab.x, ab.y, z, l1, l2, sc);
+                    }
+                }
+                const double2 src = ((l + m) & 1) ? O : E;
+                pr[k] = v * src.x;
+                pim[k] = v * src.y;
+            }
         }
 #pragma unroll
         for (int k = 0; k < kLegBlock; ++k) {
@@ -242,6 +263,7 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_leg_fwd(
 // a_lm = Omega Khat_l sum over the ring chunks, in chunk order.
 __global__ __launch_bounds__(kShtThreads) void k_sht_mul(const double2 *__restrict__ part,
                                                          const double *__restrict__ kscale,
+                                                         const int *__restrict__ ring_lo,
                                                          double2 *__restrict__ alm, int L,
                                                          int nchunk, long long nalm)
 {
@@ -250,7 +272,7 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_mul(const double2 *__restri
     if (l > L) return;
     const long long idx = alm_base(m, L) + (l - m);
     double2 s = make_double2(0.0, 0.0);
-    for (int c = 0; c < nchunk; ++c) {
+    for (int c = ring_lo[m] / kShtThreads; c < nchunk; ++c) {
         const double2 p = part[(size_t)c * nalm + idx];
         s.x += p.x;
         s.y += p.y;
@@ -260,50 +282,90 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_mul(const double2 *__restri
 
 // ----------------------------------------------------------- synthesis --
 // G_r(m) = sum_l a_lm lambda_lm(theta_r) for a northern ring and its mirror.
+// While any lane of the wave still carries a scaled value the loop steps one
+// degree at a time with the rescale check; after that every lane is in range
+// for good and four degrees run per step, their coefficients loaded together.
 __global__ __launch_bounds__(kShtThreads) void k_sht_leg_bwd(
     const ShtRing *__restrict__ rings, const double2 *__restrict__ alm,
-    const double2 *__restrict__ rec, const double *__restrict__ mnorm, double2 *__restrict__ G,
-    int L, int nrings, int nnorth)
+    const double2 *__restrict__ rec, const double *__restrict__ mnorm,
+    const int *__restrict__ ring_lo, double2 *__restrict__ G, int L, int nrings, int nnorth)
 {
     const int m = blockIdx.y;
     const int i = blockIdx.x * kShtThreads + threadIdx.x;
-    if (i >= nnorth) return;
-    const ShtRing R = rings[i];
+    const bool act = i < nnorth;
+    if ((blockIdx.x + 1) * kShtThreads <= ring_lo[m]) {   // every term negligible
+        if (act) {
+            G[(size_t)m * nrings + i] = make_double2(0.0, 0.0);
+            G[(size_t)m * nrings + (nrings - 1 - i)] = make_double2(0.0, 0.0);
+        }
+        return;
+    }
+    const ShtRing R = rings[act ? i : nnorth - 1];
     const int mir = nrings - 1 - i;
     int sc;
     double l1 = lambda_mm_scaled(mnorm[m], m, R.log2s, sc);
     double l2 = 0.0;
     const long long base = alm_base(m, L);
     const double z = R.z;
-    double2 ae = make_double2(0.0, 0.0), ao = ae;   // l + m even, odd
+    double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};   // l + m even, odd
     {
         const double v = sc == 0 ? l1 : 0.0;
         const double2 a = alm[base];
-        ae.x = fma(v, a.x, ae.x);
-        ae.y = fma(v, a.y, ae.y);
+        acc[0].x = fma(v, a.x, acc[0].x);
+        acc[0].y = fma(v, a.y, acc[0].y);
     }
     int l = m + 1;
-    for (; l + 1 <= L; l += 2) {
+    for (; l <= L && __any(sc < 0); ++l) {
         const double2 r1 = rec[base + (l - m)];
-        const double v1 = lambda_step(r1.x, r1.y, z, l1, l2, sc);
-        const double2 a1 = alm[base + (l - m)];
-        ao.x = fma(v1, a1.x, ao.x);
-        ao.y = fma(v1, a1.y, ao.y);
-        const double2 r2 = rec[base + (l + 1 - m)];
-        const double v2 = lambda_step(r2.x, r2.y, z, l1, l2, sc);
-        const double2 a2 = alm[base + (l + 1 - m)];
-        ae.x = fma(v2, a2.x, ae.x);
-        ae.y = fma(v2, a2.y, ae.y);
+        const double v = lambda_step(r1.x, r1.y, z, l1, l2, sc);
+        const double2 a = alm[base + (l - m)];
+        double2 &t = acc[(l - m) & 1];
+        t.x = fma(v, a.x, t.x);
+        t.y = fma(v, a.y, t.y);
     }
-    if (l <= L) {
+    // every lane unscaled: parity of the first degree fixed by one step if needed
+    if (l <= L && ((l - m) & 1) == 1) {
         const double2 r1 = rec[base + (l - m)];
-        const double v1 = lambda_step(r1.x, r1.y, z, l1, l2, sc);
-        const double2 a1 = alm[base + (l - m)];
-        ao.x = fma(v1, a1.x, ao.x);
-        ao.y = fma(v1, a1.y, ao.y);
+        const double v = fma(r1.x * z, l1, -r1.y * l2);
+        l2 = l1;
+        l1 = v;
+        const double2 a = alm[base + (l - m)];
+        acc[1].x = fma(v, a.x, acc[1].x);
+        acc[1].y = fma(v, a.y, acc[1].y);
+        ++l;
     }
-    G[(size_t)m * nrings + i] = make_double2(ae.x + ao.x, ae.y + ao.y);
-    if (mir != i) G[(size_t)m * nrings + mir] = make_double2(ae.x - ao.x, ae.y - ao.y);
+    for (; l + 3 <= L; l += 4) {
+        const long long k = base + (l - m);
+        const double2 r0 = rec[k], r1 = rec[k + 1], r2 = rec[k + 2], r3 = rec[k + 3];
+        const double2 a0 = alm[k], a1 = alm[k + 1], a2 = alm[k + 2], a3 = alm[k + 3];
+        const double v0 = fma(r0.x * z, l1, -r0.y * l2);
+        const double v1 = fma(r1.x * z, v0, -r1.y * l1);
+        const double v2 = fma(r2.x * z, v1, -r2.y * v0);
+        const double v3 = fma(r3.x * z, v2, -r3.y * v1);
+        l2 = v2;
+        l1 = v3;
+        acc[0].x = fma(v0, a0.x, acc[0].x);
+        acc[0].y = fma(v0, a0.y, acc[0].y);
+        acc[1].x = fma(v1, a1.x, acc[1].x);
+        acc[1].y = fma(v1, a1.y, acc[1].y);
+        acc[0].x = fma(v2, a2.x, acc[0].x);
+        acc[0].y = fma(v2, a2.y, acc[0].y);
+        acc[1].x = fma(v3, a3.x, acc[1].x);
+        acc[1].y = fma(v3, a3.y, acc[1].y);
+    }
+    for (; l <= L; ++l) {
+        const double2 r1 = rec[base + (l - m)];
+        const double v = fma(r1.x * z, l1, -r1.y * l2);
+        l2 = l1;
+        l1 = v;
+        const double2 a = alm[base + (l - m)];
+        double2 &t = acc[(l - m) & 1];
+        t.x = fma(v, a.x, t.x);
+        t.y = fma(v, a.y, t.y);
+    }
+    if (!act) return;
+    G[(size_t)m * nrings + i] = make_double2(acc[0].x + acc[1].x, acc[0].y + acc[1].y);
+    if (mir != i) G[(size_t)m * nrings + mir] = make_double2(acc[0].x - acc[1].x, acc[0].y - acc[1].y);
 }
 
 // y_j = Re sum_m H_m e^{i m a_j}, a_j = 2 pi j / n, H_m = c_m G_r(m) e^{i m phi_0}:
@@ -395,6 +457,7 @@ struct Harm {
     double2 *d_rec = nullptr;
     double *d_mnorm = nullptr;
     double *d_kscale = nullptr;
+    int *d_ring_lo = nullptr;     // per m: first northern ring whose terms matter
     double2 *d_F = nullptr;       // F, then G: (lcut+1) x nrings
     double2 *d_part = nullptr;    // nchunk x nalm
     double2 *d_alm = nullptr;
@@ -409,7 +472,7 @@ static void harm_free(Harm &h)
         (void)hipSetDevice(h.device);
         (void)hipDeviceSynchronize();
         for (void *p : {(void *)h.d_rings, (void *)h.d_rec, (void *)h.d_mnorm, (void *)h.d_kscale,
-                        (void *)h.d_F, (void *)h.d_part, (void *)h.d_alm})
+                        (void *)h.d_ring_lo, (void *)h.d_F, (void *)h.d_part, (void *)h.d_alm})
             if (p) (void)hipFree(p);
         (void)hipSetDevice(cur);
     }
@@ -417,6 +480,7 @@ static void harm_free(Harm &h)
     h.d_rec = nullptr;
     h.d_mnorm = nullptr;
     h.d_kscale = nullptr;
+    h.d_ring_lo = nullptr;
     h.d_F = nullptr;
     h.d_part = nullptr;
     h.d_alm = nullptr;
@@ -473,6 +537,49 @@ static int harm_build(Harm &h)
             rec[base + (l - m)] = make_double2(a, a * b);
         }
     }
+    // Per order m, the first northern ring (rings run from the pole to the
+    // equator, sin theta increasing) on which some lambda_lm, l <= lcut,
+    // exceeds 2^-394: below it every term is negligible and the Legendre
+    // kernels skip the ring.  For fixed l and m, |lambda_lm| grows with
+    // sin theta until the oscillatory range, so the rings that matter are a
+    // suffix and a bisection finds its start.
+    std::vector<int> ring_lo(L + 1, 0);
+    auto matters = [&](int i, int m) {
+        const ShtRing &Rg = rings[i];
+        double e = mnorm[m] + m * Rg.log2s;      // log2 |lambda_mm|
+        if (e > -394.0) return true;
+        double scale = std::floor(e);               // |lambda| = v1 2^scale
+        double v1 = std::exp2(e - scale);
+        double v2 = 0.0;
+        const long long base = alm_base(m, L);
+        for (int l = m + 1; l <= L; ++l) {
+            const double2 ab = rec[base + (l - m)];
+            const double v = ab.x * Rg.z * v1 - ab.y * v2;
+            v2 = v1;
+            v1 = v;
+            if (std::fabs(v1) > 0x1p200 || (std::fabs(v1) < 0x1p-200 && v1 != 0.0)) {
+                int k = 0;
+                std::frexp(v1, &k);
+                v1 = std::ldexp(v1, -k);
+                v2 = std::ldexp(v2, -k);
+                scale += k;
+            }
+            if (v1 != 0.0 && std::log2(std::fabs(v1)) + scale > -394.0) return true;
+        }
+        return false;
+    };
+    for (int m = 0; m <= L; ++m) {
+        int lo = 0, hi = h.nnorth - 1;           // first index in [lo, hi] that matters
+        if (!matters(hi, m)) {
+            ring_lo[m] = hi;
+            continue;
+        }
+        while (lo < hi) {
+            const int mid = lo + (hi - lo) / 2;
+            if (matters(mid, m)) hi = mid; else lo = mid + 1;
+        }
+        ring_lo[m] = lo;
+    }
     ARKCOS_HIP_CHECK(hipGetDevice(&h.device));
     int rc;
     if ((rc = harm_alloc((void **)&h.d_rings, rings.size() * sizeof(ShtRing), &h.device_bytes)))
@@ -482,6 +589,8 @@ static int harm_build(Harm &h)
     if ((rc = harm_alloc((void **)&h.d_mnorm, mnorm.size() * sizeof(double), &h.device_bytes)))
         return rc;
     if ((rc = harm_alloc((void **)&h.d_kscale, (L + 1) * sizeof(double), &h.device_bytes)))
+        return rc;
+    if ((rc = harm_alloc((void **)&h.d_ring_lo, (L + 1) * sizeof(int), &h.device_bytes)))
         return rc;
     if ((rc = harm_alloc((void **)&h.d_F, (size_t)(L + 1) * h.nrings * sizeof(double2),
                          &h.device_bytes)))
@@ -496,6 +605,8 @@ static int harm_build(Harm &h)
     ARKCOS_HIP_CHECK(hipMemcpy(h.d_rec, rec.data(), rec.size() * sizeof(double2),
                                hipMemcpyHostToDevice));
     ARKCOS_HIP_CHECK(hipMemcpy(h.d_mnorm, mnorm.data(), mnorm.size() * sizeof(double),
+                               hipMemcpyHostToDevice));
+    ARKCOS_HIP_CHECK(hipMemcpy(h.d_ring_lo, ring_lo.data(), ring_lo.size() * sizeof(int),
                                hipMemcpyHostToDevice));
     return harm_upload_kernel(h);
 }
@@ -520,12 +631,12 @@ static int harm_launch(const Harm &h, const float *in, float *out, int accumulat
         }
     }
     hipLaunchKernelGGL(k_sht_leg_fwd, dim3(h.nchunk, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
-                       h.d_F, h.d_rec, h.d_mnorm, (double *)h.d_part, L, h.nrings, h.nnorth,
-                       h.nalm);
+                       h.d_F, h.d_rec, h.d_mnorm, h.d_ring_lo, (double *)h.d_part, L, h.nrings,
+                       h.nnorth, h.nalm);
     hipLaunchKernelGGL(k_sht_mul, dim3((L + kShtThreads) / kShtThreads, L + 1), dim3(kShtThreads),
-                       0, s, h.d_part, h.d_kscale, h.d_alm, L, h.nchunk, h.nalm);
+                       0, s, h.d_part, h.d_kscale, h.d_ring_lo, h.d_alm, L, h.nchunk, h.nalm);
     hipLaunchKernelGGL(k_sht_leg_bwd, dim3(h.nchunk, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
-                       h.d_alm, h.d_rec, h.d_mnorm, h.d_F, L, h.nrings, h.nnorth);
+                       h.d_alm, h.d_rec, h.d_mnorm, h.d_ring_lo, h.d_F, L, h.nrings, h.nnorth);
     hipLaunchKernelGGL(k_sht_dft_bwd, dim3(h.nrings), dim3(kShtThreads),
                        (size_t)(L + 1) * sizeof(double2), s, h.d_rings, h.d_F, out, L, h.nrings,
                        accumulate);
