@@ -421,10 +421,29 @@ def main() -> int:
         t = time.perf_counter()
         _, pairs = O.convolve(s.nside, s.theta_cut, k64, x64, pixels=pix, return_pairs=True)
         dt = time.perf_counter() - t
-        cpu = {"value": round(float(pairs.sum()) / dt / 1e9, 4), "unit": "GPair-evals/s",
-               "cores": O.threads(), "kind": "oracle",
+        rate = float(pairs.sum()) / dt
+        cores = O.threads()
+        # the same oracle on one thread, over every 16th pixel of the sample
+        O.set_threads(1)
+        sub = pix[::16]
+        t = time.perf_counter()
+        _, p1 = O.convolve(s.nside, s.theta_cut, k64, x64, pixels=sub, return_pairs=True)
+        dt1 = time.perf_counter() - t
+        O.set_threads(cores)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f
+                              if ln.startswith("model name")), "")
+        except OSError:
+            pass
+        cpu = {"value": round(rate / 1e9, 4), "unit": "GPair-evals/s",
+               "cores": cores, "kind": "oracle",
                "sample": "Nside 2048, FWHM 5', theta_cut 20', %d random output pixels "
-                         "(%d pairs, %.1f s); FP64 C/OpenMP" % (pix.size, int(pairs.sum()), dt)}
+                         "(%d pairs, %.1f s); FP64 C/OpenMP" % (pix.size, int(pairs.sum()), dt),
+               "cpu_model": model,
+               "one_thread_value": round(float(p1.sum()) / dt1 / 1e9, 4),
+               "full_map_seconds": round(fwd_pairs[2] / rate, 1)}
 
     out = {
         "metric": METRIC,

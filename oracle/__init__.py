@@ -70,6 +70,7 @@ def _load():
         lib.orc_harmonic.argtypes = [ctypes.c_long, ctypes.c_long, _dp, _dp, _dp]
         lib.orc_legendre_lm.argtypes = [ctypes.c_long, ctypes.c_double, _dp]
         lib.orc_threads.restype = ctypes.c_int
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -100,6 +101,11 @@ def _check(rc, what):
 def threads() -> int:
     """OpenMP threads the oracle runs with."""
     return int(_load().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Run the oracle's parallel loops on n OpenMP threads."""
+    _check(_load().orc_set_threads(int(n)), "set_threads")
 
 
 def npix(nside: int) -> int:

@@ -634,5 +634,11 @@ int orc_legendre_lm(long L, double theta, double *lam)
     return 0;
 }
 
-/* Number of threads the oracle runs with (for reporting). */
+/* Number of threads the oracle runs with (for reporting), and a setter. */
 int orc_threads(void) { return omp_get_max_threads(); }
+int orc_set_threads(int n)
+{
+    if (n < 1) return -1;
+    omp_set_num_threads(n);
+    return 0;
+}
