@@ -340,10 +340,18 @@ def main() -> int:
             res[label] = e0.elapsed_time(e1) / reps
         npix, nnorth = 12 * s.nside ** 2, 2 * s.nside
         nalm = (L + 1) * (L + 2) // 2
-        # algorithmic FP64 FLOP: Goertzel 3 per (pixel, m); Clenshaw 3 per
-        # (pixel, m); Legendre recurrence 4 plus 2 (analysis) or 4 (synthesis)
-        # per (l, m, northern ring)
-        flop64 = 6.0 * npix * (L + 1) + (6.0 + 8.0) * nnorth * nalm
+        # algorithmic FP64 FLOP: belt rings of power-of-two length 4 Nside by
+        # real FFTs (complex FFT of half the length, 5 M log2 M each way),
+        # the other rings by Goertzel and Clenshaw (3 per pixel and m each
+        # way); Legendre recurrence 4 plus 2 (analysis) or 4 (synthesis) per
+        # (l, m, northern ring)
+        nb = 4 * s.nside
+        M = nb // 2
+        fft = (nb & (nb - 1)) == 0 and 2 <= M <= 8192 and L < M
+        belt_rings = 2 * s.nside + 1 if fft else 0
+        dft_pix = npix - belt_rings * nb
+        flop64 = (6.0 * dft_pix * (L + 1) + belt_rings * 2 * 5.0 * M * np.log2(M)
+                  + (6.0 + 8.0) * nnorth * nalm)
         tf = flop64 / (res["l_space_half"] * 1e-3) / 1e12
         biased["split_example"] = {
             "nside": s.nside, "l_cut": L, "theta_cut_arcmin": round(s.theta_cut / W.ARCMIN, 3),

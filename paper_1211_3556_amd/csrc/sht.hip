@@ -13,7 +13,10 @@
 //
 //  1. k_sht_dft_fwd   per ring: F_r(m) = sum_j x_j e^{-i m phi_j}, m <= lcut,
 //                     by Goertzel's second-order recurrence (one FMA and one
-//                     add per sample and frequency, no phase table);
+//                     add per sample and frequency, no phase table); belt
+//                     rings whose length is a power of two (and exceeds
+//                     2 lcut) take k_sht_fft_fwd instead, a real FFT done as
+//                     one LDS-resident complex FFT of half the length;
 //  2. k_sht_leg_fwd   per (m, chunk of northern rings): lambda_lm by its
 //                     recurrence in l, times the even / odd N-S combinations
 //                     of F, reduced over the chunk's rings through LDS into
@@ -24,7 +27,8 @@
 //                     mirror;
 //  5. k_sht_dft_bwd   per ring: y_j = Re sum_m c_m G_r(m) e^{i m phi_j}
 //                     (c_0 = 1, c_m = 2) by Clenshaw's recurrence, one pass
-//                     for the pixel pair j, n - j.
+//                     for the pixel pair j, n - j; k_sht_fft_bwd is the
+//                     inverse real FFT for the rings of k_sht_fft_fwd.
 //
 // lambda_mm underflows FP64 for large m near the poles, so the recurrence
 // carries a power-of-two scale: a value is lam * 2^(512 sc) with sc <= 0, and
@@ -62,6 +66,7 @@ constexpr int kLegBlock = 8;        // degrees l per LDS reduction in k_sht_leg_
 constexpr int kLegCols = 2 * kLegBlock;            // re, im per degree
 constexpr int kLegSegs = kShtThreads / kLegCols;   // row segments of a column
 constexpr int kShtPairs = 2;        // pixel pairs per thread in k_sht_dft_bwd
+constexpr int kShtFftMaxM = 8192;   // complex FFT length in LDS (128 KB of FP64 pairs)
 constexpr double kScaleUp = 0x1p128;     // rescale threshold of a scaled value
 constexpr double kScaleStep = 0x1p-512;  // one scale step
 
@@ -111,12 +116,13 @@ __device__ __forceinline__ double lambda_step(double A, double B, double z, doub
 // covers frequencies m = m0 + thread + k kShtThreads, k < K.
 template <int K>
 __global__ __launch_bounds__(kShtThreads) void k_sht_dft_fwd(const ShtRing *__restrict__ rings,
+                                                             const int *__restrict__ ring_list,
                                                              const float *__restrict__ x,
                                                              double2 *__restrict__ F, int m0,
                                                              int L, int nrings)
 {
     __shared__ double2 sx[kShtChunk / 2];
-    const int r = blockIdx.x;
+    const int r = ring_list[blockIdx.x];
     const ShtRing R = rings[r];
     const float *xr = x + R.first;
     double c[K], s1[K], s2[K];
@@ -372,12 +378,13 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_leg_bwd(
 // with C = sum Re H_m cos(m a) and S = sum Im H_m sin(m a) (Clenshaw, shared
 // coefficient 2 cos a), y_j = C - S and y_{n-j} = C + S.
 __global__ __launch_bounds__(kShtThreads) void k_sht_dft_bwd(const ShtRing *__restrict__ rings,
+                                                             const int *__restrict__ ring_list,
                                                              const double2 *__restrict__ G,
                                                              float *__restrict__ out, int L,
                                                              int nrings, int accumulate)
 {
     extern __shared__ double2 H[];
-    const int r = blockIdx.x;
+    const int r = ring_list[blockIdx.x];
     const ShtRing R = rings[r];
     for (int m = threadIdx.x; m <= L; m += kShtThreads) {
         const double2 g = G[(size_t)m * nrings + r];
@@ -440,6 +447,118 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_dft_bwd(const ShtRing *__re
     }
 }
 
+// ----------------------------------------------------------- belt FFTs --
+// A ring of n = 2M pixels, M a power of two.  The real transform
+// X_m = sum_j x_j e^{-2 pi i m j / n} comes from the complex FFT Z of
+// z_k = x_{2k} + i x_{2k+1} (length M):
+//     X_m = (Z_m + conj Z_{M-m}) / 2 - i e^{-i pi m / M} (Z_m - conj Z_{M-m}) / 2,
+// and the inverse from Z_q = (S_q + conj S_{M-q}) + i e^{i pi q / M} (S_q - conj S_{M-q})
+// for a Hermitian spectrum S (S_{n-m} = conj S_m, zero above lcut < M), whose
+// inverse complex FFT gives z_k = y_{2k} + i y_{2k+1}.  The FFT is radix 2,
+// decimation in time, in place in LDS after a bit-reversed load; tw[t] =
+// e^{-2 pi i t / M} for t < M/2 and hw[m] = e^{-i pi m / M} for m <= M are
+// plan tables.
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b)
+{
+    return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+}
+
+__device__ __forceinline__ double2 conj2(double2 a) { return make_double2(a.x, -a.y); }
+
+// In-place FFT of z (bit-reversed input order), sign -1 (forward) or +1.
+__device__ __forceinline__ void fft_lds(double2 *z, const double2 *__restrict__ tw, int M,
+                                        int logM, bool inverse)
+{
+    for (int st = 0; st < logM; ++st) {
+        const int h = 1 << st;
+        for (int b = threadIdx.x; b < (M >> 1); b += kShtThreads) {
+            const int j = b & (h - 1);
+            const int k = ((b >> st) << (st + 1)) + j;
+            double2 w = tw[j << (logM - 1 - st)];
+            if (inverse) w.y = -w.y;
+            const double2 a = z[k];
+            const double2 t = cmul(w, z[k + h]);
+            z[k] = make_double2(a.x + t.x, a.y + t.y);
+            z[k + h] = make_double2(a.x - t.x, a.y - t.y);
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kShtThreads) void k_sht_fft_fwd(
+    const ShtRing *__restrict__ rings, const int *__restrict__ ring_list,
+    const double2 *__restrict__ tw, const double2 *__restrict__ hw, const float *__restrict__ x,
+    double2 *__restrict__ F, int L, int nrings, int M, int logM)
+{
+    extern __shared__ double2 z[];
+    const int r = ring_list[blockIdx.x];
+    const ShtRing R = rings[r];
+    const float *xr = x + R.first;
+    for (int k = threadIdx.x; k < M; k += kShtThreads) {
+        const float2 v = *reinterpret_cast<const float2 *>(xr + 2 * k);
+        z[__brev((unsigned)k) >> (32 - logM)] = make_double2((double)v.x, (double)v.y);
+    }
+    __syncthreads();
+    fft_lds(z, tw, M, logM, false);
+    for (int m = threadIdx.x; m <= L; m += kShtThreads) {
+        const double2 a = z[m & (M - 1)];
+        const double2 b = conj2(z[(M - m) & (M - 1)]);
+        const double2 e = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+        const double2 d = make_double2(0.5 * (a.x - b.x), 0.5 * (a.y - b.y));
+        // X_m = e - i hw[m] d
+        const double2 hd = cmul(hw[m], d);
+        const double2 X = make_double2(e.x + hd.y, e.y - hd.x);
+        // times e^{-i m phi_0}, phi_0 = two_o pi / n
+        const long long q = ((long long)m * R.two_o) % (2LL * R.n);
+        double sp, cp;
+        sincospi((double)q / (double)R.n, &sp, &cp);
+        F[(size_t)m * nrings + r] = make_double2(cp * X.x + sp * X.y, cp * X.y - sp * X.x);
+    }
+}
+
+__global__ __launch_bounds__(kShtThreads) void k_sht_fft_bwd(
+    const ShtRing *__restrict__ rings, const int *__restrict__ ring_list,
+    const double2 *__restrict__ tw, const double2 *__restrict__ hw, const double2 *__restrict__ G,
+    float *__restrict__ out, int L, int nrings, int M, int logM, int accumulate)
+{
+    extern __shared__ double2 z[];
+    const int r = ring_list[blockIdx.x];
+    const ShtRing R = rings[r];
+    // S_m = G_r(m) e^{i m phi_0} for 1 <= m <= lcut, S_0 = Re G_r(0), else 0
+    auto spec = [&](int m) -> double2 {
+        if (m > L) return make_double2(0.0, 0.0);
+        const double2 g = G[(size_t)m * nrings + r];
+        if (m == 0) return make_double2(g.x, 0.0);
+        const long long q = ((long long)m * R.two_o) % (2LL * R.n);
+        double sp, cp;
+        sincospi((double)q / (double)R.n, &sp, &cp);
+        return make_double2(g.x * cp - g.y * sp, g.x * sp + g.y * cp);
+    };
+    for (int qi = threadIdx.x; qi < M; qi += kShtThreads) {
+        const double2 a = spec(qi);
+        const double2 b = conj2(spec(qi == 0 ? M : M - qi));
+        const double2 e = make_double2(a.x + b.x, a.y + b.y);
+        const double2 d = make_double2(a.x - b.x, a.y - b.y);
+        // Z_q = e + i conj(hw[q]) d
+        const double2 hd = cmul(conj2(hw[qi]), d);
+        z[__brev((unsigned)qi) >> (32 - logM)] = make_double2(e.x - hd.y, e.y + hd.x);
+    }
+    __syncthreads();
+    fft_lds(z, tw, M, logM, true);
+    float *o = out + R.first;
+    for (int k = threadIdx.x; k < M; k += kShtThreads) {
+        const double2 v = z[k];
+        float2 y = make_float2((float)v.x, (float)v.y);
+        if (accumulate) {
+            const float2 p = *reinterpret_cast<const float2 *>(o + 2 * k);
+            y.x = p.x + y.x;
+            y.y = p.y + y.y;
+        }
+        *reinterpret_cast<float2 *>(o + 2 * k) = y;
+    }
+}
+
 // ---------------------------------------------------------------- host --
 struct Harm {
     int nside = 0;
@@ -458,6 +577,11 @@ struct Harm {
     double *d_mnorm = nullptr;
     double *d_kscale = nullptr;
     int *d_ring_lo = nullptr;     // per m: first northern ring whose terms matter
+    int *d_dft_rings = nullptr;   // rings of the Goertzel / Clenshaw kernels
+    int *d_fft_rings = nullptr;   // rings of the FFT kernels (belt, n = 2^k > 2 lcut)
+    double2 *d_tw = nullptr;      // FFT tables tw (M/2) and hw (M + 1)
+    double2 *d_hw = nullptr;
+    int n_dft = 0, n_fft = 0, fft_m = 0, fft_log = 0;
     double2 *d_F = nullptr;       // F, then G: (lcut+1) x nrings
     double2 *d_part = nullptr;    // nchunk x nalm
     double2 *d_alm = nullptr;
@@ -472,7 +596,9 @@ static void harm_free(Harm &h)
         (void)hipSetDevice(h.device);
         (void)hipDeviceSynchronize();
         for (void *p : {(void *)h.d_rings, (void *)h.d_rec, (void *)h.d_mnorm, (void *)h.d_kscale,
-                        (void *)h.d_ring_lo, (void *)h.d_F, (void *)h.d_part, (void *)h.d_alm})
+                        (void *)h.d_ring_lo, (void *)h.d_dft_rings, (void *)h.d_fft_rings,
+                        (void *)h.d_tw, (void *)h.d_hw, (void *)h.d_F, (void *)h.d_part,
+                        (void *)h.d_alm})
             if (p) (void)hipFree(p);
         (void)hipSetDevice(cur);
     }
@@ -481,6 +607,10 @@ static void harm_free(Harm &h)
     h.d_mnorm = nullptr;
     h.d_kscale = nullptr;
     h.d_ring_lo = nullptr;
+    h.d_dft_rings = nullptr;
+    h.d_fft_rings = nullptr;
+    h.d_tw = nullptr;
+    h.d_hw = nullptr;
     h.d_F = nullptr;
     h.d_part = nullptr;
     h.d_alm = nullptr;
@@ -580,6 +710,26 @@ static int harm_build(Harm &h)
         }
         ring_lo[m] = lo;
     }
+    // Belt rings take the FFT when their length n = 4 Nside is a power of two,
+    // n/2 fits the LDS (complex FP64) and lcut < n/2; the others Goertzel.
+    std::vector<int> dft_rings, fft_rings;
+    {
+        const int n = 4 * h.nside;
+        const bool pow2 = (n & (n - 1)) == 0;
+        const int M = n / 2;
+        const bool fft = pow2 && M >= 2 && M <= kShtFftMaxM && L < M &&
+                         std::getenv("ARKCOS_SHT_NO_FFT") == nullptr;
+        for (int i = 0; i < h.nrings; ++i) {
+            if (fft && rings[i].n == n) fft_rings.push_back(i); else dft_rings.push_back(i);
+        }
+        if (fft) {
+            h.fft_m = M;
+            h.fft_log = 0;
+            while ((1 << h.fft_log) < M) ++h.fft_log;
+        }
+    }
+    h.n_dft = (int)dft_rings.size();
+    h.n_fft = (int)fft_rings.size();
     ARKCOS_HIP_CHECK(hipGetDevice(&h.device));
     int rc;
     if ((rc = harm_alloc((void **)&h.d_rings, rings.size() * sizeof(ShtRing), &h.device_bytes)))
@@ -592,6 +742,37 @@ static int harm_build(Harm &h)
         return rc;
     if ((rc = harm_alloc((void **)&h.d_ring_lo, (L + 1) * sizeof(int), &h.device_bytes)))
         return rc;
+    if ((rc = harm_alloc((void **)&h.d_dft_rings, dft_rings.size() * sizeof(int), &h.device_bytes)))
+        return rc;
+    if ((rc = harm_alloc((void **)&h.d_fft_rings, fft_rings.size() * sizeof(int), &h.device_bytes)))
+        return rc;
+    if (h.n_fft > 0) {
+        const int M = h.fft_m;
+        std::vector<double2> tw(M / 2 > 0 ? M / 2 : 1), hw(M + 1);
+        for (int t = 0; t < M / 2; ++t)
+            tw[t] = make_double2(std::cos(2.0 * M_PI * t / M), -std::sin(2.0 * M_PI * t / M));
+        for (int m = 0; m <= M; ++m)
+            hw[m] = make_double2(std::cos(M_PI * m / M), -std::sin(M_PI * m / M));
+        if ((rc = harm_alloc((void **)&h.d_tw, tw.size() * sizeof(double2), &h.device_bytes)))
+            return rc;
+        if ((rc = harm_alloc((void **)&h.d_hw, hw.size() * sizeof(double2), &h.device_bytes)))
+            return rc;
+        ARKCOS_HIP_CHECK(hipMemcpy(h.d_tw, tw.data(), tw.size() * sizeof(double2),
+                                   hipMemcpyHostToDevice));
+        ARKCOS_HIP_CHECK(hipMemcpy(h.d_hw, hw.data(), hw.size() * sizeof(double2),
+                                   hipMemcpyHostToDevice));
+        const size_t lds = (size_t)M * sizeof(double2);
+        ARKCOS_HIP_CHECK(hipFuncSetAttribute((const void *)k_sht_fft_fwd,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        ARKCOS_HIP_CHECK(hipFuncSetAttribute((const void *)k_sht_fft_bwd,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    }
+    if (!dft_rings.empty())
+        ARKCOS_HIP_CHECK(hipMemcpy(h.d_dft_rings, dft_rings.data(), dft_rings.size() * sizeof(int),
+                                   hipMemcpyHostToDevice));
+    if (!fft_rings.empty())
+        ARKCOS_HIP_CHECK(hipMemcpy(h.d_fft_rings, fft_rings.data(), fft_rings.size() * sizeof(int),
+                                   hipMemcpyHostToDevice));
     if ((rc = harm_alloc((void **)&h.d_F, (size_t)(L + 1) * h.nrings * sizeof(double2),
                          &h.device_bytes)))
         return rc;
@@ -615,14 +796,19 @@ static int harm_build(Harm &h)
 static int harm_launch(const Harm &h, const float *in, float *out, int accumulate, hipStream_t s)
 {
     const int L = h.lcut;
+    const size_t fft_lds = (size_t)h.fft_m * sizeof(double2);
+    if (h.n_fft > 0)
+        hipLaunchKernelGGL(k_sht_fft_fwd, dim3(h.n_fft), dim3(kShtThreads), fft_lds, s, h.d_rings,
+                           h.d_fft_rings, h.d_tw, h.d_hw, in, h.d_F, L, h.nrings, h.fft_m,
+                           h.fft_log);
     // frequencies per thread, kShtMaxFreq per launch
-    for (int m0 = 0, left = (L + kShtThreads) / kShtThreads; left > 0;
+    for (int m0 = 0, left = (L + kShtThreads) / kShtThreads; h.n_dft > 0 && left > 0;
          m0 += kShtMaxFreq * kShtThreads, left -= kShtMaxFreq) {
         switch (std::min(left, kShtMaxFreq)) {
 #define ARKCOS_DFT_CASE(K)                                                                   \
     case K:                                                                                  \
-        hipLaunchKernelGGL(k_sht_dft_fwd<K>, dim3(h.nrings), dim3(kShtThreads), 0, s,       \
-                           h.d_rings, in, h.d_F, m0, L, h.nrings);                           \
+        hipLaunchKernelGGL(k_sht_dft_fwd<K>, dim3(h.n_dft), dim3(kShtThreads), 0, s,        \
+                           h.d_rings, h.d_dft_rings, in, h.d_F, m0, L, h.nrings);            \
         break;
             ARKCOS_DFT_CASE(1) ARKCOS_DFT_CASE(2) ARKCOS_DFT_CASE(3) ARKCOS_DFT_CASE(4)
             ARKCOS_DFT_CASE(5) ARKCOS_DFT_CASE(6) ARKCOS_DFT_CASE(7)
@@ -637,9 +823,14 @@ static int harm_launch(const Harm &h, const float *in, float *out, int accumulat
                        0, s, h.d_part, h.d_kscale, h.d_ring_lo, h.d_alm, L, h.nchunk, h.nalm);
     hipLaunchKernelGGL(k_sht_leg_bwd, dim3(h.nchunk, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
                        h.d_alm, h.d_rec, h.d_mnorm, h.d_ring_lo, h.d_F, L, h.nrings, h.nnorth);
-    hipLaunchKernelGGL(k_sht_dft_bwd, dim3(h.nrings), dim3(kShtThreads),
-                       (size_t)(L + 1) * sizeof(double2), s, h.d_rings, h.d_F, out, L, h.nrings,
-                       accumulate);
+    if (h.n_dft > 0)
+        hipLaunchKernelGGL(k_sht_dft_bwd, dim3(h.n_dft), dim3(kShtThreads),
+                           (size_t)(L + 1) * sizeof(double2), s, h.d_rings, h.d_dft_rings, h.d_F,
+                           out, L, h.nrings, accumulate);
+    if (h.n_fft > 0)
+        hipLaunchKernelGGL(k_sht_fft_bwd, dim3(h.n_fft), dim3(kShtThreads), fft_lds, s, h.d_rings,
+                           h.d_fft_rings, h.d_tw, h.d_hw, h.d_F, out, L, h.nrings, h.fft_m,
+                           h.fft_log, accumulate);
     ARKCOS_HIP_CHECK(hipGetLastError());
     return ARKCOS_OK;
 }

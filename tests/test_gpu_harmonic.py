@@ -38,7 +38,9 @@ def _khat(lcut, seed):
 
 
 @pytest.mark.parametrize("nside,lcut", [(1, 0), (1, 9), (2, 30), (4, 23), (8, 40), (16, 47),
-                                        (13, 50), (64, 191)])
+                                        (13, 50), (64, 191),
+                                        # belt rings by FFT: n = 4 Nside a power of two, lcut < 2 Nside
+                                        (1, 1), (8, 12), (32, 60), (64, 127), (128, 255)])
 def test_harmonic_full_maps(nside, lcut):
     khat = _khat(lcut, nside + lcut)
     x = W.white_noise(nside, 300 + nside)
@@ -49,6 +51,26 @@ def test_harmonic_full_maps(nside, lcut):
     err = rel_rms(y, ref)
     log("harmonic rel rms %.3e" % err)
     assert err <= REL_RMS_TOL
+
+
+def test_harmonic_fft_and_goertzel_paths_agree(monkeypatch):
+    """The belt-ring FFT and the Goertzel / Clenshaw sums compute the same
+    FP64 transforms: outputs agree to FP32 rounding, also when accumulating."""
+    import torch
+    nside, lcut = 256, 400
+    khat = _khat(lcut, 12)
+    x = to_dev(W.white_noise(nside, 13))
+    A = _A()
+    log("harmonic FFT vs Goertzel paths Nside %d lcut %d" % (nside, lcut))
+    y_fft = A.Harm(nside, khat).convolve(x)
+    monkeypatch.setenv("ARKCOS_SHT_NO_FFT", "1")
+    h_dft = A.Harm(nside, khat)
+    y_dft = h_dft.convolve(x)
+    acc = torch.full_like(x, 0.25)
+    h_dft.convolve(x, out=acc, accumulate=True)
+    _sync()
+    assert rel_rms(to_host(y_fft), to_host(y_dft)) <= 1e-7
+    assert rel_rms(to_host(acc) - 0.25, to_host(y_dft)) <= 1e-6
 
 
 def test_harmonic_batch_and_accumulate():
