@@ -65,6 +65,8 @@ constexpr int kShtMaxFreq = 8;      // frequencies per thread and pass in k_sht_
 constexpr int kLegBlock = 8;        // degrees l per LDS reduction in k_sht_leg_fwd
 constexpr int kLegCols = 2 * kLegBlock;            // re, im per degree
 constexpr int kLegSegs = kShtThreads / kLegCols;   // row segments of a column
+constexpr int kLegRings = 2;        // northern rings per lane in k_sht_leg_fwd
+constexpr int kLegChunk = kLegRings * kShtThreads;  // rings per k_sht_leg_fwd workgroup
 constexpr int kShtPairs = 2;        // pixel pairs per thread in k_sht_dft_bwd
 constexpr int kShtFftMaxM = 8192;   // complex FFT length in LDS (128 KB of FP64 pairs)
 constexpr double kScaleUp = 0x1p128;     // rescale threshold of a scaled value
@@ -182,31 +184,47 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_leg_fwd(
     const int chunk = blockIdx.x;
     // chunks whose rings all lie below ring_lo[m] contribute nothing (and
     // k_sht_mul skips their partials)
-    if ((chunk + 1) * kShtThreads <= ring_lo[m]) return;
-    const int i = chunk * kShtThreads + threadIdx.x;
-    const bool act = i < nnorth;
-    const int ii = act ? i : 0;
-    const ShtRing R = rings[ii];
-    const int mir = nrings - 1 - ii;
-    double2 E = make_double2(0.0, 0.0), O = E;
-    if (act) {
-        const double2 a = F[(size_t)m * nrings + ii];
-        if (mir == ii) {
-            E = a;
-        } else {
-            const double2 b = F[(size_t)m * nrings + mir];
-            E = make_double2(a.x + b.x, a.y + b.y);
-            O = make_double2(a.x - b.x, a.y - b.y);
+    if ((chunk + 1) * kLegChunk <= ring_lo[m]) return;
+    // kLegRings rings per lane: independent recurrences, summed in registers
+    // before the block reduction
+    double2 E[kLegRings], O[kLegRings];
+    double z[kLegRings], l1[kLegRings], l2[kLegRings];
+    int sc[kLegRings];
+#pragma unroll
+    for (int q = 0; q < kLegRings; ++q) {
+        const int i = chunk * kLegChunk + q * kShtThreads + threadIdx.x;
+        const bool act = i < nnorth;
+        const int ii = act ? i : 0;
+        const ShtRing R = rings[ii];
+        const int mir = nrings - 1 - ii;
+        E[q] = make_double2(0.0, 0.0);
+        O[q] = E[q];
+        if (act) {
+            const double2 a = F[(size_t)m * nrings + ii];
+            if (mir == ii) {
+                E[q] = a;
+            } else {
+                const double2 b = F[(size_t)m * nrings + mir];
+                E[q] = make_double2(a.x + b.x, a.y + b.y);
+                O[q] = make_double2(a.x - b.x, a.y - b.y);
+            }
         }
+        l1[q] = lambda_mm_scaled(mnorm[m], m, R.log2s, sc[q]);
+        l2[q] = 0.0;
+        z[q] = R.z;
     }
-    int sc;
-    double l1 = lambda_mm_scaled(mnorm[m], m, R.log2s, sc);
-    double l2 = 0.0;
     const long long base = alm_base(m, L);
-    const double z = R.z;
     for (int l0 = m; l0 <= L; l0 += kLegBlock) {
         double pr[kLegBlock], pim[kLegBlock];
-        if (l0 > m && l0 + kLegBlock - 1 <= L && !__any(sc < 0)) {
+#pragma unroll
+        for (int k = 0; k < kLegBlock; ++k) {
+            pr[k] = 0.0;
+            pim[k] = 0.0;
+        }
+        bool scaled = false;
+#pragma unroll
+        for (int q = 0; q < kLegRings; ++q) scaled |= sc[q] < 0;
+        if (l0 > m && l0 + kLegBlock - 1 <= L && !__any(scaled)) {
             // a full block with every lane of the wave unscaled: plain steps,
             // the block's coefficients loaded together
             double2 ab[kLegBlock];
@@ -214,29 +232,36 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_leg_fwd(
             for (int k = 0; k < kLegBlock; ++k) ab[k] = rec[base + (l0 + k - m)];
 #pragma unroll
             for (int k = 0; k < kLegBlock; ++k) {
-                const double v = fma(ab[k].x * z, l1, -ab[k].y * l2);
-                l2 = l1;
-                l1 = v;
-                const double2 src = ((l0 + k + m) & 1) ? O : E;
-                pr[k] = v * src.x;
-                pim[k] = v * src.y;
+                const bool odd = ((l0 + k + m) & 1) != 0;
+#pragma unroll
+                for (int q = 0; q < kLegRings; ++q) {
+                    const double v = fma(ab[k].x * z[q], l1[q], -ab[k].y * l2[q]);
+                    l2[q] = l1[q];
+                    l1[q] = v;
+                    const double2 src = odd ? O[q] : E[q];
+                    pr[k] = fma(v, src.x, pr[k]);
+                    pim[k] = fma(v, src.y, pim[k]);
+                }
             }
         } else {
 #pragma unroll
             for (int k = 0; k < kLegBlock; ++k) {
                 const int l = l0 + k;
-                double v = 0.0;
-                if (l <= L) {
+                if (l > L) continue;
+                const bool odd = ((l + m) & 1) != 0;
+#pragma unroll
+                for (int q = 0; q < kLegRings; ++q) {
+                    double v;
                     if (l == m) {
-                        v = sc == 0 ? l1 : 0.0;
+                        v = sc[q] == 0 ? l1[q] : 0.0;
                     } else {
                         const double2 ab = rec[base + (l - m)];
-                        v = lambda_step(ab.x, ab.y, z, l1, l2, sc);
+                        v = lambda_step(ab.x, ab.y, z[q], l1[q], l2[q], sc[q]);
                     }
+                    const double2 src = odd ? O[q] : E[q];
+                    pr[k] = fma(v, src.x, pr[k]);
+                    pim[k] = fma(v, src.y, pim[k]);
                 }
-                const double2 src = ((l + m) & 1) ? O : E;
-                pr[k] = v * src.x;
-                pim[k] = v * src.y;
             }
         }
 #pragma unroll
@@ -247,13 +272,13 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_leg_fwd(
         __syncthreads();
         {
             // column col (degree l0 + col/2, re or im) summed over one segment
-            // of kShtThreads / kLegSegs rings
+            // of kShtThreads / kLegSegs lanes
             constexpr int rows = kShtThreads / kLegSegs;
             const int col = threadIdx.x % kLegCols;
             const int seg = threadIdx.x / kLegCols;
-            double s = 0.0;
-            for (int q = 0; q < rows; ++q) s += red[col][seg * rows + q];
-            red2[seg][col] = s;
+            double t = 0.0;
+            for (int q = 0; q < rows; ++q) t += red[col][seg * rows + q];
+            red2[seg][col] = t;
         }
         __syncthreads();
         if (threadIdx.x < kLegCols) {
@@ -278,7 +303,7 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_mul(const double2 *__restri
     if (l > L) return;
     const long long idx = alm_base(m, L) + (l - m);
     double2 s = make_double2(0.0, 0.0);
-    for (int c = ring_lo[m] / kShtThreads; c < nchunk; ++c) {
+    for (int c = ring_lo[m] / kLegChunk; c < nchunk; ++c) {
         const double2 p = part[(size_t)c * nalm + idx];
         s.x += p.x;
         s.y += p.y;
@@ -287,91 +312,97 @@ __global__ __launch_bounds__(kShtThreads) void k_sht_mul(const double2 *__restri
 }
 
 // ----------------------------------------------------------- synthesis --
-// G_r(m) = sum_l a_lm lambda_lm(theta_r) for a northern ring and its mirror.
-// While any lane of the wave still carries a scaled value the loop steps one
-// degree at a time with the rescale check; after that every lane is in range
-// for good and four degrees run per step, their coefficients loaded together.
+// G_r(m) = sum_l a_lm lambda_lm(theta_r) for northern rings and their mirrors,
+// kLegRings rings per lane (independent recurrences sharing the loads of the
+// coefficients), in blocks of kLegBlock degrees: plain steps once every lane
+// of the wave is unscaled, steps with the rescale check before that.
 __global__ __launch_bounds__(kShtThreads) void k_sht_leg_bwd(
     const ShtRing *__restrict__ rings, const double2 *__restrict__ alm,
     const double2 *__restrict__ rec, const double *__restrict__ mnorm,
     const int *__restrict__ ring_lo, double2 *__restrict__ G, int L, int nrings, int nnorth)
 {
     const int m = blockIdx.y;
-    const int i = blockIdx.x * kShtThreads + threadIdx.x;
-    const bool act = i < nnorth;
-    if ((blockIdx.x + 1) * kShtThreads <= ring_lo[m]) {   // every term negligible
-        if (act) {
-            G[(size_t)m * nrings + i] = make_double2(0.0, 0.0);
-            G[(size_t)m * nrings + (nrings - 1 - i)] = make_double2(0.0, 0.0);
+    const int i0 = blockIdx.x * kLegChunk + threadIdx.x;
+    if ((blockIdx.x + 1) * kLegChunk <= ring_lo[m]) {   // every term negligible
+#pragma unroll
+        for (int q = 0; q < kLegRings; ++q) {
+            const int i = i0 + q * kShtThreads;
+            if (i < nnorth) {
+                G[(size_t)m * nrings + i] = make_double2(0.0, 0.0);
+                G[(size_t)m * nrings + (nrings - 1 - i)] = make_double2(0.0, 0.0);
+            }
         }
         return;
     }
-    const ShtRing R = rings[act ? i : nnorth - 1];
-    const int mir = nrings - 1 - i;
-    int sc;
-    double l1 = lambda_mm_scaled(mnorm[m], m, R.log2s, sc);
-    double l2 = 0.0;
+    double z[kLegRings], l1[kLegRings], l2[kLegRings];
+    int sc[kLegRings];
+    double2 ae[kLegRings], ao[kLegRings];   // l + m even, odd
     const long long base = alm_base(m, L);
-    const double z = R.z;
-    double2 acc[2] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0)};   // l + m even, odd
-    {
-        const double v = sc == 0 ? l1 : 0.0;
-        const double2 a = alm[base];
-        acc[0].x = fma(v, a.x, acc[0].x);
-        acc[0].y = fma(v, a.y, acc[0].y);
+    const double2 a_m = alm[base];
+#pragma unroll
+    for (int q = 0; q < kLegRings; ++q) {
+        const int i = min(i0 + q * kShtThreads, nnorth - 1);
+        const ShtRing R = rings[i];
+        l1[q] = lambda_mm_scaled(mnorm[m], m, R.log2s, sc[q]);
+        l2[q] = 0.0;
+        z[q] = R.z;
+        const double v = sc[q] == 0 ? l1[q] : 0.0;
+        ae[q] = make_double2(v * a_m.x, v * a_m.y);
+        ao[q] = make_double2(0.0, 0.0);
     }
-    int l = m + 1;
-    for (; l <= L && __any(sc < 0); ++l) {
-        const double2 r1 = rec[base + (l - m)];
-        const double v = lambda_step(r1.x, r1.y, z, l1, l2, sc);
-        const double2 a = alm[base + (l - m)];
-        double2 &t = acc[(l - m) & 1];
-        t.x = fma(v, a.x, t.x);
-        t.y = fma(v, a.y, t.y);
+    // degrees m+1 .. L in blocks of kLegBlock: plain steps when every lane of
+    // the wave is unscaled, steps with the rescale check otherwise
+    for (int l0 = m + 1; l0 <= L; l0 += kLegBlock) {
+        bool scaled = false;
+#pragma unroll
+        for (int q = 0; q < kLegRings; ++q) scaled |= sc[q] < 0;
+        if (l0 + kLegBlock - 1 <= L && !__any(scaled)) {
+            double2 rb[kLegBlock], ab[kLegBlock];
+#pragma unroll
+            for (int k = 0; k < kLegBlock; ++k) {
+                rb[k] = rec[base + (l0 + k - m)];
+                ab[k] = alm[base + (l0 + k - m)];
+            }
+#pragma unroll
+            for (int k = 0; k < kLegBlock; ++k) {
+                const bool odd = ((l0 + k - m) & 1) != 0;
+#pragma unroll
+                for (int q = 0; q < kLegRings; ++q) {
+                    const double v = fma(rb[k].x * z[q], l1[q], -rb[k].y * l2[q]);
+                    l2[q] = l1[q];
+                    l1[q] = v;
+                    double2 &t = odd ? ao[q] : ae[q];
+                    t.x = fma(v, ab[k].x, t.x);
+                    t.y = fma(v, ab[k].y, t.y);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < kLegBlock; ++k) {
+                const int l = l0 + k;
+                if (l > L) continue;
+                const double2 r1 = rec[base + (l - m)];
+                const double2 a = alm[base + (l - m)];
+                const bool odd = ((l - m) & 1) != 0;
+#pragma unroll
+                for (int q = 0; q < kLegRings; ++q) {
+                    const double v = lambda_step(r1.x, r1.y, z[q], l1[q], l2[q], sc[q]);
+                    double2 &t = odd ? ao[q] : ae[q];
+                    t.x = fma(v, a.x, t.x);
+                    t.y = fma(v, a.y, t.y);
+                }
+            }
+        }
     }
-    // every lane unscaled: parity of the first degree fixed by one step if needed
-    if (l <= L && ((l - m) & 1) == 1) {
-        const double2 r1 = rec[base + (l - m)];
-        const double v = fma(r1.x * z, l1, -r1.y * l2);
-        l2 = l1;
-        l1 = v;
-        const double2 a = alm[base + (l - m)];
-        acc[1].x = fma(v, a.x, acc[1].x);
-        acc[1].y = fma(v, a.y, acc[1].y);
-        ++l;
+#pragma unroll
+    for (int q = 0; q < kLegRings; ++q) {
+        const int i = i0 + q * kShtThreads;
+        if (i >= nnorth) continue;
+        const int mir = nrings - 1 - i;
+        G[(size_t)m * nrings + i] = make_double2(ae[q].x + ao[q].x, ae[q].y + ao[q].y);
+        if (mir != i)
+            G[(size_t)m * nrings + mir] = make_double2(ae[q].x - ao[q].x, ae[q].y - ao[q].y);
     }
-    for (; l + 3 <= L; l += 4) {
-        const long long k = base + (l - m);
-        const double2 r0 = rec[k], r1 = rec[k + 1], r2 = rec[k + 2], r3 = rec[k + 3];
-        const double2 a0 = alm[k], a1 = alm[k + 1], a2 = alm[k + 2], a3 = alm[k + 3];
-        const double v0 = fma(r0.x * z, l1, -r0.y * l2);
-        const double v1 = fma(r1.x * z, v0, -r1.y * l1);
-        const double v2 = fma(r2.x * z, v1, -r2.y * v0);
-        const double v3 = fma(r3.x * z, v2, -r3.y * v1);
-        l2 = v2;
-        l1 = v3;
-        acc[0].x = fma(v0, a0.x, acc[0].x);
-        acc[0].y = fma(v0, a0.y, acc[0].y);
-        acc[1].x = fma(v1, a1.x, acc[1].x);
-        acc[1].y = fma(v1, a1.y, acc[1].y);
-        acc[0].x = fma(v2, a2.x, acc[0].x);
-        acc[0].y = fma(v2, a2.y, acc[0].y);
-        acc[1].x = fma(v3, a3.x, acc[1].x);
-        acc[1].y = fma(v3, a3.y, acc[1].y);
-    }
-    for (; l <= L; ++l) {
-        const double2 r1 = rec[base + (l - m)];
-        const double v = fma(r1.x * z, l1, -r1.y * l2);
-        l2 = l1;
-        l1 = v;
-        const double2 a = alm[base + (l - m)];
-        double2 &t = acc[(l - m) & 1];
-        t.x = fma(v, a.x, t.x);
-        t.y = fma(v, a.y, t.y);
-    }
-    if (!act) return;
-    G[(size_t)m * nrings + i] = make_double2(acc[0].x + acc[1].x, acc[0].y + acc[1].y);
-    if (mir != i) G[(size_t)m * nrings + mir] = make_double2(acc[0].x - acc[1].x, acc[0].y - acc[1].y);
 }
 
 // y_j = Re sum_m H_m e^{i m a_j}, a_j = 2 pi j / n, H_m = c_m G_r(m) e^{i m phi_0}:
@@ -566,7 +597,8 @@ struct Harm {
     int nnorth = 0;     // northern rings and the equator: 2 Nside
     int lcut = 0;
     int max_batch = 1;
-    int nchunk = 0;
+    int nchunk = 0;     // ring chunks of kShtThreads rings
+    int nchunk_fwd = 0; // ring chunks of the Legendre kernels (kLegChunk rings)
     int device = -1;
     long long npix = 0;
     long long nalm = 0;
@@ -776,7 +808,7 @@ static int harm_build(Harm &h)
     if ((rc = harm_alloc((void **)&h.d_F, (size_t)(L + 1) * h.nrings * sizeof(double2),
                          &h.device_bytes)))
         return rc;
-    if ((rc = harm_alloc((void **)&h.d_part, (size_t)h.nchunk * h.nalm * sizeof(double2),
+    if ((rc = harm_alloc((void **)&h.d_part, (size_t)h.nchunk_fwd * h.nalm * sizeof(double2),
                          &h.device_bytes)))
         return rc;
     if ((rc = harm_alloc((void **)&h.d_alm, (size_t)h.nalm * sizeof(double2), &h.device_bytes)))
@@ -816,12 +848,12 @@ static int harm_launch(const Harm &h, const float *in, float *out, int accumulat
 #undef ARKCOS_DFT_CASE
         }
     }
-    hipLaunchKernelGGL(k_sht_leg_fwd, dim3(h.nchunk, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
+    hipLaunchKernelGGL(k_sht_leg_fwd, dim3(h.nchunk_fwd, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
                        h.d_F, h.d_rec, h.d_mnorm, h.d_ring_lo, (double *)h.d_part, L, h.nrings,
                        h.nnorth, h.nalm);
     hipLaunchKernelGGL(k_sht_mul, dim3((L + kShtThreads) / kShtThreads, L + 1), dim3(kShtThreads),
-                       0, s, h.d_part, h.d_kscale, h.d_ring_lo, h.d_alm, L, h.nchunk, h.nalm);
-    hipLaunchKernelGGL(k_sht_leg_bwd, dim3(h.nchunk, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
+                       0, s, h.d_part, h.d_kscale, h.d_ring_lo, h.d_alm, L, h.nchunk_fwd, h.nalm);
+    hipLaunchKernelGGL(k_sht_leg_bwd, dim3(h.nchunk_fwd, L + 1), dim3(kShtThreads), 0, s, h.d_rings,
                        h.d_alm, h.d_rec, h.d_mnorm, h.d_ring_lo, h.d_F, L, h.nrings, h.nnorth);
     if (h.n_dft > 0)
         hipLaunchKernelGGL(k_sht_dft_bwd, dim3(h.n_dft), dim3(kShtThreads),
@@ -870,6 +902,7 @@ int arkcos_harm_create(int nside, int lcut, const double *khat, int max_batch,
     h->omega = 4.0 * M_PI / (double)h->npix;
     h->nalm = alm_base(lcut + 1, lcut);
     h->nchunk = (h->nnorth + kShtThreads - 1) / kShtThreads;
+    h->nchunk_fwd = (h->nnorth + kLegChunk - 1) / kLegChunk;
     int rc;
     try {
         h->khat.assign(khat, khat + lcut + 1);
