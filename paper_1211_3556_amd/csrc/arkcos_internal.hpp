@@ -54,10 +54,24 @@ struct DevPair {
     float w;
     int s;       // 0-based source ring
     int mode;
+    // Rows without kPairLongSin: v = m mscale (mscale a power of two that
+    // brings xscale / mscale into [1/2, 1), so v is exact in FP32), y = v^2
+    // and the polynomial sq[0] + y (sq[1] + y (sq[2] + y (sq[3] + y sq[4]))).
+    // In angle mode 0 it is the squared node coordinate u0^2 (the series of
+    // (2 asin(d/2))^2 composed with the chord and scaled by the node density);
+    // otherwise it is the squared chord d^2, through x^6 (sq[4] = 0).
+    float mscale;
+    float sq[5];
+    float pad[2];
 };
 constexpr int kPairWhole = 1;
 constexpr int kPairLongSin = 2;
-static_assert(sizeof(DevPair) == 32, "DevPair layout");
+static_assert(sizeof(DevPair) == 64, "DevPair layout");
+// Largest |x| = |dphi / 2| of a short row: the truncated series stay within
+// 1e-9 relative there (angle mode 0 through x^8, first omitted term
+// 2^10 x^10 / 10!; the squared chord through x^6, next term x^8 / 315).
+constexpr double kShortXMaxMode0 = 0.2;
+constexpr double kShortXMax = 0.09;
 
 // FP64 copy of the chord constants of a ring pair, used where the node index
 // and fraction must be exact to ~1e-9: the circulant weight rows (built once

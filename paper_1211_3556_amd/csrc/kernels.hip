@@ -57,21 +57,16 @@ __device__ __forceinline__ cptr<T> cst(const T *p)
 }
 
 // ------------------------------------------------------------ FP32 math --
-// sin(x) by its Taylor series: LONG through x^13 for |x| <= 2 (truncation
-// below 2e-8 relative), otherwise through x^7 for |x| <= 0.35 (below 1e-9).
-template <bool LONG>
+// sin(x) by its Taylor series through x^13, for |x| <= 2 (truncation below
+// 2e-8 relative).  Rows whose candidates stay at small |x| use the
+// polynomial of their pair record instead.
 __device__ __forceinline__ float sin_series(float x)
 {
     const float x2 = x * x;
-    float p;
-    if (LONG) {
-        p = 1.0f / 6227020800.0f;             // 1/13!
-        p = fmaf(p, x2, -1.0f / 39916800.0f); // 1/11!
-        p = fmaf(p, x2, 1.0f / 362880.0f);    // 1/9!
-        p = fmaf(p, x2, -1.0f / 5040.0f);     // 1/7!
-    } else {
-        p = -1.0f / 5040.0f;
-    }
+    float p = 1.0f / 6227020800.0f;           // 1/13!
+    p = fmaf(p, x2, -1.0f / 39916800.0f);     // 1/11!
+    p = fmaf(p, x2, 1.0f / 362880.0f);        // 1/9!
+    p = fmaf(p, x2, -1.0f / 5040.0f);         // 1/7!
     p = fmaf(p, x2, 1.0f / 120.0f);           // 1/5!
     p = fmaf(p, x2, -1.0f / 6.0f);            // 1/3!
     p = fmaf(p, x2, 1.0f);
@@ -510,29 +505,54 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
 {
     // every uniform operand of the loop in a vector register
     const float zslot = gc.zslot;
-    const float A = vreg(pp.A);
-    const float B = vreg(pp.B);
-    const float xscale = vreg(pp.xscale);
+    const float A = LONG ? vreg(pp.A) : 0.0f;
+    // LONG: d^2 = A + B sin^2 x with x = m xscale and the sine by its series;
+    // otherwise the row polynomial in y = (m mscale)^2: u0^2 in angle mode 0,
+    // else d^2
+    const float B = LONG ? vreg(pp.B) : 0.0f;
+    const float xscale = LONG ? vreg(pp.xscale) : 0.0f;
+    const float q0 = LONG ? 0.0f : vreg(pp.sq[0]);
+    const float q1 = LONG ? 0.0f : vreg(pp.sq[1]);
+    const float q2 = LONG ? 0.0f : vreg(pp.sq[2]);
+    const float q3 = LONG ? 0.0f : vreg(pp.sq[3]);
+    const float q4 = (LONG || AM != 0) ? 0.0f : vreg(pp.sq[4]);
     const float u_max = gc.u_max;
     const UCoef &ucf = gc.ucf;
-    const int last = vreg(cn - 1 + c0);
-    const int stepv = vreg(step);
+    // Candidates are addressed by LDS byte address: o steps by 16 step bytes,
+    // a lane's candidates end at o_a1 and reads clamp to the chunk's last
+    // staged position (the clamped reads carry weight zero).
+    typedef float v4f __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) const v4f lds_float4;
+    const int sb = (int)(size_t)(lds_float4 *)stage;
+    int o = sb + 16 * (jq - c0);
+    const int o_a1 = sb + 16 * (a1 - c0);
+    const int o_last = vreg(sb + 16 * (cn - 1));
+    const int o_step = vreg(16 * step);
     // The longitude numerator m falls by dm per candidate.  It is kept as an
     // FP32 integer, exact while |m| < 2^24 (the plan checks this per ring and
-    // otherwise selects INTM), so x = m xscale rounds once with no conversion.
-    float mf = (float)m;
-    const float dmf = vreg((float)dm);
+    // otherwise selects INTM), times a power of two on short rows, so it
+    // carries no rounding.
+    const float ms = LONG ? 1.0f : pp.mscale;
+    float mf = (float)m * ms;
+    const float dmf = vreg((float)dm * ms);
     int mi = m;
     const int dmi = vreg(dm);
-    const float4 *st = stage - c0;                           // indexed by jq >= c0
 #pragma unroll 2
     for (int t = 0; t < T; ++t) {
-        const bool valid = jq <= a1;
-        const int pos = min(jq, last);
-        const float x = (INTM ? (float)mi : mf) * xscale;   // half the longitude difference
-        const float sx = sin_series<LONG>(x);
-        const float d2 = fmaf(B, sx * sx, A);                // squared chord
-        const float u0 = node_coord<AM>(d2, ucf);
+        const bool valid = o <= o_a1;
+        const int oc = min(o, o_last);
+        float u0;
+        if (LONG) {
+            const float x = (INTM ? (float)mi : mf) * xscale;   // half the longitude difference
+            const float sx = sin_series(x);
+            u0 = node_coord<AM>(fmaf(B, sx * sx, A), ucf);
+        } else if (AM == 0) {
+            const float y = mf * mf;
+            u0 = __builtin_amdgcn_sqrtf(fmaf(fmaf(fmaf(fmaf(y, q4, q3), y, q2), y, q1), y, q0));
+        } else {
+            const float y = mf * mf;
+            u0 = node_coord<AM>(fmaf(fmaf(fmaf(y, q3, q2), y, q1), y, q0), ucf);
+        }
         const float u = BIAS ? fminf(u0, fmaf(u0, gc.br, gc.bc)) : u0;
         const float uc = (valid && u0 < u_max) ? u : zslot;
         const int node = (int)uc;
@@ -540,10 +560,11 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         const float k0 = tab[node];
         const float k1 = tab[node + 1];
         const float w = fmaf(frac, k1 - k0, k0);
-        const float4 v0 = st[pos];
-        const float4 v1 = st[kGenStage + pos];
-        const float4 v2 = st[2 * kGenStage + pos];
-        const float4 v3 = st[3 * kGenStage + pos];
+        lds_float4 *sp = (lds_float4 *)(size_t)oc;
+        const v4f v0 = sp[0];
+        const v4f v1 = sp[kGenStage];
+        const v4f v2 = sp[2 * kGenStage];
+        const v4f v3 = sp[3 * kGenStage];
         row[0] = fmaf(w, v0.x, row[0]);
         row[1] = fmaf(w, v0.y, row[1]);
         row[2] = fmaf(w, v0.z, row[2]);
@@ -560,7 +581,7 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         row[13] = fmaf(w, v3.y, row[13]);
         row[14] = fmaf(w, v3.z, row[14]);
         row[15] = fmaf(w, v3.w, row[15]);
-        jq += stepv;
+        o += o_step;
         if (INTM)
             mi -= dmi;
         else

@@ -54,6 +54,53 @@ HostRing ring_geometry(int N, int i)
     return g;
 }
 
+// Node coordinates per radian of the first (or only) grid piece: the table
+// index of angle theta is u0 = node_density theta on that piece.
+static double node_density(const arkcos_plan_desc &d)
+{
+    if (d.k_break > 0) return d.k_break / d.theta_break;
+    return (d.ntab - 1) / d.theta_cut;
+}
+
+// Coefficients of a short row's polynomial in y = (m mscale)^2 (the layout is
+// described with DevPair).  sin^2 x = sum_k (-1)^(k+1) 2^(2k-1) x^(2k) / (2k)!
+// with x^2 = s^2 y; theta^2 = (2 asin(d/2))^2 = sum_n 2 d^(2n) / (n^2 C(2n, n)).
+static void short_row_poly(double A, double B, double xscale, int angle_mode, double density,
+                           DevPair &p)
+{
+    int e = 0;
+    const double sc = std::frexp(xscale, &e);
+    p.mscale = (float)std::ldexp(1.0, e);
+    constexpr int K = 4;
+    double d[K + 1];   // d^2 = A + B sin^2 x as a polynomial in y
+    d[0] = A;
+    double term = 1.0;
+    for (int k = 1; k <= K; ++k) {
+        term *= 4.0 * sc * sc / ((2.0 * k - 1.0) * (2.0 * k));   // 2^(2k) s^(2k) / (2k)!
+        d[k] = (k % 2 ? 0.5 : -0.5) * B * term;
+    }
+    double out[K + 1] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    if (angle_mode != 0) {
+        for (int k = 0; k < K; ++k) out[k] = d[k];
+    } else {
+        // u0^2 = density^2 sum_n b_n (d^2)^n, truncated at y^K; d^2 < 0.01 on
+        // the rows of such a plan, so n <= 6 leaves terms below 1e-13
+        double pw[K + 1] = {1.0, 0.0, 0.0, 0.0, 0.0};
+        double binom = 1.0;   // C(2n, n)
+        for (int n = 1; n <= 6; ++n) {
+            double nx[K + 1] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int i = 0; i <= K; ++i)
+                for (int j = 0; i + j <= K; ++j) nx[i + j] += pw[i] * d[j];
+            for (int i = 0; i <= K; ++i) pw[i] = nx[i];
+            binom = binom * (2.0 * n - 1.0) * (2.0 * n) / ((double)n * n);
+            const double b = 2.0 / ((double)n * n * binom);
+            for (int i = 0; i <= K; ++i) out[i] += b * pw[i];
+        }
+        for (int i = 0; i <= K; ++i) out[i] *= density * density;
+    }
+    for (int i = 0; i <= K; ++i) p.sq[i] = (float)out[i];
+}
+
 DevPlanView Plan::view() const
 {
     DevPlanView v{};
@@ -79,10 +126,10 @@ DevPlanView Plan::view() const
     v.angle_mode = angle_mode;
     // node coordinate map: u0 = a0 theta, u = min(u0, r u0 + c)
     const bool biased = desc.k_break > 0;
-    double ih = (desc.ntab - 1) / desc.theta_cut, r = 1.0, c0 = 0.0;
+    const double ih = node_density(desc);
+    double r = 1.0, c0 = 0.0;
     if (biased) {
         const double a1 = (desc.ntab - 1 - desc.k_break) / (desc.theta_cut - desc.theta_break);
-        ih = desc.k_break / desc.theta_break;
         r = a1 / ih;
         // c >= 0 since the first piece is at least as fine as the second;
         // clamping its rounding keeps u >= 0 (the node index and fraction of
@@ -180,6 +227,7 @@ static int build_plan(Plan &P)
             p.A = (float)pd.A;
             p.B = (float)pd.B;
             p.xscale = (float)pd.xscale;
+            short_row_poly(pd.A, pd.B, pd.xscale, P.angle_mode, node_density(P.desc), p);
             p.a = (float)((double)S.n / (double)R.n);
             p.b = (float)(0.5 * R.two_o * (double)S.n / (double)R.n - 0.5 * S.two_o);
             // window half-width in source pixels, widened to cover FP32 rounding
@@ -193,7 +241,7 @@ static int build_plan(Plan &P)
             } else {
                 // largest |dphi/2| a candidate can have: (w + 1) pixels of ring s
                 const double xmax = (w + 1.0) * M_PI / (double)S.n;
-                p.mode = xmax > 0.35 ? kPairLongSin : 0;
+                p.mode = xmax > (P.angle_mode == 0 ? kShortXMaxMode0 : kShortXMax) ? kPairLongSin : 0;
                 p.w = (float)w;
                 per_pixel += std::floor(2.0 * w) + 1.0;
             }
