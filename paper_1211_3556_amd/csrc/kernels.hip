@@ -176,6 +176,13 @@ constexpr int kStageRegs = (kCircSeg + kCircMaxTaps + kThreads - 1) / kThreads;
 // Weights each lane prefetches per row: kGroupRings per tap.
 constexpr int kWeightRegs = kCircMaxTaps * kGroupRings / kThreads;
 
+// A load at a 32-bit byte offset from a wave-uniform base: the base stays in
+// scalar registers and no 64-bit address arithmetic is needed per lane.
+__device__ __forceinline__ float ld_off(const float *base, unsigned byte_off)
+{
+    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+
 // Issue the global loads of one staged row (pixels base .. base+nstage-1 of a
 // ring of n pixels, wrapped) into registers.
 __device__ __forceinline__ void prefetch_row(const float *src, int base, int nstage, int n,
@@ -184,7 +191,7 @@ __device__ __forceinline__ void prefetch_row(const float *src, int base, int nst
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u) {
         const int e = threadIdx.x + u * kThreads;
-        v[u] = (e < nstage) ? src[wrap_index(base + e, n)] : 0.0f;
+        v[u] = (e < nstage) ? ld_off(src, 4u * (unsigned)wrap_index(base + e, n)) : 0.0f;
     }
 }
 
@@ -194,7 +201,7 @@ __device__ __forceinline__ void prefetch_weights(const float *w, int nw, float v
 #pragma unroll
     for (int u = 0; u < kWeightRegs; ++u) {
         const int e = threadIdx.x + u * kThreads;
-        v[u] = (e < nw) ? w[e] : 0.0f;
+        v[u] = (e < nw) ? ld_off(w, 4u * (unsigned)e) : 0.0f;
     }
 }
 
@@ -442,14 +449,9 @@ __device__ __forceinline__ float node_coord(float d2, const UCoef &uc)
 // Threads at or past cn load nothing: positions past the chunk are never
 // read.  Loads address their ring by 32-bit byte offsets shared between a
 // ring and its mirror (the ring's base stays in scalar registers).
-__device__ __forceinline__ float ld_off(const float *base, unsigned byte_off)
-{
-    return *reinterpret_cast<const float *>(reinterpret_cast<const char *>(base) + byte_off);
-}
-
-__device__ __forceinline__ void prefetch16(const float *src, const float *srcm, bool mirror,
-                                           int n_s, int two_o_s, int c0, int cn, float4 &a,
-                                           float4 &b, float4 &c, float4 &d)
+__device__ __forceinline__ void prefetch16(const float *src, const float *srcm, int n_s,
+                                           int two_o_s, int c0, int cn, float4 &a, float4 &b,
+                                           float4 &c, float4 &d)
 {
     const int e = threadIdx.x;
     if (e >= cn) return;
@@ -469,15 +471,12 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
     a = make_float4(ld_off(src, od[0]), ld_off(src, od[1]), ld_off(src, od[2]), ld_off(src, od[3]));
     c = make_float4(ld_off(src, orf[0]), ld_off(src, orf[1]), ld_off(src, orf[2]),
                     ld_off(src, orf[3]));
-    if (mirror) {
-        b = make_float4(ld_off(srcm, od[0]), ld_off(srcm, od[1]), ld_off(srcm, od[2]),
-                        ld_off(srcm, od[3]));
-        d = make_float4(ld_off(srcm, orf[0]), ld_off(srcm, orf[1]), ld_off(srcm, orf[2]),
-                        ld_off(srcm, orf[3]));
-    } else {   // the equator ring is its own mirror: its south images are unused
-        b = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        d = b;
-    }
+    // loaded for the equator ring too (its south sums are never written), so
+    // that every load of the chunk issues from one branch-free sequence
+    b = make_float4(ld_off(srcm, od[0]), ld_off(srcm, od[1]), ld_off(srcm, od[2]),
+                    ld_off(srcm, od[3]));
+    d = make_float4(ld_off(srcm, orf[0]), ld_off(srcm, orf[1]), ld_off(srcm, orf[2]),
+                    ld_off(srcm, orf[3]));
 }
 
 // T candidates jq0, jq0 + 2, ... of one lane in the staged chunk; those past
@@ -661,7 +660,7 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
     {
         const DevPair pp = cst(P.pairs)[ch.k];
         const DevRing S = cst(P.rings)[pp.s];
-        prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, mirror, S.n,
+        prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, S.n,
                    S.two_o, ch.c0, ch.cn, pa, pb, pc, pd);
     }
     double acc[16];
@@ -687,7 +686,7 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
         if (nx.k < R.pair_end) {
             const DevPair pn = cst(P.pairs)[nx.k];
             const DevRing Sn = cst(P.rings)[pn.s];
-            prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
+            prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first,
                        Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
         }
         // this lane's candidates inside the chunk: a0 + ph, a0 + ph + nph, ...
@@ -1330,7 +1329,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
         {
             const DevPair pp = cst(P.pairs)[ch.k];
             const DevRing S = cst(P.rings)[pp.s];
-            prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, mirror, S.n,
+            prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, S.n,
                        S.two_o, ch.c0, ch.cn, pa, pb, pc, pd4);
         }
         while (ch.k < R.pair_end) {
@@ -1349,7 +1348,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
             if (nx.k < R.pair_end) {
                 const DevPair pn = cst(P.pairs)[nx.k];
                 const DevRing Sn = cst(P.rings)[pn.s];
-                prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first, mirror,
+                prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first,
                            Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd4);
             }
             int lo, hi;
