@@ -125,10 +125,18 @@ __device__ __forceinline__ float theta_of(float d2)
     return d * p;
 }
 
-__device__ __forceinline__ int wrap_index(int jq, int n)
+// 4 (x mod n) for byte offsets xb = 4x with -n <= x < 2n and nb = 4n: of
+// xb, xb + nb and xb - nb read as unsigned, the one in [0, nb) is the
+// smallest (the others are at least nb or wrap to above 2^31).
+__device__ __forceinline__ unsigned wrap_bytes(int xb, int nb)
 {
-    jq = (jq < 0) ? jq + n : jq;
-    return (jq >= n) ? jq - n : jq;
+    return min(min((unsigned)xb, (unsigned)(xb + nb)), (unsigned)(xb - nb));
+}
+
+// The same for 0 <= x < 2n.
+__device__ __forceinline__ unsigned wrap_bytes_up(unsigned xb, unsigned nb)
+{
+    return min(xb, xb - nb);
 }
 
 // j mod n for -n <= j < 3n.
@@ -188,10 +196,11 @@ __device__ __forceinline__ float ld_off(const float *base, unsigned byte_off)
 __device__ __forceinline__ void prefetch_row(const float *src, int base, int nstage, int n,
                                              float v[kStageRegs])
 {
+    const int xb = 4 * (base + (int)threadIdx.x);
 #pragma unroll
     for (int u = 0; u < kStageRegs; ++u) {
         const int e = threadIdx.x + u * kThreads;
-        v[u] = (e < nstage) ? ld_off(src, 4u * (unsigned)wrap_index(base + e, n)) : 0.0f;
+        v[u] = (e < nstage) ? ld_off(src, wrap_bytes(xb + 4 * u * kThreads, 4 * n)) : 0.0f;
     }
 }
 
@@ -217,7 +226,7 @@ constexpr int kCircFlush = 64;
 // an FMA with a scalar-register operand issues at about 0.6x the rate on
 // gfx950.  Lane l owns pixels 4l .. 4l+3 of the segment, so a quad of taps
 // needs 7 consecutive staged pixels, read as two aligned float4.
-__global__ __launch_bounds__(kThreads) void k_circ(const DevPlanView *__restrict__ views,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_circ(const DevPlanView *__restrict__ views,
                                                    const int2 *__restrict__ tile_map,
                                                    int ntiles, MapIO io, int nmaps,
                                                    int buf_floats, unsigned int *counter)
@@ -455,18 +464,18 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
 {
     const int e = threadIdx.x;
     if (e >= cn) return;
-    const int qs = n_s >> 2;
-    int jd = c0 + e;                       // -n_s < jd < 2 n_s
-    jd = jd < 0 ? jd + n_s : (jd >= n_s ? jd - n_s : jd);
-    int jr = qs - two_o_s - jd;           // -n_s < jr < n_s
-    jr = jr < 0 ? jr + n_s : jr;
+    // byte offsets in the ring: jd of position c0 + e (-n_s < c0 + e < 2 n_s),
+    // jr of its reflection qs - 2o_s - jd (-n_s < . < n_s), and their quarter turns
+    const int nb = 4 * n_s;
+    const unsigned qb = (unsigned)nb >> 2;
+    const unsigned jd = wrap_bytes(4 * (c0 + e), nb);
+    const int jr0 = (int)qb - 4 * two_o_s - (int)jd;
+    const unsigned jr = min((unsigned)jr0, (unsigned)(jr0 + nb));
     unsigned od[4], orf[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        int i = jd + k * qs;
-        od[k] = 4u * (unsigned)(i >= n_s ? i - n_s : i);
-        i = jr + k * qs;
-        orf[k] = 4u * (unsigned)(i >= n_s ? i - n_s : i);
+        od[k] = wrap_bytes_up(jd + k * qb, (unsigned)nb);
+        orf[k] = wrap_bytes_up(jr + k * qb, (unsigned)nb);
     }
     a = make_float4(ld_off(src, od[0]), ld_off(src, od[1]), ld_off(src, od[2]), ld_off(src, od[3]));
     c = make_float4(ld_off(src, orf[0]), ld_off(src, orf[1]), ld_off(src, orf[2]),
