@@ -148,11 +148,17 @@ __device__ __forceinline__ int wrap3(int j, int n)
 }
 
 // Exact longitude numerator m = (2j + 2o_r) n_s - (2j' + 2o_s) n_r; the
-// product terms may exceed 2^31 but the difference does not, so unsigned
-// wrap-around arithmetic gives it exactly.
+// product terms may exceed 2^31 but the difference does not, so wrap-around
+// arithmetic modulo 2^32 gives it exactly.  Every factor is below 2^23 in
+// magnitude (n <= 4 N_side, |2j' + 2o_s| < 4 n_s), so the 24-bit multiply
+// (full rate, low 32 bits of the exact product) serves.
+__device__ __forceinline__ unsigned lon_base(int j, int two_o_r, int n_s)
+{
+    return (unsigned)__mul24(2 * j + two_o_r, n_s);
+}
 __device__ __forceinline__ int lon_numerator(unsigned mbase, int jq, int two_o_s, int n_r)
 {
-    return (int)(mbase - (unsigned)(2 * jq + two_o_s) * (unsigned)n_r);
+    return (int)(mbase - (unsigned)__mul24(2 * jq + two_o_s, n_r));
 }
 
 __device__ __forceinline__ void load_table(float *lds, const float *table, int ntab)
@@ -706,7 +712,7 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
         const int mine = a1 - a0 - ph >= 0 ? ((a1 - a0 - ph) >> lp) + 1 : 0;
         const int nt = wave_max(mine);
         const int jq0 = a0 + ph;
-        const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+        const unsigned mbase = lon_base(j, R.two_o, S.n);
         const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
         const int dm = 2 * nph * R.n;
         gen_candidates16<LONG, AM, INTM, BIAS>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt,
@@ -1366,7 +1372,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
             const int a1 = min(hi, ch.c0 + ch.cn - 1);
             const int nt = wave_max(max(0, (a1 - a0 + 2 - ph) >> 1));
             const int jq0 = a0 + ph;
-            const unsigned mbase = (unsigned)(2 * j + R.two_o) * (unsigned)S.n;
+            const unsigned mbase = lon_base(j, R.two_o, S.n);
             const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
             const int dm = 4 * R.n;
             const bool lg = (pp.mode & kPairLongSin) != 0;
