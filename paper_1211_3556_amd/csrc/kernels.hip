@@ -534,7 +534,9 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
     const UCoef &ucf = gc.ucf;
     // Candidates are addressed by LDS byte address: o steps by 16 step bytes,
     // a lane's candidates end at o_a1 and reads clamp to the chunk's last
-    // staged position (the clamped reads carry weight zero).
+    // staged position (the clamped reads carry weight zero).  The staged
+    // images are read first, so their latency overlaps the weight arithmetic
+    // and the table lookup waits once for both.
     typedef float v4f __attribute__((ext_vector_type(4)));
     typedef __attribute__((address_space(3))) const v4f lds_float4;
     const int sb = (int)(size_t)(lds_float4 *)stage;
@@ -555,6 +557,11 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
     for (int t = 0; t < T; ++t) {
         const bool valid = o <= o_a1;
         const int oc = min(o, o_last);
+        lds_float4 *sp = (lds_float4 *)(size_t)oc;
+        const v4f v0 = sp[0];
+        const v4f v1 = sp[kGenStage];
+        const v4f v2 = sp[2 * kGenStage];
+        const v4f v3 = sp[3 * kGenStage];
         float u0;
         if (LONG) {
             const float x = (INTM ? (float)mi : mf) * xscale;   // half the longitude difference
@@ -574,11 +581,6 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         const float k0 = tab[node];
         const float k1 = tab[node + 1];
         const float w = fmaf(frac, k1 - k0, k0);
-        lds_float4 *sp = (lds_float4 *)(size_t)oc;
-        const v4f v0 = sp[0];
-        const v4f v1 = sp[kGenStage];
-        const v4f v2 = sp[2 * kGenStage];
-        const v4f v3 = sp[3 * kGenStage];
         row[0] = fmaf(w, v0.x, row[0]);
         row[1] = fmaf(w, v0.y, row[1]);
         row[2] = fmaf(w, v0.z, row[2]);
