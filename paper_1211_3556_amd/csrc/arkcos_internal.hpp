@@ -138,7 +138,8 @@ struct DevRow {
     int ntaps;
     int w_off;
     int g;
-    int pad0, pad1, pad2;
+    int first_s;   // RING index of pixel 0 of ring s (no dependent ring lookup per row)
+    int pad0, pad1;
 };
 
 // Kernel-argument view of a plan (passed by value).

@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
         float v[kStageRegs], wv[kWeightRegs];
         {
             const DevRow W = cst(P.rows)[G.row_begin];
-            prefetch_row(in + cst(P.rings)[W.s].first, T.j0 + W.k_lo, T.len + W.ntaps - 1, n, v);
+            prefetch_row(in + W.first_s, T.j0 + W.k_lo, T.len + W.ntaps - 1, n, v);
             prefetch_weights(P.wts + W.w_off, W.ntaps * kGroupRings, wv);
         }
         float racc[kGroupRings][kCircPix];
@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
             __syncthreads();
             if (row + 1 < G.row_end) {
                 const DevRow W1 = cst(P.rows)[row + 1];
-                prefetch_row(in + cst(P.rings)[W1.s].first, T.j0 + W1.k_lo,
+                prefetch_row(in + W1.first_s, T.j0 + W1.k_lo,
                              T.len + W1.ntaps - 1, n, v);
                 prefetch_weights(P.wts + W1.w_off, W1.ntaps * kGroupRings, wv);
             }
@@ -494,9 +494,6 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
                     ld_off(srcm, orf[3]));
 }
 
-// T candidates jq0, jq0 + 2, ... of one lane in the staged chunk; those past
-// a1 get the table's zero slot.  The loop count is wave-uniform, so the
-// compiler can overlap consecutive candidates.
 // Plan constants of the candidate loop, in vector registers.
 template <int AM>
 struct GenConst {
@@ -509,6 +506,10 @@ struct GenConst {
           bc(vreg(P.bias_c)), ucf(ucoef<AM>(P)) {}
 };
 
+// T candidates jq, jq + step, ... of one lane in the staged chunk; those past
+// a1 get the table's zero slot.  T is the wave's largest count.  One
+// candidate per iteration: its staged reads issue first and overlap the
+// weight arithmetic (unrolled by two, the loop spills at 128 VGPRs).
 // BIAS: the plan's node grid is the two-piece biased one, u = min(u0, r u0 + c);
 // otherwise u = u0 and the map costs nothing.
 template <bool LONG, int AM, bool INTM, bool BIAS>
@@ -553,7 +554,7 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
     const float dmf = vreg((float)dm * ms);
     int mi = m;
     const int dmi = vreg(dm);
-#pragma unroll 2
+#pragma unroll 1
     for (int t = 0; t < T; ++t) {
         const bool valid = o <= o_a1;
         const int oc = min(o, o_last);
@@ -1163,7 +1164,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 const int nt4 = (W.ntaps + 3) & ~3;
                 const int strip = knot_strip(nt4);
                 const float inv_strip = 1.0f / (float)strip;
-                const float *src = in + cst(P.rings)[W.s].first;
+                const float *src = in + W.first_s;
                 float *dst = xs + s_xoff[rr];
                 const int base = T.j0 + W.k_lo;
                 for (int e0 = wave * 64; e0 < nsub * strip; e0 += kThreads) {

@@ -322,6 +322,7 @@ static int build_plan(Plan &P)
                 return fail(ARKCOS_EUNSUPPORTED, "circulant row wider than the staging limit");
             DevRow row{};
             row.s = sr;
+            row.first_s = (int)P.rings[sr].first;
             row.k_lo = k_lo;
             row.ntaps = k_hi - k_lo + 1;
             row.w_off = (int)P.nweights;
