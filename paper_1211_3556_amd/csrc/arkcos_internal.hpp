@@ -69,7 +69,7 @@ constexpr int kPairLongSin = 2;
 static_assert(sizeof(DevPair) == 64, "DevPair layout");
 // Largest |x| = |dphi / 2| of a short row: the truncated series stay within
 // 1e-9 relative there (angle mode 0 through x^8, first omitted term
-// 2^10 x^10 / 10!; the squared chord through x^6, next term x^8 / 315).
+// 2^9 x^10 / 10!; the squared chord through x^6, next term x^8 / 315).
 constexpr double kShortXMaxMode0 = 0.2;
 constexpr double kShortXMax = 0.09;
 

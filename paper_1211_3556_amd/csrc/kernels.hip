@@ -486,8 +486,9 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
     a = make_float4(ld_off(src, od[0]), ld_off(src, od[1]), ld_off(src, od[2]), ld_off(src, od[3]));
     c = make_float4(ld_off(src, orf[0]), ld_off(src, orf[1]), ld_off(src, orf[2]),
                     ld_off(src, orf[3]));
-    // loaded for the equator ring too (its south sums are never written), so
-    // that every load of the chunk issues from one branch-free sequence
+    // loaded for the equator ring too, so that every load of the chunk issues
+    // from one branch-free sequence: the general gather never writes the
+    // equator's south sums, and the knot gradient gives them zero g
     b = make_float4(ld_off(srcm, od[0]), ld_off(srcm, od[1]), ld_off(srcm, od[2]),
                     ld_off(srcm, od[3]));
     d = make_float4(ld_off(srcm, orf[0]), ld_off(srcm, orf[1]), ld_off(srcm, orf[2]),
