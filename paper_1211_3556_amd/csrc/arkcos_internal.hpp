@@ -44,7 +44,8 @@ struct DevRing {
 // integer.  The longitude window of output pixel j is centred at source index
 // c = j * a + b (a = n_s/n_r, b = o_r n_s/n_r - o_s) with half-width w source
 // pixels (margin included).  mode bit 0: the window is every pixel of ring s;
-// bit 1: |dphi/2| may exceed 0.35 rad, so the sine needs its long series.
+// bit 1: |dphi/2| may exceed the short-row limit below, so the row takes the
+// long sine series instead of its polynomial.
 struct DevPair {
     float A;
     float B;
