@@ -93,6 +93,17 @@ struct DevTile {
     int len;
     int flags;     // general tiles: kTileLongSin, kTileIntM, kTileSkipNorth, kTileSkipSouth
 };
+// A general-gather tile of two adjacent northern rings r[0] < r[1] over the
+// same half-quadrant segment j0 .. j0 + len[h] - 1 of each (the two rings
+// cover nearly the same longitudes, so one staged chunk of a source ring
+// serves both).  r[1] = -1 and len[1] = 0 when the ring has no partner.
+struct DevTile2 {
+    int r[2];
+    int j0;
+    int len[2];
+    int flags[2];  // per ring: kTileSkipNorth, kTileSkipSouth; the loop form from both
+    int pad;
+};
 constexpr int kTileLongSin = 1;   // some source row needs the long sine series
 constexpr int kTileIntM = 2;      // a longitude numerator may reach 2^24: keep it in int32
 constexpr int kTileSkipNorth = 4; // the northern ring is outside the plan's ring range
@@ -109,6 +120,7 @@ constexpr int kCircMaxTaps = 256;   // wider rows make their rings general
 constexpr int kGenLanes = 128;       // pixels per general tile
 constexpr int kGenThreads = 512;     // general-gather workgroup: kGenPhases lanes per pixel
 constexpr int kGenPhases = kGenThreads / kGenLanes;
+constexpr double kGenPairMaxWindow = 64.0;   // widest row window (positions) of a paired ring
 constexpr int kGenStage = 248;       // with a 16384-node table two workgroups fit a CU
 constexpr int kGenChunk = 320;
 constexpr int kMaxMaps = 32;
@@ -157,10 +169,12 @@ struct DevPlanView {
     float *wts;              // their weight rows (written by the weight-build kernel)
     const DevTile *ctiles;   // circulant tiles: (group, j0, len)
     const DevTile *gtiles;   // general tiles: (north ring, j0, len), pixels j <= jbar of quadrant 0
+    const DevTile2 *gtiles2; // the same segments, two adjacent rings per tile (general gather)
     const DevTile *kctiles;  // circulant knot-gradient tiles: (group, j0, len)
     const double *kw;        // FP64 node coordinate per circulant weight slot, or -1
     int nctiles;
     int ngtiles;
+    int ngtiles2;
     int nkctiles;
     int nkpart_circ;         // partial rows written by the circulant knot kernel
     int nrows;
@@ -233,7 +247,8 @@ struct Plan {
     std::vector<DevTile> ctiles;      // circulant tiles, longest first
     std::vector<DevTile> gtiles;      // general tiles, longest first
     std::vector<DevTile> kctiles;     // circulant knot-gradient tiles, longest first
-    std::vector<double> ctile_cost, gtile_cost;
+    std::vector<double> ctile_cost, gtile_cost, gtile2_cost;
+    std::vector<DevTile2> gtiles2;    // general tiles of ring pairs, longest first
     long long nweights = 0;
     int max_taps = 0;
     std::vector<double> ktab;         // current host copy (FP64), if known
@@ -253,6 +268,7 @@ struct Plan {
     float *d_wts = nullptr;
     DevTile *d_ctiles = nullptr;
     DevTile *d_gtiles = nullptr;
+    DevTile2 *d_gtiles2 = nullptr;
     DevTile *d_kctiles = nullptr;
     double *d_kw = nullptr;             // knot node coordinates of the circulant slots
     DevPlanView *d_view = nullptr;      // device copy of view() (a batch of one plan)

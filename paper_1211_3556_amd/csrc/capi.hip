@@ -129,9 +129,9 @@ int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *o
             B->cmap.push_back(make_int2(k, t));
             ccost.push_back(P->ctile_cost[t]);
         }
-        for (int t = 0; t < (int)P->gtiles.size(); ++t) {
+        for (int t = 0; t < (int)P->gtiles2.size(); ++t) {
             B->gmap.push_back(make_int2(k, t));
-            gcost.push_back(P->gtile_cost[t]);
+            gcost.push_back(P->gtile2_cost[t]);
         }
     }
     // one queue per kernel over the tiles of every plan, longest first

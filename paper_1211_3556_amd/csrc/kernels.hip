@@ -564,6 +564,7 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         const v4f v1 = sp[kGenStage];
         const v4f v2 = sp[2 * kGenStage];
         const v4f v3 = sp[3 * kGenStage];
+        __builtin_amdgcn_sched_barrier(0);   // keep the four reads ahead of the arithmetic
         float u0;
         if (LONG) {
             const float x = (INTM ? (float)mi : mf) * xscale;   // half the longitude difference
@@ -643,44 +644,134 @@ __device__ __forceinline__ GenStage next_stage(const DevPlanView &P, const DevRi
 // accumulated at least this many candidates since the last move.
 constexpr int kGenFlush = 48;
 
-// One general tile: its source rows in staged chunks, the candidates of each
-// lane, the sum over the lanes of a pixel and the sixteen output images.
-// LONG, AM, INTM and BIAS are fixed per tile, so the candidate loop has one
-// form and the row sums stay in place across rows.
-template <bool LONG, int AM, bool INTM, bool BIAS>
-__device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab, float4 *stage,
-                                         const DevTile &T, const float *in, float *out)
+// The source rows of a paired general tile: ring r[h] has rows s_lo[h] ..
+// s_hi[h] (its pair records pb[h] on, one per source ring, in order); the
+// tile stages source rings s_first .. s_last, each over the union of the two
+// rings' windows, in chunks of kGenStage positions.
+struct GenRows2 {
+    int pb[2], s_lo[2], s_hi[2], len[2];
+    int j0, s_first, s_last;
+};
+
+__device__ __forceinline__ GenRows2 gen_rows2(const DevPlanView &P, const DevTile2 &T)
 {
-    const int rn = T.r;
-    const int rs = P.nrings - 1 - rn;           // mirror ring
+    GenRows2 g;
+    g.j0 = T.j0;
+    g.s_first = 0x7fffffff;
+    g.s_last = -1;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        g.len[h] = T.len[h];
+        g.pb[h] = 0;
+        g.s_lo[h] = 0;
+        g.s_hi[h] = -1;
+        if (T.len[h] > 0) {
+            const DevRing R = cst(P.rings)[T.r[h]];
+            g.pb[h] = R.pair_begin;
+            g.s_lo[h] = cst(P.pairs)[R.pair_begin].s;
+            g.s_hi[h] = cst(P.pairs)[R.pair_end - 1].s;
+            g.s_first = min(g.s_first, g.s_lo[h]);
+            g.s_last = max(g.s_last, g.s_hi[h]);
+        }
+    }
+    return g;
+}
+
+// Union over the tile's rings of their windows on source ring s.
+__device__ __forceinline__ void row_window2(const DevPlanView &P, const GenRows2 &g, int s,
+                                            int &lo_min, int &hi_max)
+{
+    lo_min = 0x7fffffff;
+    hi_max = -0x7fffffff;
+    const int n_s = cst(P.rings)[s].n;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        if (s >= g.s_lo[h] && s <= g.s_hi[h]) {
+            const DevPair pp = cst(P.pairs)[g.pb[h] + s - g.s_lo[h]];
+            int lo, hi, dummy;
+            pair_window(pp, n_s, g.j0, lo, dummy);
+            pair_window(pp, n_s, g.j0 + g.len[h] - 1, dummy, hi);
+            lo_min = min(lo_min, lo);
+            hi_max = max(hi_max, hi);
+        }
+    }
+}
+
+struct GenStage2 {
+    int s;    // source ring
+    int c0;   // first unwrapped source position of the chunk
+    int cn;   // positions staged
+    int hi;   // last unwrapped position of the ring's union window
+};
+
+__device__ __forceinline__ GenStage2 first_stage2(const DevPlanView &P, const GenRows2 &g, int s)
+{
+    GenStage2 ch;
+    ch.s = s;
+    ch.c0 = 0;
+    ch.cn = 0;
+    ch.hi = -1;
+    if (s <= g.s_last) {
+        row_window2(P, g, s, ch.c0, ch.hi);
+        ch.cn = min(kGenStage, ch.hi - ch.c0 + 1);
+    }
+    return ch;
+}
+
+// The chunk after `ch`: the rest of its source ring, else the next ring.
+__device__ __forceinline__ GenStage2 next_stage2(const DevPlanView &P, const GenRows2 &g,
+                                                 const GenStage2 &ch)
+{
+    if (ch.c0 + kGenStage <= ch.hi) {
+        GenStage2 nx = ch;
+        nx.c0 = ch.c0 + kGenStage;
+        nx.cn = min(kGenStage, ch.hi - nx.c0 + 1);
+        return nx;
+    }
+    return first_stage2(P, g, ch.s + 1);
+}
+
+// One general tile (DevTile2).  A tile of two adjacent rings gives the first
+// half of the lanes ring r[0] and the second half ring r[1] (idle where
+// len[1] = 0); a tile of one ring (r[1] = -1) gives it every lane.  Per staged
+// chunk of a source ring, each half runs the candidates of its own ring's
+// row, the sum over the lanes of a pixel follows, and each half writes the
+// sixteen images of its pixels.  LONG, AM, INTM and BIAS are fixed per tile,
+// so the candidate loop has one form and the row sums stay in place across
+// rows.
+template <bool LONG, int AM, bool INTM, bool BIAS>
+__device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab, float4 *stage,
+                                          const DevTile2 &T, const float *in, float *out)
+{
+    const int kHalf = T.r[1] >= 0 ? kGenThreads / 2 : kGenThreads;
+    // wave-uniform (a half is whole waves); made scalar so that every branch
+    // on the half is a scalar branch
+    const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x >= kHalf ? 1 : 0);
+    const int tid = (int)threadIdx.x - h * kHalf;
+    const GenRows2 g = gen_rows2(P, T);
+    const int len = g.len[h];
+    const int rn = len > 0 ? T.r[h] : T.r[0];          // an idle half reads ring r[0]
+    const int rs = P.nrings - 1 - rn;                   // mirror ring
     const bool mirror = rs != rn;
     const DevRing R = cst(P.rings)[rn];
     const int qr = R.n >> 2;
-    // 2^lp lanes per pixel: kGenPhases for a full tile, more (up to a
+    // 2^lp lanes per pixel: 2 (paired) or 4 for a full segment, more (up to a
     // wave) for a shorter one, so that every lane works
-    int lp = 2;
-    while (lp < 6 && (kGenThreads >> (lp + 1)) >= T.len) ++lp;
+    int lp = 1;
+    while (lp < 6 && (kHalf >> (lp + 1)) >= len) ++lp;
     const int nph = 1 << lp;
-    const int ph = threadIdx.x & (nph - 1);
-    const int lane_pix = threadIdx.x >> lp;
-    const bool active = lane_pix < T.len;
-    const int j = T.j0 + min(lane_pix, T.len - 1);
+    const int ph = tid & (nph - 1);
+    const int lane_pix = tid >> lp;
+    const bool active = lane_pix < len;
+    const int j = T.j0 + min(lane_pix, max(len - 1, 0));
     const GenConst<AM> gc(P);
 
-    GenStage ch;
-    ch.k = R.pair_begin;
-    {
-        const DevPair pp = cst(P.pairs)[ch.k];
-        int hi_max;
-        tile_window(pp, cst(P.rings)[pp.s].n, T, ch.c0, hi_max);
-        ch.cn = min(kGenStage, hi_max - ch.c0 + 1);
-    }
+    GenStage2 ch = first_stage2(P, g, g.s_first);
     float4 pa, pb, pc, pd;
-    {
-        const DevPair pp = cst(P.pairs)[ch.k];
-        const DevRing S = cst(P.rings)[pp.s];
-        prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, S.n,
-                   S.two_o, ch.c0, ch.cn, pa, pb, pc, pd);
+    if (ch.s <= g.s_last) {
+        const DevRing S = cst(P.rings)[ch.s];
+        prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - ch.s].first, S.n, S.two_o,
+                   ch.c0, ch.cn, pa, pb, pc, pd);
     }
     double acc[16];
     float row[16];
@@ -690,7 +781,7 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
         row[q] = 0.0f;
     }
     int since = 0;
-    while (ch.k < R.pair_end) {
+    while (ch.s <= g.s_last) {
         __syncthreads();      // the previous chunk is no longer read
         if ((int)threadIdx.x < ch.cn) {
             stage[threadIdx.x] = pa;
@@ -699,36 +790,38 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
             stage[3 * kGenStage + threadIdx.x] = pd;
         }
         __syncthreads();
-        const DevPair pp = cst(P.pairs)[ch.k];
-        const DevRing S = cst(P.rings)[pp.s];
-        const GenStage nx = next_stage(P, R, T, ch);
-        if (nx.k < R.pair_end) {
-            const DevPair pn = cst(P.pairs)[nx.k];
-            const DevRing Sn = cst(P.rings)[pn.s];
-            prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first,
-                       Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
+        const GenStage2 nx = next_stage2(P, g, ch);
+        if (nx.s <= g.s_last) {
+            const DevRing Sn = cst(P.rings)[nx.s];
+            prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - nx.s].first, Sn.n,
+                       Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
         }
-        // this lane's candidates inside the chunk: a0 + ph, a0 + ph + nph, ...
-        int lo, hi;
-        pair_window(pp, S.n, j, lo, hi);
-        const int a0 = max(lo, ch.c0);
-        const int a1 = min(hi, ch.c0 + ch.cn - 1);
-        const int mine = a1 - a0 - ph >= 0 ? ((a1 - a0 - ph) >> lp) + 1 : 0;
-        const int nt = wave_max(mine);
-        const int jq0 = a0 + ph;
-        const unsigned mbase = lon_base(j, R.two_o, S.n);
-        const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
-        const int dm = 2 * nph * R.n;
-        gen_candidates16<LONG, AM, INTM, BIAS>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn, jq0, a1, nt,
-                                   row);
-        since += nt;
-        if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
+        // this half's row of source ring ch.s, if its ring has one
+        if (len > 0 && ch.s >= g.s_lo[h] && ch.s <= g.s_hi[h]) {
+            const DevPair pp = cst(P.pairs)[g.pb[h] + ch.s - g.s_lo[h]];
+            const DevRing S = cst(P.rings)[ch.s];
+            // this lane's candidates inside the chunk: a0 + ph, a0 + ph + nph, ...
+            int lo, hi;
+            pair_window(pp, S.n, j, lo, hi);
+            const int a0 = max(lo, ch.c0);
+            const int a1 = min(hi, ch.c0 + ch.cn - 1);
+            const int mine = a1 - a0 - ph >= 0 ? ((a1 - a0 - ph) >> lp) + 1 : 0;
+            const int nt = wave_max(mine);
+            const int jq0 = a0 + ph;
+            const unsigned mbase = lon_base(j, R.two_o, S.n);
+            const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
+            const int dm = 2 * nph * R.n;
+            gen_candidates16<LONG, AM, INTM, BIAS>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn,
+                                                   jq0, a1, nt, row);
+            since += nt;
+            if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
 #pragma unroll
-            for (int q = 0; q < 16; ++q) {
-                acc[q] += (double)row[q];
-                row[q] = 0.0f;
+                for (int q = 0; q < 16; ++q) {
+                    acc[q] += (double)row[q];
+                    row[q] = 0.0f;
+                }
+                since = 0;
             }
-            since = 0;
         }
         ch = nx;
     }
@@ -739,8 +832,8 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
         for (int q = 0; q < 16; ++q) acc[q] += __shfl_xor(acc[q], x);
     }
     // a ring-range plan leaves rings outside its range untouched
-    const bool wn = (T.flags & kTileSkipNorth) == 0;
-    const bool ws = mirror && (T.flags & kTileSkipSouth) == 0;
+    const bool wn = (T.flags[h] & kTileSkipNorth) == 0;
+    const bool ws = mirror && (T.flags[h] & kTileSkipSouth) == 0;
     if (active) {
         float *o = out + R.first;
         float *om = out + cst(P.rings)[rs].first;
@@ -773,24 +866,25 @@ __device__ __forceinline__ void gen_tile(const DevPlanView &P, const float *tab,
 // type from the tile and plan, the node-grid map from BIAS.
 template <bool BIAS>
 __device__ __forceinline__ void gen_tile_variant(const DevPlanView &P, const float *tab,
-                                                 float4 *stage, const DevTile &T,
+                                                 float4 *stage, const DevTile2 &T,
                                                  const float *in, float *out)
 {
-    const bool lg = (T.flags & kTileLongSin) != 0;
-    if (T.flags & kTileIntM) {   // wide windows on large rings (long sine implied)
+    const int fl = T.flags[0] | T.flags[1];
+    const bool lg = (fl & kTileLongSin) != 0;
+    if (fl & kTileIntM) {   // wide windows on large rings (long sine implied)
         switch (P.angle_mode) {
-            case 0: gen_tile<true, 0, true, BIAS>(P, tab, stage, T, in, out); break;
-            case 1: gen_tile<true, 1, true, BIAS>(P, tab, stage, T, in, out); break;
-            default: gen_tile<true, 2, true, BIAS>(P, tab, stage, T, in, out); break;
+            case 0: gen_tile2<true, 0, true, BIAS>(P, tab, stage, T, in, out); break;
+            case 1: gen_tile2<true, 1, true, BIAS>(P, tab, stage, T, in, out); break;
+            default: gen_tile2<true, 2, true, BIAS>(P, tab, stage, T, in, out); break;
         }
     } else {
         switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-            case 0: gen_tile<false, 0, false, BIAS>(P, tab, stage, T, in, out); break;
-            case 1: gen_tile<true, 0, false, BIAS>(P, tab, stage, T, in, out); break;
-            case 2: gen_tile<false, 1, false, BIAS>(P, tab, stage, T, in, out); break;
-            case 3: gen_tile<true, 1, false, BIAS>(P, tab, stage, T, in, out); break;
-            case 4: gen_tile<false, 2, false, BIAS>(P, tab, stage, T, in, out); break;
-            default: gen_tile<true, 2, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 0: gen_tile2<false, 0, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 1: gen_tile2<true, 0, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 2: gen_tile2<false, 1, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 3: gen_tile2<true, 1, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 4: gen_tile2<false, 2, false, BIAS>(P, tab, stage, T, in, out); break;
+            default: gen_tile2<true, 2, false, BIAS>(P, tab, stage, T, in, out); break;
         }
     }
 }
@@ -822,7 +916,7 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
             if (threadIdx.x < 2) tab[P.ntab + threadIdx.x] = 0.0f;
             cur = pi;
         }
-        const DevTile T = cst(P.gtiles)[lt];
+        const DevTile2 T = cst(P.gtiles2)[lt];
         const float *in = io.in[pi] + (size_t)map * P.npix;
         float *out = io.out[pi] + (size_t)map * P.npix;
         if (P.biased)
@@ -1535,7 +1629,7 @@ int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipSt
     io.out[0] = out;
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, p.d_counter);
     const int nct = (parts & ARKCOS_PART_CIRCULANT) ? (int)p.ctiles.size() : 0;
-    const int ngt = (parts & ARKCOS_PART_GENERAL) ? (int)p.gtiles.size() : 0;
+    const int ngt = (parts & ARKCOS_PART_GENERAL) ? (int)p.gtiles2.size() : 0;
     if (nct > 0) {
         const int grid = std::max(1, std::min(nct * nbatch, p.occ_circ * p.cus));
         hipLaunchKernelGGL(k_circ, dim3(grid), dim3(kThreads), circ_lds(), s,

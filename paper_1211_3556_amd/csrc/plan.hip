@@ -113,10 +113,12 @@ DevPlanView Plan::view() const
     v.wts = d_wts;
     v.ctiles = d_ctiles;
     v.gtiles = d_gtiles;
+    v.gtiles2 = d_gtiles2;
     v.kctiles = d_kctiles;
     v.kw = d_kw;
     v.nctiles = (int)ctiles.size();
     v.ngtiles = (int)gtiles.size();
+    v.ngtiles2 = (int)gtiles2.size();
     v.nkctiles = (int)kctiles.size();
     v.nkpart_circ = grid_kc;
     v.nrows = (int)rows.size();
@@ -171,13 +173,14 @@ static double half_width(const HostRing &r, const HostRing &s, double theta_cut,
 }
 
 // Reorder tiles (and their costs) by decreasing cost; ties keep their order.
-static void sort_by_cost(std::vector<DevTile> &tiles, std::vector<double> &cost)
+template <class Tile>
+static void sort_by_cost(std::vector<Tile> &tiles, std::vector<double> &cost)
 {
     std::vector<size_t> order(tiles.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](size_t x, size_t y) { return cost[x] > cost[y]; });
-    std::vector<DevTile> t2(tiles.size());
+    std::vector<Tile> t2(tiles.size());
     std::vector<double> c2(cost.size());
     for (size_t k = 0; k < order.size(); ++k) {
         t2[k] = tiles[order[k]];
@@ -363,6 +366,7 @@ static int build_plan(Plan &P)
     // test hook: every general tile takes the int32 numerator path
     const char *fim = getenv("ARKCOS_FORCE_INT_NUMERATOR");
     const bool force_int_m = fim && std::string(fim) == "1";
+    std::vector<int> gring, glanes, gflags, gwide;   // the general northern rings, in order
     for (int r = 0; r <= P.nrings - 1 - r; ++r) {
         if (!general[r]) continue;
         const int rm = P.nrings - 1 - r;
@@ -390,9 +394,49 @@ static int build_plan(Plan &P)
             P.gtiles.push_back(t);
             cost.push_back(ring_cost[r] * t.len + 1.0);
         }
+        // widest source window of the ring's rows, in source positions
+        double wmax = 0.0;
+        for (int k = P.dev_rings[r].pair_begin; k < P.dev_rings[r].pair_end; ++k) {
+            const DevPair &pp = P.pairs[k];
+            wmax = std::max(wmax, (pp.mode & kPairWhole) ? (double)P.rings[pp.s].n : 2.0 * pp.w + 1.0);
+        }
+        gring.push_back(r);
+        glanes.push_back(lanes);
+        gflags.push_back(flags);
+        gwide.push_back(wmax > kGenPairMaxWindow ? 1 : 0);
     }
     sort_by_cost(P.gtiles, cost);
     P.gtile_cost = cost;
+
+    // The general gather's tiles: adjacent general rings with narrow windows
+    // in pairs, each pair over the same half-quadrant segments (kGenLanes
+    // pixels of each ring, two lanes per pixel), so that a staged source row
+    // serves both; rings with a wide window keep four lanes per pixel, whose
+    // staged reads share more addresses.
+    P.gtiles2.clear();
+    cost.clear();
+    for (size_t g = 0; g < gring.size();) {
+        const bool pair = g + 1 < gring.size() && gring[g + 1] == gring[g] + 1 && !gwide[g] &&
+                          !gwide[g + 1];
+        const int nr = pair ? 2 : 1;
+        const int lanes = pair ? std::max(glanes[g], glanes[g + 1]) : glanes[g];
+        for (int j0 = 0; j0 < lanes; j0 += kGenLanes) {
+            DevTile2 t{};
+            double c = 1.0;
+            for (int h = 0; h < 2; ++h) {
+                t.r[h] = h < nr ? gring[g + h] : -1;
+                t.len[h] = h < nr ? std::max(0, std::min(kGenLanes, glanes[g + h] - j0)) : 0;
+                t.flags[h] = h < nr ? gflags[g + h] : 0;
+                if (t.len[h] > 0) c += ring_cost[t.r[h]] * t.len[h];
+            }
+            t.j0 = j0;
+            P.gtiles2.push_back(t);
+            cost.push_back(c);
+        }
+        g += nr;
+    }
+    sort_by_cost(P.gtiles2, cost);
+    P.gtile2_cost = cost;
 
     // Circulant knot-gradient tiles: kKnotSeg consecutive pixels of every
     // ring of a group.
@@ -548,6 +592,7 @@ static void free_device(Plan &P)
         (void)hipFree(P.d_wts);
         (void)hipFree(P.d_ctiles);
         (void)hipFree(P.d_gtiles);
+        (void)hipFree(P.d_gtiles2);
         (void)hipFree(P.d_kctiles);
         (void)hipFree(P.d_kw);
         (void)hipFree(P.d_view);
@@ -564,6 +609,7 @@ static void free_device(Plan &P)
     P.d_wts = nullptr;
     P.d_ctiles = nullptr;
     P.d_gtiles = nullptr;
+    P.d_gtiles2 = nullptr;
     P.d_kctiles = nullptr;
     P.d_kw = nullptr;
     P.d_view = nullptr;
@@ -618,6 +664,7 @@ static int to_device(Plan &P)
     if ((rc = upload(&P.d_rows, P.rows, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_ctiles, P.ctiles, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_gtiles, P.gtiles, &P.device_bytes))) return rc;
+    if ((rc = upload(&P.d_gtiles2, P.gtiles2, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_wts, std::vector<float>((size_t)std::max<long long>(P.nweights, 1), 0.0f),
                      &P.device_bytes)))
         return rc;
