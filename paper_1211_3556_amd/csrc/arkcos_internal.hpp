@@ -120,7 +120,7 @@ constexpr int kCircMaxTaps = 256;   // wider rows make their rings general
 constexpr int kGenLanes = 128;       // pixels per general tile
 constexpr int kGenThreads = 512;     // general-gather workgroup: kGenPhases lanes per pixel
 constexpr int kGenPhases = kGenThreads / kGenLanes;
-constexpr double kGenPairMaxWindow = 64.0;   // widest row window (positions) of a paired ring
+constexpr double kGenPairMaxWindow = 200.0;  // widest row window (positions) of a paired ring
 constexpr int kGenStage = 248;       // with a 16384-node table two workgroups fit a CU
 constexpr int kGenChunk = 320;
 constexpr int kMaxMaps = 32;

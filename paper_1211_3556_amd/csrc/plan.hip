@@ -411,8 +411,9 @@ static int build_plan(Plan &P)
     // The general gather's tiles: adjacent general rings with narrow windows
     // in pairs, each pair over the same half-quadrant segments (kGenLanes
     // pixels of each ring, two lanes per pixel), so that a staged source row
-    // serves both; rings with a wide window keep four lanes per pixel, whose
-    // staged reads share more addresses.
+    // serves both; rings with a very wide window, whose time is the loop's
+    // LDS reads, keep four lanes per pixel, whose staged reads share more
+    // addresses.
     P.gtiles2.clear();
     cost.clear();
     for (size_t g = 0; g < gring.size();) {
