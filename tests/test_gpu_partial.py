@@ -35,6 +35,7 @@ def _ring_pixels(nside, rings):
     (64, 6.0, (120, 136)),     # belt, circulant rings, equator included
     (64, 6.0, (200, 255)),     # southern half only
     (64, 6.0, (128, 128)),     # the equator alone
+    (64, 6.0, (30, 221)),      # a tile's two cap rings differ: one has its mirror in range
     (16, 74.7, (3, 50)),       # wide discs, full-range angles
 ])
 def test_ring_range_matches_oracle_and_leaves_the_rest(nside, tc_deg, rings):
