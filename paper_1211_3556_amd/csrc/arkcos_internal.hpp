@@ -93,17 +93,30 @@ struct DevTile {
     int len;
     int flags;     // general tiles: kTileLongSin, kTileIntM, kTileSkipNorth, kTileSkipSouth
 };
-// A general-gather tile of two adjacent northern rings r[0] < r[1] over the
-// same half-quadrant segment j0 .. j0 + len[h] - 1 of each (the two rings
-// cover nearly the same longitudes, so one staged chunk of a source ring
-// serves both).  r[1] = -1 and len[1] = 0 when the ring has no partner.
-struct DevTile2 {
-    int r[2];
-    int j0;
-    int len[2];
-    int flags[2];  // per ring: kTileSkipNorth, kTileSkipSouth; the loop form from both
-    int pad;
+// One ring of a general-gather tile: northern ring r, pixels j0 .. j0 + len - 1
+// of its half-quadrant (len may be 0 at the end of a shorter ring), its
+// flags, and its rows: source rings s_lo .. s_hi, pair records pb on.
+struct GenRing {
+    int r;
+    int len;
+    int flags;     // kTileSkipNorth, kTileSkipSouth; the loop form from all rings
+    int pb;
+    int s_lo;
+    int s_hi;
 };
+// A general-gather tile of nr = 1, 2 or 4 adjacent northern rings over the
+// same half-quadrant segment (adjacent rings cover nearly the same
+// longitudes, so one staged chunk of a source ring serves all of them);
+// source rings s_first .. s_last are staged.
+constexpr int kGenMaxRings = 4;
+struct DevTile2 {
+    int nr;
+    int j0;
+    int s_first;
+    int s_last;
+    GenRing q[kGenMaxRings];
+};
+static_assert(sizeof(DevTile2) == 112, "DevTile2 layout");
 constexpr int kTileLongSin = 1;   // some source row needs the long sine series
 constexpr int kTileIntM = 2;      // a longitude numerator may reach 2^24: keep it in int32
 constexpr int kTileSkipNorth = 4; // the northern ring is outside the plan's ring range
@@ -121,6 +134,7 @@ constexpr int kGenLanes = 128;       // pixels per general tile
 constexpr int kGenThreads = 512;     // general-gather workgroup: kGenPhases lanes per pixel
 constexpr int kGenPhases = kGenThreads / kGenLanes;
 constexpr double kGenPairMaxWindow = 200.0;  // widest row window (positions) of a paired ring
+constexpr double kGenQuadMaxWindow = 64.0;   // ... of a ring in a tile of four
 constexpr int kGenStage = 248;       // with a 16384-node table two workgroups fit a CU
 constexpr int kGenChunk = 320;
 constexpr int kMaxMaps = 32;

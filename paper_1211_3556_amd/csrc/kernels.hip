@@ -644,53 +644,24 @@ __device__ __forceinline__ GenStage next_stage(const DevPlanView &P, const DevRi
 // accumulated at least this many candidates since the last move.
 constexpr int kGenFlush = 48;
 
-// The source rows of a paired general tile: ring r[h] has rows s_lo[h] ..
-// s_hi[h] (its pair records pb[h] on, one per source ring, in order); the
-// tile stages source rings s_first .. s_last, each over the union of the two
-// rings' windows, in chunks of kGenStage positions.
-struct GenRows2 {
-    int pb[2], s_lo[2], s_hi[2], len[2];
-    int j0, s_first, s_last;
-};
-
-__device__ __forceinline__ GenRows2 gen_rows2(const DevPlanView &P, const DevTile2 &T)
-{
-    GenRows2 g;
-    g.j0 = T.j0;
-    g.s_first = 0x7fffffff;
-    g.s_last = -1;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        g.len[h] = T.len[h];
-        g.pb[h] = 0;
-        g.s_lo[h] = 0;
-        g.s_hi[h] = -1;
-        if (T.len[h] > 0) {
-            const DevRing R = cst(P.rings)[T.r[h]];
-            g.pb[h] = R.pair_begin;
-            g.s_lo[h] = cst(P.pairs)[R.pair_begin].s;
-            g.s_hi[h] = cst(P.pairs)[R.pair_end - 1].s;
-            g.s_first = min(g.s_first, g.s_lo[h]);
-            g.s_last = max(g.s_last, g.s_hi[h]);
-        }
-    }
-    return g;
-}
-
-// Union over the tile's rings of their windows on source ring s.
-__device__ __forceinline__ void row_window2(const DevPlanView &P, const GenRows2 &g, int s,
+// Union over a tile's rings of their windows on source ring s.  The tile's
+// ring records are read from global memory by a wave-uniform index (scalar
+// loads), so nothing is indexed dynamically in registers.
+__device__ __forceinline__ void row_window2(const DevPlanView &P, const DevTile2 *Tp, int s,
                                             int &lo_min, int &hi_max)
 {
     lo_min = 0x7fffffff;
     hi_max = -0x7fffffff;
     const int n_s = cst(P.rings)[s].n;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        if (s >= g.s_lo[h] && s <= g.s_hi[h]) {
-            const DevPair pp = cst(P.pairs)[g.pb[h] + s - g.s_lo[h]];
+    const int nr = Tp->nr;
+    const int j0 = Tp->j0;
+    for (int k = 0; k < nr; ++k) {
+        const GenRing q = cst(Tp->q)[k];
+        if (q.len > 0 && s >= q.s_lo && s <= q.s_hi) {
+            const DevPair pp = cst(P.pairs)[q.pb + s - q.s_lo];
             int lo, hi, dummy;
-            pair_window(pp, n_s, g.j0, lo, dummy);
-            pair_window(pp, n_s, g.j0 + g.len[h] - 1, dummy, hi);
+            pair_window(pp, n_s, j0, lo, dummy);
+            pair_window(pp, n_s, j0 + q.len - 1, dummy, hi);
             lo_min = min(lo_min, lo);
             hi_max = max(hi_max, hi);
         }
@@ -704,23 +675,24 @@ struct GenStage2 {
     int hi;   // last unwrapped position of the ring's union window
 };
 
-__device__ __forceinline__ GenStage2 first_stage2(const DevPlanView &P, const GenRows2 &g, int s)
+__device__ __forceinline__ GenStage2 first_stage2(const DevPlanView &P, const DevTile2 *Tp,
+                                                  int s_last, int s)
 {
     GenStage2 ch;
     ch.s = s;
     ch.c0 = 0;
     ch.cn = 0;
     ch.hi = -1;
-    if (s <= g.s_last) {
-        row_window2(P, g, s, ch.c0, ch.hi);
+    if (s <= s_last) {
+        row_window2(P, Tp, s, ch.c0, ch.hi);
         ch.cn = min(kGenStage, ch.hi - ch.c0 + 1);
     }
     return ch;
 }
 
 // The chunk after `ch`: the rest of its source ring, else the next ring.
-__device__ __forceinline__ GenStage2 next_stage2(const DevPlanView &P, const GenRows2 &g,
-                                                 const GenStage2 &ch)
+__device__ __forceinline__ GenStage2 next_stage2(const DevPlanView &P, const DevTile2 *Tp,
+                                                 int s_last, const GenStage2 &ch)
 {
     if (ch.c0 + kGenStage <= ch.hi) {
         GenStage2 nx = ch;
@@ -728,47 +700,48 @@ __device__ __forceinline__ GenStage2 next_stage2(const DevPlanView &P, const Gen
         nx.cn = min(kGenStage, ch.hi - nx.c0 + 1);
         return nx;
     }
-    return first_stage2(P, g, ch.s + 1);
+    return first_stage2(P, Tp, s_last, ch.s + 1);
 }
 
-// One general tile (DevTile2).  A tile of two adjacent rings gives the first
-// half of the lanes ring r[0] and the second half ring r[1] (idle where
-// len[1] = 0); a tile of one ring (r[1] = -1) gives it every lane.  Per staged
-// chunk of a source ring, each half runs the candidates of its own ring's
-// row, the sum over the lanes of a pixel follows, and each half writes the
-// sixteen images of its pixels.  LONG, AM, INTM and BIAS are fixed per tile,
-// so the candidate loop has one form and the row sums stay in place across
-// rows.
+// One general tile (DevTile2) of nr adjacent rings: the lanes form nr equal
+// parts of whole waves, part h taking ring q[h] (idle where its len is 0).
+// Per staged chunk of a source ring, each part runs the candidates of its
+// own ring's row, the sum over the lanes of a pixel follows, and each part
+// writes the sixteen images of its pixels.  LONG, AM, INTM and BIAS are fixed
+// per tile, so the candidate loop has one form and the row sums stay in place
+// across rows.
 template <bool LONG, int AM, bool INTM, bool BIAS>
 __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab, float4 *stage,
-                                          const DevTile2 &T, const float *in, float *out)
+                                          const DevTile2 *Tp, const float *in, float *out)
 {
-    const int kHalf = T.r[1] >= 0 ? kGenThreads / 2 : kGenThreads;
-    // wave-uniform (a half is whole waves); made scalar so that every branch
-    // on the half is a scalar branch
-    const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x >= kHalf ? 1 : 0);
-    const int tid = (int)threadIdx.x - h * kHalf;
-    const GenRows2 g = gen_rows2(P, T);
-    const int len = g.len[h];
-    const int rn = len > 0 ? T.r[h] : T.r[0];          // an idle half reads ring r[0]
+    const int nr = Tp->nr;
+    const int kPart = kGenThreads / nr;   // lanes per ring: 512, 256 or 128
+    // wave-uniform (a part is whole waves); made scalar so that every branch
+    // on the part is a scalar branch
+    const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kPart);
+    const int tid = (int)threadIdx.x - h * kPart;
+    const GenRing my = cst(Tp->q)[h];
+    const int s_last = Tp->s_last;
+    const int len = my.len;
+    const int rn = my.r;                                // an idle part holds a valid ring
     const int rs = P.nrings - 1 - rn;                   // mirror ring
     const bool mirror = rs != rn;
     const DevRing R = cst(P.rings)[rn];
     const int qr = R.n >> 2;
-    // 2^lp lanes per pixel: 2 (paired) or 4 for a full segment, more (up to a
-    // wave) for a shorter one, so that every lane works
-    int lp = 1;
-    while (lp < 6 && (kHalf >> (lp + 1)) >= len) ++lp;
+    // 2^lp lanes per pixel: 4 / nr for a full segment, more (up to a wave)
+    // for a shorter one, so that every lane works
+    int lp = 0;
+    while (lp < 6 && (kPart >> (lp + 1)) >= len) ++lp;
     const int nph = 1 << lp;
     const int ph = tid & (nph - 1);
     const int lane_pix = tid >> lp;
     const bool active = lane_pix < len;
-    const int j = T.j0 + min(lane_pix, max(len - 1, 0));
+    const int j = Tp->j0 + min(lane_pix, max(len - 1, 0));
     const GenConst<AM> gc(P);
 
-    GenStage2 ch = first_stage2(P, g, g.s_first);
+    GenStage2 ch = first_stage2(P, Tp, s_last, Tp->s_first);
     float4 pa, pb, pc, pd;
-    if (ch.s <= g.s_last) {
+    if (ch.s <= s_last) {
         const DevRing S = cst(P.rings)[ch.s];
         prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - ch.s].first, S.n, S.two_o,
                    ch.c0, ch.cn, pa, pb, pc, pd);
@@ -781,7 +754,7 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
         row[q] = 0.0f;
     }
     int since = 0;
-    while (ch.s <= g.s_last) {
+    while (ch.s <= s_last) {
         __syncthreads();      // the previous chunk is no longer read
         if ((int)threadIdx.x < ch.cn) {
             stage[threadIdx.x] = pa;
@@ -790,15 +763,15 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
             stage[3 * kGenStage + threadIdx.x] = pd;
         }
         __syncthreads();
-        const GenStage2 nx = next_stage2(P, g, ch);
-        if (nx.s <= g.s_last) {
+        const GenStage2 nx = next_stage2(P, Tp, s_last, ch);
+        if (nx.s <= s_last) {
             const DevRing Sn = cst(P.rings)[nx.s];
             prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - nx.s].first, Sn.n,
                        Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
         }
         // this half's row of source ring ch.s, if its ring has one
-        if (len > 0 && ch.s >= g.s_lo[h] && ch.s <= g.s_hi[h]) {
-            const DevPair pp = cst(P.pairs)[g.pb[h] + ch.s - g.s_lo[h]];
+        if (len > 0 && ch.s >= my.s_lo && ch.s <= my.s_hi) {
+            const DevPair pp = cst(P.pairs)[my.pb + ch.s - my.s_lo];
             const DevRing S = cst(P.rings)[ch.s];
             // this lane's candidates inside the chunk: a0 + ph, a0 + ph + nph, ...
             int lo, hi;
@@ -832,8 +805,8 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
         for (int q = 0; q < 16; ++q) acc[q] += __shfl_xor(acc[q], x);
     }
     // a ring-range plan leaves rings outside its range untouched
-    const bool wn = (T.flags[h] & kTileSkipNorth) == 0;
-    const bool ws = mirror && (T.flags[h] & kTileSkipSouth) == 0;
+    const bool wn = (my.flags & kTileSkipNorth) == 0;
+    const bool ws = mirror && (my.flags & kTileSkipSouth) == 0;
     if (active) {
         float *o = out + R.first;
         float *om = out + cst(P.rings)[rs].first;
@@ -846,7 +819,8 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
 #pragma unroll
                 for (int q = 0; q < 4; ++q) om[j + q * qr] = (float)acc[4 + q];
             }
-        } else if (ph == 1) {
+        }
+        if (ph == (nph > 1 ? 1 : 0)) {   // a second lane, or the only one
             const int jb = qr - R.two_o - j;   // reflected pixel; j itself at a fixed point
             if (jb != j && jb != qr) {
                 if (wn) {
@@ -866,25 +840,26 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
 // type from the tile and plan, the node-grid map from BIAS.
 template <bool BIAS>
 __device__ __forceinline__ void gen_tile_variant(const DevPlanView &P, const float *tab,
-                                                 float4 *stage, const DevTile2 &T,
+                                                 float4 *stage, const DevTile2 *Tp,
                                                  const float *in, float *out)
 {
-    const int fl = T.flags[0] | T.flags[1];
+    int fl = 0;
+    for (int k = 0; k < Tp->nr; ++k) fl |= cst(Tp->q)[k].flags;
     const bool lg = (fl & kTileLongSin) != 0;
     if (fl & kTileIntM) {   // wide windows on large rings (long sine implied)
         switch (P.angle_mode) {
-            case 0: gen_tile2<true, 0, true, BIAS>(P, tab, stage, T, in, out); break;
-            case 1: gen_tile2<true, 1, true, BIAS>(P, tab, stage, T, in, out); break;
-            default: gen_tile2<true, 2, true, BIAS>(P, tab, stage, T, in, out); break;
+            case 0: gen_tile2<true, 0, true, BIAS>(P, tab, stage, Tp, in, out); break;
+            case 1: gen_tile2<true, 1, true, BIAS>(P, tab, stage, Tp, in, out); break;
+            default: gen_tile2<true, 2, true, BIAS>(P, tab, stage, Tp, in, out); break;
         }
     } else {
         switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-            case 0: gen_tile2<false, 0, false, BIAS>(P, tab, stage, T, in, out); break;
-            case 1: gen_tile2<true, 0, false, BIAS>(P, tab, stage, T, in, out); break;
-            case 2: gen_tile2<false, 1, false, BIAS>(P, tab, stage, T, in, out); break;
-            case 3: gen_tile2<true, 1, false, BIAS>(P, tab, stage, T, in, out); break;
-            case 4: gen_tile2<false, 2, false, BIAS>(P, tab, stage, T, in, out); break;
-            default: gen_tile2<true, 2, false, BIAS>(P, tab, stage, T, in, out); break;
+            case 0: gen_tile2<false, 0, false, BIAS>(P, tab, stage, Tp, in, out); break;
+            case 1: gen_tile2<true, 0, false, BIAS>(P, tab, stage, Tp, in, out); break;
+            case 2: gen_tile2<false, 1, false, BIAS>(P, tab, stage, Tp, in, out); break;
+            case 3: gen_tile2<true, 1, false, BIAS>(P, tab, stage, Tp, in, out); break;
+            case 4: gen_tile2<false, 2, false, BIAS>(P, tab, stage, Tp, in, out); break;
+            default: gen_tile2<true, 2, false, BIAS>(P, tab, stage, Tp, in, out); break;
         }
     }
 }
@@ -916,13 +891,13 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
             if (threadIdx.x < 2) tab[P.ntab + threadIdx.x] = 0.0f;
             cur = pi;
         }
-        const DevTile2 T = cst(P.gtiles2)[lt];
+        const DevTile2 *Tp = P.gtiles2 + lt;
         const float *in = io.in[pi] + (size_t)map * P.npix;
         float *out = io.out[pi] + (size_t)map * P.npix;
         if (P.biased)
-            gen_tile_variant<true>(P, tab, stage, T, in, out);
+            gen_tile_variant<true>(P, tab, stage, Tp, in, out);
         else
-            gen_tile_variant<false>(P, tab, stage, T, in, out);
+            gen_tile_variant<false>(P, tab, stage, Tp, in, out);
     }
 }
 

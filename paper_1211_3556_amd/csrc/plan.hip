@@ -403,34 +403,55 @@ static int build_plan(Plan &P)
         gring.push_back(r);
         glanes.push_back(lanes);
         gflags.push_back(flags);
-        gwide.push_back(wmax > kGenPairMaxWindow ? 1 : 0);
+        gwide.push_back(wmax > kGenPairMaxWindow ? 2 : (wmax > kGenQuadMaxWindow ? 1 : 0));
     }
     sort_by_cost(P.gtiles, cost);
     P.gtile_cost = cost;
 
     // The general gather's tiles: adjacent general rings with narrow windows
-    // in pairs, each pair over the same half-quadrant segments (kGenLanes
-    // pixels of each ring, two lanes per pixel), so that a staged source row
-    // serves both; rings with a very wide window, whose time is the loop's
-    // LDS reads, keep four lanes per pixel, whose staged reads share more
-    // addresses.
+    // in groups of four (one lane per pixel) or two (two lanes per pixel),
+    // each group over the same half-quadrant segments (kGenLanes pixels of
+    // each ring), so that a staged source row serves the whole group; rings
+    // with a very wide window, whose time is the loop's LDS reads, keep four
+    // lanes per pixel, whose staged reads share more addresses.
     P.gtiles2.clear();
     cost.clear();
+    auto run_of = [&](size_t g, int n, int widest) {
+        if (g + n > gring.size()) return false;
+        for (int i = 0; i < n; ++i) {
+            if (gwide[g + i] > widest) return false;
+            if (i > 0 && gring[g + i] != gring[g + i - 1] + 1) return false;
+        }
+        return true;
+    };
     for (size_t g = 0; g < gring.size();) {
-        const bool pair = g + 1 < gring.size() && gring[g + 1] == gring[g] + 1 && !gwide[g] &&
-                          !gwide[g + 1];
-        const int nr = pair ? 2 : 1;
-        const int lanes = pair ? std::max(glanes[g], glanes[g + 1]) : glanes[g];
+        const int nr = run_of(g, 4, 0) ? 4 : (run_of(g, 2, 1) ? 2 : 1);
+        int lanes = 0;
+        for (int i = 0; i < nr; ++i) lanes = std::max(lanes, glanes[g + i]);
         for (int j0 = 0; j0 < lanes; j0 += kGenLanes) {
             DevTile2 t{};
             double c = 1.0;
-            for (int h = 0; h < 2; ++h) {
-                t.r[h] = h < nr ? gring[g + h] : -1;
-                t.len[h] = h < nr ? std::max(0, std::min(kGenLanes, glanes[g + h] - j0)) : 0;
-                t.flags[h] = h < nr ? gflags[g + h] : 0;
-                if (t.len[h] > 0) c += ring_cost[t.r[h]] * t.len[h];
-            }
+            t.nr = nr;
             t.j0 = j0;
+            t.s_first = 0x7fffffff;
+            t.s_last = -1;
+            for (int h = 0; h < kGenMaxRings; ++h) {
+                GenRing &q = t.q[h];
+                q.r = h < nr ? gring[g + h] : gring[g];
+                q.len = h < nr ? std::max(0, std::min(kGenLanes, glanes[g + h] - j0)) : 0;
+                q.flags = h < nr ? gflags[g + h] : 0;
+                q.s_lo = 0;
+                q.s_hi = -1;
+                if (q.len > 0) {
+                    const DevRing &dr = P.dev_rings[q.r];
+                    q.pb = dr.pair_begin;
+                    q.s_lo = P.pairs[dr.pair_begin].s;
+                    q.s_hi = P.pairs[dr.pair_end - 1].s;
+                    t.s_first = std::min(t.s_first, q.s_lo);
+                    t.s_last = std::max(t.s_last, q.s_hi);
+                    c += ring_cost[q.r] * q.len;
+                }
+            }
             P.gtiles2.push_back(t);
             cost.push_back(c);
         }
