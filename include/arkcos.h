@@ -58,7 +58,7 @@ enum {
 /* Largest supported Nside (ring indices and longitudes stay exact in int32). */
 #define ARKCOS_MAX_NSIDE 8192
 /* Largest node count for which knot gradients are supported. */
-#define ARKCOS_MAX_GRAD_NTAB 8192
+#define ARKCOS_MAX_GRAD_NTAB 2048
 /* Largest l_cut of the harmonic-space half (one order's coefficients fit LDS). */
 #define ARKCOS_MAX_LCUT 4095
 
@@ -90,7 +90,7 @@ typedef struct {
     double theta_break;
     int k_break;
     /* Output ring range (partial sky, e.g. a survey patch placed on a polar
-     * cap, the use the paper's Sec. 5 suggests for small-area maps):
+     * cap, the use the paper's conclusions (Sec. 4) suggest for small-area maps):
      * ring_first = ring_last = 0 computes every ring; otherwise only output
      * rings ring_first..ring_last (1-based, inclusive, within 1..4 Nside-1,
      * else EINVAL) are written, the other output pixels are left untouched,
@@ -279,8 +279,11 @@ int arkcos_convolve_part(arkcos_plan_t plan, const float *d_in, float *d_out, in
  *   d_grad_knots device FP32, ntab, overwritten, or NULL                      [out]
  * At least one output must be non-NULL; outputs must not overlap inputs.
  * Knot gradients need ARKCOS_PLAN_LEARNABLE and ntab <= ARKCOS_MAX_GRAD_NTAB
- * (EUNSUPPORTED otherwise).  The knot gradient is reduced in a fixed order
- * from FP64 partials.
+ * (EUNSUPPORTED otherwise).  Both outputs are bitwise reproducible for a
+ * plan on a given device: every output pixel of d_grad_in is written by one
+ * lane, and the knot gradient is accumulated in FP64 with a static
+ * assignment of work to waves, one histogram per wave, and fixed-order
+ * merges of the wave and workgroup partials.
  */
 int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const float *d_in,
                              float *d_grad_in, float *d_grad_knots, int nbatch, void *stream);

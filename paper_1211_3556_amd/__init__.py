@@ -37,7 +37,7 @@ PART_CIRCULANT = 1
 PART_GENERAL = 2
 PART_ALL = 3
 MAX_NSIDE = 8192
-MAX_GRAD_NTAB = 8192
+MAX_GRAD_NTAB = 2048
 MAX_LCUT = 4095
 
 _STATUS = {0: "ARKCOS_OK", -1: "ARKCOS_EINVAL", -2: "ARKCOS_ENOMEM", -3: "ARKCOS_EDEVICE",

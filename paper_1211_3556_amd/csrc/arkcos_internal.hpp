@@ -136,7 +136,6 @@ constexpr int kGenPhases = kGenThreads / kGenLanes;
 constexpr double kGenPairMaxWindow = 200.0;  // widest row window (positions) of a paired ring
 constexpr double kGenQuadMaxWindow = 64.0;   // ... of a ring in a tile of four
 constexpr int kGenStage = 248;       // with a 16384-node table two workgroups fit a CU
-constexpr int kGenChunk = 320;
 constexpr int kMaxMaps = 32;
 // Circulant knot-gradient tiles: kKnotSeg pixels of a ring group, split into
 // sub-segments of kKnotSub; up to kKnotRows source rows and kKnotStage staged

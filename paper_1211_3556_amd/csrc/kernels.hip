@@ -331,18 +331,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
     }
 }
 
-// ------------------------------------------- 8-image staging helpers --
-// Source pixels each lane prefetches per staged chunk.
-constexpr int kGenRegs = (kGenChunk + kThreads - 1) / kThreads;
-
-// One staged chunk of one source row of a general tile: row k of the output
-// ring's pair list, unwrapped source pixels c0 .. c0+cn-1.
-struct GenChunk {
-    int k;
-    int c0;
-    int cn;
-};
-
+// ------------------------------------------------------- staging helpers --
 // Window bounds of a tile's first and last pixel on the row of pair pp.
 __device__ __forceinline__ void tile_window(const DevPair &pp, int n_s, const DevTile &T,
                                             int &lo_min, int &hi_max)
@@ -351,30 +340,6 @@ __device__ __forceinline__ void tile_window(const DevPair &pp, int n_s, const De
     pair_window(pp, n_s, T.j0, lo_min, dummy);
     pair_window(pp, n_s, T.j0 + T.len - 1, dummy, hi_max);
 }
-
-// Issue the loads of the 8 images of a chunk: the four quarter turns of ring s
-// and of its mirror ring.
-__device__ __forceinline__ void prefetch_chunk(const float *src, const float *srcm, bool mirror,
-                                               int n_s, int c0, int cn, float4 a[kGenRegs],
-                                               float4 b[kGenRegs])
-{
-    const int qs = n_s >> 2;
-#pragma unroll
-    for (int u = 0; u < kGenRegs; ++u) {
-        const int e = threadIdx.x + u * kThreads;
-        a[u] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        b[u] = a[u];
-        if (e < cn) {
-            const int i0 = wrap3(c0 + e, n_s);
-            const int i1 = wrap3(c0 + e + qs, n_s);
-            const int i2 = wrap3(c0 + e + 2 * qs, n_s);
-            const int i3 = wrap3(c0 + e + 3 * qs, n_s);
-            a[u] = make_float4(src[i0], src[i1], src[i2], src[i3]);
-            if (mirror) b[u] = make_float4(srcm[i0], srcm[i1], srcm[i2], srcm[i3]);
-        }
-    }
-}
-
 
 // --------------------------------------------------------- general gather --
 // Reflection about phi = pi/4 (phi -> pi/2 - phi) maps pixel j of quadrant 0
@@ -918,6 +883,25 @@ __global__ void k_set_table(float *table, const float *knots, int ntab, float om
 // table: rounded up to 16 bytes.
 __host__ __device__ constexpr int hist_offset_floats(int ntab) { return (ntab + 3) & ~3; }
 
+// The knot-gradient kernels bin into one FP64 histogram per wave, so no two
+// waves ever add to the same LDS word: with the static tile assignment below
+// every bin receives the same additions in the same order on every run (the
+// lanes of one atomic instruction are applied in a fixed hardware order).  At
+// the end the wave histograms are added in wave order.
+constexpr int kKnotWaves = kThreads / 64;
+__host__ __device__ constexpr int hist_stride(int ntab) { return (ntab + 1) & ~1; }
+
+__device__ __forceinline__ void write_partials(const double *hists, int hstride, int ntab,
+                                               double *dst)
+{
+    for (int i = threadIdx.x; i < ntab; i += blockDim.x) {
+        double t = hists[i];
+#pragma unroll
+        for (int w = 1; w < kKnotWaves; ++w) t += hists[w * hstride + i];
+        dst[i] = t;
+    }
+}
+
 // ------------------------------------------------------------ FP64 math --
 // Coefficients of the series below, evaluated at compile time:
 // asin(y) = sum_k c_k y^(2k+1), c_k = (2k)! / (4^k (k!)^2 (2k+1)), and
@@ -1016,9 +1000,9 @@ __device__ __forceinline__ bool pair_node_d(const DevPairD &pd, const NodeMapD &
 }
 
 // The knot gradient is sum_p g[p] sum_q hat_k(theta_pq) x[q] over the in-disc
-// pairs of all maps.  Both kernels below scatter into a per-workgroup FP64
-// LDS histogram, written to partials[row][ntab] and reduced in a fixed order
-// by k_knot_reduce.
+// pairs of all maps.  Both kernels below scatter into per-wave FP64 LDS
+// histograms, merged per workgroup into partials[row][ntab] and reduced in a
+// fixed order by k_knot_reduce.
 
 // Circulant weight slots (row w_off + tap * kGroupRings + ring): tap k of
 // ring r of a group on source ring s is the pair at the exact longitude
@@ -1139,24 +1123,24 @@ __device__ __forceinline__ void load_to_lds(const float *, float *) {}
 __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__restrict__ views,
                                                         const float *__restrict__ g,
                                                         const float *__restrict__ x, int nmaps,
-                                                        unsigned int *counter,
                                                         double *__restrict__ partials)
 {
-    extern __shared__ __align__(16) double hist[];
-    __shared__ int s_item;
+    extern __shared__ __align__(16) double hists[];
     __shared__ int s_rows;                   // rows in the current batch
     __shared__ int s_uprefix[kKnotRows + 1]; // units before each row of the batch
     __shared__ int s_xoff[kKnotRows];        // its staged x strips
     __shared__ int s_woff[kKnotRows];        // its weight-slot offset
     __shared__ int s_ntaps[kKnotRows];       // and tap count
     const DevPlanView P = cst(views)[0];
-    float4 *gs = reinterpret_cast<float4 *>(hist + ((P.ntab + 1) & ~1));
+    const int hstride = hist_stride(P.ntab);
+    float4 *gs = reinterpret_cast<float4 *>(hists + kKnotWaves * hstride);
     float *xs = reinterpret_cast<float *>(gs + kKnotSubs * (kKnotSub + 1));
-    for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) hist[i] = 0.0;
+    for (int i = threadIdx.x; i < kKnotWaves * hstride; i += blockDim.x) hists[i] = 0.0;
+    double *hist = hists + (threadIdx.x >> 6) * hstride;   // this wave's own bins
+    __syncthreads();
     const int nitems = P.nkctiles * nmaps;
-    for (;;) {
-        const int item = next_item(counter, &s_item);
-        if (item >= nitems) break;
+    // static assignment: the tiles (longest first) are dealt round-robin
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int ti = item / nmaps;
         const int map = item - ti * nmaps;
         const DevTile T = cst(P.kctiles)[ti];
@@ -1309,8 +1293,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
         __syncthreads();   // gs is restaged by the next item
     }
     __syncthreads();
-    double *dst = partials + (size_t)blockIdx.x * P.ntab;
-    for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) dst[i] = hist[i];
+    write_partials(hists, hstride, P.ntab, partials + (size_t)blockIdx.x * P.ntab);
 }
 
 // ------------------------------------------------- general rings: per pair --
@@ -1364,21 +1347,20 @@ __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const Node
 __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__restrict__ views,
                                                        const float *__restrict__ g,
                                                        const float *__restrict__ x, int nmaps,
-                                                       unsigned int *counter,
                                                        double *__restrict__ partials)
 {
-    extern __shared__ __align__(16) double hist[];
-    __shared__ int s_item;
+    extern __shared__ __align__(16) double hists[];
     const DevPlanView P = cst(views)[0];
-    float4 *stage = reinterpret_cast<float4 *>(hist + ((P.ntab + 1) & ~1));
-    for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) hist[i] = 0.0;
+    const int hstride = hist_stride(P.ntab);
+    float4 *stage = reinterpret_cast<float4 *>(hists + kKnotWaves * hstride);
+    for (int i = threadIdx.x; i < kKnotWaves * hstride; i += blockDim.x) hists[i] = 0.0;
+    double *hist = hists + (threadIdx.x >> 6) * hstride;   // this wave's own bins
+    __syncthreads();
     const NodeMapD nm(P);
     const int ph = threadIdx.x & 1;
     const int lane_pix = threadIdx.x >> 1;
     const int nitems = P.ngtiles * nmaps;
-    for (;;) {
-        const int item = next_item(counter, &s_item);
-        if (item >= nitems) break;
+    for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int ti = item / nmaps;
         const int map = item - ti * nmaps;
         const DevTile T = cst(P.gtiles)[ti];
@@ -1461,8 +1443,8 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
         }
     }
     __syncthreads();
-    double *dst = partials + ((size_t)P.nkpart_circ + blockIdx.x) * P.ntab;
-    for (int i = threadIdx.x; i < P.ntab; i += blockDim.x) dst[i] = hist[i];
+    write_partials(hists, hstride, P.ntab,
+                   partials + ((size_t)P.nkpart_circ + blockIdx.x) * P.ntab);
 }
 // Fixed-order reduction of the per-workgroup partials, scaled by Omega: a
 // block of kReduceWaves waves covers 64 knots, wave w sums rows w, w + kReduceWaves, ...,
@@ -1533,7 +1515,10 @@ static size_t gen_lds(int ntab)
 }
 // FP64 histogram (16-byte aligned), then the staged g and x of a circulant
 // knot tile, or the general stage.
-static size_t knot_hist_bytes(int ntab) { return (size_t)((ntab + 1) & ~1) * sizeof(double); }
+static size_t knot_hist_bytes(int ntab)
+{
+    return (size_t)kKnotWaves * hist_stride(ntab) * sizeof(double);
+}
 static size_t knot_circ_lds(int ntab)
 {
     return knot_hist_bytes(ntab) + (size_t)kKnotSubs * (kKnotSub + 1) * sizeof(float4) +
@@ -1636,15 +1621,12 @@ static int launch_knot(const Plan &p, const float *g, const float *x, float *gk,
                        hipStream_t s)
 {
     const int ntab = p.desc.ntab;
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, p.d_counter + 2);
     if (p.grid_kc > 0)
         hipLaunchKernelGGL(k_knot_circ, dim3(p.grid_kc), dim3(kThreads), knot_circ_lds(ntab), s,
-                           (const DevPlanView *)p.d_view, g, x, nbatch, p.d_counter + 2,
-                           p.d_kpart);
+                           (const DevPlanView *)p.d_view, g, x, nbatch, p.d_kpart);
     if (p.grid_kg > 0)
         hipLaunchKernelGGL(k_knot_gen, dim3(p.grid_kg), dim3(kThreads), knot_gen_lds(ntab), s,
-                           (const DevPlanView *)p.d_view, g, x, nbatch, p.d_counter + 3,
-                           p.d_kpart);
+                           (const DevPlanView *)p.d_view, g, x, nbatch, p.d_kpart);
     ARKCOS_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 63) / 64), dim3(64 * kReduceWaves), 0, s,
                        p.d_kpart, p.grid_kc + p.grid_kg, ntab, p.omega, gk);

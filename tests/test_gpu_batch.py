@@ -102,7 +102,9 @@ def test_graph_replay():
 
 def test_c4_full_batch_matches_plain_and_oracle():
     """The 16-map batch (Nside 256..2048, FWHM 5..30 arcmin, cut 3 FWHM) in one
-    launch: bitwise equal to plain launches, oracle-checked on sampled pixels."""
+    launch: every map is bitwise equal to its plain launch and agrees with the
+    FP64 oracle on 1024 uniform pixels plus the polar, cap/belt and equatorial
+    strata."""
     import torch
     A = _A()
     specs = W.batch_specs()
@@ -118,10 +120,11 @@ def test_c4_full_batch_matches_plain_and_oracle():
         _sync()
         yh = to_host(y)
         assert np.array_equal(yh, to_host(yp))
-        if k % 3 == 0 or k == 15:
-            pix = W.eval_pixels(s.nside, 1024, s.seed, max_strata_ring_pixels=64)
-            ref = O.convolve(s.nside, s.theta_cut, oracle_table(s), to_host(x), pixels=pix)
-            assert rel_rms(yh[pix], ref) <= REL_RMS_TOL
+        pix = W.eval_pixels(s.nside, 1024, s.seed, max_strata_ring_pixels=64)
+        ref = O.convolve(s.nside, s.theta_cut, oracle_table(s), to_host(x), pixels=pix)
+        err = rel_rms(yh[pix], ref)
+        log("c4 map %d rel rms %.3e over %d pixels" % (k, err, pix.size))
+        assert err <= REL_RMS_TOL
         del yp
     del ys
     torch.cuda.empty_cache()

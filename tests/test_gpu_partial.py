@@ -1,7 +1,7 @@
 """GPU parity of ring-range (partial-sky) plans: only the output rings of the
 range are written, each as the oracle computes it; every other output pixel
 is left as it was.  The last case is a ~500 square-degree polar-cap patch of
-an Nside 8192 map, the survey geometry the paper's Sec. 5 suggests for
+an Nside 8192 map, the survey geometry the paper's conclusions (Sec. 4) suggest for
 small-area, high-resolution maps."""
 import numpy as np
 import pytest

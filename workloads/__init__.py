@@ -165,10 +165,10 @@ SPLIT_EXAMPLE = MapSpec(nside=2048, fwhm=7.0 * ARCMIN, theta_cut=240.0 * ARCMIN,
                         seed=7, lmax=4096)
 
 
-# All-sky maps beyond the single-GPU limit of the paper's time (its Sec. 5
-# puts l ~ 8000-16000 on several GPUs): Nside 4096 and 8192, with the beam
-# and cut scaled to the pixel size so that a disc holds as many pixels as in
-# the 15 arcmin Nside-2048 workload (about 240 pairs per pixel).
+# All-sky maps beyond the single-GPU limit of the paper's time (its
+# conclusions, Sec. 4, put l ~ 8000-16000 on several GPUs): Nside 4096 and
+# 8192, with the beam and cut scaled to the pixel size so that a disc holds as
+# many pixels as in the 15 arcmin Nside-2048 workload (about 240 pairs per pixel).
 LARGE = (MapSpec(nside=4096, fwhm=2.5 * ARCMIN, theta_cut=7.5 * ARCMIN, ntab=16384, seed=41),
          MapSpec(nside=8192, fwhm=1.25 * ARCMIN, theta_cut=3.75 * ARCMIN, ntab=16384, seed=42))
 
