@@ -61,6 +61,9 @@ enum {
 #define ARKCOS_MAX_GRAD_NTAB 2048
 /* Largest l_cut of the harmonic-space half (one order's coefficients fit LDS). */
 #define ARKCOS_MAX_LCUT 4095
+/* Bytes of the per-device static workspace of arkcos_convolve_backward_static
+ * (16 MiB: two queue counters, then the knot-gradient partial rows). */
+#define ARKCOS_STATIC_SCRATCH_BYTES (16u << 20)
 
 typedef struct {
     int nside;            /* HEALPix resolution, 1 .. ARKCOS_MAX_NSIDE (any integer)       */
@@ -287,6 +290,30 @@ int arkcos_convolve_part(arkcos_plan_t plan, const float *d_in, float *d_out, in
  */
 int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const float *d_in,
                              float *d_grad_in, float *d_grad_knots, int nbatch, void *stream);
+
+/*
+ * arkcos_convolve_backward for callers that cannot allocate device memory at
+ * call time or cannot tolerate an allocation in the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  Arguments,
+ * results and errors are those of arkcos_convolve_backward, and the results
+ * are bit for bit the same; the difference is the workspace.  The gathers'
+ * queue counters and the knot-gradient partial rows live in a file-scope
+ * device array of ARKCOS_STATIC_SCRATCH_BYTES bytes instead of the plan's
+ * workspace; each device that runs this call holds its own copy from the
+ * library's load until the process ends.  The call itself allocates nothing
+ * (no hipMalloc, no allocating library routine); its device address is looked
+ * up once per device, on the first call there.  EUNSUPPORTED if the plan's
+ * knot-gradient partials (one row of ntab FP64 values per resident workgroup
+ * of the two knot kernels, at most ~12 MiB for ntab = 2048 on a 256-CU
+ * device) exceed the array.  Every call on one device shares its array, so
+ * calls whose work overlaps on a device race and give wrong results: order
+ * them on one stream (or synchronise between streams).  The array keeps the
+ * last call's contents; everything a call reads from it is first written by
+ * that call.
+ */
+int arkcos_convolve_backward_static(arkcos_plan_t plan, const float *d_grad_out,
+                                    const float *d_in, float *d_grad_in, float *d_grad_knots,
+                                    int nbatch, void *stream);
 
 /* ------------------------------------------------------------- batches -- */
 

@@ -110,6 +110,7 @@ def load_library():
         "arkcos_plan_pair_count_parts": [_vp, ctypes.POINTER(ctypes.c_ulonglong),
                                          ctypes.POINTER(ctypes.c_ulonglong)],
         "arkcos_convolve_backward": [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp],
+        "arkcos_convolve_backward_static": [_vp, _vp, _vp, _vp, _vp, ctypes.c_int, _vp],
         "arkcos_batch_create": [ctypes.POINTER(_vp), ctypes.c_int, ctypes.POINTER(_vp)],
         "arkcos_batch_convolve": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp],
         "arkcos_batch_convolve_part": [_vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.c_int,
@@ -349,17 +350,33 @@ class Plan:
         return out
 
     def backward(self, grad_out, x=None, want_map: bool = True, want_knots: bool = False,
-                 stream=None):
-        """(dL/dx, dL/dknots) for dL/d(out) = grad_out; either may be None."""
+                 stream=None, gx=None, gk=None, static_workspace: bool = False):
+        """(dL/dx, dL/dknots) for dL/d(out) = grad_out; either may be None.
+
+        ``gx``/``gk`` may be given as preallocated outputs.  With
+        ``static_workspace=True`` the call goes to arkcos_convolve_backward_static,
+        whose workspace is the library's per-device static array."""
         import torch
         g = _dev_f32(grad_out, "grad_out")
         nb = self._shape(g)
-        gx = torch.empty_like(g) if want_map else None
-        gk = torch.empty(self.ntab, dtype=torch.float32, device=g.device) if want_knots else None
+        if want_map:
+            gx = torch.empty_like(g) if gx is None else _dev_f32(gx, "gx")
+            if gx.shape != g.shape:
+                raise ValueError("gx must have the shape of grad_out")
+        else:
+            gx = None
+        if want_knots:
+            gk = torch.empty(self.ntab, dtype=torch.float32, device=g.device) if gk is None \
+                else _dev_f32(gk, "gk")
+            if gk.numel() != self.ntab:
+                raise ValueError("gk must hold ntab values")
+        else:
+            gk = None
         xp = _vp(_dev_f32(x, "x").data_ptr()) if x is not None else _vp()
         if want_knots and x is None:
             raise ValueError("knot gradients need the input map x")
-        _call("arkcos_convolve_backward", self._h, _vp(g.data_ptr()), xp,
+        fn = "arkcos_convolve_backward_static" if static_workspace else "arkcos_convolve_backward"
+        _call(fn, self._h, _vp(g.data_ptr()), xp,
               _vp(gx.data_ptr()) if gx is not None else _vp(),
               _vp(gk.data_ptr()) if gk is not None else _vp(), nb, _stream_ptr(stream))
         return gx, gk

@@ -320,10 +320,14 @@ struct Batch {
 // ----------------------------------------------------------------- launch --
 // Implemented in kernels.hip.
 int launch_set_table(const Plan &p, const float *d_knots, hipStream_t s);
+// `counter` (two queue counters) and `kpart` (knot-gradient partial rows,
+// knot_partial_bytes) replace the plan's own workspace when non-NULL.
 int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s,
-                   int parts = ARKCOS_PART_ALL);
+                   int parts = ARKCOS_PART_ALL, unsigned int *counter = nullptr);
 int launch_backward(const Plan &p, const float *g, const float *x, float *gx, float *gk,
-                    int nbatch, hipStream_t s);
+                    int nbatch, hipStream_t s, unsigned int *counter = nullptr,
+                    double *kpart = nullptr);
+long long knot_partial_bytes(const Plan &p);
 int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s,
                  int parts = ARKCOS_PART_ALL);
 int launch_build_weights(const Plan &p, hipStream_t s);

@@ -2,6 +2,7 @@
 // launches (kernels.hip).  Plan construction lives in plan.hip.
 #include <algorithm>
 #include <cstdint>
+#include <mutex>
 #include <numeric>
 #include <string>
 
@@ -9,7 +10,33 @@
 
 using namespace arkcos;
 
+// Workspace of arkcos_convolve_backward_static: the two queue counters of the
+// gathers in the first 256 bytes, then the knot-gradient partial rows.  One
+// copy per device, held for the life of the process.  In host code this name
+// is only a handle: its device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[ARKCOS_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr size_t kScratchCounterBytes = 256;
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current.
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[64] = {};
+
+int scratch_address(int device, void **ptr)
+{
+    if (device < 0 || device >= 64) return fail(ARKCOS_EUNSUPPORTED, "device ordinal above 63");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        ARKCOS_HIP_CHECK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return ARKCOS_OK;
+}
 
 bool overlaps(const void *a, size_t na, const void *b, size_t nb)
 {
@@ -66,12 +93,10 @@ int arkcos_convolve(arkcos_plan_t plan, const float *d_in, float *d_out, int nba
     return arkcos_convolve_part(plan, d_in, d_out, nbatch, ARKCOS_PART_ALL, stream);
 }
 
-int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const float *d_in,
-                             float *d_grad_in, float *d_grad_knots, int nbatch, void *stream)
+// Argument checks shared by the two backward entry points.
+static int check_backward(const Plan *P, const float *d_grad_out, const float *d_in,
+                          const float *d_grad_in, const float *d_grad_knots, int nbatch)
 {
-    clear_error();
-    if (!plan || !d_grad_out) return fail(ARKCOS_EINVAL, "NULL pointer");
-    const Plan *P = reinterpret_cast<const Plan *>(plan);
     if (!d_grad_in && !d_grad_knots)
         return fail(ARKCOS_EINVAL, "at least one of d_grad_in, d_grad_knots must be non-NULL");
     int rc = check_compute(P, nbatch);
@@ -97,9 +122,47 @@ int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const 
                           overlaps(d_grad_in, bytes, d_grad_knots, kbytes)))
             return fail(ARKCOS_EINVAL, "d_grad_in overlaps d_in or d_grad_knots");
     }
+    return ARKCOS_OK;
+}
+
+int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const float *d_in,
+                             float *d_grad_in, float *d_grad_knots, int nbatch, void *stream)
+{
+    clear_error();
+    if (!plan || !d_grad_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    int rc = check_backward(P, d_grad_out, d_in, d_grad_in, d_grad_knots, nbatch);
+    if (rc) return rc;
     DeviceGuard g(P->device);
     return launch_backward(*P, d_grad_out, d_in, d_grad_in, d_grad_knots, nbatch,
                            (hipStream_t)stream);
+}
+
+int arkcos_convolve_backward_static(arkcos_plan_t plan, const float *d_grad_out,
+                                    const float *d_in, float *d_grad_in, float *d_grad_knots,
+                                    int nbatch, void *stream)
+{
+    clear_error();
+    if (!plan || !d_grad_out) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    int rc = check_backward(P, d_grad_out, d_in, d_grad_in, d_grad_knots, nbatch);
+    if (rc) return rc;
+    const long long need = d_grad_knots ? knot_partial_bytes(*P) : 0;
+    if (need > (long long)(ARKCOS_STATIC_SCRATCH_BYTES - kScratchCounterBytes))
+        return fail(ARKCOS_EUNSUPPORTED,
+                    "knot-gradient partials need " + std::to_string(need) +
+                        " bytes, more than the static workspace holds (" +
+                        std::to_string(ARKCOS_STATIC_SCRATCH_BYTES - kScratchCounterBytes) + ")");
+    DeviceGuard g(P->device);
+    void *base = nullptr;
+    if ((rc = scratch_address(P->device, &base))) return rc;
+    // the counters are reset by a kernel at the start of each gather, and every
+    // partial row is written before it is reduced, so nothing is cleared here
+    unsigned int *counter = reinterpret_cast<unsigned int *>(base);
+    double *kpart = reinterpret_cast<double *>(static_cast<unsigned char *>(base) +
+                                               kScratchCounterBytes);
+    return launch_backward(*P, d_grad_out, d_in, d_grad_in, d_grad_knots, nbatch,
+                           (hipStream_t)stream, counter, kpart);
 }
 
 int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *out)

@@ -1582,25 +1582,26 @@ int launch_build_weights(const Plan &p, hipStream_t s)
 
 // The two gathers of one plan over nbatch maps; they write disjoint rings.
 int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s,
-                   int parts)
+                   int parts, unsigned int *counter)
 {
     MapIO io{};
     io.in[0] = in;
     io.out[0] = out;
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, p.d_counter);
+    if (!counter) counter = p.d_counter;
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, counter);
     const int nct = (parts & ARKCOS_PART_CIRCULANT) ? (int)p.ctiles.size() : 0;
     const int ngt = (parts & ARKCOS_PART_GENERAL) ? (int)p.gtiles2.size() : 0;
     if (nct > 0) {
         const int grid = std::max(1, std::min(nct * nbatch, p.occ_circ * p.cus));
         hipLaunchKernelGGL(k_circ, dim3(grid), dim3(kThreads), circ_lds(), s,
                            (const DevPlanView *)p.d_view, (const int2 *)nullptr, nct, io, nbatch,
-                           circ_buf_floats(), p.d_counter);
+                           circ_buf_floats(), counter);
     }
     if (ngt > 0) {
         const int grid = std::max(1, std::min(ngt * nbatch, p.occ_gen * p.cus));
         hipLaunchKernelGGL(k_general, dim3(grid), dim3(kGenThreads), gen_lds(p.desc.ntab), s,
                            (const DevPlanView *)p.d_view, (const int2 *)nullptr, ngt, io, nbatch,
-                           gen_tab_floats(p.desc.ntab), p.d_counter + 1);
+                           gen_tab_floats(p.desc.ntab), counter + 1);
     }
     ARKCOS_HIP_CHECK(hipGetLastError());
     return ARKCOS_OK;
@@ -1618,32 +1619,37 @@ int launch_build_knotw(const Plan &p, hipStream_t s)
 // Circulant rings by correlation, general rings per pair; every partial row
 // is written (the grids are the rows reserved at plan creation), then reduced.
 static int launch_knot(const Plan &p, const float *g, const float *x, float *gk, int nbatch,
-                       hipStream_t s)
+                       hipStream_t s, double *kpart)
 {
     const int ntab = p.desc.ntab;
     if (p.grid_kc > 0)
         hipLaunchKernelGGL(k_knot_circ, dim3(p.grid_kc), dim3(kThreads), knot_circ_lds(ntab), s,
-                           (const DevPlanView *)p.d_view, g, x, nbatch, p.d_kpart);
+                           (const DevPlanView *)p.d_view, g, x, nbatch, kpart);
     if (p.grid_kg > 0)
         hipLaunchKernelGGL(k_knot_gen, dim3(p.grid_kg), dim3(kThreads), knot_gen_lds(ntab), s,
-                           (const DevPlanView *)p.d_view, g, x, nbatch, p.d_kpart);
+                           (const DevPlanView *)p.d_view, g, x, nbatch, kpart);
     ARKCOS_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 63) / 64), dim3(64 * kReduceWaves), 0, s,
-                       p.d_kpart, p.grid_kc + p.grid_kg, ntab, p.omega, gk);
+                       kpart, p.grid_kc + p.grid_kg, ntab, p.omega, gk);
     ARKCOS_HIP_CHECK(hipGetLastError());
     return ARKCOS_OK;
 }
 
 int launch_backward(const Plan &p, const float *g, const float *x, float *gx, float *gk,
-                    int nbatch, hipStream_t s)
+                    int nbatch, hipStream_t s, unsigned int *counter, double *kpart)
 {
     // The operator is symmetric, so d/dmap is the same gather applied to g.
     if (gx) {
-        int rc = launch_forward(p, g, gx, nbatch, s);
+        int rc = launch_forward(p, g, gx, nbatch, s, ARKCOS_PART_ALL, counter);
         if (rc) return rc;
     }
-    if (gk) return launch_knot(p, g, x, gk, nbatch, s);
+    if (gk) return launch_knot(p, g, x, gk, nbatch, s, kpart ? kpart : p.d_kpart);
     return ARKCOS_OK;
+}
+
+long long knot_partial_bytes(const Plan &p)
+{
+    return (long long)(p.grid_kc + p.grid_kg) * p.desc.ntab * (long long)sizeof(double);
 }
 
 int launch_batch(const Batch &b, const float *const *in, float *const *out, hipStream_t s,
