@@ -11,9 +11,18 @@ Sec. 3):
            theta_cut swept over 10, 15 and 20 arcmin;
   fwdbwd   Nside 2048, theta_cut 15 arcmin, 256 learnable knots: forward, then
            the adjoint (d/dmap: the same gathers on g) and the knot gradient;
+           the knots are bound to the plan before each pass, as the autograd
+           function does (node table and circulant weights rebuilt);
+  grad     the differentiation workload: Nside 1024, 8 maps, theta_cut
+           30 arcmin, 256 learnable knots, forward + adjoint + knot gradient
+           with the same knot binding;
   batch    16 maps of Nside 256..2048 and FWHM 5..30 arcmin (cut 3 FWHM) as one
            batch, each of its two gathers one persistent launch replayed from
            a captured graph.
+
+General-gather tile shapes come from the tuning cache the package ships
+(python -m paper_1211_3556_amd.autotune); the breakdown says which plans used
+tuned shapes.
 
 Every gather launch is bracketed by HIP events on the stream it runs on, so
 each kernel's launch time is measured inside the timed region.  The unit of
@@ -145,8 +154,24 @@ def main() -> int:
     gin = dev_map(2048, 13)
     g_out = torch.empty_like(x2048)
     g_gx = torch.empty_like(x2048)
+    g_gk = torch.empty(gspec.ntab, dtype=torch.float32, device=dev)
     g_parts = gplan.pair_count_parts()
     g_pairs = sum(g_parts)
+
+    # the differentiation workload: 8 maps of Nside 1024, 30 arcmin, 256 knots
+    c5 = W.C5
+    c5plan = A.Plan(c5.nside, c5.theta_cut, ntab=c5.nknots, max_batch=c5.nbatch, learnable=True)
+    c5knots = torch.from_numpy(W.gaussian_profile_knots(c5.fwhm, c5.theta_cut,
+                                                        c5.nknots).astype(np.float32)).to(dev)
+    c5plan.set_knots(c5knots)
+    c5x = torch.from_numpy(W.white_noise(c5.nside, c5.seed0, nbatch=c5.nbatch)
+                           .astype(np.float32)).to(dev)
+    c5g = torch.from_numpy(W.white_noise(c5.nside, c5.seed0 + 100, nbatch=c5.nbatch)
+                           .astype(np.float32)).to(dev)
+    c5y, c5gx = torch.empty_like(c5x), torch.empty_like(c5x)
+    c5gk = torch.empty(c5.nknots, dtype=torch.float32, device=dev)
+    c5_parts = c5plan.pair_count_parts()
+    c5_pairs = c5.nbatch * sum(c5_parts)
 
     bspecs = W.batch_specs()
     bplans = [A.Plan(s.nside, s.theta_cut, table(s)) for s in bspecs]
@@ -191,19 +216,28 @@ def main() -> int:
                   lambda: p.convolve_part(x2048, o, CIRC))
             timed(record, "fwd%d" % i, "k_general", fl("k_general", pg),
                   lambda: p.convolve_part(x2048, o, GEN))
-        pc, pg = g_parts
-        timed(record, "fwdbwd", "k_circ", fl("k_circ", pc),
-              lambda: gplan.convolve_part(x2048, g_out, CIRC))
-        timed(record, "fwdbwd", "k_general", fl("k_general", pg),
-              lambda: gplan.convolve_part(x2048, g_out, GEN))
-        # adjoint: the operator is symmetric, so d/dmap is the same two gathers on g
-        timed(record, "fwdbwd", "k_circ", fl("k_circ", pc),
-              lambda: gplan.convolve_part(gin, g_gx, CIRC))
-        timed(record, "fwdbwd", "k_general", fl("k_general", pg),
-              lambda: gplan.convolve_part(gin, g_gx, GEN))
-        # knot gradient: correlation on circulant rings, per pair on general rings
-        timed(record, "fwdbwd", "k_knot", fl("k_knot_circ", pc) + fl("k_knot_gen", pg),
-              lambda: gplan.backward(gin, x2048, want_map=False, want_knots=True))
+        def fwdbwd(part, plan, knots, x, y, g, gx, gk, nb, parts):
+            pc, pg = parts
+            pc, pg = nb * pc, nb * pg
+            # forward with the knots bound to the plan (table + circulant weights)
+            timed(record, part, "k_set_knots", 0.0, lambda: plan.set_knots(knots))
+            timed(record, part, "k_circ", fl("k_circ", pc),
+                  lambda: plan.convolve_part(x, y, CIRC))
+            timed(record, part, "k_general", fl("k_general", pg),
+                  lambda: plan.convolve_part(x, y, GEN))
+            # backward: knots bound again; the operator is symmetric, so d/dmap
+            # is the same two gathers on g
+            timed(record, part, "k_set_knots", 0.0, lambda: plan.set_knots(knots))
+            timed(record, part, "k_circ", fl("k_circ", pc),
+                  lambda: plan.convolve_part(g, gx, CIRC))
+            timed(record, part, "k_general", fl("k_general", pg),
+                  lambda: plan.convolve_part(g, gx, GEN))
+            # knot gradient: correlation on circulant rings, per pair on general rings
+            timed(record, part, "k_knot", fl("k_knot_circ", pc) + fl("k_knot_gen", pg),
+                  lambda: plan.backward(g, x, want_map=False, want_knots=True, gk=gk))
+
+        fwdbwd("fwdbwd", gplan, knots, x2048, g_out, gin, g_gx, g_gk, 1, g_parts)
+        fwdbwd("grad", c5plan, c5knots, c5x, c5y, c5g, c5gx, c5gk, c5.nbatch, c5_parts)
         timed(record, "batch", "k_circ", fl("k_circ", b_circ), graphs[CIRC].replay)
         timed(record, "batch", "k_general", fl("k_general", b_gen), graphs[GEN].replay)
 
@@ -224,15 +258,17 @@ def main() -> int:
         return sum(m for part, _, _, m in ms if part == name) / args.steps
 
     fwd_ms = [part_ms("fwd%d" % i) for i in range(3)]
-    fb_ms, b_ms = part_ms("fwdbwd"), part_ms("batch")
+    fb_ms, b_ms, c5_ms = part_ms("fwdbwd"), part_ms("batch"), part_ms("grad")
     fwd_pairs = [c + g for c, g in fwd_parts]
-    step_pairs = sum(fwd_pairs) + 2 * g_pairs + b_circ + b_gen
+    step_pairs = sum(fwd_pairs) + 2 * g_pairs + 2 * c5_pairs + b_circ + b_gen
     ms_per_step = 1e3 * wall / args.steps
     value = step_pairs / (wall / args.steps) / 1e9
 
     # per-kernel totals; the dominant kernel is the one with the most time
     kern = {}
     for _, k, fl, m in ms:
+        if k == "k_set_knots":      # no pair work of its own
+            continue
         t = kern.setdefault(k, [0.0, 0.0, 0])
         t[0] += fl
         t[1] += m
@@ -243,6 +279,9 @@ def main() -> int:
     kernels = {k: {"launches_per_step": v[2] // args.steps,
                    "avg_launch_ms": round(v[1] / v[2], 4),
                    "tflops": round(v[0] / (v[1] * 1e-3) / 1e12, 2)} for k, v in kern.items()}
+    sk = [m for _, k, _, m in ms if k == "k_set_knots"]
+    kernels["k_set_knots"] = {"launches_per_step": len(sk) // args.steps,
+                              "avg_launch_ms": round(sum(sk) / len(sk), 4)}
 
     if args.copy_calibration:
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev).uniform_()
@@ -468,10 +507,11 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": "step = Nside-2048 fwd at theta_cut 10/15/20' + Nside-2048 fwd+bwd "
-                        "(15', 256 knots) + 16-map batch (Nside 256-2048, FWHM 5-30', 3 FWHM "
-                        "cut) replayed from captured graphs; white-noise FP32 maps",
+                        "(15', 256 knots) + Nside-1024 x 8 fwd+bwd (30', 256 knots; knots "
+                        "bound before each pass) + 16-map batch (Nside 256-2048, FWHM 5-30', "
+                        "3 FWHM cut) replayed from captured graphs; white-noise FP32 maps",
             "pairs_per_step": int(step_pairs),
-            "maps_per_step": len(fwd_plans) + 1 + len(bplans),
+            "maps_per_step": len(fwd_plans) + 1 + c5.nbatch + len(bplans),
         },
         "breakdown": {
             "fwd": {"theta_cut_arcmin": [10, 15, 20], "ms": [round(m, 4) for m in fwd_ms],
@@ -481,6 +521,12 @@ def main() -> int:
             "fwdbwd": {"ms": round(fb_ms, 4), "pairs": 2 * g_pairs,
                        "gpair_per_s": round(2 * g_pairs / (fb_ms * 1e-3) / 1e9, 2),
                        "maps_per_s": round(1e3 / fb_ms, 1)},
+            "grad_nside1024x8": {"ms": round(c5_ms, 4), "pairs": 2 * c5_pairs,
+                                 "gpair_per_s": round(2 * c5_pairs / (c5_ms * 1e-3) / 1e9, 2),
+                                 "maps_per_s": round(c5.nbatch * 1e3 / c5_ms, 1)},
+            "tiles": {"tuned_plans": sum(1 for p in fwd_plans + [gplan, c5plan] + bplans
+                                         if p.info()["tile_source"] == 1),
+                      "plans": len(fwd_plans) + 2 + len(bplans)},
             "batch": {"ms": round(b_ms, 4), "pairs": int(b_circ + b_gen),
                       "gpair_per_s": round((b_circ + b_gen) / (b_ms * 1e-3) / 1e9, 2),
                       "maps_per_s": round(16e3 / b_ms, 1),

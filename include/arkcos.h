@@ -65,6 +65,28 @@ enum {
  * (16 MiB: two queue counters, then the knot-gradient partial rows). */
 #define ARKCOS_STATIC_SCRATCH_BYTES (16u << 20)
 
+/*
+ * Tile shapes of the general gather (polar caps and belt rings near them).  A
+ * tile is a segment of gen_pixels pixels of one northern ring (of the first
+ * half-quadrant; each pixel stands for its sixteen symmetric images), or the
+ * same segment of two or four adjacent rings, which then share each staged
+ * chunk of a source ring.  A ring whose widest source window is at most
+ * gen_quad_window positions may go four to a tile, one at most
+ * gen_pair_window positions two to a tile; the 512 lanes of a tile are split
+ * evenly over its rings and the pixels of each ring.  Each field: 0 = the
+ * tuned value from the tuning cache (arkcos_set_tune_cache), else the built-in
+ * default (128, 64, 200); otherwise gen_pixels is 16, 32, 64 or 128 and a
+ * window threshold is -1 (never) or 1 .. 1000000 positions (else EINVAL).
+ * The circulant gather's tiles (4 rings x 1024 pixels) are fixed by its
+ * register layout.
+ */
+typedef struct {
+    int gen_pixels;
+    int gen_quad_window;
+    int gen_pair_window;
+    int reserved;         /* must be 0 */
+} arkcos_tiles;
+
 typedef struct {
     int nside;            /* HEALPix resolution, 1 .. ARKCOS_MAX_NSIDE (any integer)       */
     double theta_cut;     /* radians, 0 < theta_cut <= pi                                 */
@@ -73,11 +95,7 @@ typedef struct {
                              caller keeps ownership).  NULL only with ARKCOS_PLAN_LEARNABLE,
                              in which case knots must be set before the first convolve */
     int max_batch;        /* largest nbatch a call may pass (>= 1); sizes the workspace  */
-    int tile;             /* tile-size hint: 0, or 64 .. 4096 and a multiple of 64
-                             (else EINVAL).  Reported back in info; the gathers'
-                             tile shapes are fixed by their register layouts
-                             (1024-pixel circulant segments, 128-pixel general
-                             tiles), so the hint does not change them            */
+    arkcos_tiles tiles;   /* general-gather tile shapes; all 0 = tuned or default     */
     unsigned flags;       /* ARKCOS_PLAN_* bits                                         */
     /* Node grid.  theta_break = 0 and k_break = 0: uniform nodes
      * theta_k = k theta_cut/(ntab-1).  Otherwise the two-piece table of the
@@ -113,7 +131,9 @@ typedef struct {
     long long candidates;          /* window pixels the kernels visit per map           */
     double omega;                  /* 4 pi / Npix                                       */
     int ntab;
-    int tile;
+    arkcos_tiles tile_shapes;      /* general-gather tiles in use (every field resolved) */
+    int tile_source;               /* where they came from: 0 built-in defaults, 1 the
+                                      tuning cache, 2 the descriptor (any field)        */
     unsigned flags;
     int threads_per_block;
     long long device_bytes;        /* device memory the plan holds                      */
@@ -228,6 +248,15 @@ int arkcos_plan_pair_count_parts(arkcos_plan_t plan, unsigned long long *circula
  */
 int arkcos_plan_window(arkcos_plan_t plan, int ring_out, int ring_src, int j, int *lo,
                        int *hi, int *covered);
+
+/*
+ * The general gather's tiles, for tests of the tiling: one record of five ints
+ * (tile index, rings in the tile, ring (1-based, northern), first pixel, pixel
+ * count) per ring of each tile, over pixels j <= n/4 - 2o - j of the ring's
+ * first quadrant.  Writes min(cap, total) records to `out` (host, 5 ints each;
+ * may be NULL with cap 0) and the total to *count.  Host only.
+ */
+int arkcos_plan_gen_tiles(arkcos_plan_t plan, int *out, long long cap, long long *count);
 
 /*
  * Replace the node table from host FP64 values (length ntab).  The device copy
@@ -345,6 +374,46 @@ int arkcos_batch_convolve_part(arkcos_batch_t batch, const float *const *d_in,
 
 /* Release a batch (not its plans).  NULL is accepted. */
 int arkcos_batch_destroy(arkcos_batch_t batch);
+
+/* ---------------------------------------------------------- autotuning -- */
+
+/*
+ * Tile autotuning.  The best general-gather tiles depend on the device, on
+ * Nside and on the disc radius in pixels, which sets the source windows; the
+ * tuning cache is a text file with one line per (arch, Nside, window class):
+ *     <arch> <nside> <class> <gen_pixels> <gen_quad_window> <gen_pair_window> <ms>
+ * ('#' starts a comment; a later line for the same key wins).  The window
+ * class is round(2 log2(theta_cut / sqrt(Omega))), Omega = 4 pi / Npix.
+ *
+ * arkcos_set_tune_cache: the cache that plans with all-zero tiles read at
+ * creation (copied; NULL or "" = none).  Until it is called the environment
+ * variable ARKCOS_TUNE_CACHE names it.  Process-wide.
+ */
+int arkcos_set_tune_cache(const char *path);
+
+/*
+ * The cache key of a descriptor: arch (the current device's gfx name, or the
+ * library's build target gfx950 without a device), Nside and window class.
+ *   arch  host buffer of len bytes, NUL-terminated on return (may be NULL)  [out]
+ * EINVAL on a bad nside / theta_cut.
+ */
+int arkcos_tune_key(int nside, double theta_cut, char *arch, int len, int *window_class);
+
+/*
+ * Autotune the general-gather tiles of a descriptor on the current device:
+ * builds the plan once (with desc->ktab, or a flat table if it is NULL),
+ * allocates an input and an output map, and times the general gather (median
+ * of reps >= 1 launches after a warm-up) over candidate tiles by coordinate
+ * descent: gen_pixels in {32, 64, 128}, gen_quad_window in {-1, 32, 64, 96,
+ * 128}, gen_pair_window in {-1, 100, 200, 400, 800}.  Fields of desc->tiles
+ * that are non-zero stay fixed.  The best tiles and their time go to *best
+ * and *best_ms, the built-in defaults' time to *default_ms (either pointer may
+ * be NULL), and, if cache_path is non-NULL, a line is appended to that file.
+ * Synchronous; allocates device memory.  Errors as arkcos_plan_create, EDEVICE
+ * on timing failures, EINVAL if the cache file cannot be written.
+ */
+int arkcos_tune(const arkcos_plan_desc *desc, int reps, const char *cache_path,
+                arkcos_tiles *best, double *best_ms, double *default_ms);
 
 /* ----------------------------------------------------------- diagnostics -- */
 

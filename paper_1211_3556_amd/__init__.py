@@ -24,12 +24,13 @@ import numpy as np
 
 __all__ = ["ArkcosError", "Plan", "Batch", "Harm", "split_convolve", "ArkcosConvFn", "conv",
            "tabulate_legendre",
-           "tabulate_legendre_at", "grid_nodes", "paper_bias", "ring_info", "gaussian_bl", "library_path", "load_library", "PLAN_HOST_ONLY",
+           "tabulate_legendre_at", "grid_nodes", "paper_bias", "tune", "tune_key", "set_tune_cache", "ring_info", "gaussian_bl", "library_path", "load_library", "PLAN_HOST_ONLY",
            "PLAN_LEARNABLE", "PART_CIRCULANT", "PART_GENERAL", "PART_ALL", "MAX_GRAD_NTAB",
            "MAX_NSIDE"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "libarkcos.so")
+_TUNE_CACHE = os.path.join(_HERE, "tiles_gfx950.txt")
 
 PLAN_HOST_ONLY = 1
 PLAN_LEARNABLE = 2
@@ -52,10 +53,33 @@ class ArkcosError(RuntimeError):
         super().__init__("%s failed: %s (%s)" % (fn, _STATUS.get(status, status), detail))
 
 
+class _Tiles(ctypes.Structure):
+    _fields_ = [("gen_pixels", ctypes.c_int), ("gen_quad_window", ctypes.c_int),
+                ("gen_pair_window", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+    def as_dict(self) -> dict:
+        return {"gen_pixels": self.gen_pixels, "gen_quad_window": self.gen_quad_window,
+                "gen_pair_window": self.gen_pair_window}
+
+
+def _tiles(tiles) -> _Tiles:
+    """arkcos_tiles from None (all 0: tuned or default) or a dict with any of
+    gen_pixels, gen_quad_window, gen_pair_window."""
+    if tiles is None:
+        return _Tiles(0, 0, 0, 0)
+    if isinstance(tiles, _Tiles):
+        return tiles
+    unknown = set(tiles) - {"gen_pixels", "gen_quad_window", "gen_pair_window"}
+    if unknown:
+        raise ValueError("unknown tile fields %s" % sorted(unknown))
+    return _Tiles(int(tiles.get("gen_pixels", 0)), int(tiles.get("gen_quad_window", 0)),
+                  int(tiles.get("gen_pair_window", 0)), 0)
+
+
 class _PlanDesc(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int), ("theta_cut", ctypes.c_double), ("ntab", ctypes.c_int),
                 ("ktab", ctypes.POINTER(ctypes.c_double)), ("max_batch", ctypes.c_int),
-                ("tile", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("tiles", _Tiles), ("flags", ctypes.c_uint),
                 ("theta_break", ctypes.c_double), ("k_break", ctypes.c_int),
                 ("ring_first", ctypes.c_int), ("ring_last", ctypes.c_int)]
 
@@ -64,7 +88,8 @@ class _PlanInfo(ctypes.Structure):
     _fields_ = [("nside", ctypes.c_int), ("nrings", ctypes.c_int), ("npix", ctypes.c_longlong),
                 ("ring_pairs", ctypes.c_longlong), ("tiles", ctypes.c_longlong),
                 ("candidates", ctypes.c_longlong), ("omega", ctypes.c_double),
-                ("ntab", ctypes.c_int), ("tile", ctypes.c_int), ("flags", ctypes.c_uint),
+                ("ntab", ctypes.c_int), ("tile_shapes", _Tiles), ("tile_source", ctypes.c_int),
+                ("flags", ctypes.c_uint),
                 ("threads_per_block", ctypes.c_int), ("device_bytes", ctypes.c_longlong),
                 ("circulant_rings", ctypes.c_int), ("general_rings", ctypes.c_int),
                 ("circulant_tiles", ctypes.c_longlong), ("general_tiles", ctypes.c_longlong),
@@ -104,6 +129,7 @@ def load_library():
         "arkcos_plan_pair_count": [_vp, ctypes.POINTER(ctypes.c_ulonglong)],
         "arkcos_plan_window": [_vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, _ip, _ip, _ip],
         "arkcos_plan_set_kernel_host": [_vp, _dp],
+        "arkcos_plan_gen_tiles": [_vp, _ip, ctypes.c_longlong, ctypes.POINTER(ctypes.c_longlong)],
         "arkcos_plan_set_kernel": [_vp, _vp, _vp],
         "arkcos_convolve": [_vp, _vp, _vp, ctypes.c_int, _vp],
         "arkcos_convolve_part": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
@@ -123,6 +149,10 @@ def load_library():
                                  ctypes.POINTER(ctypes.c_longlong)],
         "arkcos_harm_convolve": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_int, _vp],
         "arkcos_split_convolve": [_vp, _vp, _vp, _vp, ctypes.c_int, _vp],
+        "arkcos_set_tune_cache": [ctypes.c_char_p],
+        "arkcos_tune_key": [ctypes.c_int, ctypes.c_double, ctypes.c_char_p, ctypes.c_int, _ip],
+        "arkcos_tune": [ctypes.POINTER(_PlanDesc), ctypes.c_int, ctypes.c_char_p,
+                        ctypes.POINTER(_Tiles), _dp, _dp],
         "arkcos_status_string": [ctypes.c_int],
         "arkcos_last_error": [],
         "arkcos_version": [],
@@ -132,6 +162,10 @@ def load_library():
         fn.argtypes = args
         fn.restype = ctypes.c_char_p if name in ("arkcos_status_string", "arkcos_last_error") \
             else ctypes.c_int
+    # plans with all-zero tiles read the tuning cache: ARKCOS_TUNE_CACHE if set,
+    # else the cache measured for this package's target
+    if "ARKCOS_TUNE_CACHE" not in os.environ and os.path.exists(_TUNE_CACHE):
+        lib.arkcos_set_tune_cache(_TUNE_CACHE.encode())
     _lib = lib
     return lib
 
@@ -213,6 +247,37 @@ def ring_info(nside: int, ring: int) -> dict:
     return {"z": z.value, "sin_theta": s.value, "n": n.value, "first": f.value, "phi0": p0.value}
 
 
+def set_tune_cache(path) -> None:
+    """Tuning cache read by plans created with all-zero tiles (None: none)."""
+    _call("arkcos_set_tune_cache", None if path is None else str(path).encode())
+
+
+def tune_key(nside: int, theta_cut: float) -> tuple[str, int]:
+    """(arch, window class) of the tuning-cache key of (nside, theta_cut)."""
+    buf = ctypes.create_string_buffer(64)
+    cls = ctypes.c_int()
+    _call("arkcos_tune_key", int(nside), float(theta_cut), buf, 64, ctypes.byref(cls))
+    return buf.value.decode(), cls.value
+
+
+def tune(nside: int, theta_cut: float, ntab: int, ktab=None, reps: int = 5, cache=None,
+         tiles=None, theta_break: float = 0.0, k_break: int = 0, rings=None) -> dict:
+    """Autotune the general-gather tiles of a plan on the current device
+    (arkcos_tune); appends the result to ``cache`` if given.  Returns the best
+    tiles with their time and the defaults' time (ms per launch)."""
+    k = None if ktab is None else np.ascontiguousarray(ktab, dtype=np.float64)
+    desc = _PlanDesc(int(nside), float(theta_cut), int(ntab),
+                     k.ctypes.data_as(_dp) if k is not None else None, 1, _tiles(tiles),
+                     PLAN_LEARNABLE if k is None else 0, float(theta_break), int(k_break),
+                     *((0, 0) if rings is None else (int(rings[0]), int(rings[1]))))
+    best = _Tiles()
+    bms, dms = ctypes.c_double(), ctypes.c_double()
+    _call("arkcos_tune", ctypes.byref(desc), int(reps),
+          None if cache is None else str(cache).encode(), ctypes.byref(best), ctypes.byref(bms),
+          ctypes.byref(dms))
+    return {"tiles": best.as_dict(), "ms": bms.value, "default_ms": dms.value}
+
+
 class Plan:
     """A plan for one (Nside, theta_cut, node table) on the current device.
 
@@ -222,10 +287,12 @@ class Plan:
     ``grid_nodes`` and ``paper_bias``); ``biased=True`` is the Sec. 3 bias.
     ``rings=(first, last)`` (1-based, inclusive) restricts the output to a
     ring range (partial sky); other output pixels are left untouched.
+    ``tiles`` (a dict of arkcos_tiles fields) fixes general-gather tile
+    shapes; by default they come from the tuning cache (see ``tune``).
     """
 
     def __init__(self, nside: int, theta_cut: float, ktab=None, ntab: int | None = None,
-                 max_batch: int = 1, tile: int = 0, learnable: bool = False,
+                 max_batch: int = 1, tiles=None, learnable: bool = False,
                  host_only: bool = False, theta_break: float = 0.0, k_break: int = 0,
                  biased: bool = False, rings=None):
         if ktab is not None:
@@ -242,7 +309,7 @@ class Plan:
         flags = (PLAN_LEARNABLE if learnable else 0) | (PLAN_HOST_ONLY if host_only else 0)
         desc = _PlanDesc(int(nside), float(theta_cut), int(ntab),
                          ktab.ctypes.data_as(_dp) if ktab is not None else None,
-                         int(max_batch), int(tile), flags, float(theta_break), int(k_break),
+                         int(max_batch), _tiles(tiles), flags, float(theta_break), int(k_break),
                          *((0, 0) if rings is None else (int(rings[0]), int(rings[1]))))
         h = _vp()
         _call("arkcos_plan_create", ctypes.byref(desc), ctypes.byref(h))
@@ -277,7 +344,9 @@ class Plan:
     def info(self) -> dict:
         inf = _PlanInfo()
         _call("arkcos_plan_get_info", self._h, ctypes.byref(inf))
-        return {k: getattr(inf, k) for k, _ in _PlanInfo._fields_}
+        d = {k: getattr(inf, k) for k, _ in _PlanInfo._fields_}
+        d["tile_shapes"] = inf.tile_shapes.as_dict()
+        return d
 
     def nodes(self) -> np.ndarray:
         """Node angles of the plan's table."""
@@ -293,6 +362,14 @@ class Plan:
         c, g = ctypes.c_ulonglong(), ctypes.c_ulonglong()
         _call("arkcos_plan_pair_count_parts", self._h, ctypes.byref(c), ctypes.byref(g))
         return int(c.value), int(g.value)
+
+    def gen_tiles(self) -> np.ndarray:
+        """General-gather tiles: rows (tile, rings in tile, ring, first pixel, pixels)."""
+        n = ctypes.c_longlong()
+        _call("arkcos_plan_gen_tiles", self._h, None, 0, ctypes.byref(n))
+        out = np.zeros((max(n.value, 1), 5), dtype=np.int32)
+        _call("arkcos_plan_gen_tiles", self._h, out.ctypes.data_as(_ip), n.value, ctypes.byref(n))
+        return out[:n.value]
 
     def window(self, ring_out: int, ring_src: int, j: int):
         lo, hi, cov = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()

@@ -130,11 +130,14 @@ constexpr int kGroupRings = 4;
 constexpr int kCircPix = 4;
 constexpr int kCircSeg = kThreads * kCircPix;
 constexpr int kCircMaxTaps = 256;   // wider rows make their rings general
-constexpr int kGenLanes = 128;       // pixels per general tile
+constexpr int kGenLanes = 128;       // most pixels of one ring per general tile
 constexpr int kGenThreads = 512;     // general-gather workgroup: kGenPhases lanes per pixel
 constexpr int kGenPhases = kGenThreads / kGenLanes;
-constexpr double kGenPairMaxWindow = 200.0;  // widest row window (positions) of a paired ring
-constexpr double kGenQuadMaxWindow = 64.0;   // ... of a ring in a tile of four
+// Built-in general-gather tile shapes (arkcos_tiles): pixels per ring, and the
+// widest row window (positions) of a ring in a tile of four / of two rings.
+constexpr int kGenPixelsDefault = 128;
+constexpr int kGenQuadWindowDefault = 64;
+constexpr int kGenPairWindowDefault = 200;
 constexpr int kGenStage = 248;       // with a 16384-node table two workgroups fit a CU
 constexpr int kMaxMaps = 32;
 // Circulant knot-gradient tiles: kKnotSeg pixels of a ring group, split into
@@ -245,7 +248,6 @@ struct Plan {
     int nrings = 0;
     long long npix = 0;
     double omega = 0.0;
-    int tile = 0;
     int threads = 0;
     bool host_only = false;
     bool knots_set = false;
@@ -261,7 +263,14 @@ struct Plan {
     std::vector<DevTile> gtiles;      // general tiles, longest first
     std::vector<DevTile> kctiles;     // circulant knot-gradient tiles, longest first
     std::vector<double> ctile_cost, gtile_cost, gtile2_cost;
-    std::vector<DevTile2> gtiles2;    // general tiles of ring pairs, longest first
+    std::vector<DevTile2> gtiles2;    // general-gather tiles (1, 2 or 4 rings), longest first
+    arkcos_tiles tiles{};             // resolved general-gather tile shapes
+    int tile_source = 0;              // 0 defaults, 1 tuning cache, 2 descriptor
+    // the general northern rings in order, for the general-gather tiling:
+    // ring, pixels of its half-quadrant, tile flags, widest row window
+    std::vector<int> gen_ring, gen_lanes, gen_flags;
+    std::vector<double> gen_wmax;
+    std::vector<double> ring_cost;    // candidates per output pixel of each ring
     long long nweights = 0;
     int max_taps = 0;
     std::vector<double> ktab;         // current host copy (FP64), if known
@@ -334,6 +343,14 @@ int launch_build_weights(const Plan &p, hipStream_t s);
 int launch_build_knotw(const Plan &p, hipStream_t s);
 int device_lds_limit(int device, size_t *bytes);
 int prepare_launches(Plan &p);   // occupancy of every kernel variant, grid sizes
+// General-gather tiles of a built plan from P.tiles (plan.hip).
+void build_gen_tiles(Plan &P);
+// Replace the device copy of the general-gather tiles (and the plan view).
+int upload_gen_tiles(Plan &P);
+// Resolve the tile shapes of a descriptor: descriptor fields, else the tuning
+// cache, else the defaults (tune.hip); EINVAL on invalid fields.
+int resolve_tiles(const arkcos_plan_desc &d, arkcos_tiles *out, int *source);
+int check_tiles(const arkcos_tiles &t);
 int prepare_batch(Batch &b);
 int forward_threads();
 int batch_max_maps();

@@ -190,6 +190,72 @@ static void sort_by_cost(std::vector<Tile> &tiles, std::vector<double> &cost)
     cost.swap(c2);
 }
 
+// The general gather's tiles: adjacent general rings with narrow windows in
+// groups of four (one lane per pixel at full length) or two (two lanes per
+// pixel), each group over the same half-quadrant segments (tiles.gen_pixels
+// pixels of each ring), so that a staged source row serves the whole group;
+// rings with a very wide window, whose time is the loop's LDS reads, keep a
+// tile of their own with more lanes per pixel, whose staged reads share more
+// addresses.  Built from the general rings recorded by build_plan, so the
+// tuner can re-tile a plan without rebuilding it.
+void build_gen_tiles(Plan &P)
+{
+    const int seg = P.tiles.gen_pixels;
+    const double quad_max = P.tiles.gen_quad_window;   // -1: never
+    const double pair_max = P.tiles.gen_pair_window;
+    const std::vector<int> &gring = P.gen_ring, &glanes = P.gen_lanes, &gflags = P.gen_flags;
+    std::vector<int> gwide(gring.size());
+    for (size_t g = 0; g < gring.size(); ++g) {
+        const double w = P.gen_wmax[g];
+        gwide[g] = (pair_max < 0 || w > pair_max) ? 2 : ((quad_max < 0 || w > quad_max) ? 1 : 0);
+    }
+    P.gtiles2.clear();
+    std::vector<double> cost;
+    auto run_of = [&](size_t g, int n, int widest) {
+        if (g + n > gring.size()) return false;
+        for (int i = 0; i < n; ++i) {
+            if (gwide[g + i] > widest) return false;
+            if (i > 0 && gring[g + i] != gring[g + i - 1] + 1) return false;
+        }
+        return true;
+    };
+    for (size_t g = 0; g < gring.size();) {
+        const int nr = run_of(g, 4, 0) ? 4 : (run_of(g, 2, 1) ? 2 : 1);
+        int lanes = 0;
+        for (int i = 0; i < nr; ++i) lanes = std::max(lanes, glanes[g + i]);
+        for (int j0 = 0; j0 < lanes; j0 += seg) {
+            DevTile2 t{};
+            double c = 1.0;
+            t.nr = nr;
+            t.j0 = j0;
+            t.s_first = 0x7fffffff;
+            t.s_last = -1;
+            for (int h = 0; h < kGenMaxRings; ++h) {
+                GenRing &q = t.q[h];
+                q.r = h < nr ? gring[g + h] : gring[g];
+                q.len = h < nr ? std::max(0, std::min(seg, glanes[g + h] - j0)) : 0;
+                q.flags = h < nr ? gflags[g + h] : 0;
+                q.s_lo = 0;
+                q.s_hi = -1;
+                if (q.len > 0) {
+                    const DevRing &dr = P.dev_rings[q.r];
+                    q.pb = dr.pair_begin;
+                    q.s_lo = P.pairs[dr.pair_begin].s;
+                    q.s_hi = P.pairs[dr.pair_end - 1].s;
+                    t.s_first = std::min(t.s_first, q.s_lo);
+                    t.s_last = std::max(t.s_last, q.s_hi);
+                    c += P.ring_cost[q.r] * q.len;
+                }
+            }
+            P.gtiles2.push_back(t);
+            cost.push_back(c);
+        }
+        g += nr;
+    }
+    sort_by_cost(P.gtiles2, cost);
+    P.gtile2_cost = cost;
+}
+
 static int build_plan(Plan &P)
 {
     const int N = P.nside;
@@ -205,7 +271,8 @@ static int build_plan(Plan &P)
     P.pairs.clear();
     P.pairs_d.clear();
     P.candidates = 0;
-    std::vector<double> ring_cost(P.nrings, 0.0);
+    std::vector<double> &ring_cost = P.ring_cost;
+    ring_cost.assign(P.nrings, 0.0);
     for (int r = 0; r < P.nrings; ++r) {
         const HostRing &R = P.rings[r];
         DevRing &dr = P.dev_rings[r];
@@ -366,7 +433,10 @@ static int build_plan(Plan &P)
     // test hook: every general tile takes the int32 numerator path
     const char *fim = getenv("ARKCOS_FORCE_INT_NUMERATOR");
     const bool force_int_m = fim && std::string(fim) == "1";
-    std::vector<int> gring, glanes, gflags, gwide;   // the general northern rings, in order
+    P.gen_ring.clear();
+    P.gen_lanes.clear();
+    P.gen_flags.clear();
+    P.gen_wmax.clear();
     for (int r = 0; r <= P.nrings - 1 - r; ++r) {
         if (!general[r]) continue;
         const int rm = P.nrings - 1 - r;
@@ -400,65 +470,14 @@ static int build_plan(Plan &P)
             const DevPair &pp = P.pairs[k];
             wmax = std::max(wmax, (pp.mode & kPairWhole) ? (double)P.rings[pp.s].n : 2.0 * pp.w + 1.0);
         }
-        gring.push_back(r);
-        glanes.push_back(lanes);
-        gflags.push_back(flags);
-        gwide.push_back(wmax > kGenPairMaxWindow ? 2 : (wmax > kGenQuadMaxWindow ? 1 : 0));
+        P.gen_ring.push_back(r);
+        P.gen_lanes.push_back(lanes);
+        P.gen_flags.push_back(flags);
+        P.gen_wmax.push_back(wmax);
     }
     sort_by_cost(P.gtiles, cost);
     P.gtile_cost = cost;
-
-    // The general gather's tiles: adjacent general rings with narrow windows
-    // in groups of four (one lane per pixel) or two (two lanes per pixel),
-    // each group over the same half-quadrant segments (kGenLanes pixels of
-    // each ring), so that a staged source row serves the whole group; rings
-    // with a very wide window, whose time is the loop's LDS reads, keep four
-    // lanes per pixel, whose staged reads share more addresses.
-    P.gtiles2.clear();
-    cost.clear();
-    auto run_of = [&](size_t g, int n, int widest) {
-        if (g + n > gring.size()) return false;
-        for (int i = 0; i < n; ++i) {
-            if (gwide[g + i] > widest) return false;
-            if (i > 0 && gring[g + i] != gring[g + i - 1] + 1) return false;
-        }
-        return true;
-    };
-    for (size_t g = 0; g < gring.size();) {
-        const int nr = run_of(g, 4, 0) ? 4 : (run_of(g, 2, 1) ? 2 : 1);
-        int lanes = 0;
-        for (int i = 0; i < nr; ++i) lanes = std::max(lanes, glanes[g + i]);
-        for (int j0 = 0; j0 < lanes; j0 += kGenLanes) {
-            DevTile2 t{};
-            double c = 1.0;
-            t.nr = nr;
-            t.j0 = j0;
-            t.s_first = 0x7fffffff;
-            t.s_last = -1;
-            for (int h = 0; h < kGenMaxRings; ++h) {
-                GenRing &q = t.q[h];
-                q.r = h < nr ? gring[g + h] : gring[g];
-                q.len = h < nr ? std::max(0, std::min(kGenLanes, glanes[g + h] - j0)) : 0;
-                q.flags = h < nr ? gflags[g + h] : 0;
-                q.s_lo = 0;
-                q.s_hi = -1;
-                if (q.len > 0) {
-                    const DevRing &dr = P.dev_rings[q.r];
-                    q.pb = dr.pair_begin;
-                    q.s_lo = P.pairs[dr.pair_begin].s;
-                    q.s_hi = P.pairs[dr.pair_end - 1].s;
-                    t.s_first = std::min(t.s_first, q.s_lo);
-                    t.s_last = std::max(t.s_last, q.s_hi);
-                    c += ring_cost[q.r] * q.len;
-                }
-            }
-            P.gtiles2.push_back(t);
-            cost.push_back(c);
-        }
-        g += nr;
-    }
-    sort_by_cost(P.gtiles2, cost);
-    P.gtile2_cost = cost;
+    build_gen_tiles(P);
 
     // Circulant knot-gradient tiles: kKnotSeg consecutive pixels of every
     // ring of a group.
@@ -654,6 +673,17 @@ static int upload(T **dst, const std::vector<T> &src, long long *bytes)
     return ARKCOS_OK;
 }
 
+int upload_gen_tiles(Plan &P)
+{
+    (void)hipFree(P.d_gtiles2);
+    P.d_gtiles2 = nullptr;
+    int rc = upload(&P.d_gtiles2, P.gtiles2, &P.device_bytes);
+    if (rc) return rc;
+    const DevPlanView v = P.view();
+    ARKCOS_HIP_CHECK(hipMemcpy(P.d_view, &v, sizeof(v), hipMemcpyHostToDevice));
+    return ARKCOS_OK;
+}
+
 static int write_table_host(Plan &P)
 {
     std::vector<float> t(P.desc.ntab);
@@ -810,8 +840,7 @@ int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
         return fail(ARKCOS_EINVAL, "theta_cut must lie in (0, pi]");
     if (desc->ntab < 2) return fail(ARKCOS_EINVAL, "ntab must be >= 2");
     if (desc->max_batch < 1) return fail(ARKCOS_EINVAL, "max_batch must be >= 1");
-    if (desc->tile != 0 && (desc->tile < 64 || desc->tile > 4096 || desc->tile % 64 != 0))
-        return fail(ARKCOS_EINVAL, "tile must be 0 or a multiple of 64 in 64..4096");
+    if (int rc = check_tiles(desc->tiles)) return rc;
     if (!desc->ktab && !(desc->flags & ARKCOS_PLAN_LEARNABLE))
         return fail(ARKCOS_EINVAL, "ktab may be NULL only for a learnable plan");
     if (desc->flags & ~(ARKCOS_PLAN_HOST_ONLY | ARKCOS_PLAN_LEARNABLE))
@@ -835,7 +864,10 @@ int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
     P->nrings = 4 * desc->nside - 1;
     P->npix = npix;
     P->omega = 4.0 * M_PI / (double)npix;
-    P->tile = desc->tile ? desc->tile : 256;
+    if (int rc = resolve_tiles(*desc, &P->tiles, &P->tile_source)) {
+        delete P;
+        return rc;
+    }
     P->threads = forward_threads();
     P->host_only = (desc->flags & ARKCOS_PLAN_HOST_ONLY) != 0;
     P->angle_mode = desc->theta_cut <= 0.1 ? 0 : (desc->theta_cut <= 0.5 ? 1 : 2);
@@ -879,7 +911,8 @@ int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info)
     info->candidates = P->candidates;
     info->omega = P->omega;
     info->ntab = P->desc.ntab;
-    info->tile = P->tile;
+    info->tile_shapes = P->tiles;
+    info->tile_source = P->tile_source;
     info->flags = P->desc.flags;
     info->threads_per_block = P->threads;
     info->device_bytes = P->device_bytes;
@@ -944,6 +977,31 @@ int arkcos_plan_window(arkcos_plan_t plan, int ring_out, int ring_src, int j, in
         pair_window(P->pairs[k], P->dev_rings[ring_src - 1].n, j, *lo, *hi);
         *covered = 1;
     }
+    return ARKCOS_OK;
+}
+
+int arkcos_plan_gen_tiles(arkcos_plan_t plan, int *out, long long cap, long long *count)
+{
+    clear_error();
+    if (!plan || !count || (cap > 0 && !out)) return fail(ARKCOS_EINVAL, "NULL pointer");
+    const Plan *P = reinterpret_cast<const Plan *>(plan);
+    long long k = 0;
+    for (size_t t = 0; t < P->gtiles2.size(); ++t) {
+        const DevTile2 &T = P->gtiles2[t];
+        for (int h = 0; h < T.nr; ++h) {
+            if (T.q[h].len <= 0) continue;
+            if (k < cap) {
+                int *o = out + 5 * k;
+                o[0] = (int)t;
+                o[1] = T.nr;
+                o[2] = T.q[h].r + 1;
+                o[3] = T.j0;
+                o[4] = T.q[h].len;
+            }
+            ++k;
+        }
+    }
+    *count = k;
     return ARKCOS_OK;
 }
 

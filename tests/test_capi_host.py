@@ -44,10 +44,12 @@ def test_status_strings_and_version():
     (dict(nside=0), "nside"), (dict(nside=8193), "nside"),
     (dict(theta_cut=0.0), "theta_cut"), (dict(theta_cut=3.2), "theta_cut"),
     (dict(ntab=1, ktab=None), "ntab"), (dict(max_batch=0), "max_batch"),
-    (dict(tile=100), "tile"), (dict(tile=8192), "tile"),
+    (dict(tiles=dict(gen_pixels=100)), "gen_pixels"),
+    (dict(tiles=dict(gen_quad_window=-2)), "window"),
+    (dict(tiles=dict(gen_pair_window=2000000)), "window"),
 ])
 def test_plan_argument_errors(kw, msg):
-    args = dict(nside=8, theta_cut=0.1, ktab=np.ones(16), max_batch=1, tile=0, host_only=True)
+    args = dict(nside=8, theta_cut=0.1, ktab=np.ones(16), max_batch=1, host_only=True)
     args.update(kw)
     if "ntab" in kw:
         args["ktab"] = np.ones(kw["ntab"])
@@ -59,12 +61,12 @@ def test_plan_argument_errors(kw, msg):
 
 def test_null_knots_need_learnable_and_bad_flags():
     lib = A.load_library()
-    desc = A._PlanDesc(8, 0.1, 16, None, 1, 0, 1)
+    desc = A._PlanDesc(8, 0.1, 16, None, 1, A._tiles(None), 1)
     h = ctypes.c_void_p()
     assert lib.arkcos_plan_create(ctypes.byref(desc), ctypes.byref(h)) == -1
     assert b"learnable" in lib.arkcos_last_error()
     assert not h.value
-    desc = A._PlanDesc(8, 0.1, 16, None, 1, 0, 1 | 2 | 64)
+    desc = A._PlanDesc(8, 0.1, 16, None, 1, A._tiles(None), 1 | 2 | 64)
     assert lib.arkcos_plan_create(ctypes.byref(desc), ctypes.byref(h)) == -1
     assert lib.arkcos_plan_create(None, ctypes.byref(h)) == -1
     assert lib.arkcos_plan_create(ctypes.byref(desc), None) == -1
@@ -198,10 +200,12 @@ def test_windows_cover_every_in_disc_pair(nside, tc_deg):
 
 
 def test_plan_info_is_consistent():
-    p = A.Plan(32, np.radians(5.0), np.ones(100), host_only=True, tile=128)
+    p = A.Plan(32, np.radians(5.0), np.ones(100), host_only=True, tiles=dict(gen_pixels=64))
     inf = p.info()
     assert inf["nside"] == 32 and inf["nrings"] == 127 and inf["npix"] == 12288
-    assert inf["tile"] == 128 and inf["ntab"] == 100 and inf["device_bytes"] == 0
+    assert inf["tile_shapes"] == dict(gen_pixels=64, gen_quad_window=64, gen_pair_window=200)
+    assert inf["tile_source"] == 2
+    assert inf["ntab"] == 100 and inf["device_bytes"] == 0
     assert abs(inf["omega"] - 4 * np.pi / 12288) < 1e-18
     assert inf["tiles"] == inf["circulant_tiles"] + inf["general_tiles"]
     assert inf["candidates"] >= p.pair_count()
