@@ -62,8 +62,8 @@ enum {
 /* Largest l_cut of the harmonic-space half (one order's coefficients fit LDS). */
 #define ARKCOS_MAX_LCUT 4095
 /* Bytes of the per-device static workspace of arkcos_convolve_backward_static
- * (16 MiB: two queue counters, then the knot-gradient partial rows). */
-#define ARKCOS_STATIC_SCRATCH_BYTES (16u << 20)
+ * (32 MiB: two queue counters, then the knot-gradient partial rows). */
+#define ARKCOS_STATIC_SCRATCH_BYTES (32u << 20)
 
 /*
  * Tile shapes of the general gather (polar caps and belt rings near them).  A
@@ -333,8 +333,8 @@ int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const 
  * (no hipMalloc, no allocating library routine); its device address is looked
  * up once per device, on the first call there.  EUNSUPPORTED if the plan's
  * knot-gradient partials (one row of ntab FP64 values per resident workgroup
- * of the two knot kernels, at most ~12 MiB for ntab = 2048 on a 256-CU
- * device) exceed the array.  Every call on one device shares its array, so
+ * of the two knot kernels, no more than their work items; 16 MiB for
+ * ntab = 2048 on a 256-CU device) exceed the array.  Every call on one device shares its array, so
  * calls whose work overlaps on a device race and give wrong results: order
  * them on one stream (or synchronise between streams).  The array keeps the
  * last call's contents; everything a call reads from it is first written by

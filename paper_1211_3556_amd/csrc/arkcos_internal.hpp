@@ -140,13 +140,8 @@ constexpr int kGenQuadWindowDefault = 64;
 constexpr int kGenPairWindowDefault = 200;
 constexpr int kGenStage = 248;       // with a 16384-node table two workgroups fit a CU
 constexpr int kMaxMaps = 32;
-// Circulant knot-gradient tiles: kKnotSeg pixels of a ring group, split into
-// sub-segments of kKnotSub; up to kKnotRows source rows and kKnotStage staged
-// floats per batch.
-constexpr int kKnotSeg = 256;
-constexpr int kKnotSub = 64;
-constexpr int kKnotRows = 64;
-constexpr int kKnotStage = 10240;
+// Circulant knot-gradient tiles: kKnotSeg pixels of a ring group.
+constexpr int kKnotSeg = 512;
 
 // A group of up to kGroupRings consecutive belt rings r0 .. r0+nr-1 whose
 // source rings all have the ring's own pixel count: the weight of a pair then

@@ -1097,28 +1097,28 @@ __device__ __forceinline__ void hat_scatter(double *hist, double u, float c)
 //   sum_j g_r[j] sum_k hat(u(r, s, k)) x_s[j + k]
 //     = sum_k hat(u(r, s, k)) C(r, s, k),   C(r, s, k) = sum_j g_r[j] x_s[j + k]:
 // the pair loop becomes a cross-correlation of ring r of g with ring s of x,
-// and each distinct (r, s, k) is binned once.  A tile is kKnotSeg pixels of
-// the kGroupRings rings of a group; its g is staged once as float4 (one
-// value per ring) in strips of kKnotSub pixels, and its source rows are
-// staged in batches, each row as one strip of x per sub-segment.  A unit of
-// work is (row, 4 consecutive taps, sub-segment): 16 FP32 sums of kKnotSub
-// products, scattered with the node coordinates of k_build_knotw.
-constexpr int kKnotSubs = kKnotSeg / kKnotSub;
+// and each distinct (r, s, k) is binned once per tile.  A tile is kKnotSeg
+// pixels of the kGroupRings rings of a group; its g is staged once, as float4
+// (one value per ring).  Each wave takes whole source rows (rows w, w + 4, ...
+// of the group for wave w), so a row needs no workgroup barrier: the wave
+// stages the row's x in its own LDS strip, and its lanes split into tap quads
+// q and pixel strides c.  Lane (q, c) sums g_r[4p + i] x_s[4p + i + 4q + t]
+// over the pixel quads p = c, c + nc, ... into 16 FP32 sums (4 rings x 4
+// taps); two aligned float4 reads of x and four of g feed 64 FMAs, as in the
+// circulant gather.  The nc partial sums of a (ring, tap) are then added in
+// stride order and binned with the FP64 node coordinates of k_build_knotw into
+// the wave's own histogram.
 
-__device__ __forceinline__ int knot_strip(int ntaps4) { return (kKnotSub + ntaps4 - 1) | 1; }
+constexpr int kKnotXW = kKnotSeg + kCircMaxTaps + 8;   // staged x of one row (floats)
 
-// Direct global -> LDS load of one float per active lane: lane l's value
-// lands at dst[l] (dst wave-uniform).  Nothing passes through registers, so
-// a wave can issue all its staging loads back to back and wait once.
-#if defined(__HIP_DEVICE_COMPILE__)
-__device__ __forceinline__ void load_to_lds(const float *src, float *dst)
+// Orders a wave's LDS stores before its later LDS loads (the hardware keeps a
+// wave's LDS operations in order; this keeps the compiler from moving them).
+__device__ __forceinline__ void wave_lds_order()
 {
-    __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)src,
-                                     (__attribute__((address_space(3))) void *)dst, 4, 0, 0);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
-#else
-__device__ __forceinline__ void load_to_lds(const float *, float *) {}
-#endif
 
 __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__restrict__ views,
                                                         const float *__restrict__ g,
@@ -1126,20 +1126,17 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                                                         double *__restrict__ partials)
 {
     extern __shared__ __align__(16) double hists[];
-    __shared__ int s_rows;                   // rows in the current batch
-    __shared__ int s_uprefix[kKnotRows + 1]; // units before each row of the batch
-    __shared__ int s_xoff[kKnotRows];        // its staged x strips
-    __shared__ int s_woff[kKnotRows];        // its weight-slot offset
-    __shared__ int s_ntaps[kKnotRows];       // and tap count
     const DevPlanView P = cst(views)[0];
     const int hstride = hist_stride(P.ntab);
-    float4 *gs = reinterpret_cast<float4 *>(hists + kKnotWaves * hstride);
-    float *xs = reinterpret_cast<float *>(gs + kKnotSubs * (kKnotSub + 1));
-    for (int i = threadIdx.x; i < kKnotWaves * hstride; i += blockDim.x) hists[i] = 0.0;
-    double *hist = hists + (threadIdx.x >> 6) * hstride;   // this wave's own bins
-    __syncthreads();
+    float4 *gs = reinterpret_cast<float4 *>(hists + kKnotWaves * hstride);   // kKnotSeg
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int lane = (int)threadIdx.x & 63;
+    float *xs = reinterpret_cast<float *>(gs + kKnotSeg) + wave * kKnotXW;
+    float *red = reinterpret_cast<float *>(gs + kKnotSeg) + kKnotWaves * kKnotXW + wave * 64 * 16;
+    for (int i = threadIdx.x; i < kKnotWaves * hstride; i += kThreads) hists[i] = 0.0;
+    double *hist = hists + wave * hstride;   // this wave's own bins
     const int nitems = P.nkctiles * nmaps;
-    // static assignment: the tiles (longest first) are dealt round-robin
+    // static assignment: the tiles are dealt round-robin
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int ti = item / nmaps;
         const int map = item - ti * nmaps;
@@ -1148,149 +1145,95 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
         const int n = cst(P.rings)[G.r0].n;
         const float *in = x + (size_t)map * P.npix;
         const float *gm = g + (size_t)map * P.npix;
-        const int nsub = (T.len + kKnotSub - 1) / kKnotSub;
-        // g of the group's rings over the tile: sub-segment q holds float4
-        // (one value per ring) for its pixels, 64 per q plus a pad entry.
-        // Rings past the group's last and pixels past the tile are left
-        // unset: their sums are never scattered.
-        const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-        int firsts[kGroupRings];      // (uniform) first pixel of each ring of the group
+        const int npq = (T.len + 3) >> 2;     // pixel quads of the tile
+        int firsts[kGroupRings];              // (uniform) first pixel of each ring of the group
 #pragma unroll
         for (int i = 0; i < kGroupRings; ++i)
             firsts[i] = cst(P.rings)[G.r0 + min(i, G.nr - 1)].first + T.j0;
-        for (int c = wave; c < nsub * kGroupRings; c += kThreads / 64) {
-            const int q = c / kGroupRings;            // 64 floats: 16 pixels x 4 rings
-            const int f = (c - q * kGroupRings) * 64 + lane;
-            const int e = q * kKnotSub + (f >> 2);
-            const int i = f & 3;
-            const int fi = i == 0 ? firsts[0] : i == 1 ? firsts[1] : i == 2 ? firsts[2] : firsts[3];
-            if (i < G.nr && e < T.len)
-                load_to_lds(gm + fi + e, reinterpret_cast<float *>(gs + q * (kKnotSub + 1)) + (f - lane));
-        }
-        for (int rb = G.row_begin; rb < G.row_end;) {
-            __syncthreads();   // the previous batch is no longer read
-            if (wave == 0) {
-                // the batch: the longest run of rows from rb whose strips fit
-                // kKnotStage (the first always does), by prefix sums over a wave
-                const int r = rb + lane;
-                int need = 0, units = 0, woff = 0, ntaps = 0;
-                if (r < G.row_end) {
-                    const DevRow W = cst(P.rows)[r];
-                    ntaps = W.ntaps;
-                    woff = W.w_off;
-                    const int nt4 = (ntaps + 3) & ~3;
-                    need = nsub * knot_strip(nt4);
-                    units = (nt4 >> 2) * kKnotSubs;   // (tap quad, sub-segment) pairs
-                }
-                int cneed = need, cunits = units;
+        __syncthreads();   // the previous item no longer reads gs
+        // g of the group's rings over the tile, zero past the tile or the group
+        for (int p = threadIdx.x; p < kKnotSeg; p += kThreads) {
+            float gv[kGroupRings];
 #pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    const int a = __shfl_up(cneed, d);
-                    const int b = __shfl_up(cunits, d);
-                    if (lane >= d) {
-                        cneed += a;
-                        cunits += b;
-                    }
-                }
-                const bool fits = r < G.row_end && (lane == 0 || cneed <= kKnotStage);
-                const int nfit = __popcll(__ballot(fits));   // the whole wave votes
-                if (fits) {   // need > 0, so the fitting rows are a prefix
-                    s_xoff[lane] = cneed - need;
-                    s_uprefix[lane + 1] = cunits;
-                    s_woff[lane] = woff;
-                    s_ntaps[lane] = ntaps;
-                }
-                if (lane == 0) {
-                    s_uprefix[0] = 0;
-                    s_rows = nfit;
-                }
-            }
-            __syncthreads();
-            const int nrows = s_rows;
-            // stage x: row r, sub-segment q, strip position p holds
-            // x_s[j0 + q kKnotSub + k_lo + p] for the positions its units read
-            // (-n < k_lo and k_lo + ntaps + 2 < n/2 + 4, so wrap3 applies).
-            // Waves take 64-float pieces of each row; q = e / strip by a float
-            // reciprocal, exact here: e < 2^11, and (e + 1/2) / strip stays at
-            // least 1 / (2 strip) > 2^-10 away from an integer.
-            for (int rr = 0; rr < nrows; ++rr) {
-                const DevRow W = cst(P.rows)[rb + rr];
-                const int nt4 = (W.ntaps + 3) & ~3;
-                const int strip = knot_strip(nt4);
-                const float inv_strip = 1.0f / (float)strip;
+            for (int i = 0; i < kGroupRings; ++i)
+                gv[i] = (p < T.len && i < G.nr) ? gm[firsts[i] + p] : 0.0f;
+            gs[p] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+        }
+        __syncthreads();
+        for (int row = G.row_begin + wave; row < G.row_end; row += kKnotWaves) {
+            const DevRow W = cst(P.rows)[row];
+            const int nq = (W.ntaps + 3) >> 2;        // tap quads (<= 64)
+            const int nc = 64 / nq;                   // lanes per tap quad
+            // the row's source pixels j0 + k_lo + e, e < nx (-n < k_lo and the
+            // positions stay below 3n, so wrap3 applies)
+            {
+                const int nx = 4 * (npq + nq);
                 const float *src = in + W.first_s;
-                float *dst = xs + s_xoff[rr];
                 const int base = T.j0 + W.k_lo;
-                for (int e0 = wave * 64; e0 < nsub * strip; e0 += kThreads) {
-                    const int e = e0 + lane;
-                    const int q = (int)(((float)e + 0.5f) * inv_strip);
-                    const int p = e - q * strip;
-                    const int used = min(kKnotSub, T.len - q * kKnotSub) + nt4 - 1;
-                    if (e < nsub * strip && p < used)
-                        load_to_lds(src + wrap3(base + q * kKnotSub + p, n), dst + e0);
+                float v[kKnotXW / 64 + 1];
+#pragma unroll
+                for (int u = 0; u < kKnotXW / 64 + 1; ++u) {
+                    const int e = lane + 64 * u;
+                    v[u] = e < nx ? src[wrap3(base + e, n)] : 0.0f;
                 }
+                wave_lds_order();   // the previous row's reads of xs are done
+#pragma unroll
+                for (int u = 0; u < kKnotXW / 64 + 1; ++u) {
+                    const int e = lane + 64 * u;
+                    if (e < kKnotXW) xs[e] = v[u];
+                }
+                wave_lds_order();
             }
-            __builtin_amdgcn_s_waitcnt(0);   // this wave's direct loads have landed
-            __syncthreads();
-            const int nunits = s_uprefix[nrows];
-            for (int u = threadIdx.x; u < nunits; u += blockDim.x) {
-                int rr = 0, rh = nrows - 1;   // last row whose units start at or before u
-                while (rr < rh) {
-                    const int mid = (rr + rh + 1) >> 1;
-                    if (s_uprefix[mid] <= u) rr = mid;
-                    else rh = mid - 1;
-                }
-                const int v = u - s_uprefix[rr];
-                const int tb = v / kKnotSubs;            // tap quad
-                const int q = v - tb * kKnotSubs;        // sub-segment
-                if (q >= nsub) continue;                 // short tile
-                const int ntaps = s_ntaps[rr];
-                const int strip = knot_strip((ntaps + 3) & ~3);
-                const float *xp = xs + s_xoff[rr] + q * strip + 4 * tb;
-                const float4 *gp = gs + q * (kKnotSub + 1);
-                const int len = min(kKnotSub, T.len - q * kKnotSub);
-                // node coordinates of the unit's taps, loaded ahead of the sums
-                // (clamped into the row; taps past it are dropped below)
-                const double *kw = P.kw + s_woff[rr];
-                double uu[4][kGroupRings];
+            const int q = lane / nc;
+            const int c = lane - q * nc;
+            float acc[kGroupRings][4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
+            for (int r = 0; r < kGroupRings; ++r)
 #pragma unroll
-                    for (int i = 0; i < kGroupRings; ++i)
-                        uu[t][i] = kw[min(4 * tb + t, ntaps - 1) * kGroupRings + i];
-                float c[kGroupRings][4];
+                for (int t = 0; t < 4; ++t) acc[r][t] = 0.0f;
+            if (q < nq) {
+                const float4 *x4 = reinterpret_cast<const float4 *>(xs) + q;
+                for (int p = c; p < npq; p += nc) {
+                    const float4 xa = x4[p];
+                    const float4 xb = x4[p + 1];
+                    const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
 #pragma unroll
-                for (int i = 0; i < kGroupRings; ++i)
+                    for (int i = 0; i < 4; ++i) {
+                        const float4 gq = gs[4 * p + i];
+                        const float gr[kGroupRings] = {gq.x, gq.y, gq.z, gq.w};
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) c[i][t] = 0.0f;
-                float x0 = xp[0], x1 = xp[1], x2 = xp[2];
-#pragma unroll 4
-                for (int e = 0; e < len; ++e) {
-                    const float x3 = xp[e + 3];
-                    const float4 gv = gp[e];
-                    const float gg[kGroupRings] = {gv.x, gv.y, gv.z, gv.w};
+                        for (int t = 0; t < 4; ++t)
 #pragma unroll
-                    for (int i = 0; i < kGroupRings; ++i) {
-                        c[i][0] = fmaf(gg[i], x0, c[i][0]);
-                        c[i][1] = fmaf(gg[i], x1, c[i][1]);
-                        c[i][2] = fmaf(gg[i], x2, c[i][2]);
-                        c[i][3] = fmaf(gg[i], x3, c[i][3]);
+                            for (int r = 0; r < kGroupRings; ++r)
+                                acc[r][t] = fmaf(gr[r], xv[i + t], acc[r][t]);
                     }
-                    x0 = x1;
-                    x1 = x2;
-                    x2 = x3;
-                }
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    if (4 * tb + t >= ntaps) break;
-#pragma unroll
-                    for (int i = 0; i < kGroupRings; ++i)
-                        if (uu[t][i] >= 0.0 && c[i][t] != 0.0f) hat_scatter(hist, uu[t][i], c[i][t]);
                 }
             }
-            rb += nrows;
+            float4 *red4 = reinterpret_cast<float4 *>(red) + 4 * lane;
+#pragma unroll
+            for (int r = 0; r < kGroupRings; ++r)
+                red4[r] = make_float4(acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+            wave_lds_order();
+            // totals of entry o = 4 k + r (tap k, ring r) over the strides, in
+            // stride order, then binned
+            const double *kw = cst(P.kw) + W.w_off;
+            for (int o = lane; o < 4 * W.ntaps; o += 64) {
+                const int k = o >> 2, r = o & 3;
+                const float *src = red + ((k >> 2) * nc) * 16 + r * 4 + (k & 3);
+                float s0 = 0.0f, s1 = 0.0f;
+                int cc = 0;
+                for (; cc + 2 <= nc; cc += 2) {
+                    s0 += src[cc * 16];
+                    s1 += src[(cc + 1) * 16];
+                }
+                if (cc < nc) s0 += src[cc * 16];
+                const float sum = s0 + s1;
+                if (r < G.nr && sum != 0.0f) {
+                    const double u = kw[k * kGroupRings + r];
+                    if (u >= 0.0) hat_scatter(hist, u, sum);
+                }
+            }
         }
-        __syncthreads();   // gs is restaged by the next item
     }
     __syncthreads();
     write_partials(hists, hstride, P.ntab, partials + (size_t)blockIdx.x * P.ntab);
@@ -1299,13 +1242,21 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
 // ------------------------------------------------- general rings: per pair --
 // Candidates T of one lane, as in the general gather: the sixteen products
 // g x of a candidate share its FP64 node coordinate.
+// A lane visits its cnt candidates starting at candidate `skew` and wrapping
+// around: neighbouring pixels, whose candidates at the same step have nearly
+// the same separation, then add into different bins of the wave's histogram
+// at each step instead of contending for one.
 template <bool LONG, int AM>
 __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const NodeMapD &nm,
-                                                  int m, int dm, const float4 *stage, int c0,
-                                                  int cn, int jq, int a1, int T,
+                                                  int m0, int dm, const float4 *stage, int c0,
+                                                  int cn, int jq0, int cnt, int skew, int T,
                                                   const float gv[16], double *hist)
 {
     for (int t = 0; t < T; ++t) {
+        int tt = t + skew;
+        tt = tt >= cnt ? tt - cnt : tt;
+        const int jq = jq0 + 2 * tt;
+        const int m = m0 - __mul24(tt, dm);
         const int pos = min(max(jq - c0, 0), cn - 1);
         const float4 v0 = stage[pos];
         const float4 v1 = stage[kGenStage + pos];
@@ -1327,7 +1278,7 @@ __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const Node
         c = fmaf(gv[13], v3.y, c);
         c = fmaf(gv[14], v3.z, c);
         c = fmaf(gv[15], v3.w, c);
-        if (jq <= a1 && c != 0.0f) {
+        if (t < cnt && c != 0.0f) {
             int node;
             double frac;
             if (pair_node_d<LONG, AM>(pd, nm, m, node, frac)) {
@@ -1335,8 +1286,6 @@ __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const Node
                 atomicAdd(&hist[node + 1], frac * (double)c);
             }
         }
-        jq += 2;
-        m -= dm;
     }
 }
 
@@ -1425,19 +1374,23 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
             pair_window(pp, S.n, j, lo, hi);
             const int a0 = max(lo, ch.c0);
             const int a1 = min(hi, ch.c0 + ch.cn - 1);
-            const int nt = wave_max(max(0, (a1 - a0 + 2 - ph) >> 1));
+            const int cnt = max(0, (a1 - a0 + 2 - ph) >> 1);   // this lane's candidates
+            const int nt = wave_max(cnt);
             const int jq0 = a0 + ph;
+            // start candidate: the pixel's index modulo its count (exact: the
+            // quotient of the float division is never within 1/(2 cnt) of an integer)
+            const int skew = cnt > 0 ? lane_pix - cnt * (int)(((float)lane_pix + 0.5f) / (float)cnt) : 0;
             const unsigned mbase = lon_base(j, R.two_o, S.n);
             const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
             const int dm = 4 * R.n;
             const bool lg = (pp.mode & kPairLongSin) != 0;
             switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                case 0: knot_candidates16<false, 0>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                case 1: knot_candidates16<true, 0>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                case 2: knot_candidates16<false, 1>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                case 3: knot_candidates16<true, 1>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                case 4: knot_candidates16<false, 2>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
-                default: knot_candidates16<true, 2>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, a1, nt, gv, hist); break;
+                case 0: knot_candidates16<false, 0>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                case 1: knot_candidates16<true, 0>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                case 2: knot_candidates16<false, 1>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                case 3: knot_candidates16<true, 1>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                case 4: knot_candidates16<false, 2>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                default: knot_candidates16<true, 2>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
             }
             ch = nx;
         }
@@ -1519,10 +1472,12 @@ static size_t knot_hist_bytes(int ntab)
 {
     return (size_t)kKnotWaves * hist_stride(ntab) * sizeof(double);
 }
+// Per-wave FP64 histograms, the tile's g, and per wave one staged row of x and
+// the partial sums of its lanes.
 static size_t knot_circ_lds(int ntab)
 {
-    return knot_hist_bytes(ntab) + (size_t)kKnotSubs * (kKnotSub + 1) * sizeof(float4) +
-           (size_t)kKnotStage * sizeof(float);
+    return knot_hist_bytes(ntab) + (size_t)kKnotSeg * sizeof(float4) +
+           (size_t)kKnotWaves * (kKnotXW + 64 * 16) * sizeof(float);
 }
 static size_t knot_gen_lds(int ntab)
 {
@@ -1542,9 +1497,13 @@ int prepare_launches(Plan &p)
     if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
         if ((rc = occupancy(k_knot_circ, knot_circ_lds(p.desc.ntab), &p.occ_kc))) return rc;
         if ((rc = occupancy(k_knot_gen, knot_gen_lds(p.desc.ntab), &p.occ_kg))) return rc;
-        // one partial row per resident workgroup of each knot kernel
-        p.grid_kc = p.kctiles.empty() ? 0 : p.occ_kc * p.cus;
-        p.grid_kg = p.gtiles.empty() ? 0 : p.occ_kg * p.cus;
+        // one partial row per resident workgroup of each knot kernel, and no
+        // more workgroups than work items
+        const long long mb = std::max(1, p.desc.max_batch);
+        p.grid_kc = (int)std::min<long long>((long long)p.occ_kc * p.cus,
+                                             (long long)p.kctiles.size() * mb);
+        p.grid_kg = (int)std::min<long long>((long long)p.occ_kg * p.cus,
+                                             (long long)p.gtiles.size() * mb);
     }
     p.grid = std::max(1, p.grid_kc + p.grid_kg);
     return ARKCOS_OK;

@@ -12,11 +12,12 @@ from gpu_util import REL_RMS_TOL, assert_tie_free, log, rel_rms, to_dev, to_host
 pytestmark = pytest.mark.gpu
 
 
-def _case(nside, nb, tc_deg, nk, seed):
+def _case(nside, nb, tc_deg, nk, seed, oracle=True):
     import torch
     import paper_1211_3556_amd as A
     tc = np.radians(tc_deg)
-    assert_tie_free(nside, tc)
+    if oracle:
+        assert_tie_free(nside, tc)
     knots = W.gaussian_profile_knots(tc / 3, tc, nk)
     x = W.white_noise(nside, seed, nbatch=nb)
     g = W.white_noise(nside, seed + 1, nbatch=nb)
@@ -33,6 +34,9 @@ def _case(nside, nb, tc_deg, nk, seed):
     assert np.array_equal(gx_s, gx_p)
     assert np.array_equal(gk_s, gk_p)
     assert np.array_equal(gk_s2, gk_p)
+    if not oracle:
+        plan.close()
+        return
     gk_ref = sum(O.knot_grad(nside, tc, nk, x[b], g[b]) for b in range(nb))
     for b in range(nb):
         assert rel_rms(gx_s[b], O.map_grad(nside, tc, knots, g[b])) <= REL_RMS_TOL
@@ -65,5 +69,8 @@ def test_static_workspace_rejects_what_the_plan_rejects():
 
 
 def test_static_workspace_holds_the_largest_knot_table():
-    # ntab = ARKCOS_MAX_GRAD_NTAB: the partial rows of both knot kernels fit
-    _case(16, 1, 40.3, 2048, 830)
+    # ntab = ARKCOS_MAX_GRAD_NTAB on a map with more knot-gradient tiles than
+    # resident workgroups, so both knot kernels use every partial row they can
+    # (bitwise against the plan workspace; the oracle is too slow at this size)
+    _case(1024, 1, 1.03, 2048, 830, oracle=False)
+    _case(16, 1, 40.3, 2048, 840)
