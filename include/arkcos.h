@@ -116,8 +116,12 @@ typedef struct {
      * rings ring_first..ring_last (1-based, inclusive, within 1..4 Nside-1,
      * else EINVAL) are written, the other output pixels are left untouched,
      * and the cost scales with the range.  Input pixels are read wherever
-     * they lie within theta_cut of the range.  Such plans support the forward
-     * and batched calls; arkcos_convolve_backward returns EUNSUPPORTED.       */
+     * they lie within theta_cut of the range.  The adjoint of such a plan
+     * takes dL/d(out) on the range only (values outside it are ignored): its
+     * map gradient is nonzero on the rings within theta_cut of the range
+     * (arkcos_plan_info.adjoint_ring_*) and zero elsewhere, and its knot
+     * gradient sums over the range's output pixels.  The plan holds a second,
+     * internal plan for the adjoint.                                          */
     int ring_first;
     int ring_last;
 } arkcos_plan_desc;
@@ -146,6 +150,8 @@ typedef struct {
     int k_break;
     int ring_first;                /* output ring range of the descriptor (0, 0: all)   */
     int ring_last;
+    int adjoint_ring_first;        /* ring-range plans: rings the adjoint writes, every */
+    int adjoint_ring_last;         /* ring within theta_cut of the range (0, 0: all)    */
 } arkcos_plan_info;
 
 /* The two gathers of a forward convolution (they write disjoint rings). */

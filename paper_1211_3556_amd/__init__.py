@@ -95,7 +95,8 @@ class _PlanInfo(ctypes.Structure):
                 ("circulant_tiles", ctypes.c_longlong), ("general_tiles", ctypes.c_longlong),
                 ("weights", ctypes.c_longlong), ("theta_break", ctypes.c_double),
                 ("k_break", ctypes.c_int), ("ring_first", ctypes.c_int),
-                ("ring_last", ctypes.c_int)]
+                ("ring_last", ctypes.c_int), ("adjoint_ring_first", ctypes.c_int),
+                ("adjoint_ring_last", ctypes.c_int)]
 
 
 _lib = None
@@ -322,6 +323,7 @@ class Plan:
         self.max_batch = int(max_batch)
         self.learnable = learnable
         self.host_only = host_only
+        self.rings = None if rings is None else (int(rings[0]), int(rings[1]))
         self.npix = 12 * self.nside * self.nside
 
     # -- lifetime -------------------------------------------------------------
@@ -405,7 +407,8 @@ class Plan:
         x = _dev_f32(x, "x")
         nb = self._shape(x)
         if out is None:
-            out = torch.empty_like(x)
+            # a ring-range plan leaves the other rings as they are: zero here
+            out = torch.zeros_like(x) if self.rings is not None else torch.empty_like(x)
         else:
             _dev_f32(out, "out")
             if out.shape != x.shape:

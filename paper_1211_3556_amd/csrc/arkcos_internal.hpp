@@ -78,12 +78,18 @@ constexpr double kShortXMax = 0.09;
 // and fraction must be exact to ~1e-9: the circulant weight rows (built once
 // per table) and the knot gradient (the hat basis has slope 1/h, so an FP32
 // angle moves node fractions by ~1e-7 u).
+// The FP64 short-row polynomial (rows without kPairLongSin) is the one of
+// DevPair before its rounding to FP32: in y = (m mscale)^2, the squared node
+// coordinate in angle mode 0, the squared chord otherwise.
 struct DevPairD {
     double A;
     double B;
     double xscale;
+    double mscale;
+    double sq[5];
     double pad;
 };
+static_assert(sizeof(DevPairD) == 80, "DevPairD layout");
 
 // One work item: pixels j0 .. j0 + len - 1 of output ring r (or of the rings
 // of group r, for the circulant kernel).
@@ -198,6 +204,8 @@ struct DevPlanView {
     // on the two-piece biased grid (a0 = k_break/theta_break the fine piece's
     // 1/h; r u0 + c the coarse piece's coordinate, which is the smaller one
     // beyond the break).  r = 1 and c = 0 on a uniform grid.
+    int src_lo;              // source rings read (0-based, inclusive): images of rings
+    int src_hi;              // outside count as zero (the adjoint of a ring range)
     int biased;
     float inv_h;             // a0
     float u_max;             // ntab - 1 (strict upper bound of u)
@@ -266,6 +274,14 @@ struct Plan {
     std::vector<int> gen_ring, gen_lanes, gen_flags;
     std::vector<double> gen_wmax;
     std::vector<double> ring_cost;    // candidates per output pixel of each ring
+    // Source rings read by the gathers (0-based, inclusive; all if src_hi < 0).
+    // Only the adjoint sub-plan of a ring-range plan restricts them.
+    int src_lo = 0;
+    int src_hi = -1;
+
+    // Ring-range plans: the adjoint's plan, whose output rings are every
+    // source ring of the range and whose source rings are the range.
+    Plan *adj = nullptr;
     long long nweights = 0;
     int max_taps = 0;
     std::vector<double> ktab;         // current host copy (FP64), if known

@@ -101,9 +101,6 @@ static int check_backward(const Plan *P, const float *d_grad_out, const float *d
         return fail(ARKCOS_EINVAL, "at least one of d_grad_in, d_grad_knots must be non-NULL");
     int rc = check_compute(P, nbatch);
     if (rc) return rc;
-    if (P->desc.ring_first > 0)
-        return fail(ARKCOS_EUNSUPPORTED, "a ring-range plan computes part of the output only; "
-                                         "its adjoint needs every output ring");
     const size_t bytes = (size_t)nbatch * (size_t)P->npix * sizeof(float);
     const size_t kbytes = (size_t)P->desc.ntab * sizeof(float);
     if (d_grad_in && overlaps(d_grad_in, bytes, d_grad_out, bytes))

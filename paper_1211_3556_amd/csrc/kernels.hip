@@ -259,7 +259,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
 #pragma unroll
             for (int i = 0; i < kCircPix; ++i) acc[r][i] = 0.0;
         float v[kStageRegs], wv[kWeightRegs];
-        {
+        if (G.row_begin < G.row_end) {
             const DevRow W = cst(P.rows)[G.row_begin];
             prefetch_row(in + W.first_s, T.j0 + W.k_lo, T.len + W.ntaps - 1, n, v);
             prefetch_weights(P.wts + W.w_off, W.ntaps * kGroupRings, wv);
@@ -458,6 +458,17 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
                     ld_off(srcm, od[3]));
     d = make_float4(ld_off(srcm, orf[0]), ld_off(srcm, orf[1]), ld_off(srcm, orf[2]),
                     ld_off(srcm, orf[3]));
+}
+
+// Images of a staged position whose ring lies outside the plan's source rings
+// count as zero: ring s (a, c) and its mirror (b, d).  Wave-uniform.
+__device__ __forceinline__ void mask_sources(const DevPlanView &P, int s, float4 &a, float4 &b,
+                                             float4 &c, float4 &d)
+{
+    const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const int sm = P.nrings - 1 - s;
+    if (s < P.src_lo || s > P.src_hi) a = c = z;
+    if (sm < P.src_lo || sm > P.src_hi) b = d = z;
 }
 
 // Plan constants of the candidate loop, in vector registers.
@@ -710,6 +721,7 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
         const DevRing S = cst(P.rings)[ch.s];
         prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - ch.s].first, S.n, S.two_o,
                    ch.c0, ch.cn, pa, pb, pc, pd);
+        mask_sources(P, ch.s, pa, pb, pc, pd);
     }
     double acc[16];
     float row[16];
@@ -733,6 +745,7 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
             const DevRing Sn = cst(P.rings)[nx.s];
             prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - nx.s].first, Sn.n,
                        Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
+            mask_sources(P, nx.s, pa, pb, pc, pd);
         }
         // this half's row of source ring ch.s, if its ring has one
         if (len > 0 && ch.s >= my.s_lo && ch.s <= my.s_hi) {
@@ -999,6 +1012,42 @@ __device__ __forceinline__ bool pair_node_d(const DevPairD &pd, const NodeMapD &
     return u < nm.u_max;
 }
 
+// sqrt in FP64 from the FP32 reciprocal square root (relative error near
+// 2^-23) and one Newton step, which squares it (below 1e-13); sqrt(a) = 0
+// for a below 1e-30.
+__device__ __forceinline__ double sqrt_d_seeded(double a)
+{
+    const double r0 = (double)__builtin_amdgcn_rsqf((float)a);
+    const double r = r0 * fma(-0.5 * a, r0 * r0, 1.5);
+    return a > 1e-30 ? a * r : 0.0;
+}
+
+// Node index and fraction of a pair of the knot gradient.  Short rows
+// evaluate their FP64 row polynomial in y = (m mscale)^2 (truncation below
+// 1e-9 relative, so fractions stay within ~1e-7 at 2048 nodes); long rows
+// take pair_node_d.
+template <bool LONG, int AM>
+__device__ __forceinline__ bool pair_node_knot(const DevPairD &pd, const NodeMapD &nm, int m,
+                                               int &node, double &frac)
+{
+    if (LONG) return pair_node_d<true, AM>(pd, nm, m, node, frac);
+    const double v = (double)m * pd.mscale;
+    const double y = v * v;
+    double u0;
+    if (AM == 0) {
+        const double q = fma(fma(fma(fma(pd.sq[4], y, pd.sq[3]), y, pd.sq[2]), y, pd.sq[1]), y,
+                             pd.sq[0]);
+        u0 = sqrt_d_seeded(q);
+    } else {
+        const double d2 = fma(fma(fma(pd.sq[3], y, pd.sq[2]), y, pd.sq[1]), y, pd.sq[0]);
+        u0 = theta_d<AM>(d2) * nm.a0;
+    }
+    const double u = fmin(u0, fma(u0, nm.r, nm.c));
+    node = (int)fmin(u, nm.u_max - 1.0);
+    frac = u - (double)node;
+    return u < nm.u_max;
+}
+
 // The knot gradient is sum_p g[p] sum_q hat_k(theta_pq) x[q] over the in-disc
 // pairs of all maps.  Both kernels below scatter into per-wave FP64 LDS
 // histograms, merged per workgroup into partials[row][ntab] and reduced in a
@@ -1098,14 +1147,14 @@ __device__ __forceinline__ void hat_scatter(double *hist, double u, float c)
 //     = sum_k hat(u(r, s, k)) C(r, s, k),   C(r, s, k) = sum_j g_r[j] x_s[j + k]:
 // the pair loop becomes a cross-correlation of ring r of g with ring s of x,
 // and each distinct (r, s, k) is binned once per tile.  A tile is kKnotSeg
-// pixels of the kGroupRings rings of a group; its g is staged once, as float4
-// (one value per ring).  Each wave takes whole source rows (rows w, w + 4, ...
+// pixels of the kGroupRings rings of a group; its g is staged once, one array
+// per ring.  Each wave takes whole source rows (rows w, w + 4, ...
 // of the group for wave w), so a row needs no workgroup barrier: the wave
 // stages the row's x in its own LDS strip, and its lanes split into tap quads
 // q and pixel strides c.  Lane (q, c) sums g_r[4p + i] x_s[4p + i + 4q + t]
 // over the pixel quads p = c, c + nc, ... into 16 FP32 sums (4 rings x 4
-// taps); two aligned float4 reads of x and four of g feed 64 FMAs, as in the
-// circulant gather.  The nc partial sums of a (ring, tap) are then added in
+// taps); two aligned float4 reads of x and four of g (four pixels of each
+// ring; consecutive lanes read consecutive float4) feed 64 FMAs.  The nc partial sums of a (ring, tap) are then added in
 // stride order and binned with the FP64 node coordinates of k_build_knotw into
 // the wave's own histogram.
 
@@ -1128,11 +1177,11 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
     extern __shared__ __align__(16) double hists[];
     const DevPlanView P = cst(views)[0];
     const int hstride = hist_stride(P.ntab);
-    float4 *gs = reinterpret_cast<float4 *>(hists + kKnotWaves * hstride);   // kKnotSeg
+    float *gs = reinterpret_cast<float *>(hists + kKnotWaves * hstride);   // [ring][kKnotSeg]
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int lane = (int)threadIdx.x & 63;
-    float *xs = reinterpret_cast<float *>(gs + kKnotSeg) + wave * kKnotXW;
-    float *red = reinterpret_cast<float *>(gs + kKnotSeg) + kKnotWaves * kKnotXW + wave * 64 * 16;
+    float *xs = gs + kGroupRings * kKnotSeg + wave * kKnotXW;
+    float *red = gs + kGroupRings * kKnotSeg + kKnotWaves * kKnotXW + wave * 64 * 16;
     for (int i = threadIdx.x; i < kKnotWaves * hstride; i += kThreads) hists[i] = 0.0;
     double *hist = hists + wave * hstride;   // this wave's own bins
     const int nitems = P.nkctiles * nmaps;
@@ -1153,11 +1202,9 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
         __syncthreads();   // the previous item no longer reads gs
         // g of the group's rings over the tile, zero past the tile or the group
         for (int p = threadIdx.x; p < kKnotSeg; p += kThreads) {
-            float gv[kGroupRings];
 #pragma unroll
             for (int i = 0; i < kGroupRings; ++i)
-                gv[i] = (p < T.len && i < G.nr) ? gm[firsts[i] + p] : 0.0f;
-            gs[p] = make_float4(gv[0], gv[1], gv[2], gv[3]);
+                gs[i * kKnotSeg + p] = (p < T.len && i < G.nr) ? gm[firsts[i] + p] : 0.0f;
         }
         __syncthreads();
         for (int row = G.row_begin + wave; row < G.row_end; row += kKnotWaves) {
@@ -1193,19 +1240,20 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 for (int t = 0; t < 4; ++t) acc[r][t] = 0.0f;
             if (q < nq) {
                 const float4 *x4 = reinterpret_cast<const float4 *>(xs) + q;
+                const float4 *g4 = reinterpret_cast<const float4 *>(gs);
                 for (int p = c; p < npq; p += nc) {
                     const float4 xa = x4[p];
                     const float4 xb = x4[p + 1];
                     const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const float4 gq = gs[4 * p + i];
-                        const float gr[kGroupRings] = {gq.x, gq.y, gq.z, gq.w};
+                    for (int r = 0; r < kGroupRings; ++r) {
+                        const float4 gq = g4[r * (kKnotSeg / 4) + p];
+                        const float gp[4] = {gq.x, gq.y, gq.z, gq.w};
 #pragma unroll
-                        for (int t = 0; t < 4; ++t)
+                        for (int i = 0; i < 4; ++i)
 #pragma unroll
-                            for (int r = 0; r < kGroupRings; ++r)
-                                acc[r][t] = fmaf(gr[r], xv[i + t], acc[r][t]);
+                            for (int t = 0; t < 4; ++t)
+                                acc[r][t] = fmaf(gp[i], xv[i + t], acc[r][t]);
                     }
                 }
             }
@@ -1281,7 +1329,7 @@ __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const Node
         if (t < cnt && c != 0.0f) {
             int node;
             double frac;
-            if (pair_node_d<LONG, AM>(pd, nm, m, node, frac)) {
+            if (pair_node_knot<LONG, AM>(pd, nm, m, node, frac)) {
                 atomicAdd(&hist[node], (1.0 - frac) * (double)c);
                 atomicAdd(&hist[node + 1], frac * (double)c);
             }
@@ -1318,7 +1366,10 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
         const bool mirror = rs != rn;
         const DevRing R = cst(P.rings)[rn];
         const int qr = R.n >> 2;
+        // a ring-range plan's outputs outside the range carry no g
         const bool active = lane_pix < T.len;
+        const bool gn_ok = active && (T.flags & kTileSkipNorth) == 0;
+        const bool gs_ok = active && mirror && (T.flags & kTileSkipSouth) == 0;
         const int j = T.j0 + min(lane_pix, T.len - 1);
         const int jb = qr - R.two_o - j;
         const bool refl = active && jb != j && jb != qr;
@@ -1330,10 +1381,10 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
             const float *gsm = gm + cst(P.rings)[rs].first;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                gv[q] = active ? gn[j + q * qr] : 0.0f;
-                gv[4 + q] = (active && mirror) ? gsm[j + q * qr] : 0.0f;
-                gv[8 + q] = refl ? gn[jb + q * qr] : 0.0f;
-                gv[12 + q] = (refl && mirror) ? gsm[jb + q * qr] : 0.0f;
+                gv[q] = gn_ok ? gn[j + q * qr] : 0.0f;
+                gv[4 + q] = gs_ok ? gsm[j + q * qr] : 0.0f;
+                gv[8 + q] = (refl && gn_ok) ? gn[jb + q * qr] : 0.0f;
+                gv[12 + q] = (refl && gs_ok) ? gsm[jb + q * qr] : 0.0f;
             }
         }
         GenStage ch;
@@ -1476,7 +1527,7 @@ static size_t knot_hist_bytes(int ntab)
 // the partial sums of its lanes.
 static size_t knot_circ_lds(int ntab)
 {
-    return knot_hist_bytes(ntab) + (size_t)kKnotSeg * sizeof(float4) +
+    return knot_hist_bytes(ntab) + (size_t)kGroupRings * kKnotSeg * sizeof(float) +
            (size_t)kKnotWaves * (kKnotXW + 64 * 16) * sizeof(float);
 }
 static size_t knot_gen_lds(int ntab)
@@ -1594,12 +1645,38 @@ static int launch_knot(const Plan &p, const float *g, const float *x, float *gk,
     return ARKCOS_OK;
 }
 
+// Zero the pixels [0, lo) and [hi, npix) of nbatch maps.
+__global__ void k_zero_outside(float *x, long long npix, long long lo, long long hi,
+                               long long total)
+{
+    const long long nout = npix - (hi - lo);
+    for (long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (long long)gridDim.x * blockDim.x) {
+        const long long b = t / nout, i = t - b * nout;
+        x[b * npix + (i < lo ? i : i + (hi - lo))] = 0.0f;
+    }
+}
+
 int launch_backward(const Plan &p, const float *g, const float *x, float *gx, float *gk,
                     int nbatch, hipStream_t s, unsigned int *counter, double *kpart)
 {
-    // The operator is symmetric, so d/dmap is the same gather applied to g.
+    // The operator is symmetric, so d/dmap is the same gather applied to g;
+    // for a ring range it is the adjoint plan's gather (rings within theta_cut
+    // of the range, reading g on the range only), and zero elsewhere.
     if (gx) {
-        int rc = launch_forward(p, g, gx, nbatch, s, ARKCOS_PART_ALL, counter);
+        const Plan &a = p.adj ? *p.adj : p;
+        if (p.adj) {
+            const long long lo = p.rings[a.desc.ring_first - 1].first;
+            const HostRing &last = p.rings[a.desc.ring_last - 1];
+            const long long hi = last.first + last.n;
+            const long long total = (p.npix - (hi - lo)) * nbatch;
+            if (total > 0) {
+                const long long blocks = std::min<long long>((total + 255) / 256, 8192);
+                hipLaunchKernelGGL(k_zero_outside, dim3((unsigned)blocks), dim3(256), 0, s, gx,
+                                   p.npix, lo, hi, total);
+            }
+        }
+        int rc = launch_forward(a, g, gx, nbatch, s, ARKCOS_PART_ALL, counter);
         if (rc) return rc;
     }
     if (gk) return launch_knot(p, g, x, gk, nbatch, s, kpart ? kpart : p.d_kpart);

@@ -66,7 +66,7 @@ static double node_density(const arkcos_plan_desc &d)
 // described with DevPair).  sin^2 x = sum_k (-1)^(k+1) 2^(2k-1) x^(2k) / (2k)!
 // with x^2 = s^2 y; theta^2 = (2 asin(d/2))^2 = sum_n 2 d^(2n) / (n^2 C(2n, n)).
 static void short_row_poly(double A, double B, double xscale, int angle_mode, double density,
-                           DevPair &p)
+                           DevPair &p, DevPairD &pd)
 {
     int e = 0;
     const double sc = std::frexp(xscale, &e);
@@ -98,7 +98,11 @@ static void short_row_poly(double A, double B, double xscale, int angle_mode, do
         }
         for (int i = 0; i <= K; ++i) out[i] *= density * density;
     }
-    for (int i = 0; i <= K; ++i) p.sq[i] = (float)out[i];
+    pd.mscale = std::ldexp(1.0, e);
+    for (int i = 0; i <= K; ++i) {
+        p.sq[i] = (float)out[i];
+        pd.sq[i] = out[i];
+    }
 }
 
 DevPlanView Plan::view() const
@@ -126,6 +130,8 @@ DevPlanView Plan::view() const
     v.ntab = desc.ntab;
     v.npix = (int)npix;
     v.angle_mode = angle_mode;
+    v.src_lo = src_hi >= 0 ? src_lo : 0;
+    v.src_hi = src_hi >= 0 ? src_hi : nrings - 1;
     // node coordinate map: u0 = a0 theta, u = min(u0, r u0 + c)
     const bool biased = desc.k_break > 0;
     const double ih = node_density(desc);
@@ -204,6 +210,12 @@ void build_gen_tiles(Plan &P)
     const double quad_max = P.tiles.gen_quad_window;   // -1: never
     const double pair_max = P.tiles.gen_pair_window;
     const std::vector<int> &gring = P.gen_ring, &glanes = P.gen_lanes, &gflags = P.gen_flags;
+    // a row is needed if its source ring or that ring's mirror is read
+    int clip_lo = 0, clip_hi = P.nrings - 1;
+    if (P.src_hi >= 0) {
+        clip_lo = std::min(P.src_lo, P.nrings - 1 - P.src_hi);
+        clip_hi = std::max(P.src_hi, P.nrings - 1 - P.src_lo);
+    }
     std::vector<int> gwide(gring.size());
     for (size_t g = 0; g < gring.size(); ++g) {
         const double w = P.gen_wmax[g];
@@ -239,11 +251,16 @@ void build_gen_tiles(Plan &P)
                 q.s_hi = -1;
                 if (q.len > 0) {
                     const DevRing &dr = P.dev_rings[q.r];
-                    q.pb = dr.pair_begin;
-                    q.s_lo = P.pairs[dr.pair_begin].s;
-                    q.s_hi = P.pairs[dr.pair_end - 1].s;
-                    t.s_first = std::min(t.s_first, q.s_lo);
-                    t.s_last = std::max(t.s_last, q.s_hi);
+                    const int s0 = P.pairs[dr.pair_begin].s;
+                    // rows whose ring or mirror ring is read (all rows unless
+                    // the source rings are restricted)
+                    q.s_lo = std::max(s0, clip_lo);
+                    q.s_hi = std::min(P.pairs[dr.pair_end - 1].s, clip_hi);
+                    q.pb = dr.pair_begin + (q.s_lo - s0);
+                    if (q.s_lo <= q.s_hi) {
+                        t.s_first = std::min(t.s_first, q.s_lo);
+                        t.s_last = std::max(t.s_last, q.s_hi);
+                    }
                     c += P.ring_cost[q.r] * q.len;
                 }
             }
@@ -297,7 +314,7 @@ static int build_plan(Plan &P)
             p.A = (float)pd.A;
             p.B = (float)pd.B;
             p.xscale = (float)pd.xscale;
-            short_row_poly(pd.A, pd.B, pd.xscale, P.angle_mode, node_density(P.desc), p);
+            short_row_poly(pd.A, pd.B, pd.xscale, P.angle_mode, node_density(P.desc), p, pd);
             p.a = (float)((double)S.n / (double)R.n);
             p.b = (float)(0.5 * R.two_o * (double)S.n / (double)R.n - 0.5 * S.two_o);
             // window half-width in source pixels, widened to cover FP32 rounding
@@ -377,6 +394,7 @@ static int build_plan(Plan &P)
             s_hi = std::max(s_hi, P.pairs[dr.pair_end - 1].s);
         }
         for (int sr = s_lo; sr <= s_hi; ++sr) {
+            if (P.src_hi >= 0 && (sr < P.src_lo || sr > P.src_hi)) continue;   // not read
             int k_lo = 1 << 30, k_hi = -(1 << 30);
             for (int i = 0; i < G.nr; ++i) {
                 const DevRing &dr = P.dev_rings[G.r0 + i];
@@ -745,6 +763,40 @@ static int to_device(Plan &P)
     return ARKCOS_OK;
 }
 
+// Descriptor-derived fields of a plan (before tiles and build).
+static void init_plan(Plan &P, const arkcos_plan_desc &d)
+{
+    P.desc = d;
+    P.desc.ktab = nullptr;
+    P.nside = d.nside;
+    P.nrings = 4 * d.nside - 1;
+    P.npix = 12LL * d.nside * d.nside;
+    P.omega = 4.0 * M_PI / (double)P.npix;
+    P.threads = forward_threads();
+    P.host_only = (d.flags & ARKCOS_PLAN_HOST_ONLY) != 0;
+    P.angle_mode = d.theta_cut <= 0.1 ? 0 : (d.theta_cut <= 0.5 ? 1 : 2);
+    if (d.ktab) P.ktab.assign(d.ktab, d.ktab + d.ntab);
+}
+
+static int build_and_upload(Plan &P)
+{
+    int rc;
+    try {
+        rc = build_plan(P);
+    } catch (const std::bad_alloc &) {
+        rc = fail(ARKCOS_ENOMEM, "host allocation failed while building the plan");
+    }
+    if (rc == ARKCOS_OK && !P.host_only) rc = to_device(P);
+    return rc;
+}
+
+static void destroy_plan(Plan *P)
+{
+    if (P->adj) destroy_plan(P->adj);
+    free_device(*P);
+    delete P;
+}
+
 }  // namespace arkcos
 
 using namespace arkcos;
@@ -858,30 +910,42 @@ int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
 
     Plan *P = new (std::nothrow) Plan();
     if (!P) return fail(ARKCOS_ENOMEM, "host allocation failed");
-    P->desc = *desc;
-    P->desc.ktab = nullptr;
-    P->nside = desc->nside;
-    P->nrings = 4 * desc->nside - 1;
-    P->npix = npix;
-    P->omega = 4.0 * M_PI / (double)npix;
+    init_plan(*P, *desc);
     if (int rc = resolve_tiles(*desc, &P->tiles, &P->tile_source)) {
         delete P;
         return rc;
     }
-    P->threads = forward_threads();
-    P->host_only = (desc->flags & ARKCOS_PLAN_HOST_ONLY) != 0;
-    P->angle_mode = desc->theta_cut <= 0.1 ? 0 : (desc->theta_cut <= 0.5 ? 1 : 2);
-    if (desc->ktab) P->ktab.assign(desc->ktab, desc->ktab + desc->ntab);
-    int rc;
-    try {
-        rc = build_plan(*P);
-    } catch (const std::bad_alloc &) {
-        rc = fail(ARKCOS_ENOMEM, "host allocation failed while building the plan");
+    int rc = build_and_upload(*P);
+    if (rc == ARKCOS_OK && desc->ring_first > 0) {
+        // The adjoint of a ring range R: output rings are every source ring of
+        // R (the rings within theta_cut of it), source rings are R itself,
+        // whose images outside R count as zero.  The same gathers then give
+        // A^T g for g supported on R, by the symmetry of the operator.
+        int e1 = P->nrings, e2 = -1;
+        for (int r = desc->ring_first - 1; r <= desc->ring_last - 1; ++r) {
+            const DevRing &dr = P->dev_rings[r];
+            e1 = std::min(e1, P->pairs[dr.pair_begin].s);
+            e2 = std::max(e2, P->pairs[dr.pair_end - 1].s);
+        }
+        Plan *A = new (std::nothrow) Plan();
+        if (!A) {
+            rc = fail(ARKCOS_ENOMEM, "host allocation failed");
+        } else {
+            arkcos_plan_desc ad = *desc;
+            ad.ring_first = e1 + 1;
+            ad.ring_last = e2 + 1;
+            ad.flags &= ~ARKCOS_PLAN_LEARNABLE;   // gathers only
+            init_plan(*A, ad);
+            A->tiles = P->tiles;
+            A->tile_source = P->tile_source;
+            A->src_lo = desc->ring_first - 1;
+            A->src_hi = desc->ring_last - 1;
+            P->adj = A;
+            rc = build_and_upload(*A);
+        }
     }
-    if (rc == ARKCOS_OK && !P->host_only) rc = to_device(*P);
     if (rc != ARKCOS_OK) {
-        free_device(*P);
-        delete P;
+        destroy_plan(P);
         return rc;
     }
     *out = reinterpret_cast<arkcos_plan_t>(P);
@@ -892,9 +956,7 @@ int arkcos_plan_destroy(arkcos_plan_t plan)
 {
     clear_error();
     if (!plan) return ARKCOS_OK;
-    Plan *P = reinterpret_cast<Plan *>(plan);
-    free_device(*P);
-    delete P;
+    destroy_plan(reinterpret_cast<Plan *>(plan));
     return ARKCOS_OK;
 }
 
@@ -924,6 +986,8 @@ int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info)
     info->general_rings = nout - circ;
     info->ring_first = P->desc.ring_first;
     info->ring_last = P->desc.ring_last;
+    info->adjoint_ring_first = P->adj ? P->adj->desc.ring_first : 0;
+    info->adjoint_ring_last = P->adj ? P->adj->desc.ring_last : 0;
     info->circulant_tiles = (long long)P->ctiles.size();
     info->general_tiles = (long long)P->gtiles.size();
     info->weights = P->nweights;
@@ -1012,10 +1076,12 @@ int arkcos_plan_set_kernel_host(arkcos_plan_t plan, const double *ktab)
     Plan *P = reinterpret_cast<Plan *>(plan);
     if (P->host_only) return fail(ARKCOS_ESTATE, "host-only plan has no device table");
     P->ktab.assign(ktab, ktab + P->desc.ntab);
+    if (P->adj) P->adj->ktab = P->ktab;
     int cur = 0;
     ARKCOS_HIP_CHECK(hipGetDevice(&cur));
     ARKCOS_HIP_CHECK(hipSetDevice(P->device));
     int rc = write_table_host(*P);
+    if (rc == ARKCOS_OK && P->adj) rc = write_table_host(*P->adj);
     (void)hipSetDevice(cur);
     if (rc == ARKCOS_OK) P->knots_set = true;
     return rc;
@@ -1031,6 +1097,8 @@ int arkcos_plan_set_kernel(arkcos_plan_t plan, const float *d_knots, void *strea
         return fail(ARKCOS_ESTATE, "plan was not created with ARKCOS_PLAN_LEARNABLE");
     int rc = launch_set_table(*P, d_knots, (hipStream_t)stream);
     if (rc == ARKCOS_OK) rc = launch_build_weights(*P, (hipStream_t)stream);
+    if (rc == ARKCOS_OK && P->adj) rc = launch_set_table(*P->adj, d_knots, (hipStream_t)stream);
+    if (rc == ARKCOS_OK && P->adj) rc = launch_build_weights(*P->adj, (hipStream_t)stream);
     if (rc == ARKCOS_OK) {
         P->knots_set = true;
         P->ktab.clear();

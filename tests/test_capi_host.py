@@ -346,3 +346,16 @@ def test_ring_range_errors(rings):
     with pytest.raises(A.ArkcosError) as e:
         A.Plan(16, 0.1, np.ones(8), host_only=True, rings=rings)
     assert e.value.status == -1 and "ring range" in str(e.value)
+
+
+@pytest.mark.parametrize("nside,tc_deg,rings", [(32, 9.0, (5, 60)), (32, 9.0, (1, 10)),
+                                                (64, 6.0, (120, 136)), (16, 40.3, (2, 9))])
+def test_ring_range_adjoint_rings(nside, tc_deg, rings):
+    """The adjoint of a ring range writes every ring within theta_cut of it."""
+    tc = np.radians(tc_deg)
+    inf = A.Plan(nside, tc, np.ones(8), host_only=True, rings=rings).info()
+    th = np.arccos(O.ring_geometry(nside)["z"])
+    near = [s + 1 for s in range(4 * nside - 1)
+            if np.min(np.abs(th[s] - th[rings[0] - 1:rings[1]])) < tc]
+    assert (inf["adjoint_ring_first"], inf["adjoint_ring_last"]) == (near[0], near[-1])
+    assert A.Plan(nside, tc, np.ones(8), host_only=True).info()["adjoint_ring_first"] == 0
