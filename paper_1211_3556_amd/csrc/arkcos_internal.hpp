@@ -135,7 +135,7 @@ constexpr int kThreads = 256;
 constexpr int kGroupRings = 4;
 constexpr int kCircPix = 4;
 constexpr int kCircSeg = kThreads * kCircPix;
-constexpr int kCircMaxTaps = 256;   // wider rows make their rings general
+constexpr int kCircMaxTaps = 256;   // taps of one circulant row (wider rows are split)
 constexpr int kGenLanes = 128;       // most pixels of one ring per general tile
 constexpr int kGenThreads = 512;     // general-gather workgroup: kGenPhases lanes per pixel
 constexpr int kGenPhases = kGenThreads / kGenLanes;

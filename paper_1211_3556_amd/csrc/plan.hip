@@ -358,8 +358,7 @@ static int build_plan(Plan &P)
             const DevPair &pp = P.pairs[k];
             const bool whole = (pp.mode & kPairWhole) != 0;
             if (whole || P.rings[pp.s].n != nbelt) circ = false;
-            // a group row spans the union of up to kGroupRings windows
-            if (!whole && 2.0 * pp.w + 3.0 + kGroupRings > kCircMaxTaps) circ = false;
+
         }
         general[r] = circ ? 0 : 1;
     }
@@ -406,18 +405,20 @@ static int build_plan(Plan &P)
                 k_hi = std::max(k_hi, hi);
             }
             if (k_hi < k_lo) continue;
-            if (k_hi - k_lo + 1 > kCircMaxTaps)
-                return fail(ARKCOS_EUNSUPPORTED, "circulant row wider than the staging limit");
-            DevRow row{};
-            row.s = sr;
-            row.first_s = (int)P.rings[sr].first;
-            row.k_lo = k_lo;
-            row.ntaps = k_hi - k_lo + 1;
-            row.w_off = (int)P.nweights;
-            row.g = (int)P.groups.size();
-            P.nweights += (long long)row.ntaps * kGroupRings;
-            P.max_taps = std::max(P.max_taps, row.ntaps);
-            P.rows.push_back(row);
+            // a row wider than one staging pass becomes consecutive rows of at
+            // most kCircMaxTaps taps each
+            for (int k0 = k_lo; k0 <= k_hi; k0 += kCircMaxTaps) {
+                DevRow row{};
+                row.s = sr;
+                row.first_s = (int)P.rings[sr].first;
+                row.k_lo = k0;
+                row.ntaps = std::min(kCircMaxTaps, k_hi - k0 + 1);
+                row.w_off = (int)std::min<long long>(P.nweights, 0x7fffffffLL);
+                row.g = (int)P.groups.size();
+                P.nweights += (long long)row.ntaps * kGroupRings;
+                P.max_taps = std::max(P.max_taps, row.ntaps);
+                P.rows.push_back(row);
+            }
         }
         G.row_end = (int)P.rows.size();
         P.groups.push_back(G);

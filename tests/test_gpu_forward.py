@@ -278,3 +278,30 @@ def test_large_nside_sampled(k):
     err = rel_rms(y[pix], ref)
     log("large Nside %d rel rms %.3e over %d pixels" % (s.nside, err, pix.size))
     assert err <= REL_RMS_TOL
+
+
+def test_wide_circulant_rows_split():
+    """Belt rings whose rows are wider than one circulant staging pass (256
+    taps) stay circulant, their rows split into consecutive passes: Nside 512
+    with a 29.8 degree cut (rows up to ~340 taps; the equator's disc stays in
+    the belt), against the oracle on sampled pixels."""
+    import torch
+    A = _A()
+    nside, tc = 512, np.radians(29.8)
+    knots = W.gaussian_profile_knots(tc / 3, tc, 4096)
+    plan = A.Plan(nside, tc, knots)
+    inf = plan.info()
+    assert inf["circulant_rings"] > 0
+    x = W.white_noise(nside, 970)
+    log("wide circulant rows Nside %d" % nside)
+    xd = to_dev(x)
+    yc = torch.zeros_like(xd)
+    plan.convolve_part(xd, yc, A.PART_CIRCULANT)
+    y = to_host(plan.convolve(xd))
+    torch.cuda.synchronize()
+    circ = to_host(yc) != 0
+    rng = np.random.default_rng(971)
+    pix = np.unique(np.concatenate([rng.choice(np.flatnonzero(circ), 160, replace=False),
+                                    rng.choice(12 * nside * nside, 40, replace=False)]))
+    ref = O.convolve(nside, tc, knots, x, pixels=pix)
+    assert rel_rms(y[pix], ref) <= REL_RMS_TOL
