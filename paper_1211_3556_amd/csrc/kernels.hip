@@ -489,7 +489,9 @@ struct GenConst {
 // weight arithmetic (unrolled by two, the loop spills at 128 VGPRs).
 // BIAS: the plan's node grid is the two-piece biased one, u = min(u0, r u0 + c);
 // otherwise u = u0 and the map costs nothing.
-template <bool LONG, int AM, bool INTM, bool BIAS>
+// SIDE 0: all sixteen images; SIDE 1 (2): only the ring's (the mirror ring's)
+// eight, for tiles whose other half lies outside a ring-range plan.
+template <bool LONG, int AM, bool INTM, bool BIAS, int SIDE>
 __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenConst<AM> &gc,
                                                  const float *tab, int m, int dm, int step,
                                                  const float4 *stage, int c0, int cn, int jq,
@@ -536,11 +538,13 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         const bool valid = o <= o_a1;
         const int oc = min(o, o_last);
         lds_float4 *sp = (lds_float4 *)(size_t)oc;
-        const v4f v0 = sp[0];
-        const v4f v1 = sp[kGenStage];
-        const v4f v2 = sp[2 * kGenStage];
-        const v4f v3 = sp[3 * kGenStage];
-        __builtin_amdgcn_sched_barrier(0);   // keep the four reads ahead of the arithmetic
+        // SIDE 0: ring and mirror at j' and at the reflection of j'; one-sided:
+        // the side's two arrays only (row[0..3] direct, row[4..7] reflected)
+        const v4f v0 = sp[(SIDE == 2 ? 1 : 0) * kGenStage];
+        const v4f v1 = sp[(SIDE == 0 ? 1 : (SIDE == 1 ? 2 : 3)) * kGenStage];
+        const v4f v2 = SIDE == 0 ? sp[2 * kGenStage] : v0;
+        const v4f v3 = SIDE == 0 ? sp[3 * kGenStage] : v1;
+        __builtin_amdgcn_sched_barrier(0);   // keep the reads ahead of the arithmetic
         float u0;
         if (LONG) {
             const float x = (INTM ? (float)mi : mf) * xscale;   // half the longitude difference
@@ -568,14 +572,16 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         row[5] = fmaf(w, v1.y, row[5]);
         row[6] = fmaf(w, v1.z, row[6]);
         row[7] = fmaf(w, v1.w, row[7]);
-        row[8] = fmaf(w, v2.x, row[8]);
-        row[9] = fmaf(w, v2.y, row[9]);
-        row[10] = fmaf(w, v2.z, row[10]);
-        row[11] = fmaf(w, v2.w, row[11]);
-        row[12] = fmaf(w, v3.x, row[12]);
-        row[13] = fmaf(w, v3.y, row[13]);
-        row[14] = fmaf(w, v3.z, row[14]);
-        row[15] = fmaf(w, v3.w, row[15]);
+        if (SIDE == 0) {
+            row[8] = fmaf(w, v2.x, row[8]);
+            row[9] = fmaf(w, v2.y, row[9]);
+            row[10] = fmaf(w, v2.z, row[10]);
+            row[11] = fmaf(w, v2.w, row[11]);
+            row[12] = fmaf(w, v3.x, row[12]);
+            row[13] = fmaf(w, v3.y, row[13]);
+            row[14] = fmaf(w, v3.z, row[14]);
+            row[15] = fmaf(w, v3.w, row[15]);
+        }
         o += o_step;
         if (INTM)
             mi -= dmi;
@@ -686,10 +692,11 @@ __device__ __forceinline__ GenStage2 next_stage2(const DevPlanView &P, const Dev
 // writes the sixteen images of its pixels.  LONG, AM, INTM and BIAS are fixed
 // per tile, so the candidate loop has one form and the row sums stay in place
 // across rows.
-template <bool LONG, int AM, bool INTM, bool BIAS>
+template <bool LONG, int AM, bool INTM, bool BIAS, int SIDE>
 __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab, float4 *stage,
                                           const DevTile2 *Tp, const float *in, float *out)
 {
+    constexpr int NI = SIDE == 0 ? 16 : 8;   // images summed per lane
     const int nr = Tp->nr;
     const int kPart = kGenThreads / nr;   // lanes per ring: 512, 256 or 128
     // wave-uniform (a part is whole waves); made scalar so that every branch
@@ -762,12 +769,12 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
             const unsigned mbase = lon_base(j, R.two_o, S.n);
             const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
             const int dm = 2 * nph * R.n;
-            gen_candidates16<LONG, AM, INTM, BIAS>(pp, gc, tab, m0, dm, nph, stage, ch.c0, ch.cn,
-                                                   jq0, a1, nt, row);
+            gen_candidates16<LONG, AM, INTM, BIAS, SIDE>(pp, gc, tab, m0, dm, nph, stage, ch.c0,
+                                                         ch.cn, jq0, a1, nt, row);
             since += nt;
             if (since >= kGenFlush) {   // FP32 partial sums into the FP64 totals
 #pragma unroll
-                for (int q = 0; q < 16; ++q) {
+                for (int q = 0; q < NI; ++q) {
                     acc[q] += (double)row[q];
                     row[q] = 0.0f;
                 }
@@ -777,10 +784,28 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
         ch = nx;
     }
 #pragma unroll
-    for (int q = 0; q < 16; ++q) acc[q] += (double)row[q];
+    for (int q = 0; q < NI; ++q) acc[q] += (double)row[q];
     for (int x = 1; x < nph; x <<= 1) {       // the lanes of a pixel, same order in each
 #pragma unroll
-        for (int q = 0; q < 16; ++q) acc[q] += __shfl_xor(acc[q], x);
+        for (int q = 0; q < NI; ++q) acc[q] += __shfl_xor(acc[q], x);
+    }
+    if (SIDE != 0) {   // one side: acc[0..3] at j, acc[4..7] at the reflected pixel
+        const bool wr = (SIDE == 1 ? (my.flags & kTileSkipNorth) : (my.flags & kTileSkipSouth)) == 0;
+        if (active && wr && (SIDE == 1 || mirror)) {
+            float *o = out + cst(P.rings)[SIDE == 1 ? rn : rs].first;
+            if (ph == 0) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) o[j + q * qr] = (float)acc[q];
+            }
+            if (ph == (nph > 1 ? 1 : 0)) {
+                const int jb = qr - R.two_o - j;
+                if (jb != j && jb != qr) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) o[jb + q * qr] = (float)acc[4 + q];
+                }
+            }
+        }
+        return;
     }
     // a ring-range plan leaves rings outside its range untouched
     const bool wn = (my.flags & kTileSkipNorth) == 0;
@@ -821,23 +846,39 @@ __device__ __forceinline__ void gen_tile_variant(const DevPlanView &P, const flo
                                                  float4 *stage, const DevTile2 *Tp,
                                                  const float *in, float *out)
 {
-    int fl = 0;
-    for (int k = 0; k < Tp->nr; ++k) fl |= cst(Tp->q)[k].flags;
+    int fl = 0, skip_all = kTileSkipNorth | kTileSkipSouth;
+    for (int k = 0; k < Tp->nr; ++k) {
+        const GenRing q = cst(Tp->q)[k];
+        fl |= q.flags;
+        if (q.len > 0) skip_all &= q.flags;
+    }
     const bool lg = (fl & kTileLongSin) != 0;
     if (fl & kTileIntM) {   // wide windows on large rings (long sine implied)
         switch (P.angle_mode) {
-            case 0: gen_tile2<true, 0, true, BIAS>(P, tab, stage, Tp, in, out); break;
-            case 1: gen_tile2<true, 1, true, BIAS>(P, tab, stage, Tp, in, out); break;
-            default: gen_tile2<true, 2, true, BIAS>(P, tab, stage, Tp, in, out); break;
+            case 0: gen_tile2<true, 0, true, BIAS, 0>(P, tab, stage, Tp, in, out); break;
+            case 1: gen_tile2<true, 1, true, BIAS, 0>(P, tab, stage, Tp, in, out); break;
+            default: gen_tile2<true, 2, true, BIAS, 0>(P, tab, stage, Tp, in, out); break;
+        }
+    } else if (!lg && (skip_all & kTileSkipSouth)) {   // every ring writes its own side only
+        switch (P.angle_mode) {
+            case 0: gen_tile2<false, 0, false, BIAS, 1>(P, tab, stage, Tp, in, out); break;
+            case 1: gen_tile2<false, 1, false, BIAS, 1>(P, tab, stage, Tp, in, out); break;
+            default: gen_tile2<false, 2, false, BIAS, 1>(P, tab, stage, Tp, in, out); break;
+        }
+    } else if (!lg && (skip_all & kTileSkipNorth)) {   // ... its mirror's side only
+        switch (P.angle_mode) {
+            case 0: gen_tile2<false, 0, false, BIAS, 2>(P, tab, stage, Tp, in, out); break;
+            case 1: gen_tile2<false, 1, false, BIAS, 2>(P, tab, stage, Tp, in, out); break;
+            default: gen_tile2<false, 2, false, BIAS, 2>(P, tab, stage, Tp, in, out); break;
         }
     } else {
         switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-            case 0: gen_tile2<false, 0, false, BIAS>(P, tab, stage, Tp, in, out); break;
-            case 1: gen_tile2<true, 0, false, BIAS>(P, tab, stage, Tp, in, out); break;
-            case 2: gen_tile2<false, 1, false, BIAS>(P, tab, stage, Tp, in, out); break;
-            case 3: gen_tile2<true, 1, false, BIAS>(P, tab, stage, Tp, in, out); break;
-            case 4: gen_tile2<false, 2, false, BIAS>(P, tab, stage, Tp, in, out); break;
-            default: gen_tile2<true, 2, false, BIAS>(P, tab, stage, Tp, in, out); break;
+            case 0: gen_tile2<false, 0, false, BIAS, 0>(P, tab, stage, Tp, in, out); break;
+            case 1: gen_tile2<true, 0, false, BIAS, 0>(P, tab, stage, Tp, in, out); break;
+            case 2: gen_tile2<false, 1, false, BIAS, 0>(P, tab, stage, Tp, in, out); break;
+            case 3: gen_tile2<true, 1, false, BIAS, 0>(P, tab, stage, Tp, in, out); break;
+            case 4: gen_tile2<false, 2, false, BIAS, 0>(P, tab, stage, Tp, in, out); break;
+            default: gen_tile2<true, 2, false, BIAS, 0>(P, tab, stage, Tp, in, out); break;
         }
     }
 }
