@@ -635,8 +635,8 @@ __device__ __forceinline__ void row_window2(const DevPlanView &P, const DevTile2
     lo_min = 0x7fffffff;
     hi_max = -0x7fffffff;
     const int n_s = cst(P.rings)[s].n;
-    const int nr = Tp->nr;
-    const int j0 = Tp->j0;
+    const int nr = cst(Tp)->nr;   // scalar loads: the tile record is wave-uniform
+    const int j0 = cst(Tp)->j0;
     for (int k = 0; k < nr; ++k) {
         const GenRing q = cst(Tp->q)[k];
         if (q.len > 0 && s >= q.s_lo && s <= q.s_hi) {
@@ -697,14 +697,14 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
                                           const DevTile2 *Tp, const float *in, float *out)
 {
     constexpr int NI = SIDE == 0 ? 16 : 8;   // images summed per lane
-    const int nr = Tp->nr;
+    const int nr = cst(Tp)->nr;
     const int kPart = kGenThreads / nr;   // lanes per ring: 512, 256 or 128
     // wave-uniform (a part is whole waves); made scalar so that every branch
     // on the part is a scalar branch
     const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kPart);
     const int tid = (int)threadIdx.x - h * kPart;
     const GenRing my = cst(Tp->q)[h];
-    const int s_last = Tp->s_last;
+    const int s_last = cst(Tp)->s_last;
     const int len = my.len;
     const int rn = my.r;                                // an idle part holds a valid ring
     const int rs = P.nrings - 1 - rn;                   // mirror ring
@@ -719,10 +719,10 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
     const int ph = tid & (nph - 1);
     const int lane_pix = tid >> lp;
     const bool active = lane_pix < len;
-    const int j = Tp->j0 + min(lane_pix, max(len - 1, 0));
+    const int j = cst(Tp)->j0 + min(lane_pix, max(len - 1, 0));
     const GenConst<AM> gc(P);
 
-    GenStage2 ch = first_stage2(P, Tp, s_last, Tp->s_first);
+    GenStage2 ch = first_stage2(P, Tp, s_last, cst(Tp)->s_first);
     float4 pa, pb, pc, pd;
     if (ch.s <= s_last) {
         const DevRing S = cst(P.rings)[ch.s];
@@ -847,7 +847,7 @@ __device__ __forceinline__ void gen_tile_variant(const DevPlanView &P, const flo
                                                  const float *in, float *out)
 {
     int fl = 0, skip_all = kTileSkipNorth | kTileSkipSouth;
-    for (int k = 0; k < Tp->nr; ++k) {
+    for (int k = 0; k < cst(Tp)->nr; ++k) {
         const GenRing q = cst(Tp->q)[k];
         fl |= q.flags;
         if (q.len > 0) skip_all &= q.flags;
