@@ -113,7 +113,8 @@ struct GenRing {
 // A general-gather tile of nr = 1, 2 or 4 adjacent northern rings over the
 // same half-quadrant segment (adjacent rings cover nearly the same
 // longitudes, so one staged chunk of a source ring serves all of them);
-// source rings s_first .. s_last are staged.
+// source rings s_first .. s_last are read, staged as the nchunks chunks
+// from c_begin on of the plan's chunk list.
 constexpr int kGenMaxRings = 4;
 struct DevTile2 {
     int nr;
@@ -121,8 +122,28 @@ struct DevTile2 {
     int s_first;
     int s_last;
     GenRing q[kGenMaxRings];
+    int c_begin;
+    int nchunks;
+    int pad[2];
 };
-static_assert(sizeof(DevTile2) == 112, "DevTile2 layout");
+static_assert(sizeof(DevTile2) == 128, "DevTile2 layout");
+// One staged chunk of a general tile: unwrapped positions c0 .. c0 + cn - 1
+// of source ring s (inside the union of the tile's row windows on s), with
+// the geometry of s and of its mirror ring, and which of the two count as
+// zero (bit 0: ring s, bit 1: the mirror; outside a plan's source rings).
+// Built on the host with the kernels' own window arithmetic, so that the
+// kernel reads one record per chunk instead of every ring's pair record.
+struct GenChunk {
+    int s;
+    int c0;
+    int cn;
+    int n;
+    int two_o;
+    int first;
+    int first_m;
+    int mask;
+};
+static_assert(sizeof(GenChunk) == 32, "GenChunk layout");
 constexpr int kTileLongSin = 1;   // some source row needs the long sine series
 constexpr int kTileIntM = 2;      // a longitude numerator may reach 2^24: keep it in int32
 constexpr int kTileSkipNorth = 4; // the northern ring is outside the plan's ring range
@@ -187,6 +208,7 @@ struct DevPlanView {
     const DevTile *ctiles;   // circulant tiles: (group, j0, len)
     const DevTile *gtiles;   // general tiles: (north ring, j0, len), pixels j <= jbar of quadrant 0
     const DevTile2 *gtiles2; // the same segments, two adjacent rings per tile (general gather)
+    const GenChunk *gchunks; // their staged chunks, tile by tile
     const DevTile *kctiles;  // circulant knot-gradient tiles: (group, j0, len)
     const double *kw;        // FP64 node coordinate per circulant weight slot, or -1
     int nctiles;
@@ -267,6 +289,7 @@ struct Plan {
     std::vector<DevTile> kctiles;     // circulant knot-gradient tiles, longest first
     std::vector<double> ctile_cost, gtile_cost, gtile2_cost;
     std::vector<DevTile2> gtiles2;    // general-gather tiles (1, 2 or 4 rings), longest first
+    std::vector<GenChunk> gchunks;    // their staged chunks
     arkcos_tiles tiles{};             // resolved general-gather tile shapes
     int tile_source = 0;              // 0 defaults, 1 tuning cache, 2 descriptor
     // the general northern rings in order, for the general-gather tiling:
@@ -302,6 +325,8 @@ struct Plan {
     DevTile *d_ctiles = nullptr;
     DevTile *d_gtiles = nullptr;
     DevTile2 *d_gtiles2 = nullptr;
+    GenChunk *d_gchunks = nullptr;
+    long long gen_tile_bytes = 0;       // device bytes of d_gtiles2 and d_gchunks
     DevTile *d_kctiles = nullptr;
     double *d_kw = nullptr;             // knot node coordinates of the circulant slots
     DevPlanView *d_view = nullptr;      // device copy of view() (a batch of one plan)

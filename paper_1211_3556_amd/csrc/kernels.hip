@@ -461,14 +461,21 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
 }
 
 // Images of a staged position whose ring lies outside the plan's source rings
-// count as zero: ring s (a, c) and its mirror (b, d).  Wave-uniform.
-__device__ __forceinline__ void mask_sources(const DevPlanView &P, int s, float4 &a, float4 &b,
-                                             float4 &c, float4 &d)
+// count as zero: ring s (a, c; mask bit 0) and its mirror (b, d; bit 1).
+// Wave-uniform.
+__device__ __forceinline__ void mask_sources(int mask, float4 &a, float4 &b, float4 &c, float4 &d)
 {
     const float4 z = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    const int sm = P.nrings - 1 - s;
-    if (s < P.src_lo || s > P.src_hi) a = c = z;
-    if (sm < P.src_lo || sm > P.src_hi) b = d = z;
+    if (mask & 1) a = c = z;
+    if (mask & 2) b = d = z;
+}
+
+// Issue the loads of a staged chunk (its record read by scalar loads).
+__device__ __forceinline__ void prefetch_chunk(const float *in, const GenChunk &c, float4 &a,
+                                               float4 &b, float4 &d2, float4 &d)
+{
+    prefetch16(in + c.first, in + c.first_m, c.n, c.two_o, c.c0, c.cn, a, b, d2, d);
+    mask_sources(c.mask, a, b, d2, d);
 }
 
 // Plan constants of the candidate loop, in vector registers.
@@ -626,65 +633,6 @@ __device__ __forceinline__ GenStage next_stage(const DevPlanView &P, const DevRi
 // accumulated at least this many candidates since the last move.
 constexpr int kGenFlush = 48;
 
-// Union over a tile's rings of their windows on source ring s.  The tile's
-// ring records are read from global memory by a wave-uniform index (scalar
-// loads), so nothing is indexed dynamically in registers.
-__device__ __forceinline__ void row_window2(const DevPlanView &P, const DevTile2 *Tp, int s,
-                                            int &lo_min, int &hi_max)
-{
-    lo_min = 0x7fffffff;
-    hi_max = -0x7fffffff;
-    const int n_s = cst(P.rings)[s].n;
-    const int nr = cst(Tp)->nr;   // scalar loads: the tile record is wave-uniform
-    const int j0 = cst(Tp)->j0;
-    for (int k = 0; k < nr; ++k) {
-        const GenRing q = cst(Tp->q)[k];
-        if (q.len > 0 && s >= q.s_lo && s <= q.s_hi) {
-            const DevPair pp = cst(P.pairs)[q.pb + s - q.s_lo];
-            int lo, hi, dummy;
-            pair_window(pp, n_s, j0, lo, dummy);
-            pair_window(pp, n_s, j0 + q.len - 1, dummy, hi);
-            lo_min = min(lo_min, lo);
-            hi_max = max(hi_max, hi);
-        }
-    }
-}
-
-struct GenStage2 {
-    int s;    // source ring
-    int c0;   // first unwrapped source position of the chunk
-    int cn;   // positions staged
-    int hi;   // last unwrapped position of the ring's union window
-};
-
-__device__ __forceinline__ GenStage2 first_stage2(const DevPlanView &P, const DevTile2 *Tp,
-                                                  int s_last, int s)
-{
-    GenStage2 ch;
-    ch.s = s;
-    ch.c0 = 0;
-    ch.cn = 0;
-    ch.hi = -1;
-    if (s <= s_last) {
-        row_window2(P, Tp, s, ch.c0, ch.hi);
-        ch.cn = min(kGenStage, ch.hi - ch.c0 + 1);
-    }
-    return ch;
-}
-
-// The chunk after `ch`: the rest of its source ring, else the next ring.
-__device__ __forceinline__ GenStage2 next_stage2(const DevPlanView &P, const DevTile2 *Tp,
-                                                 int s_last, const GenStage2 &ch)
-{
-    if (ch.c0 + kGenStage <= ch.hi) {
-        GenStage2 nx = ch;
-        nx.c0 = ch.c0 + kGenStage;
-        nx.cn = min(kGenStage, ch.hi - nx.c0 + 1);
-        return nx;
-    }
-    return first_stage2(P, Tp, s_last, ch.s + 1);
-}
-
 // One general tile (DevTile2) of nr adjacent rings: the lanes form nr equal
 // parts of whole waves, part h taking ring q[h] (idle where its len is 0).
 // Per staged chunk of a source ring, each part runs the candidates of its
@@ -704,7 +652,6 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
     const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kPart);
     const int tid = (int)threadIdx.x - h * kPart;
     const GenRing my = cst(Tp->q)[h];
-    const int s_last = cst(Tp)->s_last;
     const int len = my.len;
     const int rn = my.r;                                // an idle part holds a valid ring
     const int rs = P.nrings - 1 - rn;                   // mirror ring
@@ -722,13 +669,15 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
     const int j = cst(Tp)->j0 + min(lane_pix, max(len - 1, 0));
     const GenConst<AM> gc(P);
 
-    GenStage2 ch = first_stage2(P, Tp, s_last, cst(Tp)->s_first);
+    // the tile's staged chunks: record k + 1 is read (scalar loads, no
+    // dependence on earlier loads) while chunk k is used
+    const cptr<GenChunk> C = cst(P.gchunks) + cst(Tp)->c_begin;
+    const int nch = cst(Tp)->nchunks;
     float4 pa, pb, pc, pd;
-    if (ch.s <= s_last) {
-        const DevRing S = cst(P.rings)[ch.s];
-        prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - ch.s].first, S.n, S.two_o,
-                   ch.c0, ch.cn, pa, pb, pc, pd);
-        mask_sources(P, ch.s, pa, pb, pc, pd);
+    GenChunk ch{};
+    if (nch > 0) {   // (a tile whose rows are all empty has no record)
+        ch = C[0];
+        prefetch_chunk(in, ch, pa, pb, pc, pd);
     }
     double acc[16];
     float row[16];
@@ -738,7 +687,8 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
         row[q] = 0.0f;
     }
     int since = 0;
-    while (ch.s <= s_last) {
+    for (int k = 0; k < nch; ++k) {
+        const GenChunk nx = C[min(k + 1, nch - 1)];
         __syncthreads();      // the previous chunk is no longer read
         if ((int)threadIdx.x < ch.cn) {
             stage[threadIdx.x] = pa;
@@ -747,27 +697,20 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
             stage[3 * kGenStage + threadIdx.x] = pd;
         }
         __syncthreads();
-        const GenStage2 nx = next_stage2(P, Tp, s_last, ch);
-        if (nx.s <= s_last) {
-            const DevRing Sn = cst(P.rings)[nx.s];
-            prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - nx.s].first, Sn.n,
-                       Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd);
-            mask_sources(P, nx.s, pa, pb, pc, pd);
-        }
-        // this half's row of source ring ch.s, if its ring has one
+        if (k + 1 < nch) prefetch_chunk(in, nx, pa, pb, pc, pd);
+        // this part's row of source ring ch.s, if its ring has one
         if (len > 0 && ch.s >= my.s_lo && ch.s <= my.s_hi) {
             const DevPair pp = cst(P.pairs)[my.pb + ch.s - my.s_lo];
-            const DevRing S = cst(P.rings)[ch.s];
             // this lane's candidates inside the chunk: a0 + ph, a0 + ph + nph, ...
             int lo, hi;
-            pair_window(pp, S.n, j, lo, hi);
+            pair_window(pp, ch.n, j, lo, hi);
             const int a0 = max(lo, ch.c0);
             const int a1 = min(hi, ch.c0 + ch.cn - 1);
             const int mine = a1 - a0 - ph >= 0 ? ((a1 - a0 - ph) >> lp) + 1 : 0;
             const int nt = wave_max(mine);
             const int jq0 = a0 + ph;
-            const unsigned mbase = lon_base(j, R.two_o, S.n);
-            const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
+            const unsigned mbase = lon_base(j, R.two_o, ch.n);
+            const int m0 = lon_numerator(mbase, jq0, ch.two_o, R.n);
             const int dm = 2 * nph * R.n;
             gen_candidates16<LONG, AM, INTM, BIAS, SIDE>(pp, gc, tab, m0, dm, nph, stage, ch.c0,
                                                          ch.cn, jq0, a1, nt, row);

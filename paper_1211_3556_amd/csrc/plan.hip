@@ -118,6 +118,7 @@ DevPlanView Plan::view() const
     v.ctiles = d_ctiles;
     v.gtiles = d_gtiles;
     v.gtiles2 = d_gtiles2;
+    v.gchunks = d_gchunks;
     v.kctiles = d_kctiles;
     v.kw = d_kw;
     v.nctiles = (int)ctiles.size();
@@ -196,6 +197,52 @@ static void sort_by_cost(std::vector<Tile> &tiles, std::vector<double> &cost)
     cost.swap(c2);
 }
 
+// Staged chunks of every general tile, in tile order: for each source ring s
+// of the tile, the union of its rings' row windows on s (the window of the
+// first pixel's lower end to the last pixel's upper end, exactly as the kernel
+// bounds a row: the windows move monotonically with the pixel), cut into
+// chunks of kGenStage positions.  Rings whose rows all have empty windows
+// are not staged.
+static void build_gen_chunks(Plan &P)
+{
+    P.gchunks.clear();
+    for (DevTile2 &t : P.gtiles2) {
+        t.c_begin = (int)P.gchunks.size();
+        for (int s = t.s_first; s <= t.s_last; ++s) {
+            int lo_min = 0x7fffffff, hi_max = -0x7fffffff;
+            const DevRing &S = P.dev_rings[s];
+            for (int k = 0; k < t.nr; ++k) {
+                const GenRing &q = t.q[k];
+                if (q.len <= 0 || s < q.s_lo || s > q.s_hi) continue;
+                const DevPair &pp = P.pairs[q.pb + s - q.s_lo];
+                int lo, hi, dummy;
+                pair_window(pp, S.n, t.j0, lo, dummy);
+                pair_window(pp, S.n, t.j0 + q.len - 1, dummy, hi);
+                lo_min = std::min(lo_min, lo);
+                hi_max = std::max(hi_max, hi);
+            }
+            if (lo_min > hi_max) continue;
+            const int sm = P.nrings - 1 - s;
+            int mask = 0;
+            if (P.src_hi >= 0 && (s < P.src_lo || s > P.src_hi)) mask |= 1;
+            if (P.src_hi >= 0 && (sm < P.src_lo || sm > P.src_hi)) mask |= 2;
+            for (int c0 = lo_min; c0 <= hi_max; c0 += kGenStage) {
+                GenChunk c{};
+                c.s = s;
+                c.c0 = c0;
+                c.cn = std::min(kGenStage, hi_max - c0 + 1);
+                c.n = S.n;
+                c.two_o = S.two_o;
+                c.first = S.first;
+                c.first_m = P.dev_rings[sm].first;
+                c.mask = mask;
+                P.gchunks.push_back(c);
+            }
+        }
+        t.nchunks = (int)P.gchunks.size() - t.c_begin;
+    }
+}
+
 // The general gather's tiles: adjacent general rings with narrow windows in
 // groups of four (one lane per pixel at full length) or two (two lanes per
 // pixel), each group over the same half-quadrant segments (tiles.gen_pixels
@@ -271,6 +318,7 @@ void build_gen_tiles(Plan &P)
     }
     sort_by_cost(P.gtiles2, cost);
     P.gtile2_cost = cost;
+    build_gen_chunks(P);
 }
 
 static int build_plan(Plan &P)
@@ -653,6 +701,7 @@ static void free_device(Plan &P)
         (void)hipFree(P.d_ctiles);
         (void)hipFree(P.d_gtiles);
         (void)hipFree(P.d_gtiles2);
+        (void)hipFree(P.d_gchunks);
         (void)hipFree(P.d_kctiles);
         (void)hipFree(P.d_kw);
         (void)hipFree(P.d_view);
@@ -670,6 +719,8 @@ static void free_device(Plan &P)
     P.d_ctiles = nullptr;
     P.d_gtiles = nullptr;
     P.d_gtiles2 = nullptr;
+    P.d_gchunks = nullptr;
+    P.gen_tile_bytes = 0;
     P.d_kctiles = nullptr;
     P.d_kw = nullptr;
     P.d_view = nullptr;
@@ -695,8 +746,14 @@ static int upload(T **dst, const std::vector<T> &src, long long *bytes)
 int upload_gen_tiles(Plan &P)
 {
     (void)hipFree(P.d_gtiles2);
+    (void)hipFree(P.d_gchunks);
     P.d_gtiles2 = nullptr;
-    int rc = upload(&P.d_gtiles2, P.gtiles2, &P.device_bytes);
+    P.d_gchunks = nullptr;
+    P.device_bytes -= P.gen_tile_bytes;
+    P.gen_tile_bytes = 0;
+    int rc = upload(&P.d_gtiles2, P.gtiles2, &P.gen_tile_bytes);
+    if (!rc) rc = upload(&P.d_gchunks, P.gchunks, &P.gen_tile_bytes);
+    P.device_bytes += P.gen_tile_bytes;
     if (rc) return rc;
     const DevPlanView v = P.view();
     ARKCOS_HIP_CHECK(hipMemcpy(P.d_view, &v, sizeof(v), hipMemcpyHostToDevice));
@@ -735,7 +792,11 @@ static int to_device(Plan &P)
     if ((rc = upload(&P.d_rows, P.rows, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_ctiles, P.ctiles, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_gtiles, P.gtiles, &P.device_bytes))) return rc;
-    if ((rc = upload(&P.d_gtiles2, P.gtiles2, &P.device_bytes))) return rc;
+    P.gen_tile_bytes = 0;
+    rc = upload(&P.d_gtiles2, P.gtiles2, &P.gen_tile_bytes);
+    if (!rc) rc = upload(&P.d_gchunks, P.gchunks, &P.gen_tile_bytes);
+    P.device_bytes += P.gen_tile_bytes;
+    if (rc) return rc;
     if ((rc = upload(&P.d_wts, std::vector<float>((size_t)std::max<long long>(P.nweights, 1), 0.0f),
                      &P.device_bytes)))
         return rc;
