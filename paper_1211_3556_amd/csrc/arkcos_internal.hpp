@@ -144,6 +144,19 @@ struct GenChunk {
     int mask;
 };
 static_assert(sizeof(GenChunk) == 32, "GenChunk layout");
+// The same for the single-ring tiles of the general knot gradient: one
+// chunk of the row of pair k (source ring s = pairs[k].s).
+struct KnotChunk {
+    int k;
+    int c0;
+    int cn;
+    int n;
+    int two_o;
+    int first;
+    int first_m;
+    int pad;
+};
+static_assert(sizeof(KnotChunk) == 32, "KnotChunk layout");
 constexpr int kTileLongSin = 1;   // some source row needs the long sine series
 constexpr int kTileIntM = 2;      // a longitude numerator may reach 2^24: keep it in int32
 constexpr int kTileSkipNorth = 4; // the northern ring is outside the plan's ring range
@@ -209,6 +222,8 @@ struct DevPlanView {
     const DevTile *gtiles;   // general tiles: (north ring, j0, len), pixels j <= jbar of quadrant 0
     const DevTile2 *gtiles2; // the same segments, two adjacent rings per tile (general gather)
     const GenChunk *gchunks; // their staged chunks, tile by tile
+    const KnotChunk *kgchunks; // staged chunks of the single-ring general tiles (gtiles)
+    const int2 *kgrange;     // per such tile: first chunk, number of chunks
     const DevTile *kctiles;  // circulant knot-gradient tiles: (group, j0, len)
     const double *kw;        // FP64 node coordinate per circulant weight slot, or -1
     int nctiles;
@@ -290,6 +305,8 @@ struct Plan {
     std::vector<double> ctile_cost, gtile_cost, gtile2_cost;
     std::vector<DevTile2> gtiles2;    // general-gather tiles (1, 2 or 4 rings), longest first
     std::vector<GenChunk> gchunks;    // their staged chunks
+    std::vector<KnotChunk> kgchunks;  // staged chunks of the single-ring tiles (knot gradient)
+    std::vector<int2> kgrange;        // per single-ring tile: first chunk, count
     arkcos_tiles tiles{};             // resolved general-gather tile shapes
     int tile_source = 0;              // 0 defaults, 1 tuning cache, 2 descriptor
     // the general northern rings in order, for the general-gather tiling:
@@ -326,6 +343,8 @@ struct Plan {
     DevTile *d_gtiles = nullptr;
     DevTile2 *d_gtiles2 = nullptr;
     GenChunk *d_gchunks = nullptr;
+    KnotChunk *d_kgchunks = nullptr;
+    int2 *d_kgrange = nullptr;
     long long gen_tile_bytes = 0;       // device bytes of d_gtiles2 and d_gchunks
     DevTile *d_kctiles = nullptr;
     double *d_kw = nullptr;             // knot node coordinates of the circulant slots

@@ -331,16 +331,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
     }
 }
 
-// ------------------------------------------------------- staging helpers --
-// Window bounds of a tile's first and last pixel on the row of pair pp.
-__device__ __forceinline__ void tile_window(const DevPair &pp, int n_s, const DevTile &T,
-                                            int &lo_min, int &hi_max)
-{
-    int dummy;
-    pair_window(pp, n_s, T.j0, lo_min, dummy);
-    pair_window(pp, n_s, T.j0 + T.len - 1, dummy, hi_max);
-}
-
 // --------------------------------------------------------- general gather --
 // Reflection about phi = pi/4 (phi -> pi/2 - phi) maps pixel j of quadrant 0
 // of a ring with offset o to jbar = n/4 - 2o - j, and a pair (j, j') to
@@ -595,38 +585,6 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
         else
             mf -= dmf;
     }
-}
-
-// Source rows of a tile are staged in chunks of kGenStage positions.
-struct GenStage {
-    int k;    // pair (row) index
-    int c0;   // first unwrapped source position
-    int cn;   // positions staged
-};
-
-// The chunk after `ch`: the rest of its row, else the first of the next row.
-__device__ __forceinline__ GenStage next_stage(const DevPlanView &P, const DevRing &R,
-                                               const DevTile &T, const GenStage &ch)
-{
-    GenStage nx;
-    const DevPair pp = cst(P.pairs)[ch.k];
-    int lo_min, hi_max;
-    tile_window(pp, cst(P.rings)[pp.s].n, T, lo_min, hi_max);
-    if (ch.c0 + kGenStage <= hi_max) {
-        nx.k = ch.k;
-        nx.c0 = ch.c0 + kGenStage;
-        nx.cn = min(kGenStage, hi_max - nx.c0 + 1);
-        return nx;
-    }
-    nx.k = ch.k + 1;
-    nx.c0 = 0;
-    nx.cn = 0;
-    if (nx.k < R.pair_end) {
-        const DevPair pn = cst(P.pairs)[nx.k];
-        tile_window(pn, cst(P.rings)[pn.s].n, T, nx.c0, hi_max);
-        nx.cn = min(kGenStage, hi_max - nx.c0 + 1);
-    }
-    return nx;
 }
 
 // FP32 partial sums are moved into the FP64 totals once a lane has
@@ -1371,22 +1329,19 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
                 gv[12 + q] = (refl && gs_ok) ? gsm[jb + q * qr] : 0.0f;
             }
         }
-        GenStage ch;
-        ch.k = R.pair_begin;
-        {
-            const DevPair pp = cst(P.pairs)[ch.k];
-            int hi_max;
-            tile_window(pp, cst(P.rings)[pp.s].n, T, ch.c0, hi_max);
-            ch.cn = min(kGenStage, hi_max - ch.c0 + 1);
-        }
+        // the tile's staged chunks (one record each, built on the host)
+        const int2 rg = cst(P.kgrange)[ti];
+        const cptr<KnotChunk> C = cst(P.kgchunks) + rg.x;
+        const int nch = rg.y;
         float4 pa, pb, pc, pd4;
-        {
-            const DevPair pp = cst(P.pairs)[ch.k];
-            const DevRing S = cst(P.rings)[pp.s];
-            prefetch16(in + S.first, in + cst(P.rings)[P.nrings - 1 - pp.s].first, S.n,
-                       S.two_o, ch.c0, ch.cn, pa, pb, pc, pd4);
+        KnotChunk ch{};
+        if (nch > 0) {
+            ch = C[0];
+            prefetch16(in + ch.first, in + ch.first_m, ch.n, ch.two_o, ch.c0, ch.cn, pa, pb, pc,
+                       pd4);
         }
-        while (ch.k < R.pair_end) {
+        for (int kc = 0; kc < nch; ++kc) {
+            const KnotChunk nx = C[min(kc + 1, nch - 1)];
             __syncthreads();
             if ((int)threadIdx.x < ch.cn) {
                 stage[threadIdx.x] = pa;
@@ -1397,16 +1352,11 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
             __syncthreads();
             const DevPair pp = cst(P.pairs)[ch.k];
             const DevPairD pd = cst(P.pairs_d)[ch.k];
-            const DevRing S = cst(P.rings)[pp.s];
-            const GenStage nx = next_stage(P, R, T, ch);
-            if (nx.k < R.pair_end) {
-                const DevPair pn = cst(P.pairs)[nx.k];
-                const DevRing Sn = cst(P.rings)[pn.s];
-                prefetch16(in + Sn.first, in + cst(P.rings)[P.nrings - 1 - pn.s].first,
-                           Sn.n, Sn.two_o, nx.c0, nx.cn, pa, pb, pc, pd4);
-            }
+            if (kc + 1 < nch)
+                prefetch16(in + nx.first, in + nx.first_m, nx.n, nx.two_o, nx.c0, nx.cn, pa, pb,
+                           pc, pd4);
             int lo, hi;
-            pair_window(pp, S.n, j, lo, hi);
+            pair_window(pp, ch.n, j, lo, hi);
             const int a0 = max(lo, ch.c0);
             const int a1 = min(hi, ch.c0 + ch.cn - 1);
             const int cnt = max(0, (a1 - a0 + 2 - ph) >> 1);   // this lane's candidates
@@ -1415,8 +1365,8 @@ __global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__rest
             // start candidate: the pixel's index modulo its count (exact: the
             // quotient of the float division is never within 1/(2 cnt) of an integer)
             const int skew = cnt > 0 ? lane_pix - cnt * (int)(((float)lane_pix + 0.5f) / (float)cnt) : 0;
-            const unsigned mbase = lon_base(j, R.two_o, S.n);
-            const int m0 = lon_numerator(mbase, jq0, S.two_o, R.n);
+            const unsigned mbase = lon_base(j, R.two_o, ch.n);
+            const int m0 = lon_numerator(mbase, jq0, ch.two_o, R.n);
             const int dm = 4 * R.n;
             const bool lg = (pp.mode & kPairLongSin) != 0;
             switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
