@@ -1149,30 +1149,36 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 gs[i * kKnotSeg + p] = (p < T.len && i < G.nr) ? gm[firsts[i] + p] : 0.0f;
         }
         __syncthreads();
+        // each wave takes every kKnotWaves-th row; the loads of its next row's
+        // source pixels are in flight while it works on the current one
+        constexpr int kXR = kKnotXW / 64 + 1;
+        float v[kXR];
+        auto load_row = [&](int row) {
+            const DevRow W = cst(P.rows)[row];
+            // the row's source pixels j0 + k_lo + e, e < nx (-n < k_lo and the
+            // positions stay below 3n, so wrap3 applies)
+            const int nx = 4 * (npq + ((W.ntaps + 3) >> 2));
+            const float *src = in + W.first_s;
+            const int base = T.j0 + W.k_lo;
+#pragma unroll
+            for (int u = 0; u < kXR; ++u) {
+                const int e = lane + 64 * u;
+                v[u] = e < nx ? src[wrap3(base + e, n)] : 0.0f;
+            }
+        };
+        if (G.row_begin + wave < G.row_end) load_row(G.row_begin + wave);
         for (int row = G.row_begin + wave; row < G.row_end; row += kKnotWaves) {
             const DevRow W = cst(P.rows)[row];
             const int nq = (W.ntaps + 3) >> 2;        // tap quads (<= 64)
             const int nc = 64 / nq;                   // lanes per tap quad
-            // the row's source pixels j0 + k_lo + e, e < nx (-n < k_lo and the
-            // positions stay below 3n, so wrap3 applies)
-            {
-                const int nx = 4 * (npq + nq);
-                const float *src = in + W.first_s;
-                const int base = T.j0 + W.k_lo;
-                float v[kKnotXW / 64 + 1];
+            wave_lds_order();   // the previous row's reads of xs are done
 #pragma unroll
-                for (int u = 0; u < kKnotXW / 64 + 1; ++u) {
-                    const int e = lane + 64 * u;
-                    v[u] = e < nx ? src[wrap3(base + e, n)] : 0.0f;
-                }
-                wave_lds_order();   // the previous row's reads of xs are done
-#pragma unroll
-                for (int u = 0; u < kKnotXW / 64 + 1; ++u) {
-                    const int e = lane + 64 * u;
-                    if (e < kKnotXW) xs[e] = v[u];
-                }
-                wave_lds_order();
+            for (int u = 0; u < kXR; ++u) {
+                const int e = lane + 64 * u;
+                if (e < kKnotXW) xs[e] = v[u];
             }
+            wave_lds_order();
+            if (row + kKnotWaves < G.row_end) load_row(row + kKnotWaves);
             const int q = lane / nc;
             const int c = lane - q * nc;
             float acc[kGroupRings][4];
@@ -1283,7 +1289,7 @@ __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const Node
 // per pixel, two lanes per pixel, source rows staged as in k_general).  A
 // lane holds g at the sixteen output images of its pixel; at a fixed point
 // of the reflection the reflected images are the pixel's own and get zero.
-__global__ __launch_bounds__(kThreads) void k_knot_gen(const DevPlanView *__restrict__ views,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_knot_gen(const DevPlanView *__restrict__ views,
                                                        const float *__restrict__ g,
                                                        const float *__restrict__ x, int nmaps,
                                                        double *__restrict__ partials)
