@@ -143,8 +143,11 @@ typedef struct {
     long long device_bytes;        /* device memory the plan holds                      */
     int circulant_rings;           /* output rings gathered with precomputed weight rows */
     int general_rings;             /* output rings gathered with per-pair weights       */
-    long long circulant_tiles;     /* work items of the two gathers per map             */
-    long long general_tiles;
+    long long circulant_tiles;     /* work items of the circulant gather per map        */
+    long long general_tiles;       /* half-quadrant segments (<= 128 pixels of one ring)
+                                      of the general rings; the general gather and its
+                                      knot gradient group them into tiles of 1, 2 or 4
+                                      rings (arkcos_plan_gen_tiles)                     */
     long long weights;             /* FP32 entries of the circulant weight rows         */
     double theta_break;            /* node grid of the descriptor (0, 0: uniform)       */
     int k_break;

@@ -144,19 +144,7 @@ struct GenChunk {
     int mask;
 };
 static_assert(sizeof(GenChunk) == 32, "GenChunk layout");
-// The same for the single-ring tiles of the general knot gradient: one
-// chunk of the row of pair k (source ring s = pairs[k].s).
-struct KnotChunk {
-    int k;
-    int c0;
-    int cn;
-    int n;
-    int two_o;
-    int first;
-    int first_m;
-    int pad;
-};
-static_assert(sizeof(KnotChunk) == 32, "KnotChunk layout");
+
 constexpr int kTileLongSin = 1;   // some source row needs the long sine series
 constexpr int kTileIntM = 2;      // a longitude numerator may reach 2^24: keep it in int32
 constexpr int kTileSkipNorth = 4; // the northern ring is outside the plan's ring range
@@ -219,15 +207,11 @@ struct DevPlanView {
     const DevRow *rows;      // their source rows
     float *wts;              // their weight rows (written by the weight-build kernel)
     const DevTile *ctiles;   // circulant tiles: (group, j0, len)
-    const DevTile *gtiles;   // general tiles: (north ring, j0, len), pixels j <= jbar of quadrant 0
     const DevTile2 *gtiles2; // the same segments, two adjacent rings per tile (general gather)
     const GenChunk *gchunks; // their staged chunks, tile by tile
-    const KnotChunk *kgchunks; // staged chunks of the single-ring general tiles (gtiles)
-    const int2 *kgrange;     // per such tile: first chunk, number of chunks
     const DevTile *kctiles;  // circulant knot-gradient tiles: (group, j0, len)
     const double *kw;        // FP64 node coordinate per circulant weight slot, or -1
     int nctiles;
-    int ngtiles;
     int ngtiles2;
     int nkctiles;
     int nkpart_circ;         // partial rows written by the circulant knot kernel
@@ -300,13 +284,11 @@ struct Plan {
     std::vector<DevGroup> groups;
     std::vector<DevRow> rows;
     std::vector<DevTile> ctiles;      // circulant tiles, longest first
-    std::vector<DevTile> gtiles;      // general tiles, longest first
+    std::vector<DevTile> gtiles;      // half-quadrant segments of the general rings (host only)
     std::vector<DevTile> kctiles;     // circulant knot-gradient tiles, longest first
     std::vector<double> ctile_cost, gtile_cost, gtile2_cost;
     std::vector<DevTile2> gtiles2;    // general-gather tiles (1, 2 or 4 rings), longest first
     std::vector<GenChunk> gchunks;    // their staged chunks
-    std::vector<KnotChunk> kgchunks;  // staged chunks of the single-ring tiles (knot gradient)
-    std::vector<int2> kgrange;        // per single-ring tile: first chunk, count
     arkcos_tiles tiles{};             // resolved general-gather tile shapes
     int tile_source = 0;              // 0 defaults, 1 tuning cache, 2 descriptor
     // the general northern rings in order, for the general-gather tiling:
@@ -340,11 +322,8 @@ struct Plan {
     DevRow *d_rows = nullptr;
     float *d_wts = nullptr;
     DevTile *d_ctiles = nullptr;
-    DevTile *d_gtiles = nullptr;
     DevTile2 *d_gtiles2 = nullptr;
     GenChunk *d_gchunks = nullptr;
-    KnotChunk *d_kgchunks = nullptr;
-    int2 *d_kgrange = nullptr;
     long long gen_tile_bytes = 0;       // device bytes of d_gtiles2 and d_gchunks
     DevTile *d_kctiles = nullptr;
     double *d_kw = nullptr;             // knot node coordinates of the circulant slots

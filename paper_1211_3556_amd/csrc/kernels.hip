@@ -846,13 +846,14 @@ __host__ __device__ constexpr int hist_offset_floats(int ntab) { return (ntab + 
 constexpr int kKnotWaves = kThreads / 64;
 __host__ __device__ constexpr int hist_stride(int ntab) { return (ntab + 1) & ~1; }
 
+template <int WAVES>
 __device__ __forceinline__ void write_partials(const double *hists, int hstride, int ntab,
                                                double *dst)
 {
     for (int i = threadIdx.x; i < ntab; i += blockDim.x) {
         double t = hists[i];
 #pragma unroll
-        for (int w = 1; w < kKnotWaves; ++w) t += hists[w * hstride + i];
+        for (int w = 1; w < WAVES; ++w) t += hists[w * hstride + i];
         dst[i] = t;
     }
 }
@@ -1232,7 +1233,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
         }
     }
     __syncthreads();
-    write_partials(hists, hstride, P.ntab, partials + (size_t)blockIdx.x * P.ntab);
+    write_partials<kKnotWaves>(hists, hstride, P.ntab, partials + (size_t)blockIdx.x * P.ntab);
 }
 
 // ------------------------------------------------- general rings: per pair --
@@ -1244,14 +1245,14 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
 // at each step instead of contending for one.
 template <bool LONG, int AM>
 __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const NodeMapD &nm,
-                                                  int m0, int dm, const float4 *stage, int c0,
-                                                  int cn, int jq0, int cnt, int skew, int T,
-                                                  const float gv[16], double *hist)
+                                                  int m0, int dm, int lp, const float4 *stage,
+                                                  int c0, int cn, int jq0, int cnt, int skew,
+                                                  int T, const float gv[16], double *hist)
 {
     for (int t = 0; t < T; ++t) {
         int tt = t + skew;
         tt = tt >= cnt ? tt - cnt : tt;
-        const int jq = jq0 + 2 * tt;
+        const int jq = jq0 + (tt << lp);
         const int m = m0 - __mul24(tt, dm);
         const int pos = min(max(jq - c0, 0), cn - 1);
         const float4 v0 = stage[pos];
@@ -1285,42 +1286,52 @@ __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const Node
     }
 }
 
-// Pairs whose output ring is general, over the general tiles (sixteen images
-// per pixel, two lanes per pixel, source rows staged as in k_general).  A
-// lane holds g at the sixteen output images of its pixel; at a fixed point
-// of the reflection the reflected images are the pixel's own and get zero.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_knot_gen(const DevPlanView *__restrict__ views,
-                                                       const float *__restrict__ g,
-                                                       const float *__restrict__ x, int nmaps,
-                                                       double *__restrict__ partials)
+// Pairs whose output ring is general, over the general gather's tiles and
+// staged chunks (1, 2 or 4 adjacent rings sharing each staged source chunk,
+// 2^lp lanes per pixel taking every 2^lp-th candidate).  A lane holds g at the
+// sixteen output images of its pixel (zero where a ring-range plan writes no
+// output, and for the reflected images at a fixed point of the reflection).
+// Workgroups take the items blockIdx.x, blockIdx.x + gridDim.x, ... and bin
+// into one histogram per wave.
+constexpr int kGenWaves = kGenThreads / 64;
+__global__ __launch_bounds__(kGenThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void k_knot_gen(const DevPlanView *__restrict__ views, const float *__restrict__ g,
+                const float *__restrict__ x, int nmaps, double *__restrict__ partials)
 {
     extern __shared__ __align__(16) double hists[];
     const DevPlanView P = cst(views)[0];
     const int hstride = hist_stride(P.ntab);
-    float4 *stage = reinterpret_cast<float4 *>(hists + kKnotWaves * hstride);
-    for (int i = threadIdx.x; i < kKnotWaves * hstride; i += blockDim.x) hists[i] = 0.0;
+    float4 *stage = reinterpret_cast<float4 *>(hists + kGenWaves * hstride);
+    for (int i = threadIdx.x; i < kGenWaves * hstride; i += blockDim.x) hists[i] = 0.0;
     double *hist = hists + (threadIdx.x >> 6) * hstride;   // this wave's own bins
     __syncthreads();
     const NodeMapD nm(P);
-    const int ph = threadIdx.x & 1;
-    const int lane_pix = threadIdx.x >> 1;
-    const int nitems = P.ngtiles * nmaps;
+    const int nitems = P.ngtiles2 * nmaps;
     for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
         const int ti = item / nmaps;
         const int map = item - ti * nmaps;
-        const DevTile T = cst(P.gtiles)[ti];
-        const int rn = T.r;
+        const DevTile2 *Tp = P.gtiles2 + ti;
+        const int nr = cst(Tp)->nr;
+        const int kPart = kGenThreads / nr;
+        const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x / kPart);
+        const int tid = (int)threadIdx.x - h * kPart;
+        const GenRing my = cst(Tp->q)[h];
+        const int len = my.len;
+        const int rn = my.r;
         const int rs = P.nrings - 1 - rn;
-        const bool mirror = rs != rn;
         const DevRing R = cst(P.rings)[rn];
         const int qr = R.n >> 2;
-        // a ring-range plan's outputs outside the range carry no g
-        const bool active = lane_pix < T.len;
-        const bool gn_ok = active && (T.flags & kTileSkipNorth) == 0;
-        const bool gs_ok = active && mirror && (T.flags & kTileSkipSouth) == 0;
-        const int j = T.j0 + min(lane_pix, T.len - 1);
+        int lp = 0;
+        while (lp < 6 && (kPart >> (lp + 1)) >= len) ++lp;
+        const int nph = 1 << lp;
+        const int ph = tid & (nph - 1);
+        const int lane_pix = tid >> lp;
+        const bool active = lane_pix < len;
+        const int j = cst(Tp)->j0 + min(lane_pix, max(len - 1, 0));
         const int jb = qr - R.two_o - j;
-        const bool refl = active && jb != j && jb != qr;
+        const bool gn_ok = active && (my.flags & kTileSkipNorth) == 0;
+        const bool gs_ok = active && rs != rn && (my.flags & kTileSkipSouth) == 0;
+        const bool refl = jb != j && jb != qr;
         const float *in = x + (size_t)map * P.npix;
         const float *gm = g + (size_t)map * P.npix;
         float gv[16];
@@ -1335,19 +1346,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                 gv[12 + q] = (refl && gs_ok) ? gsm[jb + q * qr] : 0.0f;
             }
         }
-        // the tile's staged chunks (one record each, built on the host)
-        const int2 rg = cst(P.kgrange)[ti];
-        const cptr<KnotChunk> C = cst(P.kgchunks) + rg.x;
-        const int nch = rg.y;
+        const cptr<GenChunk> C = cst(P.gchunks) + cst(Tp)->c_begin;
+        const int nch = cst(Tp)->nchunks;
         float4 pa, pb, pc, pd4;
-        KnotChunk ch{};
+        GenChunk ch{};
         if (nch > 0) {
             ch = C[0];
-            prefetch16(in + ch.first, in + ch.first_m, ch.n, ch.two_o, ch.c0, ch.cn, pa, pb, pc,
-                       pd4);
+            prefetch_chunk(in, ch, pa, pb, pc, pd4);
         }
-        for (int kc = 0; kc < nch; ++kc) {
-            const KnotChunk nx = C[min(kc + 1, nch - 1)];
+        for (int k = 0; k < nch; ++k) {
+            const GenChunk nx = C[min(k + 1, nch - 1)];
             __syncthreads();
             if ((int)threadIdx.x < ch.cn) {
                 stage[threadIdx.x] = pa;
@@ -1356,39 +1364,40 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
                 stage[3 * kGenStage + threadIdx.x] = pd4;
             }
             __syncthreads();
-            const DevPair pp = cst(P.pairs)[ch.k];
-            const DevPairD pd = cst(P.pairs_d)[ch.k];
-            if (kc + 1 < nch)
-                prefetch16(in + nx.first, in + nx.first_m, nx.n, nx.two_o, nx.c0, nx.cn, pa, pb,
-                           pc, pd4);
-            int lo, hi;
-            pair_window(pp, ch.n, j, lo, hi);
-            const int a0 = max(lo, ch.c0);
-            const int a1 = min(hi, ch.c0 + ch.cn - 1);
-            const int cnt = max(0, (a1 - a0 + 2 - ph) >> 1);   // this lane's candidates
-            const int nt = wave_max(cnt);
-            const int jq0 = a0 + ph;
-            // start candidate: the pixel's index modulo its count (exact: the
-            // quotient of the float division is never within 1/(2 cnt) of an integer)
-            const int skew = cnt > 0 ? lane_pix - cnt * (int)(((float)lane_pix + 0.5f) / (float)cnt) : 0;
-            const unsigned mbase = lon_base(j, R.two_o, ch.n);
-            const int m0 = lon_numerator(mbase, jq0, ch.two_o, R.n);
-            const int dm = 4 * R.n;
-            const bool lg = (pp.mode & kPairLongSin) != 0;
-            switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                case 0: knot_candidates16<false, 0>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                case 1: knot_candidates16<true, 0>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                case 2: knot_candidates16<false, 1>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                case 3: knot_candidates16<true, 1>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                case 4: knot_candidates16<false, 2>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                default: knot_candidates16<true, 2>(pd, nm, m0, dm, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+            if (k + 1 < nch) prefetch_chunk(in, nx, pa, pb, pc, pd4);
+            if (len > 0 && ch.s >= my.s_lo && ch.s <= my.s_hi) {
+                const int kk = my.pb + ch.s - my.s_lo;
+                const DevPair pp = cst(P.pairs)[kk];
+                const DevPairD pd = cst(P.pairs_d)[kk];
+                int lo, hi;
+                pair_window(pp, ch.n, j, lo, hi);
+                const int a0 = max(lo, ch.c0);
+                const int a1 = min(hi, ch.c0 + ch.cn - 1);
+                const int cnt = a1 - a0 - ph >= 0 ? ((a1 - a0 - ph) >> lp) + 1 : 0;
+                const int nt = wave_max(cnt);
+                const int jq0 = a0 + ph;
+                // start candidate: the pixel's index modulo its count (exact: the
+                // quotient of the float division is never within 1/(2 cnt) of an integer)
+                const int skew = cnt > 0 ? lane_pix - cnt * (int)(((float)lane_pix + 0.5f) / (float)cnt) : 0;
+                const unsigned mbase = lon_base(j, R.two_o, ch.n);
+                const int m0 = lon_numerator(mbase, jq0, ch.two_o, R.n);
+                const int dm = 2 * nph * R.n;
+                const bool lg = (pp.mode & kPairLongSin) != 0;
+                switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
+                    case 0: knot_candidates16<false, 0>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                    case 1: knot_candidates16<true, 0>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                    case 2: knot_candidates16<false, 1>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                    case 3: knot_candidates16<true, 1>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                    case 4: knot_candidates16<false, 2>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                    default: knot_candidates16<true, 2>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
+                }
             }
             ch = nx;
         }
     }
     __syncthreads();
-    write_partials(hists, hstride, P.ntab,
-                   partials + ((size_t)P.nkpart_circ + blockIdx.x) * P.ntab);
+    write_partials<kGenWaves>(hists, hstride, P.ntab,
+                              partials + ((size_t)P.nkpart_circ + blockIdx.x) * P.ntab);
 }
 // Fixed-order reduction of the per-workgroup partials, scaled by Omega: a
 // block of kReduceWaves waves covers 64 knots, wave w sums rows w, w + kReduceWaves, ...,
@@ -1472,7 +1481,8 @@ static size_t knot_circ_lds(int ntab)
 }
 static size_t knot_gen_lds(int ntab)
 {
-    return knot_hist_bytes(ntab) + (size_t)4 * kGenStage * sizeof(float4);
+    return (size_t)kGenWaves * hist_stride(ntab) * sizeof(double) +
+           (size_t)4 * kGenStage * sizeof(float4);
 }
 
 
@@ -1487,14 +1497,15 @@ int prepare_launches(Plan &p)
     p.grid_kc = p.grid_kg = 0;
     if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
         if ((rc = occupancy(k_knot_circ, knot_circ_lds(p.desc.ntab), &p.occ_kc))) return rc;
-        if ((rc = occupancy(k_knot_gen, knot_gen_lds(p.desc.ntab), &p.occ_kg))) return rc;
+        if ((rc = occupancy(k_knot_gen, knot_gen_lds(p.desc.ntab), &p.occ_kg, kGenThreads)))
+            return rc;
         // one partial row per resident workgroup of each knot kernel, and no
         // more workgroups than work items
         const long long mb = std::max(1, p.desc.max_batch);
         p.grid_kc = (int)std::min<long long>((long long)p.occ_kc * p.cus,
                                              (long long)p.kctiles.size() * mb);
         p.grid_kg = (int)std::min<long long>((long long)p.occ_kg * p.cus,
-                                             (long long)p.gtiles.size() * mb);
+                                             (long long)p.gtiles2.size() * mb);
     }
     p.grid = std::max(1, p.grid_kc + p.grid_kg);
     return ARKCOS_OK;
@@ -1576,7 +1587,7 @@ static int launch_knot(const Plan &p, const float *g, const float *x, float *gk,
         hipLaunchKernelGGL(k_knot_circ, dim3(p.grid_kc), dim3(kThreads), knot_circ_lds(ntab), s,
                            (const DevPlanView *)p.d_view, g, x, nbatch, kpart);
     if (p.grid_kg > 0)
-        hipLaunchKernelGGL(k_knot_gen, dim3(p.grid_kg), dim3(kThreads), knot_gen_lds(ntab), s,
+        hipLaunchKernelGGL(k_knot_gen, dim3(p.grid_kg), dim3(kGenThreads), knot_gen_lds(ntab), s,
                            (const DevPlanView *)p.d_view, g, x, nbatch, kpart);
     ARKCOS_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 63) / 64), dim3(64 * kReduceWaves), 0, s,

@@ -116,15 +116,11 @@ DevPlanView Plan::view() const
     v.rows = d_rows;
     v.wts = d_wts;
     v.ctiles = d_ctiles;
-    v.gtiles = d_gtiles;
     v.gtiles2 = d_gtiles2;
     v.gchunks = d_gchunks;
-    v.kgchunks = d_kgchunks;
-    v.kgrange = d_kgrange;
     v.kctiles = d_kctiles;
     v.kw = d_kw;
     v.nctiles = (int)ctiles.size();
-    v.ngtiles = (int)gtiles.size();
     v.ngtiles2 = (int)gtiles2.size();
     v.nkctiles = (int)kctiles.size();
     v.nkpart_circ = grid_kc;
@@ -242,40 +238,6 @@ static void build_gen_chunks(Plan &P)
             }
         }
         t.nchunks = (int)P.gchunks.size() - t.c_begin;
-    }
-}
-
-// Staged chunks of the single-ring general tiles (the knot gradient's), in
-// tile order: each row of the tile's ring, over the window of the tile's
-// first pixel's lower end to its last pixel's upper end, in chunks of
-// kGenStage positions; rows with an empty window are not staged.
-static void build_knot_chunks(Plan &P)
-{
-    P.kgchunks.clear();
-    P.kgrange.assign(P.gtiles.size(), int2{0, 0});
-    for (size_t t = 0; t < P.gtiles.size(); ++t) {
-        const DevTile &T = P.gtiles[t];
-        const DevRing &R = P.dev_rings[T.r];
-        P.kgrange[t].x = (int)P.kgchunks.size();
-        for (int k = R.pair_begin; k < R.pair_end; ++k) {
-            const DevPair &pp = P.pairs[k];
-            const DevRing &S = P.dev_rings[pp.s];
-            int lo, hi, dummy;
-            pair_window(pp, S.n, T.j0, lo, dummy);
-            pair_window(pp, S.n, T.j0 + T.len - 1, dummy, hi);
-            for (int c0 = lo; c0 <= hi; c0 += kGenStage) {
-                KnotChunk c{};
-                c.k = k;
-                c.c0 = c0;
-                c.cn = std::min(kGenStage, hi - c0 + 1);
-                c.n = S.n;
-                c.two_o = S.two_o;
-                c.first = S.first;
-                c.first_m = P.dev_rings[P.nrings - 1 - pp.s].first;
-                P.kgchunks.push_back(c);
-            }
-        }
-        P.kgrange[t].y = (int)P.kgchunks.size() - P.kgrange[t].x;
     }
 }
 
@@ -581,7 +543,6 @@ static int build_plan(Plan &P)
     sort_by_cost(P.gtiles, cost);
     P.gtile_cost = cost;
     build_gen_tiles(P);
-    build_knot_chunks(P);
 
     // Circulant knot-gradient tiles: kKnotSeg consecutive pixels of every
     // ring of a group.
@@ -736,11 +697,8 @@ static void free_device(Plan &P)
         (void)hipFree(P.d_rows);
         (void)hipFree(P.d_wts);
         (void)hipFree(P.d_ctiles);
-        (void)hipFree(P.d_gtiles);
         (void)hipFree(P.d_gtiles2);
         (void)hipFree(P.d_gchunks);
-        (void)hipFree(P.d_kgchunks);
-        (void)hipFree(P.d_kgrange);
         (void)hipFree(P.d_kctiles);
         (void)hipFree(P.d_kw);
         (void)hipFree(P.d_view);
@@ -756,11 +714,8 @@ static void free_device(Plan &P)
     P.d_rows = nullptr;
     P.d_wts = nullptr;
     P.d_ctiles = nullptr;
-    P.d_gtiles = nullptr;
     P.d_gtiles2 = nullptr;
     P.d_gchunks = nullptr;
-    P.d_kgchunks = nullptr;
-    P.d_kgrange = nullptr;
     P.gen_tile_bytes = 0;
     P.d_kctiles = nullptr;
     P.d_kw = nullptr;
@@ -832,7 +787,6 @@ static int to_device(Plan &P)
     if ((rc = upload(&P.d_groups, P.groups, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_rows, P.rows, &P.device_bytes))) return rc;
     if ((rc = upload(&P.d_ctiles, P.ctiles, &P.device_bytes))) return rc;
-    if ((rc = upload(&P.d_gtiles, P.gtiles, &P.device_bytes))) return rc;
     P.gen_tile_bytes = 0;
     rc = upload(&P.d_gtiles2, P.gtiles2, &P.gen_tile_bytes);
     if (!rc) rc = upload(&P.d_gchunks, P.gchunks, &P.gen_tile_bytes);
@@ -849,8 +803,6 @@ static int to_device(Plan &P)
         std::vector<double> z((size_t)P.grid * P.desc.ntab, 0.0);
         if ((rc = upload(&P.d_kpart, z, &P.device_bytes))) return rc;
         if ((rc = upload(&P.d_kctiles, P.kctiles, &P.device_bytes))) return rc;
-        if ((rc = upload(&P.d_kgchunks, P.kgchunks, &P.device_bytes))) return rc;
-        if ((rc = upload(&P.d_kgrange, P.kgrange, &P.device_bytes))) return rc;
         if ((rc = upload(&P.d_kw, std::vector<double>((size_t)std::max<long long>(P.nweights, 1), -1.0),
                          &P.device_bytes)))
             return rc;
