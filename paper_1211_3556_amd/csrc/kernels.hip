@@ -1293,7 +1293,10 @@ __device__ __forceinline__ void knot_candidates16(const DevPairD &pd, const Node
 // output, and for the reflected images at a fixed point of the reflection).
 // Workgroups take the items blockIdx.x, blockIdx.x + gridDim.x, ... and bin
 // into one histogram per wave.
+// One instantiation per angle mode (AM), so that only that mode's FP64 series
+// constants occupy registers.
 constexpr int kGenWaves = kGenThreads / 64;
+template <int AM>
 __global__ __launch_bounds__(kGenThreads) __attribute__((amdgpu_waves_per_eu(4)))
 void k_knot_gen(const DevPlanView *__restrict__ views, const float *__restrict__ g,
                 const float *__restrict__ x, int nmaps, double *__restrict__ partials)
@@ -1382,15 +1385,12 @@ void k_knot_gen(const DevPlanView *__restrict__ views, const float *__restrict__
                 const unsigned mbase = lon_base(j, R.two_o, ch.n);
                 const int m0 = lon_numerator(mbase, jq0, ch.two_o, R.n);
                 const int dm = 2 * nph * R.n;
-                const bool lg = (pp.mode & kPairLongSin) != 0;
-                switch (P.angle_mode * 2 + (lg ? 1 : 0)) {
-                    case 0: knot_candidates16<false, 0>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                    case 1: knot_candidates16<true, 0>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                    case 2: knot_candidates16<false, 1>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                    case 3: knot_candidates16<true, 1>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                    case 4: knot_candidates16<false, 2>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                    default: knot_candidates16<true, 2>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0, cnt, skew, nt, gv, hist); break;
-                }
+                if (pp.mode & kPairLongSin)
+                    knot_candidates16<true, AM>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0,
+                                                cnt, skew, nt, gv, hist);
+                else
+                    knot_candidates16<false, AM>(pd, nm, m0, dm, lp, stage, ch.c0, ch.cn, jq0,
+                                                 cnt, skew, nt, gv, hist);
             }
             ch = nx;
         }
@@ -1497,7 +1497,8 @@ int prepare_launches(Plan &p)
     p.grid_kc = p.grid_kg = 0;
     if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
         if ((rc = occupancy(k_knot_circ, knot_circ_lds(p.desc.ntab), &p.occ_kc))) return rc;
-        if ((rc = occupancy(k_knot_gen, knot_gen_lds(p.desc.ntab), &p.occ_kg, kGenThreads)))
+        // (the three angle-mode instantiations have the same resource limits)
+        if ((rc = occupancy(k_knot_gen<0>, knot_gen_lds(p.desc.ntab), &p.occ_kg, kGenThreads)))
             return rc;
         // one partial row per resident workgroup of each knot kernel, and no
         // more workgroups than work items
@@ -1586,9 +1587,12 @@ static int launch_knot(const Plan &p, const float *g, const float *x, float *gk,
     if (p.grid_kc > 0)
         hipLaunchKernelGGL(k_knot_circ, dim3(p.grid_kc), dim3(kThreads), knot_circ_lds(ntab), s,
                            (const DevPlanView *)p.d_view, g, x, nbatch, kpart);
-    if (p.grid_kg > 0)
-        hipLaunchKernelGGL(k_knot_gen, dim3(p.grid_kg), dim3(kGenThreads), knot_gen_lds(ntab), s,
+    if (p.grid_kg > 0) {
+        auto kg = p.angle_mode == 0 ? k_knot_gen<0>
+                                    : (p.angle_mode == 1 ? k_knot_gen<1> : k_knot_gen<2>);
+        hipLaunchKernelGGL(kg, dim3(p.grid_kg), dim3(kGenThreads), knot_gen_lds(ntab), s,
                            (const DevPlanView *)p.d_view, g, x, nbatch, kpart);
+    }
     ARKCOS_HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_knot_reduce, dim3((ntab + 63) / 64), dim3(64 * kReduceWaves), 0, s,
                        kpart, p.grid_kc + p.grid_kg, ntab, p.omega, gk);
