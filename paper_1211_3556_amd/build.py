@@ -21,6 +21,7 @@ LIB = os.path.join(HERE, "libarkcos.so")
 SOURCES = ["plan.hip", "kernels.hip", "capi.hip", "sht.hip", "tune.hip"]
 HEADERS = [os.path.join(CSRC, "arkcos_internal.hpp"), os.path.join(INCLUDE, "arkcos.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+ROCM_LIB = "/opt/rocm/lib"   # roctx (profiler ranges around the entry points)
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -56,7 +57,7 @@ def build(force: bool = True) -> str:
         list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH, *[_obj(s) for s in SOURCES],
-           "-o", tmp]
+           "-L" + ROCM_LIB, "-lrocprofiler-sdk-roctx", "-Wl,-rpath," + ROCM_LIB, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))

@@ -16,6 +16,17 @@ namespace arkcos {
 int fail(int status, const std::string &msg);   // records arkcos_last_error text
 void clear_error();
 
+// ------------------------------------------------------- profiler ranges --
+// A roctx range named after an entry point, open for the lifetime of the
+// object, so that traces (rocprofv3 --marker-trace) show plan builds and
+// gathers under the call that issued them.
+struct TraceRange {
+    explicit TraceRange(const char *name);
+    ~TraceRange();
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
+
 #define ARKCOS_HIP_CHECK(call)                                                        \
     do {                                                                              \
         hipError_t e_ = (call);                                                       \

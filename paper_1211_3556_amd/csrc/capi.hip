@@ -75,6 +75,7 @@ extern "C" {
 int arkcos_convolve_part(arkcos_plan_t plan, const float *d_in, float *d_out, int nbatch, int part,
                          void *stream)
 {
+    TraceRange tr("arkcos_convolve");
     clear_error();
     if (!plan || !d_in || !d_out) return fail(ARKCOS_EINVAL, "NULL pointer");
     if (part < 1 || part > ARKCOS_PART_ALL) return fail(ARKCOS_EINVAL, "unknown part");
@@ -125,6 +126,7 @@ static int check_backward(const Plan *P, const float *d_grad_out, const float *d
 int arkcos_convolve_backward(arkcos_plan_t plan, const float *d_grad_out, const float *d_in,
                              float *d_grad_in, float *d_grad_knots, int nbatch, void *stream)
 {
+    TraceRange tr("arkcos_convolve_backward");
     clear_error();
     if (!plan || !d_grad_out) return fail(ARKCOS_EINVAL, "NULL pointer");
     const Plan *P = reinterpret_cast<const Plan *>(plan);
@@ -139,6 +141,7 @@ int arkcos_convolve_backward_static(arkcos_plan_t plan, const float *d_grad_out,
                                     const float *d_in, float *d_grad_in, float *d_grad_knots,
                                     int nbatch, void *stream)
 {
+    TraceRange tr("arkcos_convolve_backward_static");
     clear_error();
     if (!plan || !d_grad_out) return fail(ARKCOS_EINVAL, "NULL pointer");
     const Plan *P = reinterpret_cast<const Plan *>(plan);
@@ -246,6 +249,7 @@ int arkcos_batch_convolve_part(arkcos_batch_t batch, const float *const *d_in,
                                float *const *d_out, int part, void *stream)
 {
     clear_error();
+    TraceRange tr("arkcos_batch_convolve");
     if (!batch || !d_in || !d_out) return fail(ARKCOS_EINVAL, "NULL pointer");
     if (part < 1 || part > ARKCOS_PART_ALL) return fail(ARKCOS_EINVAL, "unknown part");
     const Batch *B = reinterpret_cast<const Batch *>(batch);

@@ -12,11 +12,34 @@
 #include <string>
 #include <thread>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "arkcos_internal.hpp"
 
 namespace arkcos {
 
 static thread_local std::string g_last_error;
+
+TraceRange::TraceRange(const char *name) { roctxRangePushA(name); }
+TraceRange::~TraceRange() { roctxRangePop(); }
+
+// ARKCOS_LOG=1: one line of plan statistics on stderr per plan built.
+static void log_plan(const Plan &P)
+{
+    const char *v = getenv("ARKCOS_LOG");
+    if (!v || std::string(v) != "1") return;
+    const int ngen_rings = (int)std::count(P.general_ring.begin(), P.general_ring.end(), 1);
+    fprintf(stderr,
+            "[arkcos] plan nside %d theta_cut %.6g rad ntab %d%s%s: rings %d circulant / %d "
+            "general, ring pairs %zu, circulant tiles %zu, general tiles %zu (%zu staged "
+            "chunks; shapes %d/%d/%d from %s), weights %lld, device bytes %lld\n",
+            P.nside, P.desc.theta_cut, P.desc.ntab, P.desc.k_break > 0 ? " biased" : "",
+            P.desc.ring_first > 0 ? " ring range" : "", P.nrings - ngen_rings, ngen_rings,
+            P.pairs.size(), P.ctiles.size(), P.gtiles2.size(), P.gchunks.size(),
+            P.tiles.gen_pixels, P.tiles.gen_quad_window, P.tiles.gen_pair_window,
+            P.tile_source == 0 ? "defaults" : (P.tile_source == 1 ? "tuning cache" : "descriptor"),
+            P.nweights, P.device_bytes);
+}
 
 int fail(int status, const std::string &msg)
 {
@@ -940,6 +963,7 @@ int arkcos_ring_info(int nside, int ring, double *z, double *sin_theta, int *npi
 int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
 {
     clear_error();
+    TraceRange tr("arkcos_plan_create");
     if (!out) return fail(ARKCOS_EINVAL, "NULL output pointer");
     *out = nullptr;
     if (!desc) return fail(ARKCOS_EINVAL, "NULL descriptor");
@@ -1005,6 +1029,7 @@ int arkcos_plan_create(const arkcos_plan_desc *desc, arkcos_plan_t *out)
         destroy_plan(P);
         return rc;
     }
+    log_plan(*P);
     *out = reinterpret_cast<arkcos_plan_t>(P);
     return ARKCOS_OK;
 }

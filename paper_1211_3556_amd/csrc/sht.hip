@@ -960,6 +960,7 @@ int arkcos_harm_convolve(arkcos_harm_t harm, const float *d_in, float *d_out, in
                          int accumulate, void *stream)
 {
     clear_error();
+    TraceRange tr("arkcos_harm_convolve");
     if (!harm || !d_in || !d_out) return fail(ARKCOS_EINVAL, "NULL pointer");
     const Harm *h = reinterpret_cast<const Harm *>(harm);
     if (nbatch < 1 || nbatch > h->max_batch)
@@ -979,6 +980,7 @@ int arkcos_split_convolve(arkcos_plan_t plan, arkcos_harm_t harm, const float *d
                           float *d_out, int nbatch, void *stream)
 {
     clear_error();
+    TraceRange tr("arkcos_split_convolve");
     if (!plan || !harm) return fail(ARKCOS_EINVAL, "NULL plan");
     const Plan *P = reinterpret_cast<const Plan *>(plan);
     const Harm *h = reinterpret_cast<const Harm *>(harm);

@@ -359,3 +359,22 @@ def test_ring_range_adjoint_rings(nside, tc_deg, rings):
             if np.min(np.abs(th[s] - th[rings[0] - 1:rings[1]])) < tc]
     assert (inf["adjoint_ring_first"], inf["adjoint_ring_last"]) == (near[0], near[-1])
     assert A.Plan(nside, tc, np.ones(8), host_only=True).info()["adjoint_ring_first"] == 0
+
+
+def test_plan_log_line():
+    """ARKCOS_LOG=1 prints one line of plan statistics per plan to stderr."""
+    import subprocess
+    import sys
+    code = ("import numpy as np, paper_1211_3556_amd as A; "
+            "A.Plan(32, np.radians(5.0), np.ones(64), host_only=True)")
+    env = dict(os.environ, ARKCOS_LOG="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       cwd=os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    assert r.returncode == 0, r.stderr
+    lines = [l for l in r.stderr.splitlines() if l.startswith("[arkcos] plan")]
+    assert len(lines) == 1
+    p = A.Plan(32, np.radians(5.0), np.ones(64), host_only=True)
+    inf = p.info()
+    assert "nside 32" in lines[0] and "ring pairs %d" % inf["ring_pairs"] in lines[0]
+    assert "rings %d circulant / %d general" % (inf["circulant_rings"], inf["general_rings"]) \
+        in lines[0]
