@@ -488,6 +488,31 @@ int arkcos_harm_convolve(arkcos_harm_t harm, const float *d_in, float *d_out, in
 int arkcos_split_convolve(arkcos_plan_t plan, arkcos_harm_t harm, const float *d_in,
                           float *d_out, int nbatch, void *stream);
 
+/* ------------------------------------------ polar-cap reorientation -- */
+/*
+ * The rotation that takes the direction (theta, phi) (colatitude and
+ * longitude, radians) to the north pole: R = R_y(-theta) R_z(-phi), written
+ * row-major into rot[9] (host).  With it, arkcos_rotate_map moves a survey
+ * patch centred on (theta, phi) onto the north polar cap, where a ring-range
+ * plan convolves it over the few rings it spans (Sec. 4, Conclusions).
+ * EINVAL on NULL or non-finite angles.
+ */
+int arkcos_rotation_to_pole(double theta, double phi, double *rot);
+
+/*
+ * Rotated copy of nbatch RING maps (stride Npix) at nearest-pixel resampling:
+ * for every pixel p of output rings ring_first..ring_last (1-based,
+ * inclusive; 0, 0 = all), with centre n_p,
+ *     d_out[p] = d_in[q],  q the pixel whose boundaries contain R^T n_p,
+ * so a feature at direction c of d_in appears at R c of d_out.  Pixels of
+ * other rings are not written.  rot: 9 host doubles, row-major, a rotation
+ * (|R R^T - I| <= 1e-9 and det R > 0, else EINVAL); copied.  Geometry and
+ * point location run in FP64 on the device.  d_in and d_out must not overlap
+ * (EINVAL).  Asynchronous on `stream`; allocates nothing.
+ */
+int arkcos_rotate_map(int nside, const double *rot, const float *d_in, float *d_out, int nbatch,
+                      int ring_first, int ring_last, void *stream);
+
 const char *arkcos_status_string(int status);
 
 /* Per-thread detail of the last failing call ("" if none). */

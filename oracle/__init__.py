@@ -58,6 +58,9 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         lib.orc_ring.argtypes = [ctypes.c_long, ctypes.c_long, _dp, _dp, _dp, _lp, _lp, _dp]
         lib.orc_pix2vec.argtypes = [ctypes.c_long, ctypes.c_long, _lp, _dp]
+        lib.orc_vec2pix.argtypes = [ctypes.c_long, ctypes.c_long, _dp, _lp]
+        lib.orc_rotate_map.argtypes = [ctypes.c_long, _dp, ctypes.c_long, ctypes.c_long, _dp,
+                                       _dp]
         lib.orc_tabulate.argtypes = [_dp, ctypes.c_long, ctypes.c_double, ctypes.c_long, _dp,
                                      _dp]
         for name in ("orc_convolve", "orc_convolve_exhaustive"):
@@ -137,6 +140,36 @@ def pix2vec(nside: int, pix=None) -> np.ndarray:
     out = np.empty((pix.size, 3))
     _check(_load().orc_pix2vec(nside, pix.size, _l(pix), _d(out)), "pix2vec")
     return out
+
+
+def vec2pix(nside: int, vec) -> np.ndarray:
+    """RING pixels containing the directions of the rows of `vec` (n, 3),
+    from the HEALPix pixel boundaries (Gorski et al. 2005)."""
+    v = np.ascontiguousarray(np.atleast_2d(vec), dtype=np.float64)
+    out = np.empty(v.shape[0], dtype=np.int64)
+    _check(_load().orc_vec2pix(nside, v.shape[0], _d(v), _l(out)), "vec2pix")
+    return out
+
+
+def rotation_to_pole(theta: float, phi: float) -> np.ndarray:
+    """The rotation R_y(-theta) R_z(-phi), which takes the direction
+    (theta, phi) to the north pole."""
+    ct, st, cp, sp = np.cos(theta), np.sin(theta), np.cos(phi), np.sin(phi)
+    rz = np.array([[cp, sp, 0.0], [-sp, cp, 0.0], [0.0, 0.0, 1.0]])
+    ry = np.array([[ct, 0.0, -st], [0.0, 1.0, 0.0], [st, 0.0, ct]])
+    return ry @ rz
+
+
+def rotate_map(nside: int, rot, x, rings=None, out=None) -> np.ndarray:
+    """out[p] = x[pixel containing R^T n_p] for the pixels of `rings`
+    (1-based, inclusive; all by default): the map rotated by R, resampled at
+    the nearest pixel.  Other pixels of `out` (zeros if not given) are kept."""
+    r = np.ascontiguousarray(rot, dtype=np.float64).reshape(3, 3)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros_like(x) if out is None else np.array(out, dtype=np.float64, copy=True)
+    lo, hi = (1, 4 * nside - 1) if rings is None else rings
+    _check(_load().orc_rotate_map(nside, _d(r), lo, hi, _d(x), _d(y)), "rotate_map")
+    return y
 
 
 def gaussian_bl(fwhm_rad: float, lmax: int) -> np.ndarray:

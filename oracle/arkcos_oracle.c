@@ -634,6 +634,92 @@ int orc_legendre_lm(long L, double theta, double *lam)
     return 0;
 }
 
+/*
+ * The RING pixel containing a direction (z = cos theta, phi), from the
+ * HEALPix pixel boundaries (Gorski et al. 2005).  With t = phi / (pi/2):
+ *   equatorial zone |z| <= 2/3: the boundaries are the lines
+ *     N (1/2 + t - 3z/4) = integer  and  N (1/2 + t + 3z/4) = integer;
+ *     with a = floor of the first and b = floor of the second, the point is
+ *     in ring i = N + a - b (1-based) at in-ring index
+ *     floor((a + b - N + [i - N odd] + 1) / 2) mod 4N;
+ *   polar caps |z| > 2/3: with r = N sqrt(3 (1 - |z|)) and tq = t - floor(t)
+ *     the longitude within the quadrant, the boundaries are the curves
+ *     tq r = integer and (1 - tq) r = integer; the ring counted from the
+ *     nearest pole is k = floor(tq r) + floor((1 - tq) r) + 1, and the index
+ *     floor(t k) mod 4k.
+ * At every pixel centre both reduce to the centre's own ring and index.
+ */
+static long vec2pix_ring(long N, double z, double phi)
+{
+    const double dN = (double)N;
+    double t = phi / (0.5 * M_PI);
+    t = fmod(t, 4.0);
+    if (t < 0.0) t += 4.0;
+    if (fabs(z) <= 2.0 / 3.0) {
+        const long a = (long)floor(dN * (0.5 + t - 0.75 * z));
+        const long b = (long)floor(dN * (0.5 + t + 0.75 * z));
+        const long ir = N + 1 + a - b;              /* 1 .. 2N+1 from ring N */
+        const long odd = (ir & 1) ? 0 : 1;           /* ring i = N + ir - 1: [i - N odd] */
+        long ip = (a + b - N + odd + 1) / 2;
+        ip %= 4 * N;
+        if (ip < 0) ip += 4 * N;
+        return 2 * N * (N - 1) + 4 * N * (ir - 1) + ip;
+    }
+    const double tq = t - floor(t);
+    const double r = dN * sqrt(3.0 * (1.0 - fabs(z)));
+    const long a = (long)floor(tq * r);
+    const long b = (long)floor((1.0 - tq) * r);
+    long k = a + b + 1;                              /* N only next to |z| = 2/3 */
+    if (k > N) k = N;
+    if (k < 1) k = 1;
+    long ip = (long)floor(t * (double)k);
+    ip %= 4 * k;
+    if (z > 0.0) return 2 * k * (k - 1) + ip;
+    return 12L * N * N - 2 * k * (k + 1) + ip;
+}
+
+/* RING pixels of a list of unit vectors (3*n doubles). */
+int orc_vec2pix(long nside, long n, const double *xyz, long *pix)
+{
+    if (nside < 1) return -1;
+    for (long k = 0; k < n; ++k) {
+        const double *v = xyz + 3 * k;
+        const double rr = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        if (!(rr > 0.0)) return -1;
+        pix[k] = vec2pix_ring(nside, v[2] / rr, atan2(v[1], v[0]));
+    }
+    return 0;
+}
+
+/*
+ * Rotated copy of a map: for every pixel p of rings ring_first..ring_last
+ * (1-based, inclusive), with centre n_p, out[p] = in[q] where q is the pixel
+ * containing R^T n_p; a feature at direction c of `in` appears at R c of
+ * `out` (rot: row-major 3x3 rotation).  Other pixels of out are untouched.
+ */
+int orc_rotate_map(long nside, const double *rot, long ring_first, long ring_last,
+                   const double *in, double *out)
+{
+    if (nside < 1 || ring_first < 1 || ring_last < ring_first || ring_last > 4 * nside - 1)
+        return -1;
+    ring_rec *t = ring_table(nside);
+    if (!t) return -2;
+    for (long i = ring_first; i <= ring_last; ++i) {
+        const ring_rec *r = &t[i];
+#pragma omp parallel for schedule(static)
+        for (long j = 0; j < r->n; ++j) {
+            double v[3], w[3];
+            unit_vector(r, j, v);
+            for (int c = 0; c < 3; ++c)
+                w[c] = rot[0 * 3 + c] * v[0] + rot[1 * 3 + c] * v[1] + rot[2 * 3 + c] * v[2];
+            const double rr = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+            out[r->first + j] = in[vec2pix_ring(nside, w[2] / rr, atan2(w[1], w[0]))];
+        }
+    }
+    free(t);
+    return 0;
+}
+
 /* Number of threads the oracle runs with (for reporting), and a setter. */
 int orc_threads(void) { return omp_get_max_threads(); }
 int orc_set_threads(int n)

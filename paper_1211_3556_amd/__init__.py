@@ -154,6 +154,9 @@ def load_library():
         "arkcos_tune_key": [ctypes.c_int, ctypes.c_double, ctypes.c_char_p, ctypes.c_int, _ip],
         "arkcos_tune": [ctypes.POINTER(_PlanDesc), ctypes.c_int, ctypes.c_char_p,
                         ctypes.POINTER(_Tiles), _dp, _dp],
+        "arkcos_rotation_to_pole": [ctypes.c_double, ctypes.c_double, _dp],
+        "arkcos_rotate_map": [ctypes.c_int, _dp, _vp, _vp, ctypes.c_int, ctypes.c_int,
+                              ctypes.c_int, _vp],
         "arkcos_status_string": [ctypes.c_int],
         "arkcos_last_error": [],
         "arkcos_version": [],
@@ -641,4 +644,35 @@ def split_convolve(plan: Plan, harm: Harm, x, out=None, stream=None):
             raise ValueError("out must have the shape of x")
     _call("arkcos_split_convolve", plan.handle, harm.handle, _vp(x.data_ptr()),
           _vp(out.data_ptr()), nb, _stream_ptr(stream))
+    return out
+
+
+def rotation_to_pole(theta: float, phi: float) -> np.ndarray:
+    """The 3x3 rotation taking the direction (theta, phi) to the north pole
+    (arkcos_rotation_to_pole)."""
+    r = np.empty(9)
+    _call("arkcos_rotation_to_pole", float(theta), float(phi), r.ctypes.data_as(_dp))
+    return r.reshape(3, 3)
+
+
+def rotate_map(nside: int, rot, x, out=None, rings=None, stream=None):
+    """Rotated copy of FP32 RING map(s) on the GPU, resampled at the nearest
+    pixel (arkcos_rotate_map): out[p] = x[pixel containing R^T n_p] for the
+    pixels of ``rings`` (1-based, inclusive; all by default)."""
+    import torch
+    x = _dev_f32(x, "x")
+    npix = 12 * nside * nside
+    if x.shape[-1] != npix or x.dim() > 2:
+        raise ValueError("x must hold one or more maps of 12 nside^2 pixels")
+    nb = 1 if x.dim() == 1 else x.shape[0]
+    if out is None:
+        out = torch.zeros_like(x)
+    else:
+        _dev_f32(out, "out")
+        if out.shape != x.shape:
+            raise ValueError("out must have the shape of x")
+    r = np.ascontiguousarray(rot, dtype=np.float64).reshape(9)
+    lo, hi = (0, 0) if rings is None else (int(rings[0]), int(rings[1]))
+    _call("arkcos_rotate_map", int(nside), r.ctypes.data_as(_dp), _vp(x.data_ptr()),
+          _vp(out.data_ptr()), nb, lo, hi, _stream_ptr(stream))
     return out

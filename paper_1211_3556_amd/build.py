@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libarkcos.so")
-SOURCES = ["plan.hip", "kernels.hip", "capi.hip", "sht.hip", "tune.hip"]
+SOURCES = ["plan.hip", "kernels.hip", "capi.hip", "sht.hip", "tune.hip", "rotate.hip"]
 HEADERS = [os.path.join(CSRC, "arkcos_internal.hpp"), os.path.join(INCLUDE, "arkcos.h")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ROCM_LIB = "/opt/rocm/lib"   # roctx (profiler ranges around the entry points)

@@ -378,3 +378,32 @@ def test_plan_log_line():
     assert "nside 32" in lines[0] and "ring pairs %d" % inf["ring_pairs"] in lines[0]
     assert "rings %d circulant / %d general" % (inf["circulant_rings"], inf["general_rings"]) \
         in lines[0]
+
+
+def test_rotation_to_pole_host():
+    """The library's rotation takes (theta, phi) to the pole, equals
+    R_y(-theta) R_z(-phi) built here, and rejects bad arguments; rotate_map
+    rejects matrices that are not rotations before touching the device."""
+    th, ph = 0.9, -2.4
+    r = A.rotation_to_pole(th, ph)
+    n = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    np.testing.assert_allclose(r @ n, [0, 0, 1], atol=1e-15)
+    rz = np.array([[np.cos(ph), np.sin(ph), 0], [-np.sin(ph), np.cos(ph), 0], [0, 0, 1.0]])
+    ry = np.array([[np.cos(th), 0, -np.sin(th)], [0, 1.0, 0], [np.sin(th), 0, np.cos(th)]])
+    np.testing.assert_allclose(r, ry @ rz, atol=1e-15)
+    lib = A.load_library()
+    dp = ctypes.POINTER(ctypes.c_double)
+    EINVAL = -1
+    assert lib.arkcos_rotation_to_pole(float("nan"), 0.0, np.zeros(9).ctypes.data_as(dp)) == EINVAL
+    fake = ctypes.c_void_p(0x1000)
+    far = ctypes.c_void_p(0x1000 + 12 * 16 * 16 * 4 * 8)
+    bad = np.eye(3) * 1.01
+    refl = np.diag([1.0, 1.0, -1.0])
+    for m in (bad, refl):
+        assert lib.arkcos_rotate_map(16, np.ascontiguousarray(m).ctypes.data_as(dp), fake, far, 1,
+                                     0, 0, None) == EINVAL
+    eye = np.eye(3)
+    assert lib.arkcos_rotate_map(16, eye.ctypes.data_as(dp), fake, far, 1, 0, 70,
+                                 None) == EINVAL
+    assert lib.arkcos_rotate_map(16, eye.ctypes.data_as(dp), fake, fake, 1, 0, 0,
+                                 None) == EINVAL

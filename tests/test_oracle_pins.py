@@ -546,3 +546,73 @@ def test_harmonic_band_limited_quadrature_convergence():
         errs.append(np.sqrt(np.mean((y - khat[ell] * f) ** 2) / np.mean((khat[ell] * f) ** 2)))
     assert errs[2] < 1e-2
     assert errs[1] < errs[0] / 2.0 and errs[2] < errs[1] / 2.0
+
+
+# ------------------------------------------------------ point location and map rotation --
+def _healpix_projection(vec):
+    """The HEALPix projection (Gorski et al. 2005; Calabretta & Roukema 2007)
+    of unit vectors: x = phi, y = 3 pi z / 8 in the equatorial zone, and with
+    sigma = sqrt(3 (1 - |z|)), x = phi_c + sigma (phi - phi_c),
+    y = sign(z) pi (2 - sigma) / 4 in the caps (phi_c the centre of the
+    longitude quadrant).  Pixels at resolution N are the squares
+    |dx| + |dy| <= pi/(4N)."""
+    v = np.asarray(vec, dtype=np.float64)
+    z = v[:, 2] / np.linalg.norm(v, axis=1)
+    phi = np.mod(np.arctan2(v[:, 1], v[:, 0]), 2 * np.pi)
+    x = phi.copy()
+    y = 3 * np.pi * z / 8
+    cap = np.abs(z) > 2.0 / 3.0
+    sig = np.sqrt(3 * (1 - np.abs(z[cap])))
+    phc = phi[cap] - np.mod(phi[cap], np.pi / 2) + np.pi / 4
+    x[cap] = phc + sig * (phi[cap] - phc)
+    y[cap] = np.sign(z[cap]) * np.pi * (2 - sig) / 4
+    return x, y
+
+
+@pytest.mark.parametrize("nside", [1, 2, 3, 8, 33, 64, 100])
+def test_vec2pix_returns_every_pixel_centre(nside):
+    pix = np.arange(O.npix(nside))
+    assert np.array_equal(O.vec2pix(nside, O.pix2vec(nside)), pix)
+
+
+@pytest.mark.parametrize("nside", [1, 2, 5, 16, 64])
+def test_vec2pix_point_lies_in_its_pixel_square(nside):
+    """Random directions: in the HEALPix projection the point lies in the
+    square of the pixel it is assigned to (an independent description of the
+    pixel boundaries, by the projection instead of the ring formulae)."""
+    rng = np.random.default_rng(31 + nside)
+    v = rng.standard_normal((20000, 3))
+    v /= np.linalg.norm(v, axis=1)[:, None]
+    p = O.vec2pix(nside, v)
+    x, y = _healpix_projection(v)
+    xc, yc = _healpix_projection(O.pix2vec(nside, p))
+    dx = np.abs(np.mod(x - xc + np.pi, 2 * np.pi) - np.pi)
+    d = dx + np.abs(y - yc)
+    assert np.all(d <= np.pi / (4 * nside) * (1 + 1e-9) + 1e-12)
+
+
+def test_rotation_to_pole_and_rotated_maps():
+    """R(theta, phi) takes (theta, phi) to the pole; the identity rotation
+    copies a map; a quarter turn about z is the exact in-ring shift by n/4;
+    only the requested rings are written."""
+    th, ph = 1.1, 2.3
+    r = O.rotation_to_pole(th, ph)
+    n = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    np.testing.assert_allclose(r @ n, [0, 0, 1], atol=1e-15)
+    np.testing.assert_allclose(r @ r.T, np.eye(3), atol=1e-15)
+    assert abs(np.linalg.det(r) - 1) < 1e-14
+    nside = 16
+    x = np.random.default_rng(3).standard_normal(O.npix(nside))
+    assert np.array_equal(O.rotate_map(nside, np.eye(3), x), x)
+    # R = rotation by +pi/2 about z: out(n) = x(R^T n), so out at pixel j of a
+    # ring reads pixel j - n/4 of the same ring
+    rz = np.array([[0.0, -1.0, 0.0], [1.0, 0.0, 0.0], [0.0, 0.0, 1.0]])
+    y = O.rotate_map(nside, rz, x)
+    g = O.ring_geometry(nside)
+    for i in range(4 * nside - 1):
+        f, nr = g["first"][i], g["n"][i]
+        j = np.arange(nr)
+        assert np.array_equal(y[f + j], x[f + (j - nr // 4) % nr])
+    z = O.rotate_map(nside, rz, x, rings=(3, 5), out=np.full_like(x, 7.0))
+    lo, hi = g["first"][2], g["first"][4] + g["n"][4]
+    assert np.array_equal(z[lo:hi], y[lo:hi]) and np.all(z[:lo] == 7.0) and np.all(z[hi:] == 7.0)
