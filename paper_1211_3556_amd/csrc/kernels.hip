@@ -1191,13 +1191,17 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 const float4 *x4 = reinterpret_cast<const float4 *>(xs) + q;
                 const float4 *g4 = reinterpret_cast<const float4 *>(gs);
                 for (int p = c; p < npq; p += nc) {
+                    // the quad's six LDS reads issue together, ahead of its FMAs
                     const float4 xa = x4[p];
                     const float4 xb = x4[p + 1];
+                    float4 gq[kGroupRings];
+#pragma unroll
+                    for (int r = 0; r < kGroupRings; ++r) gq[r] = g4[r * (kKnotSeg / 4) + p];
+                    __builtin_amdgcn_sched_barrier(0);
                     const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
 #pragma unroll
                     for (int r = 0; r < kGroupRings; ++r) {
-                        const float4 gq = g4[r * (kKnotSeg / 4) + p];
-                        const float gp[4] = {gq.x, gq.y, gq.z, gq.w};
+                        const float gp[4] = {gq[r].x, gq[r].y, gq[r].z, gq[r].w};
 #pragma unroll
                         for (int i = 0; i < 4; ++i)
 #pragma unroll
