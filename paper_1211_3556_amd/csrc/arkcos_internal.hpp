@@ -170,8 +170,7 @@ constexpr int kCircPix = 4;
 constexpr int kCircSeg = kThreads * kCircPix;
 constexpr int kCircMaxTaps = 256;   // taps of one circulant row (wider rows are split)
 constexpr int kGenLanes = 128;       // most pixels of one ring per general tile
-constexpr int kGenThreads = 512;     // general-gather workgroup: kGenPhases lanes per pixel
-constexpr int kGenPhases = kGenThreads / kGenLanes;
+constexpr int kGenThreads = 512;     // general-gather workgroup (one part of lanes per ring)
 // Built-in general-gather tile shapes (arkcos_tiles): pixels per ring, and the
 // widest row window (positions) of a ring in a tile of four / of two rings.
 constexpr int kGenPixelsDefault = 128;

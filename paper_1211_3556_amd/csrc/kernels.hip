@@ -336,13 +336,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
 // of a ring with offset o to jbar = n/4 - 2o - j, and a pair (j, j') to
 // (jbar, j'bar) with the opposite longitude difference: the same weight.
 // Together with the four quarter turns and the N-S mirror one weight serves
-// sixteen pairs.  A general tile holds up to kGenLanes pixels j <= jbar of the
-// first quadrant of a northern ring; kGenPhases lanes (more in a shorter
-// tile, up to one wave) share each pixel and take every kGenPhases-th
-// candidate of its window, so one staged row of kGenStage source positions
-// covers the tile, and one node table in LDS serves kGenThreads lanes.  The stage holds, per source position j', the
-// four quarter turns of x at j' on ring s and on its mirror, then the same at
-// j'bar: four float4 arrays of kGenStage entries.
+// sixteen pairs.  A general tile holds a segment of up to kGenLanes pixels
+// j <= jbar of the first quadrant of 1, 2 or 4 adjacent northern rings (the
+// tile shapes are plan parameters); the kGenThreads lanes split into one part
+// per ring, 2^lp lanes of a part share each pixel and take every 2^lp-th
+// candidate of its window, and one node table in LDS serves all of them.
+// Source rows are staged in the chunks the plan lists per tile (GenChunk):
+// per source position j', the four quarter turns of x at j' on ring s and on
+// its mirror, then the same at j'bar: four float4 arrays of kGenStage entries.
 
 // Largest value of `v` over the wave (wave-uniform result).
 __device__ __forceinline__ int wave_max(int v)
