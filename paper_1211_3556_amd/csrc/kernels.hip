@@ -322,10 +322,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
         if (4 * (int)threadIdx.x < T.len) {   // T.len is a multiple of 4
 #pragma unroll
             for (int r = 0; r < kGroupRings; ++r) {
-                if (r >= G.nr) break;
-                float *o = out + cst(P.rings)[G.r0 + r].first + T.j0 + 4 * threadIdx.x;
+                if (r < G.nr) {
+                    float *o = out + cst(P.rings)[G.r0 + r].first + T.j0 + 4 * threadIdx.x;
 #pragma unroll
-                for (int i = 0; i < kCircPix; ++i) o[i] = (float)acc[r][i];
+                    for (int i = 0; i < kCircPix; ++i) o[i] = (float)acc[r][i];
+                }
             }
         }
     }
