@@ -27,7 +27,7 @@
  *       K(theta) = sum_l (2l+1)/(4 pi) b_l P_l(cos theta),
  *   i.e. the inverse of the Legendre transform operator P_{l theta} of eq. 1.
  *
- * Readings where the paper is silent (each listed in the design doc):
+ * Readings where the paper is silent:
  *   - the table has ntab nodes at theta_k = k h, h = theta_cut/(ntab-1),
  *     and K is linear in theta between nodes;
  *   - the biased table of Sec. 3 (half the nodes inside the first 1/16 of the
