@@ -1182,6 +1182,10 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
             }
             wave_lds_order();
             if (row + kKnotWaves < G.row_end) load_row(row + kKnotWaves);
+            // the FP64 node coordinate of this lane's first (ring, tap) entry,
+            // loaded now so that its latency hides behind the row's FMAs
+            const double *kw = cst(P.kw) + W.w_off;
+            const double u_first = lane < 4 * W.ntaps ? kw[lane] : -1.0;
             const int q = lane / nc;
             const int c = lane - q * nc;
             float acc[kGroupRings][4];
@@ -1219,7 +1223,6 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
             wave_lds_order();
             // totals of entry o = 4 k + r (tap k, ring r) over the strides, in
             // stride order, then binned
-            const double *kw = cst(P.kw) + W.w_off;
             for (int o = lane; o < 4 * W.ntaps; o += 64) {
                 const int k = o >> 2, r = o & 3;
                 const float *src = red + ((k >> 2) * nc) * 16 + r * 4 + (k & 3);
@@ -1232,7 +1235,7 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 if (cc < nc) s0 += src[cc * 16];
                 const float sum = s0 + s1;
                 if (r < G.nr && sum != 0.0f) {
-                    const double u = kw[k * kGroupRings + r];
+                    const double u = o == lane ? u_first : kw[o];   // kw[4 k + r]
                     if (u >= 0.0) hat_scatter(hist, u, sum);
                 }
             }
