@@ -28,8 +28,9 @@ def _rotation(a, b, c):
     return rz(a) @ ry(b) @ rz(c)
 
 
-@pytest.mark.parametrize("nside,angles", [(64, (0.3, 1.1, -2.0)), (100, (2.9, 0.4, 0.7)),
-                                          (512, (-1.3, 2.2, 0.05))])
+@pytest.mark.parametrize("nside,angles", [(1, (0.2, 2.5, 1.0)), (2, (1.7, 0.9, -0.4)),
+                                          (3, (-2.2, 1.3, 2.6)), (64, (0.3, 1.1, -2.0)),
+                                          (100, (2.9, 0.4, 0.7)), (512, (-1.3, 2.2, 0.05))])
 def test_rotation_matches_oracle_bitwise(nside, angles):
     import torch
     r = _rotation(*angles)
