@@ -53,7 +53,9 @@ METRIC = "GPair-evals/s and maps/s at Nside 2048 (fwd, fwd+bwd, batched) vs plai
 FP32_VECTOR_PEAK_TFLOPS = 157.3
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 # Algorithmic FP32 work per in-disc pair term:
-#   k_circ       one FMA with a precomputed weight;
+#   k_circ       one FMA with a precomputed weight (vector ALUs; k_circ_mfma
+#                runs the same products on the matrix cores, for plans with
+#                long rows);
 #   k_general    one FMA, plus a 24-FLOP weight evaluation (longitude, sine
 #                series, chord, angle series, table index, interpolation)
 #                shared by the 16 quarter-turn, reflection and mirror images;
@@ -62,7 +64,8 @@ FP64_VECTOR_PEAK_TFLOPS = 78.6
 #                tap);
 #   k_knot_gen   16 products g x per candidate plus ~44 FLOP of FP64 geometry
 #                and hat weights, per 16 images (general rings).
-FLOP_PER_PAIR = {"k_circ": 2.0, "k_general": 2.0 + 24.0 / 16.0,
+FLOP_PER_PAIR = {"k_circ": 2.0, "k_circ_mfma": 2.0, "k_circ+k_circ_mfma": 2.0,
+                 "k_general": 2.0 + 24.0 / 16.0,
                  "k_knot_circ": 2.0, "k_knot_gen": (32.0 + 44.0) / 16.0}
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -210,25 +213,34 @@ def main() -> int:
     def fl(kernel, pairs):
         return FLOP_PER_PAIR[kernel] * pairs
 
+    def circ_kernel(plan):
+        """The circulant gather's kernel: vector form or matrix-core form."""
+        return "k_circ_mfma" if plan.info()["circ_form"] else "k_circ"
+
+    fwd_ck = [circ_kernel(p) for p in fwd_plans]
+    g_ck, c5_ck = circ_kernel(gplan), circ_kernel(c5plan)
+    b_forms = {circ_kernel(p) for p in bplans}
+    b_ck = "k_circ+k_circ_mfma" if len(b_forms) > 1 else b_forms.pop()
+
     def step(record: bool):
         for i, (p, o, (pc, pg)) in enumerate(zip(fwd_plans, fwd_out, fwd_parts)):
-            timed(record, "fwd%d" % i, "k_circ", fl("k_circ", pc),
+            timed(record, "fwd%d" % i, fwd_ck[i], fl(fwd_ck[i], pc),
                   lambda: p.convolve_part(x2048, o, CIRC))
             timed(record, "fwd%d" % i, "k_general", fl("k_general", pg),
                   lambda: p.convolve_part(x2048, o, GEN))
-        def fwdbwd(part, plan, knots, x, y, g, gx, gk, nb, parts):
+        def fwdbwd(part, plan, ck, knots, x, y, g, gx, gk, nb, parts):
             pc, pg = parts
             pc, pg = nb * pc, nb * pg
             # forward with the knots bound to the plan (table + circulant weights)
             timed(record, part, "k_set_knots", 0.0, lambda: plan.set_knots(knots))
-            timed(record, part, "k_circ", fl("k_circ", pc),
+            timed(record, part, ck, fl(ck, pc),
                   lambda: plan.convolve_part(x, y, CIRC))
             timed(record, part, "k_general", fl("k_general", pg),
                   lambda: plan.convolve_part(x, y, GEN))
             # backward: knots bound again; the operator is symmetric, so d/dmap
             # is the same two gathers on g
             timed(record, part, "k_set_knots", 0.0, lambda: plan.set_knots(knots))
-            timed(record, part, "k_circ", fl("k_circ", pc),
+            timed(record, part, ck, fl(ck, pc),
                   lambda: plan.convolve_part(g, gx, CIRC))
             timed(record, part, "k_general", fl("k_general", pg),
                   lambda: plan.convolve_part(g, gx, GEN))
@@ -236,9 +248,9 @@ def main() -> int:
             timed(record, part, "k_knot", fl("k_knot_circ", pc) + fl("k_knot_gen", pg),
                   lambda: plan.backward(g, x, want_map=False, want_knots=True, gk=gk))
 
-        fwdbwd("fwdbwd", gplan, knots, x2048, g_out, gin, g_gx, g_gk, 1, g_parts)
-        fwdbwd("grad", c5plan, c5knots, c5x, c5y, c5g, c5gx, c5gk, c5.nbatch, c5_parts)
-        timed(record, "batch", "k_circ", fl("k_circ", b_circ), graphs[CIRC].replay)
+        fwdbwd("fwdbwd", gplan, g_ck, knots, x2048, g_out, gin, g_gx, g_gk, 1, g_parts)
+        fwdbwd("grad", c5plan, c5_ck, c5knots, c5x, c5y, c5g, c5gx, c5gk, c5.nbatch, c5_parts)
+        timed(record, "batch", b_ck, fl(b_ck, b_circ), graphs[CIRC].replay)
         timed(record, "batch", "k_general", fl("k_general", b_gen), graphs[GEN].replay)
 
     log("warmup %d" % args.warmup)
@@ -346,6 +358,7 @@ def main() -> int:
                 rec[label] = {"ms": round(tot, 4),
                               "k_circ_ms": round(t["k_circ"], 4),
                               "k_general_ms": round(t["k_general"], 4),
+                              "circ_kernel": circ_kernel(p),
                               "gpair_per_s": round((pc + pg) / (tot * 1e-3) / 1e9, 2),
                               "k_general_tflops": round(FLOP_PER_PAIR["k_general"] * pg
                                                         / (t["k_general"] * 1e-3) / 1e12, 2)}
@@ -433,6 +446,7 @@ def main() -> int:
                           "theta_cut_arcmin": round(s.theta_cut / W.ARCMIN, 3), "ntab": s.ntab,
                           "pairs": pc + pg, "ms": round(tot, 4),
                           "k_circ_ms": round(t["k_circ"], 4), "k_general_ms": round(t["k_general"], 4),
+                          "circ_kernel": circ_kernel(p),
                           "gpair_per_s": round((pc + pg) / (tot * 1e-3) / 1e9, 2),
                           "maps_per_s": round(1e3 / tot, 2)})
             if s.nside == 8192:

@@ -160,6 +160,9 @@ typedef struct {
     int ring_last;
     int adjoint_ring_first;        /* ring-range plans: rings the adjoint writes, every */
     int adjoint_ring_last;         /* ring within theta_cut of the range (0, 0: all)    */
+    int circ_form;                 /* circulant gather: 0 vector FMAs, 1 matrix cores
+                                      (v_mfma_f32_16x16x4f32), chosen per plan from the
+                                      mean width of its weight rows                     */
 } arkcos_plan_info;
 
 /* The two gathers of a forward convolution (they write disjoint rings). */

@@ -96,7 +96,7 @@ class _PlanInfo(ctypes.Structure):
                 ("weights", ctypes.c_longlong), ("theta_break", ctypes.c_double),
                 ("k_break", ctypes.c_int), ("ring_first", ctypes.c_int),
                 ("ring_last", ctypes.c_int), ("adjoint_ring_first", ctypes.c_int),
-                ("adjoint_ring_last", ctypes.c_int)]
+                ("adjoint_ring_last", ctypes.c_int), ("circ_form", ctypes.c_int)]
 
 
 _lib = None

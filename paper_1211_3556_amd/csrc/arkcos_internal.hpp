@@ -169,6 +169,9 @@ constexpr int kGroupRings = 4;
 constexpr int kCircPix = 4;
 constexpr int kCircSeg = kThreads * kCircPix;
 constexpr int kCircMaxTaps = 256;   // taps of one circulant row (wider rows are split)
+// The circulant gather runs on the matrix cores when the plan's rows average
+// at least this many taps (a row of t taps costs products for t + 3 there).
+constexpr int kCircMfmaTaps = 12;
 constexpr int kGenLanes = 128;       // most pixels of one ring per general tile
 constexpr int kGenThreads = 512;     // general-gather workgroup (one part of lanes per ring)
 // Built-in general-gather tile shapes (arkcos_tiles): pixels per ring, and the
@@ -230,6 +233,7 @@ struct DevPlanView {
     int ntab;
     int npix;
     int angle_mode;          // angle series: 0 (theta_cut <= 0.1), 1 (<= 0.5), 2 full range
+    int circ_mfma;           // circulant gather on the matrix cores (1) or vector FMAs (0)
     // Node coordinate u of an angle (node k at u = k):  u0 = a0 theta, and
     // u = u0 on a uniform grid (a0 = (ntab-1)/theta_cut), u = min(u0, r u0 + c)
     // on the two-piece biased grid (a0 = k_break/theta_break the fine piece's
@@ -316,6 +320,7 @@ struct Plan {
     Plan *adj = nullptr;
     long long nweights = 0;
     int max_taps = 0;
+    int circ_form = 0;                // circulant gather: 0 vector FMAs, 1 matrix cores
     std::vector<double> ktab;         // current host copy (FP64), if known
     long long candidates = 0;
     bool pairs_counted = false;
@@ -356,13 +361,16 @@ struct Plan {
 
 struct Batch {
     std::vector<Plan *> plans;
-    std::vector<int2> cmap;             // circulant tiles of all plans: (plan, tile), longest first
+    std::vector<int2> cmap;             // circulant tiles of all plans: (plan, tile), those of
+                                        // vector-form plans first, each part longest first
+    int ncirc_valu = 0;                 // tiles of vector-form plans at the front of cmap
     std::vector<int2> gmap;             // general tiles of all plans
     int2 *d_cmap = nullptr;
     int2 *d_gmap = nullptr;
     DevPlanView *d_views = nullptr;
     unsigned int *d_counter = nullptr;
     int grid_circ = 0;
+    int grid_circ_mfma = 0;
     int grid_gen = 0;
     int cus = 0;
     int max_ntab = 0;

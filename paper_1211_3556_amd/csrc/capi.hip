@@ -177,7 +177,8 @@ int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *o
     Batch *B = new (std::nothrow) Batch();
     if (!B) return fail(ARKCOS_ENOMEM, "host allocation failed");
     std::vector<DevPlanView> views;
-    std::vector<double> ccost, gcost;
+    std::vector<double> ccost, gcost, mcost;
+    std::vector<int2> cmap_m;   // tiles of matrix-form plans
     for (int k = 0; k < nmaps; ++k) {
         Plan *P = reinterpret_cast<Plan *>(plans[k]);
         if (!P) { delete B; return fail(ARKCOS_EINVAL, "NULL plan in batch"); }
@@ -189,8 +190,8 @@ int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *o
         B->max_taps = std::max(B->max_taps, P->max_taps);
         views.push_back(P->view());
         for (int t = 0; t < (int)P->ctiles.size(); ++t) {
-            B->cmap.push_back(make_int2(k, t));
-            ccost.push_back(P->ctile_cost[t]);
+            (P->circ_form ? cmap_m : B->cmap).push_back(make_int2(k, t));
+            (P->circ_form ? mcost : ccost).push_back(P->ctile_cost[t]);
         }
         for (int t = 0; t < (int)P->gtiles2.size(); ++t) {
             B->gmap.push_back(make_int2(k, t));
@@ -207,6 +208,9 @@ int arkcos_batch_create(const arkcos_plan_t *plans, int nmaps, arkcos_batch_t *o
         m.swap(m2);
     };
     sort_map(B->cmap, ccost);
+    sort_map(cmap_m, mcost);
+    B->ncirc_valu = (int)B->cmap.size();
+    B->cmap.insert(B->cmap.end(), cmap_m.begin(), cmap_m.end());
     sort_map(B->gmap, gcost);
 
     DeviceGuard g(B->device);

@@ -5,16 +5,17 @@
 // Every output ring is gathered by one of two kernels, which write disjoint
 // rings:
 //
-//  * k_circ (circulant rings: belt rings whose whole disc lies in the belt).
-//    All their source rings have 4N pixels, so the weight of (r, j; s, j')
-//    depends on j' - j only.  Each (r, s) has one weight row, evaluated once
-//    per node table by k_build_weights (angles in FP64, weights rounded once
-//    to FP32).
+//  * k_circ / k_circ_mfma (circulant rings: belt rings whose whole disc lies
+//    in the belt).  All their source rings have 4N pixels, so the weight of
+//    (r, j; s, j') depends on j' - j only.  Each (r, s) has one weight row,
+//    evaluated once per node table by k_build_weights (angles in FP64,
+//    weights rounded once to FP32).
 //    The gather is then a correlation: a workgroup owns kGroupRings
-//    consecutive output rings and kCircSeg pixels of each (4 consecutive
-//    pixels per lane), stages one source row and its weights at a time in
-//    LDS, and per quad of taps two float4 reads of the row and four broadcast
-//    reads of the weights feed 64 FMAs.
+//    consecutive output rings and kCircSeg pixels of each and stages one
+//    source row and its weights at a time in LDS.  Plans whose rows are short
+//    run it on the vector ALUs (per quad of taps two float4 reads of the row
+//    and four broadcast reads of the weights feed 64 FMAs); plans with longer
+//    rows run it on the matrix cores, as a Toeplitz product per row.
 //
 //  * k_general (polar caps and belt rings whose disc reaches a cap).  Weights
 //    are evaluated per pair in FP32 from exact ring-pair constants: chord from
@@ -23,12 +24,11 @@
 //    j + n/4, the N-S mirror maps ring i to ring 4N - i and the reflection
 //    phi -> pi/2 - phi maps a pair to one with the opposite longitude
 //    difference, so one weight serves sixteen pairs; source rows are staged
-//    in LDS as four arrays of four images each.
+//    in LDS as four arrays of four images each.  With a per-pair kernel
+//    evaluation this gather runs on the vector ALUs.
 //
 // Sums are FP32 within a source-ring row and FP64 across rows.  No atomics
-// touch the outputs: results are bitwise reproducible.  This is a gather with
-// a per-pair kernel evaluation, so it runs on the vector ALUs, not on matrix
-// cores.
+// touch the outputs: results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -224,71 +224,82 @@ __device__ __forceinline__ void prefetch_weights(const float *w, int nw, float v
 // terms per output) have accumulated, and at the end of a tile.
 constexpr int kCircFlush = 64;
 
-// Persistent circulant gather over tiles (plan, group, segment) x maps.  Rows
-// are double-buffered: the loads of row t+1 (source pixels and weights) are
-// in flight while row t is multiplied, and one barrier per row separates the
-// buffers.  The weights of a tap are read from LDS by every lane at one
-// address (a broadcast), so the FMAs take all operands from vector registers:
-// an FMA with a scalar-register operand issues at about 0.6x the rate on
-// gfx950.  Lane l owns pixels 4l .. 4l+3 of the segment, so a quad of taps
-// needs 7 consecutive staged pixels, read as two aligned float4.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_circ(const DevPlanView *__restrict__ views,
-                                                   const int2 *__restrict__ tile_map,
-                                                   int ntiles, MapIO io, int nmaps,
-                                                   int buf_floats, unsigned int *counter)
+// Weight buffers in LDS: a row's taps (kGroupRings floats each) between two
+// zero tap quads, which the matrix-core form reads past both ends of a row.
+constexpr int kCircWBuf = (kCircMaxTaps + 8) * kGroupRings;   // floats per weight buffer
+constexpr int kCircWRow = 4 * kGroupRings;                     // offset of tap 0
+constexpr int kCircWavePix = kCircSeg / (kThreads / 64);       // pixels of one wave
+static_assert(kCircWavePix == 256 && kGroupRings == 4, "circulant tile shape");
+typedef float circ_v4f __attribute__((ext_vector_type(4)));
+
+// Rows of one circulant tile, double-buffered: the loads of row t+1 (source
+// pixels and weights) are in flight while row t is multiplied, and one
+// barrier per row separates the buffers.  Returns the tile's FP64 sums in
+// acc, in the form's own lane layout (see the two forms below).
+template <bool MF>
+__device__ __forceinline__ void circ_rows(const DevPlanView &P, const DevTile &T,
+                                          const DevGroup &G, int n, const float *in, float *xs,
+                                          float *wls, int buf_floats, double acc[4][4])
 {
-    extern __shared__ __align__(16) float xs[];
-    float *wls = xs + 2 * buf_floats;      // two weight buffers of kCircMaxTaps float4
-    __shared__ int s_item;
-    const int nitems = ntiles * nmaps;
-    for (;;) {
-        const int item = next_item(counter, &s_item);
-        if (item >= nitems) break;
-        const int ti = item / nmaps;
-        const int map = item - ti * nmaps;
-        const int pi = tile_map ? cst(tile_map)[ti].x : 0;
-        const int lt = tile_map ? cst(tile_map)[ti].y : ti;
-        const DevPlanView P = cst(views)[pi];
-        const DevTile T = cst(P.ctiles)[lt];
-        const DevGroup G = cst(P.groups)[T.r];
-        const int n = cst(P.rings)[G.r0].n;
-        const float *in = io.in[pi] + (size_t)map * P.npix;
-        double acc[kGroupRings][kCircPix];
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = (int)threadIdx.x >> 6;
 #pragma unroll
-        for (int r = 0; r < kGroupRings; ++r)
+    for (int q = 0; q < 4; ++q)
 #pragma unroll
-            for (int i = 0; i < kCircPix; ++i) acc[r][i] = 0.0;
-        float v[kStageRegs], wv[kWeightRegs];
-        if (G.row_begin < G.row_end) {
-            const DevRow W = cst(P.rows)[G.row_begin];
-            prefetch_row(in + W.first_s, T.j0 + W.k_lo, T.len + W.ntaps - 1, n, v);
-            prefetch_weights(P.wts + W.w_off, W.ntaps * kGroupRings, wv);
+        for (int c = 0; c < 4; ++c) acc[q][c] = 0.0;
+    // vector form: racc[r][i], ring r at pixel 4 l + i of lane l.
+    // matrix form: d[q][c], ring l >> 4 at pixel 256 w + 64 q + 4 (l & 15) + c.
+    float racc[4][4];
+    circ_v4f d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        d[q] = circ_v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) racc[q][c] = 0.0f;
+    }
+    // matrix form: A[(r,p)][u] = w[r][u - p] sits at float 4 (u - p) + r of
+    // the row; B[u][b] = x[4 b + u] at this wave's first N tile
+    const int a_lane = kCircWRow + 4 * ((lane >> 4) - (lane & 3)) + ((lane & 15) >> 2);
+    const int b_lane = kCircWavePix * wave + 4 * (lane & 15) + (lane >> 4);
+    float v[kStageRegs], wv[kWeightRegs];
+    if (G.row_begin < G.row_end) {
+        const DevRow W = cst(P.rows)[G.row_begin];
+        prefetch_row(in + W.first_s, T.j0 + W.k_lo, T.len + W.ntaps - 1, n, v);
+        prefetch_weights(P.wts + W.w_off, W.ntaps * kGroupRings, wv);
+    }
+    int since = 0;   // taps summed in FP32 since the last move into FP64
+    int buf = 0;
+    for (int row = G.row_begin; row < G.row_end; ++row) {
+        const DevRow W = cst(P.rows)[row];
+        float *xb = xs + buf * buf_floats;
+        float *wb = wls + buf * kCircWBuf;
+#pragma unroll
+        for (int u = 0; u < kStageRegs; ++u) xb[threadIdx.x + u * kThreads] = v[u];
+#pragma unroll
+        for (int u = 0; u < kWeightRegs; ++u) wb[kCircWRow + threadIdx.x + u * kThreads] = wv[u];
+        __syncthreads();
+        if (row + 1 < G.row_end) {
+            const DevRow W1 = cst(P.rows)[row + 1];
+            prefetch_row(in + W1.first_s, T.j0 + W1.k_lo, T.len + W1.ntaps - 1, n, v);
+            prefetch_weights(P.wts + W1.w_off, W1.ntaps * kGroupRings, wv);
         }
-        float racc[kGroupRings][kCircPix];
+        if (MF) {
+            // K steps of four u over u = 0 .. ntaps + 2 (taps are zero past ntaps)
+            const int nks = (W.ntaps + 6) >> 2;
+            const float *ap = wb + a_lane;
+            const float *bp = xb + b_lane;
+            for (int ks = 0; ks < nks; ++ks) {
+                const float a = ap[16 * ks];
 #pragma unroll
-        for (int r = 0; r < kGroupRings; ++r)
-#pragma unroll
-            for (int i = 0; i < kCircPix; ++i) racc[r][i] = 0.0f;
-        int since = 0;   // taps summed in FP32 since the last move into FP64
-        int buf = 0;
-        for (int row = G.row_begin; row < G.row_end; ++row) {
-            const DevRow W = cst(P.rows)[row];
-            float *xb = xs + buf * buf_floats;
-            float *wb = wls + buf * kCircMaxTaps * kGroupRings;
-#pragma unroll
-            for (int u = 0; u < kStageRegs; ++u) xb[threadIdx.x + u * kThreads] = v[u];
-#pragma unroll
-            for (int u = 0; u < kWeightRegs; ++u) wb[threadIdx.x + u * kThreads] = wv[u];
-            __syncthreads();
-            if (row + 1 < G.row_end) {
-                const DevRow W1 = cst(P.rows)[row + 1];
-                prefetch_row(in + W1.first_s, T.j0 + W1.k_lo,
-                             T.len + W1.ntaps - 1, n, v);
-                prefetch_weights(P.wts + W1.w_off, W1.ntaps * kGroupRings, wv);
+                for (int q = 0; q < 4; ++q)
+                    d[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bp[64 * q + 4 * ks], d[q], 0,
+                                                                0, 0);
             }
-            // lane l owns pixels 4l .. 4l+3: taps t0 .. t0+3 need x[4l + t0 .. 4l + t0 + 6],
-            // two aligned float4 reads (rows are zero-padded to whole tap quads)
-            const float4 *w4 = reinterpret_cast<const float4 *>(wb);
+        } else {
+            // lane l owns pixels 4l .. 4l+3: taps t0 .. t0+3 need
+            // x[4l + t0 .. 4l + t0 + 6], two aligned float4 reads (the buffer is
+            // zero past the row's taps, so whole tap quads are read)
+            const float4 *w4 = reinterpret_cast<const float4 *>(wb + kCircWRow);
             const float4 *x4 = reinterpret_cast<const float4 *>(xb) + threadIdx.x;
             for (int q = 0; q < W.ntaps; q += 4) {
                 const float4 xa = x4[q >> 2];
@@ -305,21 +316,94 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
                             racc[r][i] = fmaf(wr[r], xv[i + tt], racc[r][i]);
                 }
             }
-            since += W.ntaps;
-            if (since >= kCircFlush || row + 1 == G.row_end) {
-#pragma unroll
-                for (int r = 0; r < kGroupRings; ++r)
-#pragma unroll
-                    for (int i = 0; i < kCircPix; ++i) {
-                        acc[r][i] += (double)racc[r][i];
-                        racc[r][i] = 0.0f;
-                    }
-                since = 0;
-            }
-            buf ^= 1;
         }
+        since += W.ntaps;
+        if (since >= kCircFlush || row + 1 == G.row_end) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    acc[q][c] += MF ? (double)d[q][c] : (double)racc[q][c];
+                    racc[q][c] = 0.0f;
+                }
+                d[q] = circ_v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            }
+            since = 0;
+        }
+        buf ^= 1;
+    }
+}
+
+// Persistent circulant gather over tiles (plan, group, segment) x maps, in
+// one of two forms, each its own kernel, chosen per plan (circ_form):
+//  * vector FMAs: the weights of a tap are read from LDS by every lane at one
+//    address (a broadcast), so the FMAs take all operands from vector
+//    registers (an FMA with a scalar-register operand issues at about 0.6x
+//    the rate on gfx950); lane l owns pixels 4l .. 4l+3 of all four rings.
+//  * matrix cores: per row the gather is a Toeplitz product, run as
+//    v_mfma_f32_16x16x4f32 (FP32 in and out).  For output pixel 4b + p of
+//    ring r (b a block of four pixels, p its phase) and u = p + t,
+//      out[r][4b + p] = sum_u w[r][u - p] x[4b + u],
+//    so D[(r,p)][b] = sum_u A[(r,p)][u] B[u][b] with A[(r,p)][u] = w[r][u - p]
+//    (zero outside the row) and B[u][b] = x[4b + u]: M = 16 rows are four
+//    rings times four phases, N = 16 pixel blocks (64 pixels), K steps of
+//    four u.  A wave owns 256 pixels as four N tiles, so each A fragment
+//    feeds four products.  Lane l holds A[(l & 15)][l >> 4] and
+//    B[l >> 4][l & 15] and receives D[4 (l >> 4) + c][l & 15], c = 0..3:
+//    ring l >> 4 at four consecutive pixels.  K runs over ntaps + 3 values
+//    of u, so short rows waste a larger share of the products: the plan takes
+//    this form when its rows average at least kCircMfmaTaps taps.
+template <bool MF>
+__device__ __forceinline__ void circ_gather(const DevPlanView *__restrict__ views,
+                                            const int2 *__restrict__ tile_map, int ntiles,
+                                            const MapIO &io, int nmaps, int buf_floats,
+                                            unsigned int *counter)
+{
+    extern __shared__ __align__(16) float xs[];
+    float *wls = xs + 2 * buf_floats;      // two weight buffers of kCircWBuf floats
+    __shared__ int s_item;
+    // the zero tap quads around both weight buffers (rows fill only the middle)
+    if ((int)threadIdx.x < kCircWRow) {
+        const int e = (int)threadIdx.x;
+        wls[e] = 0.0f;
+        wls[kCircWBuf - kCircWRow + e] = 0.0f;
+        wls[kCircWBuf + e] = 0.0f;
+        wls[2 * kCircWBuf - kCircWRow + e] = 0.0f;
+    }
+    const int lane = (int)threadIdx.x & 63;
+    const int wave = (int)threadIdx.x >> 6;
+    const int nitems = ntiles * nmaps;
+    for (;;) {
+        const int item = next_item(counter, &s_item);
+        if (item >= nitems) break;
+        const int ti = item / nmaps;
+        const int map = item - ti * nmaps;
+        const int pi = tile_map ? cst(tile_map)[ti].x : 0;
+        const int lt = tile_map ? cst(tile_map)[ti].y : ti;
+        const DevPlanView P = cst(views)[pi];
+        const DevTile T = cst(P.ctiles)[lt];
+        const DevGroup G = cst(P.groups)[T.r];
+        const int n = cst(P.rings)[G.r0].n;
+        const float *in = io.in[pi] + (size_t)map * P.npix;
         float *out = io.out[pi] + (size_t)map * P.npix;
-        if (4 * (int)threadIdx.x < T.len) {   // T.len is a multiple of 4
+        double acc[4][4];
+        circ_rows<MF>(P, T, G, n, in, xs, wls, buf_floats, acc);
+        if (MF) {
+            // ring lane >> 4, pixels 256 w + 64 q + 4 (lane & 15) + c (T.len is
+            // a multiple of 4)
+            const int r = lane >> 4;
+            if (r < G.nr) {
+                float *o = out + cst(P.rings)[G.r0 + r].first + T.j0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int px = kCircWavePix * wave + 64 * q + 4 * (lane & 15);
+                    if (px < T.len) {
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) o[px + c] = (float)acc[q][c];
+                    }
+                }
+            }
+        } else if (4 * (int)threadIdx.x < T.len) {   // T.len is a multiple of 4
 #pragma unroll
             for (int r = 0; r < kGroupRings; ++r) {
                 if (r < G.nr) {
@@ -330,6 +414,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) v
             }
         }
     }
+}
+
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(5))) void k_circ(
+    const DevPlanView *__restrict__ views, const int2 *__restrict__ tile_map, int ntiles, MapIO io,
+    int nmaps, int buf_floats, unsigned int *counter)
+{
+    circ_gather<false>(views, tile_map, ntiles, io, nmaps, buf_floats, counter);
+}
+
+__global__ __launch_bounds__(kThreads) void k_circ_mfma(const DevPlanView *__restrict__ views,
+                                                        const int2 *__restrict__ tile_map,
+                                                        int ntiles, MapIO io, int nmaps,
+                                                        int buf_floats, unsigned int *counter)
+{
+    circ_gather<true>(views, tile_map, ntiles, io, nmaps, buf_floats, counter);
 }
 
 // --------------------------------------------------------- general gather --
@@ -825,7 +924,7 @@ void k_general(const DevPlanView *__restrict__ views, const int2 *__restrict__ t
 
 __global__ void k_reset_counters(unsigned int *counter)
 {
-    if (threadIdx.x < 2) counter[threadIdx.x] = 0u;
+    if (threadIdx.x < 3) counter[threadIdx.x] = 0u;
 }
 
 // Omega-scaled FP32 table from device knots.
@@ -1462,11 +1561,11 @@ static int occupancy(K kernel, size_t lds, int *per_cu, int threads = kThreads)
 }
 
 // Two row buffers of kStageRegs * kThreads floats each, then two weight
-// buffers of kCircMaxTaps * kGroupRings floats.
+// buffers of kCircWBuf floats (a row between two zero tap quads).
 static int circ_buf_floats() { return kStageRegs * kThreads; }
 static size_t circ_lds()
 {
-    return (size_t)2 * (circ_buf_floats() + kCircMaxTaps * kGroupRings) * sizeof(float);
+    return (size_t)2 * (circ_buf_floats() + kCircWBuf) * sizeof(float);
 }
 // Node table plus its two zero entries, rounded up to 16 bytes, then four
 // float4 arrays of kGenStage staged positions.
@@ -1501,7 +1600,7 @@ int prepare_launches(Plan &p)
     ARKCOS_HIP_CHECK(hipDeviceGetAttribute(&p.cus, hipDeviceAttributeMultiprocessorCount,
                                            p.device));
     int rc;
-    if ((rc = occupancy(k_circ, circ_lds(), &p.occ_circ))) return rc;
+    if ((rc = occupancy(p.circ_form ? k_circ_mfma : k_circ, circ_lds(), &p.occ_circ))) return rc;
     if ((rc = occupancy(k_general, gen_lds(p.desc.ntab), &p.occ_gen, kGenThreads))) return rc;
     p.grid_kc = p.grid_kg = 0;
     if ((p.desc.flags & ARKCOS_PLAN_LEARNABLE) && p.desc.ntab <= ARKCOS_MAX_GRAD_NTAB) {
@@ -1525,10 +1624,12 @@ int prepare_batch(Batch &b)
 {
     ARKCOS_HIP_CHECK(hipDeviceGetAttribute(&b.cus, hipDeviceAttributeMultiprocessorCount,
                                            b.device));
-    int occ_c = 0, occ_g = 0, rc;
+    int occ_c = 0, occ_m = 0, occ_g = 0, rc;
     if ((rc = occupancy(k_circ, circ_lds(), &occ_c))) return rc;
+    if ((rc = occupancy(k_circ_mfma, circ_lds(), &occ_m))) return rc;
     if ((rc = occupancy(k_general, gen_lds(b.max_ntab), &occ_g, kGenThreads))) return rc;
-    b.grid_circ = std::max(1, std::min((int)b.cmap.size(), occ_c * b.cus));
+    b.grid_circ = std::max(1, std::min(b.ncirc_valu, occ_c * b.cus));
+    b.grid_circ_mfma = std::max(1, std::min((int)b.cmap.size() - b.ncirc_valu, occ_m * b.cus));
     b.grid_gen = std::max(1, std::min((int)b.gmap.size(), occ_g * b.cus));
     return ARKCOS_OK;
 }
@@ -1564,9 +1665,9 @@ int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipSt
     const int ngt = (parts & ARKCOS_PART_GENERAL) ? (int)p.gtiles2.size() : 0;
     if (nct > 0) {
         const int grid = std::max(1, std::min(nct * nbatch, p.occ_circ * p.cus));
-        hipLaunchKernelGGL(k_circ, dim3(grid), dim3(kThreads), circ_lds(), s,
-                           (const DevPlanView *)p.d_view, (const int2 *)nullptr, nct, io, nbatch,
-                           circ_buf_floats(), counter);
+        hipLaunchKernelGGL(p.circ_form ? k_circ_mfma : k_circ, dim3(grid), dim3(kThreads),
+                           circ_lds(), s, (const DevPlanView *)p.d_view, (const int2 *)nullptr,
+                           nct, io, nbatch, circ_buf_floats(), counter);
     }
     if (ngt > 0) {
         const int grid = std::max(1, std::min(ngt * nbatch, p.occ_gen * p.cus));
@@ -1663,10 +1764,16 @@ int launch_batch(const Batch &b, const float *const *in, float *const *out, hipS
         io.out[k] = out[k];
     }
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, s, b.d_counter);
-    if (!b.cmap.empty() && (parts & ARKCOS_PART_CIRCULANT))
+    // the tiles of vector-form plans, then those of matrix-form plans (queue 2)
+    const int ncm = (int)b.cmap.size() - b.ncirc_valu;
+    if (b.ncirc_valu > 0 && (parts & ARKCOS_PART_CIRCULANT))
         hipLaunchKernelGGL(k_circ, dim3(b.grid_circ), dim3(kThreads), circ_lds(), s,
-                           (const DevPlanView *)b.d_views, (const int2 *)b.d_cmap,
-                           (int)b.cmap.size(), io, 1, circ_buf_floats(), b.d_counter);
+                           (const DevPlanView *)b.d_views, (const int2 *)b.d_cmap, b.ncirc_valu,
+                           io, 1, circ_buf_floats(), b.d_counter);
+    if (ncm > 0 && (parts & ARKCOS_PART_CIRCULANT))
+        hipLaunchKernelGGL(k_circ_mfma, dim3(b.grid_circ_mfma), dim3(kThreads), circ_lds(), s,
+                           (const DevPlanView *)b.d_views, (const int2 *)b.d_cmap + b.ncirc_valu,
+                           ncm, io, 1, circ_buf_floats(), b.d_counter + 2);
     if (!b.gmap.empty() && (parts & ARKCOS_PART_GENERAL))
         hipLaunchKernelGGL(k_general, dim3(b.grid_gen), dim3(kGenThreads), gen_lds(b.max_ntab), s,
                            (const DevPlanView *)b.d_views, (const int2 *)b.d_gmap,

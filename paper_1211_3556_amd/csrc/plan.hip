@@ -32,13 +32,15 @@ static void log_plan(const Plan &P)
     fprintf(stderr,
             "[arkcos] plan nside %d theta_cut %.6g rad ntab %d%s%s: rings %d circulant / %d "
             "general, ring pairs %zu, circulant tiles %zu, general tiles %zu (%zu staged "
-            "chunks; shapes %d/%d/%d from %s), weights %lld, device bytes %lld\n",
+            "chunks; shapes %d/%d/%d from %s), circulant rows %zu (weights %lld, %s), "
+            "device bytes %lld\n",
             P.nside, P.desc.theta_cut, P.desc.ntab, P.desc.k_break > 0 ? " biased" : "",
             P.desc.ring_first > 0 ? " ring range" : "", P.nrings - ngen_rings, ngen_rings,
             P.pairs.size(), P.ctiles.size(), P.gtiles2.size(), P.gchunks.size(),
             P.tiles.gen_pixels, P.tiles.gen_quad_window, P.tiles.gen_pair_window,
             P.tile_source == 0 ? "defaults" : (P.tile_source == 1 ? "tuning cache" : "descriptor"),
-            P.nweights, P.device_bytes);
+            P.rows.size(), P.nweights, P.circ_form ? "matrix cores" : "vector FMAs",
+            P.device_bytes);
 }
 
 int fail(int status, const std::string &msg)
@@ -152,6 +154,7 @@ DevPlanView Plan::view() const
     v.ntab = desc.ntab;
     v.npix = (int)npix;
     v.angle_mode = angle_mode;
+    v.circ_mfma = circ_form;
     v.src_lo = src_hi >= 0 ? src_lo : 0;
     v.src_hi = src_hi >= 0 ? src_hi : nrings - 1;
     // node coordinate map: u0 = a0 theta, u = min(u0, r u0 + c)
@@ -493,6 +496,14 @@ static int build_plan(Plan &P)
         P.groups.push_back(G);
     }
     if (P.nweights > 0x7fffffffLL) return fail(ARKCOS_EUNSUPPORTED, "circulant weight table too large");
+    // Matrix cores for rows averaging kCircMfmaTaps taps or more; the test hook
+    // ARKCOS_CIRC_FORM=valu or =mfma at plan creation forces either form.
+    P.circ_form = !P.rows.empty() &&
+                  P.nweights >= (long long)kCircMfmaTaps * kGroupRings * (long long)P.rows.size();
+    if (const char *cf = getenv("ARKCOS_CIRC_FORM")) {
+        if (std::string(cf) == "valu") P.circ_form = 0;
+        if (std::string(cf) == "mfma") P.circ_form = 1;
+    }
 
     // Circulant tiles: kCircSeg consecutive pixels of every ring of a group.
     P.ctiles.clear();
@@ -1073,6 +1084,7 @@ int arkcos_plan_get_info(arkcos_plan_t plan, arkcos_plan_info *info)
     info->circulant_tiles = (long long)P->ctiles.size();
     info->general_tiles = (long long)P->gtiles.size();
     info->weights = P->nweights;
+    info->circ_form = P->circ_form;
     info->theta_break = P->desc.theta_break;
     info->k_break = P->desc.k_break;
     return ARKCOS_OK;

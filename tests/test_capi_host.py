@@ -407,3 +407,19 @@ def test_rotation_to_pole_host():
                                  None) == EINVAL
     assert lib.arkcos_rotate_map(16, eye.ctypes.data_as(dp), fake, fake, 1, 0, 0,
                                  None) == EINVAL
+
+
+def test_circulant_form_follows_row_width(monkeypatch):
+    """Plans with short circulant rows take the vector form of the circulant
+    gather, plans whose rows average 12 taps or more the matrix-core form;
+    ARKCOS_CIRC_FORM at plan creation forces either.  The log line names it."""
+    import workloads as W
+    def plan(tc_arcmin):
+        tc = tc_arcmin * W.ARCMIN
+        return A.Plan(2048, tc, W.gaussian_profile_knots(tc / 3, tc, 512), host_only=True)
+    assert plan(10.0).info()["circ_form"] == 0
+    assert plan(90.0).info()["circ_form"] == 1
+    monkeypatch.setenv("ARKCOS_CIRC_FORM", "mfma")
+    assert plan(10.0).info()["circ_form"] == 1
+    monkeypatch.setenv("ARKCOS_CIRC_FORM", "valu")
+    assert plan(90.0).info()["circ_form"] == 0

@@ -305,3 +305,44 @@ def test_wide_circulant_rows_split():
                                     rng.choice(12 * nside * nside, 40, replace=False)]))
     ref = O.convolve(nside, tc, knots, x, pixels=pix)
     assert rel_rms(y[pix], ref) <= REL_RMS_TOL
+
+
+@pytest.mark.parametrize("nside,tc_deg,npix_sample", [(13, 40.0, 0), (64, 6.0, 0), (128, 20.0, 0),
+                                                       (512, 29.8, 300)])
+def test_circulant_vector_and_matrix_forms(monkeypatch, nside, tc_deg, npix_sample):
+    """The circulant gather has a vector-FMA form and a matrix-core form (a
+    Toeplitz product per row on v_mfma_f32_16x16x4f32), chosen per plan by its
+    mean row width.  A test hook forces either form: both match the oracle,
+    on ragged ring segments (Nside 13), short rows (Nside 64 at 6 deg), long
+    rows (Nside 128 at 20 deg) and rows split over staging passes (Nside 512
+    at 29.8 deg, sampled), and they agree with each other to FP32 rounding."""
+    import torch
+    A = _A()
+    tc = np.radians(tc_deg)
+    knots = W.gaussian_profile_knots(tc / 3, tc, 2048)
+    x = W.white_noise(nside, 880 + nside)
+    xd = to_dev(x)
+    ys = {}
+    for form, code in (("valu", 0), ("mfma", 1)):
+        monkeypatch.setenv("ARKCOS_CIRC_FORM", form)
+        plan = A.Plan(nside, tc, knots)
+        assert plan.info()["circ_form"] == code
+        assert plan.info()["circulant_rings"] > 0
+        log("circulant %s form Nside %d cut %.1f deg" % (form, nside, tc_deg))
+        yc = torch.zeros_like(xd)
+        plan.convolve_part(xd, yc, A.PART_CIRCULANT)
+        ys[form] = (to_host(yc), to_host(plan.convolve(xd)))
+        torch.cuda.synchronize()
+    circ = ys["valu"][0] != 0
+    if npix_sample:
+        rng = np.random.default_rng(881)
+        pix = np.unique(rng.choice(np.flatnonzero(circ), npix_sample, replace=False))
+    else:
+        pix = np.flatnonzero(circ)
+    ref = O.convolve(nside, tc, knots, x, pixels=pix)
+    for form in ("valu", "mfma"):
+        assert rel_rms(ys[form][1][pix], ref) <= REL_RMS_TOL, form
+    # the two forms write the same rings and differ only in FP32 summation order
+    assert np.array_equal(ys["valu"][0] != 0, ys["mfma"][0] != 0)
+    assert rel_rms(ys["mfma"][0], ys["valu"][0]) <= 5e-7
+
