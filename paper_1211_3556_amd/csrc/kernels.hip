@@ -522,6 +522,7 @@ __device__ __forceinline__ float node_coord(float d2, const UCoef &uc)
 // Threads at or past cn load nothing: positions past the chunk are never
 // read.  Loads address their ring by 32-bit byte offsets shared between a
 // ring and its mirror (the ring's base stays in scalar registers).
+template <int SIDE>
 __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, int n_s,
                                            int two_o_s, int c0, int cn, float4 &a, float4 &b,
                                            float4 &c, float4 &d)
@@ -541,16 +542,22 @@ __device__ __forceinline__ void prefetch16(const float *src, const float *srcm, 
         od[k] = wrap_bytes_up(jd + k * qb, (unsigned)nb);
         orf[k] = wrap_bytes_up(jr + k * qb, (unsigned)nb);
     }
-    a = make_float4(ld_off(src, od[0]), ld_off(src, od[1]), ld_off(src, od[2]), ld_off(src, od[3]));
-    c = make_float4(ld_off(src, orf[0]), ld_off(src, orf[1]), ld_off(src, orf[2]),
-                    ld_off(src, orf[3]));
+    // SIDE 1 (2): one-sided tiles read only ring s (its mirror), a and c (b and d)
+    if (SIDE != 2) {
+        a = make_float4(ld_off(src, od[0]), ld_off(src, od[1]), ld_off(src, od[2]),
+                        ld_off(src, od[3]));
+        c = make_float4(ld_off(src, orf[0]), ld_off(src, orf[1]), ld_off(src, orf[2]),
+                        ld_off(src, orf[3]));
+    }
     // loaded for the equator ring too, so that every load of the chunk issues
     // from one branch-free sequence: the general gather never writes the
     // equator's south sums, and the knot gradient gives them zero g
-    b = make_float4(ld_off(srcm, od[0]), ld_off(srcm, od[1]), ld_off(srcm, od[2]),
-                    ld_off(srcm, od[3]));
-    d = make_float4(ld_off(srcm, orf[0]), ld_off(srcm, orf[1]), ld_off(srcm, orf[2]),
-                    ld_off(srcm, orf[3]));
+    if (SIDE != 1) {
+        b = make_float4(ld_off(srcm, od[0]), ld_off(srcm, od[1]), ld_off(srcm, od[2]),
+                        ld_off(srcm, od[3]));
+        d = make_float4(ld_off(srcm, orf[0]), ld_off(srcm, orf[1]), ld_off(srcm, orf[2]),
+                        ld_off(srcm, orf[3]));
+    }
 }
 
 // Images of a staged position whose ring lies outside the plan's source rings
@@ -563,11 +570,13 @@ __device__ __forceinline__ void mask_sources(int mask, float4 &a, float4 &b, flo
     if (mask & 2) b = d = z;
 }
 
-// Issue the loads of a staged chunk (its record read by scalar loads).
+// Issue the loads of a staged chunk (its record read by scalar loads): all
+// four image arrays (SIDE 0) or those of one side (1: ring s, 2: its mirror).
+template <int SIDE = 0>
 __device__ __forceinline__ void prefetch_chunk(const float *in, const GenChunk &c, float4 &a,
                                                float4 &b, float4 &d2, float4 &d)
 {
-    prefetch16(in + c.first, in + c.first_m, c.n, c.two_o, c.c0, c.cn, a, b, d2, d);
+    prefetch16<SIDE>(in + c.first, in + c.first_m, c.n, c.two_o, c.c0, c.cn, a, b, d2, d);
     mask_sources(c.mask, a, b, d2, d);
 }
 
@@ -738,7 +747,7 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
     GenChunk ch{};
     if (nch > 0) {   // (a tile whose rows are all empty has no record)
         ch = C[0];
-        prefetch_chunk(in, ch, pa, pb, pc, pd);
+        prefetch_chunk<SIDE>(in, ch, pa, pb, pc, pd);
     }
     double acc[16];
     float row[16];
@@ -751,14 +760,18 @@ __device__ __forceinline__ void gen_tile2(const DevPlanView &P, const float *tab
     for (int k = 0; k < nch; ++k) {
         const GenChunk nx = C[min(k + 1, nch - 1)];
         __syncthreads();      // the previous chunk is no longer read
-        if ((int)threadIdx.x < ch.cn) {
-            stage[threadIdx.x] = pa;
-            stage[kGenStage + threadIdx.x] = pb;
-            stage[2 * kGenStage + threadIdx.x] = pc;
-            stage[3 * kGenStage + threadIdx.x] = pd;
+        if ((int)threadIdx.x < ch.cn) {   // the arrays the loop form reads
+            if (SIDE != 2) {
+                stage[threadIdx.x] = pa;
+                stage[2 * kGenStage + threadIdx.x] = pc;
+            }
+            if (SIDE != 1) {
+                stage[kGenStage + threadIdx.x] = pb;
+                stage[3 * kGenStage + threadIdx.x] = pd;
+            }
         }
         __syncthreads();
-        if (k + 1 < nch) prefetch_chunk(in, nx, pa, pb, pc, pd);
+        if (k + 1 < nch) prefetch_chunk<SIDE>(in, nx, pa, pb, pc, pd);
         // this part's row of source ring ch.s, if its ring has one
         if (len > 0 && ch.s >= my.s_lo && ch.s <= my.s_hi) {
             const DevPair pp = cst(P.pairs)[my.pb + ch.s - my.s_lo];
