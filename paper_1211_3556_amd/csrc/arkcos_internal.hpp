@@ -171,7 +171,7 @@ constexpr int kCircSeg = kThreads * kCircPix;
 constexpr int kCircMaxTaps = 256;   // taps of one circulant row (wider rows are split)
 // The circulant gather runs on the matrix cores when the plan's rows average
 // at least this many taps (a row of t taps costs products for t + 3 there).
-constexpr int kCircMfmaTaps = 12;
+constexpr int kCircMfmaTaps = 9;
 constexpr int kGenLanes = 128;       // most pixels of one ring per general tile
 constexpr int kGenThreads = 512;     // general-gather workgroup (one part of lanes per ring)
 // Built-in general-gather tile shapes (arkcos_tiles): pixels per ring, and the

@@ -411,7 +411,7 @@ def test_rotation_to_pole_host():
 
 def test_circulant_form_follows_row_width(monkeypatch):
     """Plans with short circulant rows take the vector form of the circulant
-    gather, plans whose rows average 12 taps or more the matrix-core form;
+    gather, plans whose rows average 9 taps or more the matrix-core form;
     ARKCOS_CIRC_FORM at plan creation forces either.  The log line names it."""
     import workloads as W
     def plan(tc_arcmin):
