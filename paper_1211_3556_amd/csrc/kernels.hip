@@ -1209,15 +1209,14 @@ __device__ __forceinline__ void hat_scatter(double *hist, double u, float c)
 // pixels of the kGroupRings rings of a group; its g is staged once, one array
 // per ring.  Each wave takes whole source rows (rows w, w + 4, ...
 // of the group for wave w), so a row needs no workgroup barrier: the wave
-// stages the row's x in its own LDS strip, and its lanes split into tap quads
-// q and pixel strides c.  Lane (q, c) sums g_r[4p + i] x_s[4p + i + 4q + t]
-// over the pixel quads p = c, c + nc, ... into 16 FP32 sums (4 rings x 4
-// taps); two aligned float4 reads of x and four of g (four pixels of each
-// ring; consecutive lanes read consecutive float4) feed 64 FMAs.  The nc partial sums of a (ring, tap) are then added in
-// stride order and binned with the FP64 node coordinates of k_build_knotw into
-// the wave's own histogram.
+// stages the row's x in its own LDS strip and forms the row's correlation on
+// the matrix cores, 13 taps per pass (the layout is at the loop).  Each C is
+// binned with the FP64 node coordinates of k_build_knotw into the wave's own
+// histogram.
 
-constexpr int kKnotXW = kKnotSeg + kCircMaxTaps + 8;   // staged x of one row (floats)
+// staged x of one row (floats): the matrix-core correlation reads up to
+// 16 ceil(len/16) + 13 floor((ntaps-1)/13) + 12 < kKnotSeg + kCircMaxTaps + 32
+constexpr int kKnotXW = kKnotSeg + kCircMaxTaps + 32;
 
 // Orders a wave's LDS stores before its later LDS loads (the hardware keeps a
 // wave's LDS operations in order; this keeps the compiler from moving them).
@@ -1240,7 +1239,6 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
     const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int lane = (int)threadIdx.x & 63;
     float *xs = gs + kGroupRings * kKnotSeg + wave * kKnotXW;
-    float *red = gs + kGroupRings * kKnotSeg + kKnotWaves * kKnotXW + wave * 64 * 16;
     for (int i = threadIdx.x; i < kKnotWaves * hstride; i += kThreads) hists[i] = 0.0;
     double *hist = hists + wave * hstride;   // this wave's own bins
     const int nitems = P.nkctiles * nmaps;
@@ -1286,8 +1284,6 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
         if (G.row_begin + wave < G.row_end) load_row(G.row_begin + wave);
         for (int row = G.row_begin + wave; row < G.row_end; row += kKnotWaves) {
             const DevRow W = cst(P.rows)[row];
-            const int nq = (W.ntaps + 3) >> 2;        // tap quads (<= 64)
-            const int nc = 64 / nq;                   // lanes per tap quad
             wave_lds_order();   // the previous row's reads of xs are done
 #pragma unroll
             for (int u = 0; u < kXR; ++u) {
@@ -1296,62 +1292,42 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
             }
             wave_lds_order();
             if (row + kKnotWaves < G.row_end) load_row(row + kKnotWaves);
-            // the FP64 node coordinate of this lane's first (ring, tap) entry,
-            // loaded now so that its latency hides behind the row's FMAs
+            // C(r, s, k) on the matrix cores, 13 lags k = u0 .. u0 + 12 per pass:
+            //   E[(r,p)][u] = sum_b g_r[4b + p] x[4b + u]  (M = 4 rings x 4 phases,
+            //   K = pixel blocks b, four per step, N = 16 values of u = u0 + n),
+            //   C(r, s, u0 + n) = sum_p E[(r,p)][u0 + n + p], n <= 12.
+            // Lane l holds A[(l & 15)][l >> 4] = g_r[16 ks + 4 (l >> 4) + p] with
+            // r = (l & 15) >> 2, p = l & 3, and B[l >> 4][l & 15]; it receives
+            // E[(l >> 4, c)][u0 + (l & 15)], c = 0..3, so the sum over p takes
+            // element c from lane + c of its 16-lane row.
             const double *kw = cst(P.kw) + W.w_off;
-            const double u_first = lane < 4 * W.ntaps ? kw[lane] : -1.0;
-            const int q = lane / nc;
-            const int c = lane - q * nc;
-            float acc[kGroupRings][4];
-#pragma unroll
-            for (int r = 0; r < kGroupRings; ++r)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) acc[r][t] = 0.0f;
-            if (q < nq) {
-                const float4 *x4 = reinterpret_cast<const float4 *>(xs) + q;
-                const float4 *g4 = reinterpret_cast<const float4 *>(gs);
-                for (int p = c; p < npq; p += nc) {
-                    // the quad's six LDS reads issue together, ahead of its FMAs
-                    const float4 xa = x4[p];
-                    const float4 xb = x4[p + 1];
-                    float4 gq[kGroupRings];
-#pragma unroll
-                    for (int r = 0; r < kGroupRings; ++r) gq[r] = g4[r * (kKnotSeg / 4) + p];
-                    __builtin_amdgcn_sched_barrier(0);
-                    const float xv[8] = {xa.x, xa.y, xa.z, xa.w, xb.x, xb.y, xb.z, xb.w};
-#pragma unroll
-                    for (int r = 0; r < kGroupRings; ++r) {
-                        const float gp[4] = {gq[r].x, gq[r].y, gq[r].z, gq[r].w};
-#pragma unroll
-                        for (int i = 0; i < 4; ++i)
-#pragma unroll
-                            for (int t = 0; t < 4; ++t)
-                                acc[r][t] = fmaf(gp[i], xv[i + t], acc[r][t]);
-                    }
+            const int nks = (T.len + 15) >> 4;
+            const float *ga = gs + ((lane & 15) >> 2) * kKnotSeg + 4 * (lane >> 4) + (lane & 3);
+            const float *xb = xs + 4 * (lane >> 4) + (lane & 15);
+            const int r = lane >> 4, nn = lane & 15;
+            for (int u0 = 0; u0 < W.ntaps; u0 += 13) {
+                const int k = u0 + nn;
+                const bool mine = nn < 13 && k < W.ntaps && r < G.nr;
+                // this lane's FP64 node coordinate, loaded ahead of the products
+                const double u = mine ? kw[4 * k + r] : -1.0;
+                // two accumulation chains (even and odd K steps), so that a
+                // product never waits for the one before it
+                typedef float v4f __attribute__((ext_vector_type(4)));
+                v4f d0 = {0.0f, 0.0f, 0.0f, 0.0f}, d1 = d0;
+                int ks = 0;
+                for (; ks + 1 < nks; ks += 2) {
+                    const float a0 = ga[16 * ks], b0 = xb[16 * ks + u0];
+                    const float a1 = ga[16 * ks + 16], b1 = xb[16 * ks + 16 + u0];
+                    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, d0, 0, 0, 0);
+                    d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, d1, 0, 0, 0);
                 }
-            }
-            float4 *red4 = reinterpret_cast<float4 *>(red) + 4 * lane;
-#pragma unroll
-            for (int r = 0; r < kGroupRings; ++r)
-                red4[r] = make_float4(acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
-            wave_lds_order();
-            // totals of entry o = 4 k + r (tap k, ring r) over the strides, in
-            // stride order, then binned
-            for (int o = lane; o < 4 * W.ntaps; o += 64) {
-                const int k = o >> 2, r = o & 3;
-                const float *src = red + ((k >> 2) * nc) * 16 + r * 4 + (k & 3);
-                float s0 = 0.0f, s1 = 0.0f;
-                int cc = 0;
-                for (; cc + 2 <= nc; cc += 2) {
-                    s0 += src[cc * 16];
-                    s1 += src[(cc + 1) * 16];
-                }
-                if (cc < nc) s0 += src[cc * 16];
-                const float sum = s0 + s1;
-                if (r < G.nr && sum != 0.0f) {
-                    const double u = o == lane ? u_first : kw[o];   // kw[4 k + r]
-                    if (u >= 0.0) hat_scatter(hist, u, sum);
-                }
+                if (ks < nks)
+                    d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[16 * ks], xb[16 * ks + u0], d0, 0,
+                                                              0, 0);
+                const v4f d = d0 + d1;
+                const float c = d[0] + __shfl_down(d[1], 1, 16) + __shfl_down(d[2], 2, 16) +
+                                __shfl_down(d[3], 3, 16);
+                if (mine && c != 0.0f && u >= 0.0) hat_scatter(hist, u, c);
             }
         }
     }
@@ -1600,7 +1576,7 @@ static size_t knot_hist_bytes(int ntab)
 static size_t knot_circ_lds(int ntab)
 {
     return knot_hist_bytes(ntab) + (size_t)kGroupRings * kKnotSeg * sizeof(float) +
-           (size_t)kKnotWaves * (kKnotXW + 64 * 16) * sizeof(float);
+           (size_t)kKnotWaves * kKnotXW * sizeof(float);
 }
 static size_t knot_gen_lds(int ntab)
 {
