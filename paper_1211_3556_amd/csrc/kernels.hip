@@ -1310,21 +1310,25 @@ __global__ __launch_bounds__(kThreads) void k_knot_circ(const DevPlanView *__res
                 const bool mine = nn < 13 && k < W.ntaps && r < G.nr;
                 // this lane's FP64 node coordinate, loaded ahead of the products
                 const double u = mine ? kw[4 * k + r] : -1.0;
-                // two accumulation chains (even and odd K steps), so that a
+                // four accumulation chains (K steps modulo 4), so that a
                 // product never waits for the one before it
                 typedef float v4f __attribute__((ext_vector_type(4)));
-                v4f d0 = {0.0f, 0.0f, 0.0f, 0.0f}, d1 = d0;
+                v4f d0 = {0.0f, 0.0f, 0.0f, 0.0f}, d1 = d0, d2 = d0, d3 = d0;
                 int ks = 0;
-                for (; ks + 1 < nks; ks += 2) {
+                for (; ks + 3 < nks; ks += 4) {
                     const float a0 = ga[16 * ks], b0 = xb[16 * ks + u0];
                     const float a1 = ga[16 * ks + 16], b1 = xb[16 * ks + 16 + u0];
+                    const float a2 = ga[16 * ks + 32], b2 = xb[16 * ks + 32 + u0];
+                    const float a3 = ga[16 * ks + 48], b3 = xb[16 * ks + 48 + u0];
                     d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, d0, 0, 0, 0);
                     d1 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, d1, 0, 0, 0);
+                    d2 = __builtin_amdgcn_mfma_f32_16x16x4f32(a2, b2, d2, 0, 0, 0);
+                    d3 = __builtin_amdgcn_mfma_f32_16x16x4f32(a3, b3, d3, 0, 0, 0);
                 }
-                if (ks < nks)
+                for (; ks < nks; ++ks)
                     d0 = __builtin_amdgcn_mfma_f32_16x16x4f32(ga[16 * ks], xb[16 * ks + u0], d0, 0,
                                                               0, 0);
-                const v4f d = d0 + d1;
+                const v4f d = (d0 + d1) + (d2 + d3);
                 const float c = d[0] + __shfl_down(d[1], 1, 16) + __shfl_down(d[2], 2, 16) +
                                 __shfl_down(d[3], 3, 16);
                 if (mine && c != 0.0f && u >= 0.0) hat_scatter(hist, u, c);
