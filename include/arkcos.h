@@ -67,7 +67,8 @@ enum {
 /* Largest l_cut of the harmonic-space half (one order's coefficients fit LDS). */
 #define ARKCOS_MAX_LCUT 4095
 /* Bytes of the per-device static workspace of arkcos_convolve_backward_static
- * (32 MiB: two queue counters, then the knot-gradient partial rows). */
+ * (32 MiB: the gathers' queue counters in its first 256 bytes, then the
+ * knot-gradient partial rows). */
 #define ARKCOS_STATIC_SCRATCH_BYTES (32u << 20)
 
 /*

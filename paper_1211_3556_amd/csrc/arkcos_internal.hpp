@@ -381,7 +381,7 @@ struct Batch {
 // ----------------------------------------------------------------- launch --
 // Implemented in kernels.hip.
 int launch_set_table(const Plan &p, const float *d_knots, hipStream_t s);
-// `counter` (two queue counters) and `kpart` (knot-gradient partial rows,
+// `counter` (the gathers' queue counters, three) and `kpart` (knot-gradient partial rows,
 // knot_partial_bytes) replace the plan's own workspace when non-NULL.
 int launch_forward(const Plan &p, const float *in, float *out, int nbatch, hipStream_t s,
                    int parts = ARKCOS_PART_ALL, unsigned int *counter = nullptr);

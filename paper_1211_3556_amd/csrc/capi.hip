@@ -10,7 +10,7 @@
 
 using namespace arkcos;
 
-// Workspace of arkcos_convolve_backward_static: the two queue counters of the
+// Workspace of arkcos_convolve_backward_static: the queue counters of the
 // gathers in the first 256 bytes, then the knot-gradient partial rows.  One
 // copy per device, held for the life of the process.  In host code this name
 // is only a handle: its device address comes from hipGetSymbolAddress.
