@@ -74,7 +74,12 @@ struct DevPair {
     // otherwise it is the squared chord d^2, through x^6 (sq[4] = 0).
     float mscale;
     float sq[5];
-    float pad[2];
+    // A candidate is inside the disc exactly when |m| <= mcut: the bound on
+    // the longitude numerator from the FP64 half-width on the host
+    // (|dphi| < dphi_cut with dphi = m pi / (n_r n_s)); 0x7fffffff for a
+    // whole row (every pixel of ring s inside).
+    int mcut;
+    float pad;
 };
 constexpr int kPairWhole = 1;
 constexpr int kPairLongSin = 2;

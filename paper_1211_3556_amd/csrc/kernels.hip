@@ -619,7 +619,6 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
     const float q2 = LONG ? 0.0f : vreg(pp.sq[2]);
     const float q3 = LONG ? 0.0f : vreg(pp.sq[3]);
     const float q4 = (LONG || AM != 0) ? 0.0f : vreg(pp.sq[4]);
-    const float u_max = gc.u_max;
     const UCoef &ucf = gc.ucf;
     // Candidates are addressed by LDS byte address: o steps by 16 step bytes,
     // a lane's candidates end at o_a1 and reads clamp to the chunk's last
@@ -642,6 +641,10 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
     const float dmf = vreg((float)dm * ms);
     int mi = m;
     const int dmi = vreg(dm);
+    // The disc is |m| <= mcut on the exact numerator (mf carries the same
+    // power of two on short rows); the FP32 angle only weights the pair.
+    const float mcut_f = vreg((float)pp.mcut * ms);
+    const unsigned mcut_u = (unsigned)vreg(pp.mcut);
 #pragma unroll 1
     for (int t = 0; t < T; ++t) {
         const bool valid = o <= o_a1;
@@ -667,7 +670,8 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
             u0 = node_coord<AM>(fmaf(fmaf(fmaf(y, q3, q2), y, q1), y, q0), ucf);
         }
         const float u = BIAS ? fminf(u0, fmaf(u0, gc.br, gc.bc)) : u0;
-        const float uc = (valid && u0 < u_max) ? u : zslot;
+        const bool inside = INTM ? (unsigned)mi + mcut_u <= 2u * mcut_u : fabsf(mf) <= mcut_f;
+        const float uc = (valid && inside) ? u : zslot;
         const int node = (int)uc;
         const float frac = __builtin_amdgcn_fractf(uc);
         const float k0 = tab[node];

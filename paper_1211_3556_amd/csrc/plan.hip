@@ -390,14 +390,19 @@ static int build_plan(Plan &P)
             p.a = (float)((double)S.n / (double)R.n);
             p.b = (float)(0.5 * R.two_o * (double)S.n / (double)R.n - 0.5 * S.two_o);
             // window half-width in source pixels, widened to cover FP32 rounding
-            // of the centre and of the separation near the cut
+            // of the centre; at most half the ring, so that every pixel of the
+            // window lies its shorter way round from the centre.  Membership is
+            // the exact test |m| <= mcut, with |m| < X = dphi n_r n_s / pi.
             double w = dphi * S.n / (2.0 * M_PI);
-            w = w * (1.0 + 1e-5) + 0.02;
-            if (whole || 2.0 * w + 1.0 >= (double)S.n) {
+            w = std::min(w * (1.0 + 1e-5) + 0.02, 0.5 * (double)S.n);
+            if (whole) {
                 p.mode = kPairWhole | kPairLongSin;
                 p.w = 0.0f;
+                p.mcut = 0x7fffffff;
                 per_pixel += S.n;
             } else {
+                const double X = dphi * (double)R.n * (double)S.n / M_PI;
+                p.mcut = (int)std::ceil(X) - 1;
                 // largest |dphi/2| a candidate can have: (w + 1) pixels of ring s
                 const double xmax = (w + 1.0) * M_PI / (double)S.n;
                 p.mode = xmax > (P.angle_mode == 0 ? kShortXMaxMode0 : kShortXMax) ? kPairLongSin : 0;
