@@ -243,15 +243,16 @@ struct DevPlanView {
     // u = u0 on a uniform grid (a0 = (ntab-1)/theta_cut), u = min(u0, r u0 + c)
     // on the two-piece biased grid (a0 = k_break/theta_break the fine piece's
     // 1/h; r u0 + c the coarse piece's coordinate, which is the smaller one
-    // beyond the break).  r = 1 and c = 0 on a uniform grid.
+    // beyond the break).  r = 1 and c = 0 on a uniform grid.  The FP32 gather
+    // counts the coarse coordinate from the break instead: u = k_break + v,
+    // v = r u0 + bias_c with bias_c = -r k_break (v >= 0 beyond the break).
     int src_lo;              // source rings read (0-based, inclusive): images of rings
     int src_hi;              // outside count as zero (the adjoint of a ring range)
     int biased;
+    int k_break;             // node index of the break (0 on a uniform grid)
     float inv_h;             // a0
-    float u_max;             // ntab - 1 (strict upper bound of u)
-    float u0_max;            // a0 theta_cut: the cut, tested on u0
     float bias_r;
-    float bias_c;
+    float bias_c;            // -r k_break
     float u_coef[6];         // a0 times the coefficients of the short angle series
 };
 

@@ -584,20 +584,23 @@ __device__ __forceinline__ void prefetch_chunk(const float *in, const GenChunk &
 template <int AM>
 struct GenConst {
     float zslot;     // index of the table's zero entries
-    float u_max;     // the cut on u0 (u0_max; ntab - 1 on a uniform grid)
-    float br, bc;    // coarse-piece map of a biased grid
+    float br, bc;    // coarse coordinate from the break of a biased grid, br u0 + bc
+    int kb;          // node index of the break
     UCoef ucf;
     __device__ __forceinline__ GenConst(const DevPlanView &P)
-        : zslot(vreg((float)P.ntab)), u_max(vreg(P.u0_max)), br(vreg(P.bias_r)),
-          bc(vreg(P.bias_c)), ucf(ucoef<AM>(P)) {}
+        : zslot(vreg((float)P.ntab)), br(vreg(P.bias_r)), bc(vreg(P.bias_c)),
+          kb(vreg(P.k_break)), ucf(ucoef<AM>(P)) {}
 };
 
 // T candidates jq, jq + step, ... of one lane in the staged chunk; those past
 // a1 get the table's zero slot.  T is the wave's largest count.  One
 // candidate per iteration: its staged reads issue first and overlap the
 // weight arithmetic (unrolled by two, the loop spills at 128 VGPRs).
-// BIAS: the plan's node grid is the two-piece biased one, u = min(u0, r u0 + c);
-// otherwise u = u0 and the map costs nothing.
+// BIAS: the plan's node grid is the two-piece biased one.  Beyond the break
+// the candidate's node is k_break + v, v = r u0 - r k_break counted from the
+// break, so that v keeps FP32's relative precision there (k_break + v in one
+// float would round it to ~1e-3 of a coarse node); otherwise u = u0 and the
+// map costs nothing.
 // SIDE 0: all sixteen images; SIDE 1 (2): only the ring's (the mirror ring's)
 // eight, for tiles whose other half lies outside a ring-range plan.
 template <bool LONG, int AM, bool INTM, bool BIAS, int SIDE>
@@ -645,6 +648,11 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
     // power of two on short rows); the FP32 angle only weights the pair.
     const float mcut_f = vreg((float)pp.mcut * ms);
     const unsigned mcut_u = (unsigned)vreg(pp.mcut);
+    // the node table by LDS byte address, and its coarse piece's node 0 (the
+    // break) in a vector register, so that choosing between them is one select
+    typedef __attribute__((address_space(3))) const float lds_float;
+    const int tab_b = (int)(size_t)(lds_float *)tab;
+    const int tab_cb = BIAS ? vreg(tab_b + 4 * gc.kb) : tab_b;
 #pragma unroll 1
     for (int t = 0; t < T; ++t) {
         const bool valid = o <= o_a1;
@@ -669,13 +677,17 @@ __device__ __forceinline__ void gen_candidates16(const DevPair &pp, const GenCon
             const float y = mf * mf;
             u0 = node_coord<AM>(fmaf(fmaf(fmaf(y, q3, q2), y, q1), y, q0), ucf);
         }
-        const float u = BIAS ? fminf(u0, fmaf(u0, gc.br, gc.bc)) : u0;
+        const float v = BIAS ? fmaf(u0, gc.br, gc.bc) : 0.0f;
+        const bool coarse = BIAS && v >= 0.0f;
         const bool inside = INTM ? (unsigned)mi + mcut_u <= 2u * mcut_u : fabsf(mf) <= mcut_f;
-        const float uc = (valid && inside) ? u : zslot;
+        const bool keep = valid && inside;
+        const float uc = keep ? (coarse ? v : u0) : zslot;
+        const int tb = (keep && coarse) ? tab_cb : tab_b;   // the coarse piece from the break
         const int node = (int)uc;
         const float frac = __builtin_amdgcn_fractf(uc);
-        const float k0 = tab[node];
-        const float k1 = tab[node + 1];
+        lds_float *kp = (lds_float *)(size_t)(tb + 4 * node);
+        const float k0 = kp[0];
+        const float k1 = kp[1];
         const float w = fmaf(frac, k1 - k0, k0);
         row[0] = fmaf(w, v0.x, row[0]);
         row[1] = fmaf(w, v0.y, row[1]);

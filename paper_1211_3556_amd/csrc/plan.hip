@@ -174,10 +174,12 @@ DevPlanView Plan::view() const
     v.bias_r_d = r;
     v.bias_c_d = c0;
     v.inv_h = (float)ih;
-    v.u_max = (float)(desc.ntab - 1);
-    v.u0_max = biased ? (float)(ih * desc.theta_cut) : v.u_max;
+    v.k_break = biased ? desc.k_break : 0;
     v.bias_r = (float)r;
-    v.bias_c = (float)c0;
+    // the FP32 gather's coarse coordinate from the break, v = r u0 - r k_break,
+    // with the product of the FP32 r exact in FP64, so that v = 0 at u0 = k_break
+    // to within one rounding
+    v.bias_c = (float)(-(double)v.bias_r * (double)v.k_break);
     // theta = d (1 + d^2/24 + 3 d^4/640 + 5 d^6/7168 + 35 d^8/294912 + 63 d^10/2883584)
     const double c[6] = {1.0, 1.0 / 24.0, 3.0 / 640.0, 5.0 / 7168.0, 35.0 / 294912.0,
                          63.0 / 2883584.0};

@@ -165,7 +165,9 @@ def test_split_example_240_arcmin_sampled():
     (l <= 4096), theta_cut 240 arcmin, 16384 biased nodes; about 61000 pairs
     per output pixel, on sampled pixels of every ring class.  This kernel
     oscillates across the whole disc (angle condition ~11, against ~1.4 for
-    the Gaussian beams), so the error bar is the FP32-angle bound."""
+    the Gaussian beams), so it is the hardest case for the FP32 angle and the
+    FP32 node coordinate beyond the break; it is held to the same 1e-6 bar as
+    the beams, and the FP32-angle bound is logged beside it."""
     s = W.SPLIT_EXAMPLE
     A = _A()
     mask = W.high_ell_mask(s.ell_max)
@@ -181,8 +183,8 @@ def test_split_example_240_arcmin_sampled():
     ref = O.convolve(s.nside, s.theta_cut, ko, x, pixels=pix, nodes=nodes)
     err = rel_rms(y[pix], ref)
     tol = angle_tolerance(s.theta_cut, ko, nodes)
-    log("split example rel rms %.3e over %d pixels (bar %.2e)" % (err, pix.size, tol))
-    assert err <= tol
+    log("split example rel rms %.3e over %d pixels (angle bound %.2e)" % (err, pix.size, tol))
+    assert err <= REL_RMS_TOL
 
 
 def test_mixed_uniform_and_biased_batch():
