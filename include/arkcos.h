@@ -401,7 +401,10 @@ int arkcos_batch_destroy(arkcos_batch_t batch);
  * tuning cache is a text file with one line per (arch, Nside, window class):
  *     <arch> <nside> <class> <gen_pixels> <gen_quad_window> <gen_pair_window> <ms>
  * ('#' starts a comment; a later line for the same key wins).  The window
- * class is round(2 log2(theta_cut / sqrt(Omega))), Omega = 4 pi / Npix.
+ * class is round(2 log2(theta_cut / sqrt(Omega))), Omega = 4 pi / Npix, plus
+ * ARKCOS_TUNE_RANGE_CLASS for a descriptor with an output ring range that is
+ * not the whole sky (such plans tile part of the general rings only and keep
+ * entries of their own).
  *
  * arkcos_set_tune_cache: the cache that plans with all-zero tiles read at
  * creation (copied; NULL or "" = none).  Until it is called the environment
@@ -409,9 +412,12 @@ int arkcos_batch_destroy(arkcos_batch_t batch);
  */
 int arkcos_set_tune_cache(const char *path);
 
+#define ARKCOS_TUNE_RANGE_CLASS 100
+
 /*
- * The cache key of a descriptor: arch (the current device's gfx name, or the
- * library's build target gfx950 without a device), Nside and window class.
+ * The cache key of a whole-sky descriptor: arch (the current device's gfx
+ * name, or the library's build target gfx950 without a device), Nside and
+ * window class (a ring-range descriptor adds ARKCOS_TUNE_RANGE_CLASS).
  *   arch  host buffer of len bytes, NUL-terminated on return (may be NULL)  [out]
  * EINVAL on a bad nside / theta_cut.
  */

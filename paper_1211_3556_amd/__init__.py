@@ -256,12 +256,17 @@ def set_tune_cache(path) -> None:
     _call("arkcos_set_tune_cache", None if path is None else str(path).encode())
 
 
-def tune_key(nside: int, theta_cut: float) -> tuple[str, int]:
-    """(arch, window class) of the tuning-cache key of (nside, theta_cut)."""
+TUNE_RANGE_CLASS = 100   # ARKCOS_TUNE_RANGE_CLASS
+
+
+def tune_key(nside: int, theta_cut: float, rings=None) -> tuple[str, int]:
+    """(arch, window class) of the tuning-cache key of (nside, theta_cut); a
+    ring range other than the whole sky adds TUNE_RANGE_CLASS."""
     buf = ctypes.create_string_buffer(64)
     cls = ctypes.c_int()
     _call("arkcos_tune_key", int(nside), float(theta_cut), buf, 64, ctypes.byref(cls))
-    return buf.value.decode(), cls.value
+    whole = rings is None or (rings[0] <= 1 and rings[1] >= 4 * int(nside) - 1)
+    return buf.value.decode(), cls.value + (0 if whole else TUNE_RANGE_CLASS)
 
 
 def tune(nside: int, theta_cut: float, ntab: int, ktab=None, reps: int = 5, cache=None,

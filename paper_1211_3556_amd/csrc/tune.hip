@@ -50,6 +50,17 @@ int window_class(int nside, double theta_cut)
     return (int)std::lround(2.0 * std::log2(theta_cut / pix));
 }
 
+// Tuning-cache class of a descriptor: the window class, plus
+// ARKCOS_TUNE_RANGE_CLASS for a plan restricted to a ring range.  Such a plan
+// tiles only part of the general rings, and its one-sided tiles run the
+// eight-image loop, so its best tiles are kept apart from the full sky's.
+int tune_class(const arkcos_plan_desc &d)
+{
+    const bool all = (d.ring_first == 0 && d.ring_last == 0) ||
+                     (d.ring_first <= 1 && d.ring_last >= 4 * d.nside - 1);
+    return window_class(d.nside, d.theta_cut) + (all ? 0 : ARKCOS_TUNE_RANGE_CLASS);
+}
+
 struct CacheEntry {
     arkcos_tiles tiles;
     double ms;
@@ -106,8 +117,7 @@ int resolve_tiles(const arkcos_plan_desc &d, arkcos_tiles *out, int *source)
     *source = 0;
     if (t.gen_pixels == 0 && t.gen_quad_window == 0 && t.gen_pair_window == 0) {
         CacheEntry e;
-        if (cache_lookup(cache_path(), device_arch(), d.nside, window_class(d.nside, d.theta_cut),
-                         &e)) {
+        if (cache_lookup(cache_path(), device_arch(), d.nside, tune_class(d), &e)) {
             *out = e.tiles;
             *source = 1;
         }
@@ -265,7 +275,7 @@ int arkcos_tune(const arkcos_plan_desc *desc, int reps, const char *cache_file,
         FILE *f = fopen(cache_file, "a");
         if (!f) return done(fail(ARKCOS_EINVAL, std::string("cannot append to ") + cache_file));
         fprintf(f, "%s %d %d %d %d %d %.6f\n", device_arch().c_str(), desc->nside,
-                window_class(desc->nside, desc->theta_cut), cur.gen_pixels, cur.gen_quad_window,
+                tune_class(*desc), cur.gen_pixels, cur.gen_quad_window,
                 cur.gen_pair_window, t_best);
         fclose(f);
     }

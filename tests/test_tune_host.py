@@ -64,6 +64,28 @@ def test_tune_cache_lookup_and_precedence(tmp_path):
         _restore_cache()
 
 
+def test_ring_range_plans_keep_their_own_cache_entries(tmp_path):
+    """A plan restricted to a ring range reads the entry of its window class
+    plus TUNE_RANGE_CLASS; the whole sky, also when given as the full ring
+    range, reads the plain class."""
+    tc = np.radians(6.0)
+    arch, cls = A.tune_key(64, tc)
+    assert A.tune_key(64, tc, (1, 40)) == (arch, cls + A.TUNE_RANGE_CLASS)
+    assert A.tune_key(64, tc, (1, 255)) == (arch, cls)
+    path = tmp_path / "tiles.txt"
+    path.write_text("%s 64 %d 64 32 400 1.0\n%s 64 %d 32 96 800 0.5\n"
+                    % (arch, cls, arch, cls + A.TUNE_RANGE_CLASS))
+    try:
+        A.set_tune_cache(str(path))
+        whole = dict(gen_pixels=64, gen_quad_window=32, gen_pair_window=400)
+        part = dict(gen_pixels=32, gen_quad_window=96, gen_pair_window=800)
+        for rings, want in ((None, whole), ((1, 255), whole), ((1, 40), part), ((30, 200), part)):
+            inf = A.Plan(64, tc, np.ones(8), host_only=True, rings=rings).info()
+            assert inf["tile_source"] == 1 and inf["tile_shapes"] == want, rings
+    finally:
+        _restore_cache()
+
+
 def _general_north_rings(nside):
     g = O.ring_geometry(nside)
     out = {}
